@@ -1,0 +1,205 @@
+// CPU oracle for pipeline programs: TEST INFRASTRUCTURE ONLY (see oracle.h).
+//
+// Column-at-a-time interpretation of the operations of the paper's pipeline
+// program table (Section 3.1, Table 1):
+//   LOOP           -> selection vector of all row ids, ascending
+//   FILTER         -> keep ids whose attribute lies in [lo, hi] (conjunction,
+//                     one predicate after the other)
+//   HASH_PUT       -> build pipeline: filter the dimension, then an ordered
+//                     map key -> payload (a repeated key is an error)
+//   HASH_PROBE     -> inner equi-join: keep ids whose key is in the map and
+//                     remember the payload
+//   ARITHMETIC     -> binary +, -, * over attributes/constants, 64-bit two's
+//                     complement
+//   AGGREGATE / HASH_AGGREGATE -> fold COUNT/SUM/MIN/MAX/AVG per group in an
+//                     ordered map; sums are exact 128-bit, narrow sums are the
+//                     low 64 bits of that
+//   PROJECT        -> the attributes of the surviving ids, in row order
+// The result is the plain relational answer; every variant of the paper's
+// variant space must reproduce it (Section 3.4: variations are orthogonal and
+// do not change the pipeline's semantics).
+#include "oracle.h"
+
+#include <climits>
+#include <cstring>
+#include <map>
+#include <vector>
+
+namespace {
+
+typedef __int128 i128;
+
+struct Result {
+  int kind = 0;
+  int64_t rows = 0;
+  std::vector<std::vector<int64_t>> proj;      // [col][row]
+  std::vector<std::vector<int64_t>> keys;      // [g][row]
+  std::vector<int64_t> count;                  // [row]
+  std::vector<std::vector<i128>> vals;         // [agg][row]
+  std::vector<int> fns;
+};
+
+int64_t load(const orc_col& c, int64_t i) {
+  switch (c.dtype) {
+    case ORC_I8: return static_cast<const int8_t*>(c.data)[i];
+    case ORC_I32: return static_cast<const int32_t*>(c.data)[i];
+    default: return static_cast<const int64_t*>(c.data)[i];
+  }
+}
+
+// FILTER: refine a selection vector, one conjunct at a time.
+std::vector<int64_t> select(int64_t n, const orc_col* cols, int32_t nf, const orc_filter* f) {
+  std::vector<int64_t> sv(static_cast<size_t>(n));
+  for (int64_t i = 0; i < n; ++i) sv[i] = i;
+  for (int32_t k = 0; k < nf; ++k) {
+    std::vector<int64_t> next;
+    next.reserve(sv.size());
+    const orc_col& c = cols[f[k].col];
+    for (int64_t i : sv) {
+      int64_t x = load(c, i);
+      if (x >= f[k].lo && x <= f[k].hi) next.push_back(i);
+    }
+    sv.swap(next);
+  }
+  return sv;
+}
+
+int64_t wrap(uint64_t v) { int64_t r; std::memcpy(&r, &v, 8); return r; }
+
+}  // namespace
+
+struct orc_result : Result {};
+
+extern "C" int32_t orc_run(const orc_build* builds, int32_t nbuilds, const orc_main* m,
+                           orc_result** out) {
+  if (!m || !out || m->nrows < 0) return ORC_E_ARG;
+  // build pipelines: LOOP, FILTER, HASH_PUT
+  std::vector<std::map<int64_t, int64_t>> tables(static_cast<size_t>(nbuilds));
+  for (int32_t b = 0; b < nbuilds; ++b) {
+    const orc_build& B = builds[b];
+    std::vector<int64_t> sv = select(B.nrows, B.cols, B.nfilters, B.filters);
+    for (int64_t i : sv) {
+      int64_t key = load(B.cols[B.key_col], i);
+      int64_t pay = load(B.cols[B.payload_col], i);
+      if (!tables[b].emplace(key, pay).second) return ORC_E_DUPKEY;
+    }
+  }
+  // main pipeline
+  std::vector<int64_t> sv = select(m->nrows, m->cols, m->nfilters, m->filters);
+  const int32_t nattr = m->ncols + m->nprobes + m->narith;
+  // computed attributes, materialised over the selection vector
+  std::vector<std::vector<int64_t>> comp(static_cast<size_t>(m->nprobes + m->narith));
+  for (int32_t p = 0; p < m->nprobes; ++p) {
+    const orc_probe& P = m->probes[p];
+    if (P.build < 0 || P.build >= nbuilds) return ORC_E_ARG;
+    const auto& T = tables[P.build];
+    std::vector<int64_t> keep;
+    std::vector<size_t> pos;
+    std::vector<int64_t> pay;
+    for (size_t j = 0; j < sv.size(); ++j) {
+      auto it = T.find(load(m->cols[P.fk_col], sv[j]));
+      if (it != T.end()) { keep.push_back(sv[j]); pos.push_back(j); pay.push_back(it->second); }
+    }
+    // earlier payloads follow the shrinking selection vector
+    for (int32_t q = 0; q < p; ++q) {
+      std::vector<int64_t> v(pos.size());
+      for (size_t j = 0; j < pos.size(); ++j) v[j] = comp[q][pos[j]];
+      comp[q].swap(v);
+    }
+    comp[p].swap(pay);
+    sv.swap(keep);
+  }
+  auto attr = [&](int32_t a, size_t j) -> int64_t {
+    if (a < m->ncols) return load(m->cols[a], sv[j]);
+    return comp[a - m->ncols][j];
+  };
+  for (int32_t k = 0; k < m->narith; ++k) {
+    const orc_arith& A = m->arith[k];
+    std::vector<int64_t>& dst = comp[m->nprobes + k];
+    dst.resize(sv.size());
+    for (size_t j = 0; j < sv.size(); ++j) {
+      uint64_t x = static_cast<uint64_t>(A.x_const ? A.xc : attr(A.x, j));
+      uint64_t y = static_cast<uint64_t>(A.y_const ? A.yc : attr(A.y, j));
+      uint64_t r = A.op == ORC_ADD ? x + y : A.op == ORC_SUB ? x - y : x * y;
+      dst[j] = wrap(r);
+    }
+  }
+  Result res;
+  res.kind = m->kind;
+  if (m->kind == ORC_PROJECT) {
+    res.rows = static_cast<int64_t>(sv.size());
+    res.proj.resize(static_cast<size_t>(m->nproj));
+    for (int32_t c = 0; c < m->nproj; ++c) {
+      if (m->proj[c] < 0 || m->proj[c] >= nattr) return ORC_E_ARG;
+      res.proj[c].resize(sv.size());
+      for (size_t j = 0; j < sv.size(); ++j) res.proj[c][j] = attr(m->proj[c], j);
+    }
+  } else {
+    struct Acc { int64_t count = 0; std::vector<i128> v; };
+    std::map<std::vector<int64_t>, Acc> groups;
+    std::vector<i128> init(static_cast<size_t>(m->naggs));
+    for (int32_t a = 0; a < m->naggs; ++a)
+      init[a] = m->aggs[a].fn == ORC_MIN ? i128(INT64_MAX) : m->aggs[a].fn == ORC_MAX ? i128(INT64_MIN) : 0;
+    if (m->ngroup == 0) groups[std::vector<int64_t>()].v = init;  // AGGREGATE: one row even when empty
+    std::vector<int64_t> key(static_cast<size_t>(m->ngroup));
+    for (size_t j = 0; j < sv.size(); ++j) {
+      for (int32_t g = 0; g < m->ngroup; ++g) key[g] = attr(m->group[g], j);
+      auto it = groups.find(key);
+      if (it == groups.end()) { it = groups.emplace(key, Acc()).first; it->second.v = init; }
+      Acc& acc = it->second;
+      acc.count += 1;
+      for (int32_t a = 0; a < m->naggs; ++a) {
+        const orc_agg& A = m->aggs[a];
+        if (A.fn == ORC_COUNT) continue;
+        int64_t x = attr(A.attr, j);
+        if (A.fn == ORC_SUM || A.fn == ORC_AVG) acc.v[a] += x;
+        else if (A.fn == ORC_MIN) { if (x < acc.v[a]) acc.v[a] = x; }
+        else if (A.fn == ORC_MAX) { if (x > acc.v[a]) acc.v[a] = x; }
+      }
+    }
+    res.rows = static_cast<int64_t>(groups.size());
+    res.keys.assign(static_cast<size_t>(m->ngroup), std::vector<int64_t>());
+    res.vals.assign(static_cast<size_t>(m->naggs), std::vector<i128>());
+    for (int32_t a = 0; a < m->naggs; ++a) res.fns.push_back(m->aggs[a].fn);
+    for (auto& kv : groups) {
+      for (int32_t g = 0; g < m->ngroup; ++g) res.keys[g].push_back(kv.first[g]);
+      res.count.push_back(kv.second.count);
+      for (int32_t a = 0; a < m->naggs; ++a) {
+        const orc_agg& A = m->aggs[a];
+        i128 v = A.fn == ORC_COUNT ? i128(kv.second.count) : kv.second.v[a];
+        // a narrow SUM keeps the low 64 bits (two's complement), as 64-bit hardware does
+        if (A.fn == ORC_SUM && !A.wide) v = i128(wrap(static_cast<uint64_t>(v)));
+        res.vals[a].push_back(v);
+      }
+    }
+  }
+  orc_result* r = new orc_result();
+  static_cast<Result&>(*r) = std::move(res);
+  *out = r;
+  return ORC_OK;
+}
+
+extern "C" void orc_free(orc_result* r) { delete r; }
+extern "C" int64_t orc_rows(const orc_result* r) { return r->rows; }
+
+extern "C" void orc_project_column(const orc_result* r, int32_t c, int64_t* dst) {
+  if (!r->proj[c].empty()) std::memcpy(dst, r->proj[c].data(), r->proj[c].size() * 8);
+}
+extern "C" void orc_group_key(const orc_result* r, int32_t g, int64_t* dst) {
+  if (!r->keys[g].empty()) std::memcpy(dst, r->keys[g].data(), r->keys[g].size() * 8);
+}
+extern "C" void orc_group_count(const orc_result* r, int64_t* dst) {
+  if (!r->count.empty()) std::memcpy(dst, r->count.data(), r->count.size() * 8);
+}
+extern "C" void orc_agg_value(const orc_result* r, int32_t a, uint64_t* lo, int64_t* hi) {
+  for (size_t j = 0; j < r->vals[a].size(); ++j) {
+    i128 v = r->vals[a][j];
+    lo[j] = static_cast<uint64_t>(v);
+    hi[j] = static_cast<int64_t>(v >> 64);
+  }
+}
+// AVG: the exact sum converted to double (round to nearest), divided by the count.
+extern "C" void orc_agg_avg(const orc_result* r, int32_t a, double* dst) {
+  for (size_t j = 0; j < r->vals[a].size(); ++j)
+    dst[j] = static_cast<double>(r->vals[a][j]) / static_cast<double>(r->count[j]);
+}
