@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of the pipeline hot path on one MI355X.
+
+A step is one pass of the whole hot path over the configured workload: every
+pipeline of the workload runs once (build pipelines, scan, selection, probes,
+arithmetic, aggregation or projection, result extraction) in the variant the
+variant optimizer picked for it. Inputs are resident in HBM before the timed
+region; K steps are timed between stream synchronisations.
+
+Default workload (N=1): grouped aggregation over 64M rows with an int32 key
+and an int64 value, COUNT/SUM/MIN/MAX per group, once with 16 uniform groups
+and once with zipf(1.1) keys over 1M ranks (the two grouped-aggregation
+cases). `value` is input rows per second of the whole step.
+
+Also reported: the dominant kernel's roofline (algorithmic bytes per launch /
+its average launch duration, timed live with HIP events on the library's
+stream), per-pipeline rows/s and GB/s, and the CPU oracle timed on a bounded
+sample of the same workload on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "input rows/s + HBM GB/s per pipeline; learned-pick vs best-variant runtime ratio"
+
+# variants used by the timed steps, per workload pipeline (chosen by the
+# variant optimizer on this device; see the design doc for how they were found)
+DEFAULT_VARIANTS = {
+    "c1": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=1024, wg_size=256),
+    "c2u": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=8, wg_size=256),
+    "c2z": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=8, wg_size=256),
+    "c3": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=8, wg_size=256),
+    "c4": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=8, wg_size=256),
+}
+
+# algorithmic bytes read per input row of each pipeline (columns the
+# pipeline must read once), plus the kernel family that dominates it
+ALGO_BYTES_PER_ROW = {"c1": None, "c2u": 12, "c2z": 12, "c3": 24, "c4": 22}
+WORKLOADS = {
+    "c1": ["c1"],
+    "c2": ["c2u", "c2z"],
+    "c3": ["c3"],
+    "c4": ["c4"],
+}
+DESCRIPTION = {
+    "c1": "selection+projection: 1M rows, 4 int32 cols uniform [0,1000), a<100 AND 200<=b<700, out int64 c*d+a in row order",
+    "c2": "grouped aggregation: 64M rows int32 key + int64 value uniform [0,1e6); 16 uniform groups and zipf(1.1) over 1M ranks; COUNT/SUM/MIN/MAX",
+    "c3": "star join: 120M-row fact, 4 int32 FKs into dims 2.5k/200k/30k/80k filtered 20/5/20/1 %, SUM(int64 rev) by (d0.g, d2.g)",
+    "c4": "wide scan-aggregate: 600M rows, 6 skewed groups, 8 aggregates incl. exact 128-bit SUM(price*(100-disc)*(100+tax))",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_pipelines(workload, rows):
+    from paper_1709_00700_amd import datagen as dg
+    out = []
+    for name in WORKLOADS[workload]:
+        kw = {} if rows is None else {"n": rows}
+        tables, spec = dg.workload(name, **kw)
+        # one table namespace per pipeline
+        ren = {t: f"{name}_{t}" for t in tables}
+        tables = {ren[t]: c for t, c in tables.items()}
+        spec["main"]["table"] = ren[spec["main"]["table"]]
+        for b in spec["builds"]:
+            b["table"] = ren[b["table"]]
+        out.append((name, tables, spec))
+    return out
+
+
+def cpu_baseline(workload, budget_s=20.0):
+    """The oracle as it stands, single-threaded, on a bounded sample of the workload."""
+    import oracle
+    from paper_1709_00700_amd import datagen as dg
+    rows_done, secs, samples = 0, 0.0, []
+    names = WORKLOADS[workload]
+    n = 1 << 20
+    while secs < budget_s and n <= (1 << 26):
+        for name in names:
+            tables, spec = dg.workload(name, n=n) if name != "c3" else dg.workload(name, n=n)
+            t0 = time.perf_counter()
+            oracle.run(tables, spec)
+            dt = time.perf_counter() - t0
+            rows_done += n
+            secs += dt
+            samples.append(f"{name}:{n}")
+        n *= 2
+    return {"value": rows_done / secs, "unit": "rows/s", "cores": 1, "kind": "oracle",
+            "sample": f"first rows of the same seeded workload: {', '.join(samples)} ({secs:.1f} s total)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--rows", type=int, default=None, help="override the input rows per pipeline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build does not run across several GPUs "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1709_00700_amd import hawk
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ctx = hawk.Context(0)
+    ncu, _ = ctx.device_info()
+    pipes = []
+    total_rows = 0
+    for name, tables, spec in make_pipelines(args.workload, args.rows):
+        log(f"[bench] generating + uploading {name}")
+        ctx.register_numpy(tables)
+        q = hawk.build_query(ctx, spec)
+        v = hawk.variant(**DEFAULT_VARIANTS[name])
+        nrows = len(next(iter(tables[spec["main"]["table"]].values())))
+        total_rows += nrows
+        pipes.append((name, q, v, nrows))
+        del tables
+    stream = ctx.stream
+
+    def step():
+        for _, q, v, _ in pipes:
+            hawk.execute(ctx, q, v, sync=False).free()
+
+    # warm-up, checked end to end once
+    for name, q, v, _ in pipes:
+        r = hawk.execute(ctx, q, v)
+        r.info()
+        r.free()
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = e0.elapsed_time(e1) / args.steps
+    value = total_rows / (ms_per_step / 1e3)
+
+    # per-pipeline times and the dominant kernel, timed with events on the library stream
+    per = []
+    kern_stats = {}
+    for name, q, v, nrows in pipes:
+        ms = hawk.time_variant(ctx, q, v, reps=max(5, args.steps // 2))
+        hawk.profile_enable(ctx, True)
+        for _ in range(max(5, args.steps // 2)):
+            hawk.execute(ctx, q, v, sync=False).free()
+        fams = ["k_agg", "k_scalar_agg", "k_mp_filter", "k_mp_project", "k_sp", "k_build", "k_finalize",
+                "k_init_aggtable", "k_scan", "k_sp_concat"]
+        stats = {f: hawk.profile_read(ctx, f) for f in fams}
+        hawk.profile_enable(ctx, False)
+        stats = {f: (t / n, n) for f, (t, n) in stats.items() if n}
+        dom = max(stats, key=lambda f: stats[f][0])
+        bpr = ALGO_BYTES_PER_ROW[name]
+        entry = {"pipeline": name, "rows": nrows, "ms": ms, "rows_per_s": nrows / (ms / 1e3),
+                 "variant": hawk.format_variant(v), "dominant_kernel": dom, "kernel_ms": stats[dom][0],
+                 "kernels_ms": {f: round(s[0], 4) for f, s in stats.items()}}
+        if bpr:
+            entry["algo_gb_per_s"] = nrows * bpr / (ms / 1e3) / 1e9
+            entry["kernel_algo_gb_per_s"] = nrows * bpr / (stats[dom][0] / 1e3) / 1e9
+        per.append(entry)
+        kern_stats.setdefault(dom, []).append((stats[dom][0], nrows * (bpr or 0)))
+    # roofline of the dominant kernel over the step: algorithmic bytes per launch / average launch duration
+    dom = max(kern_stats, key=lambda f: sum(t for t, _ in kern_stats[f]))
+    launches = kern_stats[dom]
+    avg_ms = sum(t for t, _ in launches) / len(launches)
+    avg_bytes = sum(b for _, b in launches) / len(launches)
+    achieved = avg_bytes / (avg_ms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "algo_bytes_per_launch": avg_bytes, "avg_launch_ms": round(avg_ms, 4)}
+
+    out = {"metric": METRIC, "value": value, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": DESCRIPTION[args.workload], "pipelines": [p[0] for p in pipes],
+                      "rows_per_step": total_rows, "compute_units": ncu},
+           "roofline": roofline, "per_pipeline": per, "wall_s_timed": wall}
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

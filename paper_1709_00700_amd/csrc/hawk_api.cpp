@@ -1,0 +1,965 @@
+// C ABI of the pipeline-variant library: contexts, table registry, pipeline
+// program validation and lowering (Section 3.1), variant space (Section 9.2),
+// the per-strategy dispatcher that sequences the kernels of a variant
+// (Section 3.4: one interpreter per execution strategy routes the
+// operations into one or more kernels), results and timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "hawk.h"
+#include "hawk_internal.h"
+#include "hawk_launch.h"
+#include "hawk_plan.h"
+
+namespace {
+
+const uint32_t kMults[7] = {1, 8, 64, 256, 1024, 16384, 65536};  // Section 9.2
+const uint32_t kWgs[7] = {16, 32, 64, 128, 256, 512, 1024};       // Section 9.2
+const int64_t kLdsBudget = 32768;  // bytes of LDS per workgroup for a local table
+const int kMaxAttempts = 12;
+
+uint64_t splitmix(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint32_t ceil_log2(uint64_t x) {
+  uint32_t l = 0;
+  while ((1ull << l) < x) ++l;
+  return l;
+}
+
+int dtype_bytes(int32_t t) { return t == HAWK_I8 ? 1 : t == HAWK_I32 ? 4 : 8; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ device memory pool
+void* DevicePool::get(size_t bytes) {
+  if (bytes < 256) bytes = 256;
+  bytes = (bytes + 255) & ~static_cast<size_t>(255);
+  int best = -1;
+  for (size_t i = 0; i < blocks.size(); ++i) {
+    const Block& b = blocks[i];
+    if (b.used || b.bytes < bytes || b.bytes > 2 * bytes + (1u << 20)) continue;
+    if (best < 0 || b.bytes < blocks[best].bytes) best = static_cast<int>(i);
+  }
+  if (best >= 0) {
+    blocks[best].used = true;
+    return blocks[best].p;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    // release idle blocks and try once more
+    for (auto it = blocks.begin(); it != blocks.end();) {
+      if (!it->used) {
+        (void)hipFree(it->p);
+        it = blocks.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  blocks.push_back({p, bytes, true});
+  return p;
+}
+
+void DevicePool::put(void* p) {
+  if (!p) return;
+  for (auto& b : blocks)
+    if (b.p == p) b.used = false;
+}
+
+void DevicePool::release_all() {
+  for (auto& b : blocks) (void)hipFree(b.p);
+  blocks.clear();
+}
+
+// ------------------------------------------------------------------ errors
+hawk_status set_error(hawk_ctx* ctx, hawk_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+static hawk_status hip_error(hawk_ctx* ctx, hipError_t e, const char* where) {
+  return set_error(ctx, HAWK_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ kernel profiling
+static hipEvent_t prof_event(hawk_ctx* ctx) {
+  if (!ctx->prof_free.empty()) {
+    hipEvent_t e = ctx->prof_free.back();
+    ctx->prof_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+ProfScope::ProfScope(hawk_ctx* c, const char* name) : ctx(c), idx(static_cast<size_t>(-1)) {
+  if (!ctx->prof_on) return;
+  ProfRec r{name, prof_event(ctx), prof_event(ctx)};
+  if (!r.a || !r.b) return;
+  (void)hipEventRecord(r.a, ctx->stream);
+  ctx->prof.push_back(r);
+  idx = ctx->prof.size() - 1;
+}
+
+ProfScope::~ProfScope() {
+  if (idx != static_cast<size_t>(-1)) (void)hipEventRecord(ctx->prof[idx].b, ctx->stream);
+}
+
+static void prof_clear(hawk_ctx* ctx) {
+  for (auto& r : ctx->prof) {
+    ctx->prof_free.push_back(r.a);
+    ctx->prof_free.push_back(r.b);
+  }
+  ctx->prof.clear();
+}
+
+extern "C" hawk_status hawk_profile_enable(hawk_ctx* ctx, int32_t on) {
+  if (!ctx) return HAWK_E_ARG;
+  if (ctx->device < 0) return set_error(ctx, HAWK_E_DEVICE, "planning context cannot execute");
+  (void)hipStreamSynchronize(ctx->stream);
+  prof_clear(ctx);
+  ctx->prof_on = on != 0;
+  return HAWK_OK;
+}
+
+extern "C" hawk_status hawk_profile_read(hawk_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches) {
+  if (!ctx || !kernel || !total_ms || !launches) return HAWK_E_ARG;
+  if (ctx->device < 0) return set_error(ctx, HAWK_E_DEVICE, "planning context cannot execute");
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return set_error(ctx, HAWK_E_DEVICE, hipGetErrorString(e));
+  double t = 0;
+  int64_t n = 0;
+  for (auto& r : ctx->prof) {
+    if (r.name != kernel) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return set_error(ctx, HAWK_E_DEVICE, "event timing");
+    t += ms;
+    ++n;
+  }
+  *total_ms = t;
+  *launches = n;
+  return HAWK_OK;
+}
+
+// ------------------------------------------------------------------ context
+extern "C" hawk_status hawk_ctx_create(int32_t device, void* hip_stream, hawk_ctx** out) {
+  if (!out) return HAWK_E_ARG;
+  *out = nullptr;
+  if (device == -1) {
+    // planning context: plans, variant spaces and features without a device
+    hawk_ctx* c = new hawk_ctx();
+    c->device = -1;
+    c->num_cus = 256;
+    c->lds_bytes = 160 * 1024;
+    c->seed = 0x48415748ull;
+    *out = c;
+    return HAWK_OK;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HAWK_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return HAWK_E_DEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return HAWK_E_DEVICE;
+  hawk_ctx* c = new hawk_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->num_cus = prop.multiProcessorCount;
+  c->lds_bytes = static_cast<int64_t>(prop.sharedMemPerBlock);
+  c->seed = 0x48415748ull;  // fixed: results never depend on it, timings stay reproducible
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    delete c;
+    return HAWK_E_DEVICE;
+  }
+  *out = c;
+  return HAWK_OK;
+}
+
+extern "C" void hawk_ctx_destroy(hawk_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->device < 0) {
+    delete ctx;
+    return;
+  }
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->pool.release_all();
+  prof_clear(ctx);
+  for (hipEvent_t e : ctx->prof_free) (void)hipEventDestroy(e);
+  (void)hipEventDestroy(ctx->ev0);
+  (void)hipEventDestroy(ctx->ev1);
+  delete ctx;
+}
+
+extern "C" const char* hawk_last_error(const hawk_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" hawk_status hawk_device_info(const hawk_ctx* ctx, int32_t* num_cus, int64_t* lds_bytes) {
+  if (!ctx) return HAWK_E_ARG;
+  if (num_cus) *num_cus = ctx->num_cus;
+  if (lds_bytes) *lds_bytes = ctx->lds_bytes;
+  return HAWK_OK;
+}
+
+// ------------------------------------------------------------------ tables
+extern "C" hawk_status hawk_table_register(hawk_ctx* ctx, const char* name, int64_t nrows, const hawk_column* cols,
+                                           int32_t ncols, int32_t* table_id) {
+  if (!ctx) return HAWK_E_ARG;
+  if (!name || !table_id || ncols <= 0 || (ncols > 0 && !cols)) return set_error(ctx, HAWK_E_ARG, "null argument");
+  if (nrows < 0 || nrows >= (int64_t(1) << 32)) return set_error(ctx, HAWK_E_ARG, "nrows must be in [0, 2^32)");
+  for (const auto& t : ctx->tables)
+    if (t.live && t.name == name) return set_error(ctx, HAWK_E_ARG, std::string("duplicate table ") + name);
+  TableReg t;
+  t.name = name;
+  t.nrows = nrows;
+  t.live = true;
+  for (int32_t i = 0; i < ncols; ++i) {
+    if (!cols[i].name) return set_error(ctx, HAWK_E_ARG, "column without name");
+    if (cols[i].dtype != HAWK_I8 && cols[i].dtype != HAWK_I32 && cols[i].dtype != HAWK_I64)
+      return set_error(ctx, HAWK_E_ARG, std::string("bad dtype of column ") + cols[i].name);
+    if (!cols[i].dev_ptr && nrows > 0) return set_error(ctx, HAWK_E_ARG, std::string("null column ") + cols[i].name);
+    for (const auto& c : t.cols)
+      if (c.name == cols[i].name) return set_error(ctx, HAWK_E_ARG, std::string("duplicate column ") + cols[i].name);
+    t.cols.push_back({cols[i].name, cols[i].dtype, cols[i].scale, cols[i].dev_ptr});
+  }
+  ctx->tables.push_back(t);
+  *table_id = static_cast<int32_t>(ctx->tables.size() - 1);
+  return HAWK_OK;
+}
+
+extern "C" hawk_status hawk_table_unregister(hawk_ctx* ctx, int32_t table_id) {
+  if (!ctx) return HAWK_E_ARG;
+  if (table_id < 0 || table_id >= static_cast<int32_t>(ctx->tables.size()) || !ctx->tables[table_id].live)
+    return set_error(ctx, HAWK_E_NOTFOUND, "unknown table id");
+  ctx->tables[table_id].live = false;
+  ctx->tables[table_id].cols.clear();
+  return HAWK_OK;
+}
+
+// ------------------------------------------------------------------ query compilation
+namespace {
+
+struct Lowering {
+  hawk_ctx* ctx;
+  const TableReg* table = nullptr;
+  HkPlan P;
+  int nreg = 0;
+  // attribute name -> register; columns are loaded on first use
+  std::map<std::string, int> reg_of;
+  std::map<std::string, int> dtype_of;  // element type of an attribute (columns, payloads)
+
+  Lowering(hawk_ctx* c) : ctx(c) { std::memset(&P, 0, sizeof(P)); }
+
+  int find_col(const std::string& nm) const {
+    for (size_t i = 0; i < table->cols.size(); ++i)
+      if (table->cols[i].name == nm) return static_cast<int>(i);
+    return -1;
+  }
+  // register holding `nm`, loading the column in `phase` (0 = A, 1 = B, 2 = C) if needed
+  hawk_status attr(const char* nm, int phase, int* reg) {
+    if (!nm) return set_error(ctx, HAWK_E_ARG, "missing attribute name");
+    auto it = reg_of.find(nm);
+    if (it != reg_of.end()) {
+      *reg = it->second;
+      return HAWK_OK;
+    }
+    int c = find_col(nm);
+    if (c < 0) return set_error(ctx, HAWK_E_NOTFOUND, std::string("unknown attribute ") + nm);
+    if (nreg >= HK_NREG) return set_error(ctx, HAWK_E_PLAN, "more than 16 live attributes");
+    HkCol col = {table->cols[c].ptr, table->cols[c].dtype, nreg};
+    if (phase == 0) {
+      if (P.ncolA >= HK_MAX_COLS_A) return set_error(ctx, HAWK_E_PLAN, "too many filter columns");
+      P.colA[P.ncolA++] = col;
+    } else if (phase == 1) {
+      if (P.ncolB >= HK_MAX_COLS_B) return set_error(ctx, HAWK_E_PLAN, "too many join-key columns");
+      P.colB[P.ncolB++] = col;
+    } else {
+      if (P.ncolC >= HK_MAX_COLS_C) return set_error(ctx, HAWK_E_PLAN, "too many value columns");
+      P.colC[P.ncolC++] = col;
+    }
+    reg_of[nm] = nreg;
+    dtype_of[nm] = table->cols[c].dtype;
+    *reg = nreg++;
+    return HAWK_OK;
+  }
+  hawk_status new_attr(const char* nm, int dtype, int* reg) {
+    if (!nm) return set_error(ctx, HAWK_E_ARG, "missing attribute name");
+    if (reg_of.count(nm) || find_col(nm) >= 0)
+      return set_error(ctx, HAWK_E_PLAN, std::string("attribute defined twice: ") + nm);
+    if (nreg >= HK_NREG) return set_error(ctx, HAWK_E_PLAN, "more than 16 live attributes");
+    reg_of[nm] = nreg;
+    dtype_of[nm] = dtype;
+    *reg = nreg++;
+    return HAWK_OK;
+  }
+};
+
+hawk_status lower_loop(hawk_ctx* ctx, const hawk_pipeline& p, Lowering& L) {
+  if (p.nops < 2 || !p.ops || p.ops[0].kind != HAWK_LOOP)
+    return set_error(ctx, HAWK_E_PLAN, "a pipeline starts with LOOP and has a sink");
+  int32_t t = p.ops[0].table;
+  if (t < 0 || t >= static_cast<int32_t>(ctx->tables.size()) || !ctx->tables[t].live)
+    return set_error(ctx, HAWK_E_NOTFOUND, "LOOP over an unknown table");
+  L.table = &ctx->tables[t];
+  L.P.nrows = L.table->nrows;
+  return HAWK_OK;
+}
+
+hawk_status lower_filter(hawk_ctx* ctx, const hawk_op& op, Lowering& L) {
+  if (L.P.nfilters >= HK_MAX_FILTERS) return set_error(ctx, HAWK_E_PLAN, "too many filters");
+  if (L.find_col(op.a ? op.a : "") < 0)
+    return set_error(ctx, HAWK_E_NOTFOUND, std::string("FILTER on unknown column ") + (op.a ? op.a : "(null)"));
+  int reg;
+  hawk_status st = L.attr(op.a, 0, &reg);
+  if (st) return st;
+  HkFilter& f = L.P.filters[L.P.nfilters++];
+  f.lo = op.lo;
+  f.hi = op.hi;
+  f.reg = reg;
+  return HAWK_OK;
+}
+
+}  // namespace
+
+extern "C" hawk_status hawk_query_create(hawk_ctx* ctx, const hawk_pipeline* pipes, int32_t npipes, hawk_query** out) {
+  if (!ctx) return HAWK_E_ARG;
+  if (!pipes || npipes < 1 || !out) return set_error(ctx, HAWK_E_ARG, "null argument");
+  *out = nullptr;
+  hawk_query* q = new hawk_query();
+  q->ctx = ctx;
+  std::map<int32_t, int> build_of_ht;  // ht id -> build index
+  // build pipelines: LOOP, FILTER*, HASH_PUT
+  for (int32_t pi = 0; pi + 1 < npipes; ++pi) {
+    const hawk_pipeline& p = pipes[pi];
+    Lowering L(ctx);
+    hawk_status st = lower_loop(ctx, p, L);
+    if (st) { delete q; return st; }
+    QueryBuild B;
+    bool put = false;
+    for (int32_t k = 1; k < p.nops; ++k) {
+      const hawk_op& op = p.ops[k];
+      if (op.kind == HAWK_FILTER && !put) {
+        st = lower_filter(ctx, op, L);
+      } else if (op.kind == HAWK_HASH_PUT && !put) {
+        int kc = L.find_col(op.a ? op.a : ""), pc = L.find_col(op.b ? op.b : "");
+        if (kc < 0 || pc < 0) st = set_error(ctx, HAWK_E_NOTFOUND, "HASH_PUT on unknown key or payload column");
+        else if (L.table->cols[kc].dtype == HAWK_I64 || L.table->cols[pc].dtype == HAWK_I64)
+          st = set_error(ctx, HAWK_E_TYPE, "HASH_PUT key and payload must be at most 32-bit");
+        else if (build_of_ht.count(op.ht)) st = set_error(ctx, HAWK_E_PLAN, "hash table built twice");
+        else {
+          B.key = {L.table->cols[kc].ptr, L.table->cols[kc].dtype, 0};
+          B.payload = {L.table->cols[pc].ptr, L.table->cols[pc].dtype, 0};
+          B.payload_dtype = L.table->cols[pc].dtype;
+          B.ht_id = op.ht;
+          put = true;
+        }
+      } else if (op.kind == HAWK_PROJECT && put) {
+        // a build pipeline may materialise attributes (Table 2); payloads are what probes see
+      } else {
+        st = set_error(ctx, HAWK_E_PLAN, "build pipelines are LOOP, FILTER*, HASH_PUT");
+      }
+      if (st) { delete q; return st; }
+    }
+    if (!put) { delete q; return set_error(ctx, HAWK_E_PLAN, "non-final pipeline without HASH_PUT"); }
+    B.plan = L.P;
+    B.nrows = L.P.nrows;
+    build_of_ht[B.ht_id] = static_cast<int>(q->builds.size());
+    q->builds.push_back(B);
+  }
+  // main pipeline
+  const hawk_pipeline& p = pipes[npipes - 1];
+  Lowering L(ctx);
+  hawk_status st = lower_loop(ctx, p, L);
+  if (st) { delete q; return st; }
+  int stage = 0;  // 0 filters, 1 probes, 2 arithmetic, 3 sink seen
+  for (int32_t k = 1; k < p.nops && !st; ++k) {
+    const hawk_op& op = p.ops[k];
+    if (stage == 3) { st = set_error(ctx, HAWK_E_PLAN, "operations after the sink"); break; }
+    switch (op.kind) {
+      case HAWK_FILTER:
+        if (stage > 0) st = set_error(ctx, HAWK_E_PLAN, "FILTER after HASH_PROBE/ARITHMETIC is not supported");
+        else st = lower_filter(ctx, op, L);
+        break;
+      case HAWK_HASH_PROBE: {
+        if (stage > 1) { st = set_error(ctx, HAWK_E_PLAN, "HASH_PROBE after ARITHMETIC"); break; }
+        stage = 1;
+        auto it = build_of_ht.find(op.ht);
+        if (it == build_of_ht.end()) { st = set_error(ctx, HAWK_E_PLAN, "HASH_PROBE of a table no pipeline builds"); break; }
+        if (L.P.nprobes >= HK_MAX_PROBES) { st = set_error(ctx, HAWK_E_PLAN, "too many probes"); break; }
+        int c = L.find_col(op.a ? op.a : "");
+        if (c < 0) { st = set_error(ctx, HAWK_E_NOTFOUND, "HASH_PROBE on unknown column"); break; }
+        if (L.table->cols[c].dtype == HAWK_I64) { st = set_error(ctx, HAWK_E_TYPE, "join keys are at most 32-bit"); break; }
+        int fk, pay;
+        if ((st = L.attr(op.a, 1, &fk))) break;
+        if ((st = L.new_attr(op.b, q->builds[it->second].payload_dtype, &pay))) break;
+        HkProbe& pr = L.P.probes[L.P.nprobes++];
+        std::memset(&pr, 0, sizeof(pr));
+        pr.fk_reg = fk;
+        pr.pay_reg = pay;
+        q->probe_build.push_back(it->second);
+        break;
+      }
+      case HAWK_ARITHMETIC: {
+        stage = 2;
+        if (L.P.narith >= HK_MAX_ARITH) { st = set_error(ctx, HAWK_E_PLAN, "too many arithmetic steps"); break; }
+        if (op.arith_op < HAWK_ADD || op.arith_op > HAWK_MUL) { st = set_error(ctx, HAWK_E_ARG, "bad arithmetic operator"); break; }
+        HkArith A;
+        std::memset(&A, 0, sizeof(A));
+        A.op = static_cast<int8_t>(op.arith_op);
+        int r;
+        if (op.b) { if ((st = L.attr(op.b, 2, &r))) break; A.x = static_cast<int8_t>(r); }
+        else { A.xc = 1; A.cx = op.lo; }
+        if (op.c) { if ((st = L.attr(op.c, 2, &r))) break; A.y = static_cast<int8_t>(r); }
+        else { A.yc = 1; A.cy = op.hi; }
+        if ((st = L.new_attr(op.a, HAWK_I64, &r))) break;
+        A.dst = static_cast<int8_t>(r);
+        L.P.arith[L.P.narith++] = A;
+        break;
+      }
+      case HAWK_PROJECT: {
+        stage = 3;
+        q->kind = 1;
+        if (op.nattrs < 1 || op.nattrs > HK_MAX_PROJ || !op.attrs) { st = set_error(ctx, HAWK_E_PLAN, "PROJECT takes 1..4 attributes"); break; }
+        for (int32_t j = 0; j < op.nattrs && !st; ++j) {
+          int r;
+          if (!(st = L.attr(op.attrs[j], 2, &r))) L.P.preg[L.P.nproj++] = r;
+        }
+        break;
+      }
+      case HAWK_AGGREGATE:
+      case HAWK_HASH_AGGREGATE: {
+        stage = 3;
+        q->kind = 2;
+        const bool grouped = op.kind == HAWK_HASH_AGGREGATE;
+        if (grouped && (op.nattrs < 1 || op.nattrs > 2 || !op.attrs)) { st = set_error(ctx, HAWK_E_PLAN, "HASH_AGGREGATE groups by 1 or 2 attributes"); break; }
+        if (op.naggs < 1 || op.naggs > HK_MAX_AGGS || !op.aggs) { st = set_error(ctx, HAWK_E_PLAN, "1..8 aggregates"); break; }
+        if (grouped) {
+          for (int32_t j = 0; j < op.nattrs && !st; ++j) {
+            int r;
+            if ((st = L.attr(op.attrs[j], 2, &r))) break;
+            int dt = L.dtype_of[op.attrs[j]];
+            if (dt == HAWK_I64) { st = set_error(ctx, HAWK_E_TYPE, "group attributes are at most 32-bit"); break; }
+            L.P.greg[L.P.ngroup++] = r;
+          }
+          if (st) break;
+        }
+        int word = 2;  // [key, count, aggregates...]
+        for (int32_t j = 0; j < op.naggs && !st; ++j) {
+          const hawk_agg& ag = op.aggs[j];
+          if (ag.fn < HAWK_COUNT || ag.fn > HAWK_AVG) { st = set_error(ctx, HAWK_E_ARG, "bad aggregate function"); break; }
+          HkAgg A;
+          std::memset(&A, 0, sizeof(A));
+          A.fn = static_cast<int8_t>(ag.fn);
+          A.wide = static_cast<int8_t>((ag.fn == HAWK_SUM || ag.fn == HAWK_AVG) && ag.wide ? 1 : 0);
+          if (ag.fn != HAWK_COUNT) {
+            int r;
+            if ((st = L.attr(ag.attr, 2, &r))) break;
+            A.reg = static_cast<int8_t>(r);
+            A.word = word;
+            word += A.wide ? 2 : 1;
+          }
+          L.P.aggs[L.P.naggs++] = A;
+          q->res_kinds.push_back(ag.fn == HAWK_AVG ? HAWK_RES_F64 : (ag.fn == HAWK_SUM && A.wide ? HAWK_RES_I128 : HAWK_RES_I64));
+        }
+        L.P.slot_words = word;
+        q->groups_hint = grouped ? std::max<int64_t>(1, op.groups_hint) : 1;
+        break;
+      }
+      default:
+        st = set_error(ctx, HAWK_E_PLAN, "unsupported operation in the main pipeline");
+    }
+  }
+  if (!st && stage != 3) st = set_error(ctx, HAWK_E_PLAN, "main pipeline has no PROJECT/AGGREGATE/HASH_AGGREGATE");
+  if (st) { delete q; return st; }
+  q->main = L.P;
+  q->has_table = L.P.nprobes > 0 || L.P.ngroup > 0;
+  *out = q;
+  return HAWK_OK;
+}
+
+extern "C" void hawk_query_free(hawk_query* q) { delete q; }
+
+extern "C" hawk_status hawk_query_kind(const hawk_query* q, int32_t* kind) {
+  if (!q || !kind) return HAWK_E_ARG;
+  *kind = q->kind;
+  return HAWK_OK;
+}
+
+// ------------------------------------------------------------------ variant space
+static void push_variant(std::vector<hawk_variant>& v, int ps, int mem, int pred, int ht, int hash, int as, uint32_t tm,
+                         uint32_t wg) {
+  hawk_variant x;
+  std::memset(&x, 0, sizeof(x));
+  x.proj_strategy = static_cast<uint8_t>(ps);
+  x.mem = static_cast<uint8_t>(mem);
+  x.pred = static_cast<uint8_t>(pred);
+  x.ht = static_cast<uint8_t>(ht);
+  x.hash = static_cast<uint8_t>(hash);
+  x.agg_strategy = static_cast<uint8_t>(as);
+  x.thread_mult = tm;
+  x.wg_size = wg;
+  v.push_back(x);
+}
+
+std::vector<hawk_variant> variant_space(const hawk_query* q) {
+  std::vector<hawk_variant> v;
+  const int nht = q->has_table ? 2 : 1;
+  if (q->kind == 1) {
+    for (int ps = 0; ps < 2; ++ps)
+      for (int mem = 0; mem < 2; ++mem)
+        for (int pred = 0; pred < 2; ++pred)
+          for (int ht = 0; ht < nht; ++ht)
+            for (int hs = 0; hs < nht; ++hs) {
+              if (ps == HAWK_SINGLE_PASS) push_variant(v, ps, mem, pred, ht, hs, 0, 1, 64);
+              else
+                for (uint32_t tm : kMults) push_variant(v, ps, mem, pred, ht, hs, 0, tm, 256);
+            }
+  } else {
+    for (int as = 0; as < 2; ++as)
+      for (int mem = 0; mem < 2; ++mem)
+        for (int pred = 0; pred < 2; ++pred)
+          for (int ht = 0; ht < nht; ++ht)
+            for (int hs = 0; hs < nht; ++hs) {
+              if (as == HAWK_LOCAL) {
+                for (uint32_t tm : kMults)
+                  for (uint32_t wg : kWgs) push_variant(v, 1, mem, pred, ht, hs, as, tm, wg);
+              } else {
+                for (uint32_t wg : kWgs) push_variant(v, 1, mem, pred, ht, hs, as, 1, wg);
+              }
+            }
+  }
+  return v;
+}
+
+extern "C" hawk_status hawk_variant_space(const hawk_query* q, hawk_variant* out, int64_t cap, int64_t* n) {
+  if (!q || !n) return HAWK_E_ARG;
+  std::vector<hawk_variant> v = variant_space(q);
+  *n = static_cast<int64_t>(v.size());
+  if (out) {
+    if (cap < *n) return HAWK_E_ARG;
+    std::copy(v.begin(), v.end(), out);
+  }
+  return HAWK_OK;
+}
+
+extern "C" hawk_status hawk_variant_format(const hawk_variant* v, char* buf, int32_t cap) {
+  if (!v || !buf || cap <= 0) return HAWK_E_ARG;
+  int k = std::snprintf(buf, static_cast<size_t>(cap), "strat=%s,mem=%s,pred=%s,ht=%s,hash=%s,agg=%s,tm=%u,wg=%u",
+                        v->proj_strategy ? "mp" : "sp", v->mem ? "coal" : "seq", v->pred ? "pred" : "br",
+                        v->ht ? "cuckoo" : "lin", v->hash ? "mulshift" : "murmur", v->agg_strategy ? "global" : "local",
+                        v->thread_mult, v->wg_size);
+  return k < cap ? HAWK_OK : HAWK_E_ARG;
+}
+
+// ------------------------------------------------------------------ results
+static void result_release(hawk_result* r) {
+  if (!r) return;
+  for (void* p : r->owned) r->ctx->pool.put(p);
+  r->owned.clear();
+}
+
+extern "C" void hawk_result_free(hawk_result* r) {
+  if (!r) return;
+  result_release(r);
+  delete r;
+}
+
+static hawk_status result_check(hawk_result* r) {
+  if (r->checked) return r->status;
+  hawk_ctx* ctx = r->ctx;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_error(ctx, e, "stream synchronize");
+  int err = 0;
+  uint64_t n = 0;
+  if ((e = hipMemcpy(&err, r->d_err, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess) return hip_error(ctx, e, "read flags");
+  if ((e = hipMemcpy(&n, r->d_count, sizeof(uint64_t), hipMemcpyDeviceToHost)) != hipSuccess) return hip_error(ctx, e, "read count");
+  r->checked = true;
+  r->err_bits = err;
+  r->nrows = static_cast<int64_t>(n);
+  if (err & HK_ERR_DUPKEY) r->status = set_error(ctx, HAWK_E_DUPKEY, "a build pipeline inserted a key twice");
+  else if (err & (HK_ERR_CAPACITY | HK_ERR_CUCKOO)) r->status = set_error(ctx, HAWK_E_CAPACITY, "hash table overflow");
+  else r->status = HAWK_OK;
+  return r->status;
+}
+
+extern "C" hawk_status hawk_result_info(hawk_result* r, int64_t* nrows, int32_t* ncols) {
+  if (!r) return HAWK_E_ARG;
+  hawk_status st = result_check(r);
+  if (st) return st;
+  if (nrows) *nrows = r->nrows;
+  if (ncols) *ncols = static_cast<int32_t>(r->cols.size());
+  return HAWK_OK;
+}
+
+extern "C" hawk_status hawk_result_column(hawk_result* r, int32_t col, int32_t* elem_kind, const void** dev_ptr) {
+  if (!r) return HAWK_E_ARG;
+  if (col < 0 || col >= static_cast<int32_t>(r->cols.size())) return set_error(r->ctx, HAWK_E_ARG, "bad column index");
+  if (elem_kind) *elem_kind = r->cols[col].kind;
+  if (dev_ptr) *dev_ptr = r->cols[col].ptr;
+  return HAWK_OK;
+}
+
+extern "C" hawk_status hawk_result_copy_column(hawk_result* r, int32_t col, void* host_dst, int64_t cap_bytes) {
+  if (!r) return HAWK_E_ARG;
+  hawk_status st = result_check(r);
+  if (st) return st;
+  if (col < 0 || col >= static_cast<int32_t>(r->cols.size())) return set_error(r->ctx, HAWK_E_ARG, "bad column index");
+  const int64_t bytes = r->nrows * (r->cols[col].kind == HAWK_RES_I128 ? 16 : 8);
+  if (bytes > cap_bytes || (!host_dst && bytes > 0)) return set_error(r->ctx, HAWK_E_ARG, "destination too small");
+  if (bytes == 0) return HAWK_OK;
+  hipError_t e = hipMemcpy(host_dst, r->cols[col].ptr, static_cast<size_t>(bytes), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_error(r->ctx, e, "copy column");
+  return HAWK_OK;
+}
+
+// ------------------------------------------------------------------ execution
+namespace {
+
+struct Exec {
+  hawk_ctx* ctx;
+  const hawk_query* q;
+  const hawk_variant* v;
+  hawk_result* res;
+  std::vector<void*> scratch;
+  int attempt;
+  hipStream_t st;
+
+  void* get(size_t bytes, bool owned) {
+    void* p = ctx->pool.get(bytes);
+    if (p) (owned ? res->owned : scratch).push_back(p);
+    return p;
+  }
+  ~Exec() {
+    for (void* p : scratch) ctx->pool.put(p);
+  }
+};
+
+#define HIPCHK(call, where)                          \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return hip_error(X.ctx, e_, where); \
+  } while (0)
+#define ALLOC(ptr, type, bytes, owned)                                        \
+  do {                                                                        \
+    ptr = static_cast<type>(X.get((bytes), (owned)));                         \
+    if (!ptr) return set_error(X.ctx, HAWK_E_OOM, "device allocation failed"); \
+  } while (0)
+
+HkHash make_hash(hawk_ctx* ctx, const hawk_variant* v, int attempt) {
+  uint64_t s = ctx->seed + 0x1000193ull * static_cast<uint64_t>(attempt);
+  HkHash h;
+  for (int i = 0; i < HK_CUCKOO_D; ++i) {
+    uint64_t a = splitmix(s);
+    h.a[i] = v->hash == HAWK_MULTIPLY_SHIFT ? (a | 1ull) : a;
+  }
+  return h;
+}
+
+hawk_status run_builds(Exec& X, HkPlan& main, const HkHash& h, int grow) {
+  const hawk_query* q = X.q;
+  std::vector<HkJoinTable> tabs;
+  for (const QueryBuild& B : q->builds) {
+    HkJoinTable t;
+    t.log2cap = std::max<uint32_t>(4, ceil_log2(static_cast<uint64_t>(std::max<int64_t>(1, B.nrows)) * 2)) + grow;
+    if (t.log2cap > 31) return set_error(X.ctx, HAWK_E_CAPACITY, "join table beyond 2^31 slots");
+    t.pad = 0;
+    ALLOC(t.slots, uint64_t*, (static_cast<size_t>(1) << t.log2cap) * 8, false);
+    ALLOC(t.side, uint64_t*, 8, false);
+    HIPCHK(hk_fill_u64(X.st, t.slots, int64_t(1) << t.log2cap, HK_EMPTY), "fill join table");
+    HIPCHK(hk_fill_u64(X.st, t.side, 1, 0), "fill side slot");
+    HkPlan bp = B.plan;
+    bp.hash = h;
+    {
+      ProfScope ps(X.ctx, "k_build");
+      HIPCHK(hk_build(X.st, bp, B.key, B.payload, t, X.v->ht, X.v->hash, X.res->d_err), "build");
+    }
+    tabs.push_back(t);
+  }
+  for (int i = 0; i < main.nprobes; ++i) main.probes[i].t = tabs[q->probe_build[i]];
+  return HAWK_OK;
+}
+
+hawk_status run_projection(Exec& X, const HkPlan& P) {
+  hawk_ctx* ctx = X.ctx;
+  const hawk_variant* v = X.v;
+  const int64_t n = P.nrows;
+  hawk_result* res = X.res;
+  int64_t* out[HK_MAX_PROJ] = {};
+  for (int c = 0; c < P.nproj; ++c) {
+    ALLOC(out[c], int64_t*, static_cast<size_t>(n + 1) * 8, true);
+    res->cols.push_back({HAWK_RES_I64, out[c]});
+  }
+  if (v->proj_strategy == HAWK_MULTI_PASS) {
+    const int64_t T = static_cast<int64_t>(v->thread_mult) * ctx->num_cus;  // threads (Section 9.2)
+    const int64_t threads = std::max<int64_t>(256, (T + 255) / 256 * 256);
+    const int64_t nblk = (n + 63) / 64;
+    uint64_t* masks;
+    ALLOC(masks, uint64_t*, static_cast<size_t>(nblk) * 8, false);
+    int64_t m, nact = 0;
+    if (v->mem == HAWK_COALESCED) {
+      m = nblk;
+    } else {
+      int64_t chunk = (n + threads - 1) / threads;
+      chunk = (chunk + 63) / 64 * 64;
+      nact = chunk > 0 ? (n + chunk - 1) / chunk : 0;
+      m = nact;
+    }
+    uint32_t *counts, *offsets, *tmp;
+    ALLOC(counts, uint32_t*, static_cast<size_t>(m) * 4, false);
+    ALLOC(offsets, uint32_t*, static_cast<size_t>(m) * 4, false);
+    ALLOC(tmp, uint32_t*, static_cast<size_t>(hk_scan_tmp_words(m)) * 4, false);
+    {
+      ProfScope ps(ctx, "k_mp_filter");
+      HIPCHK(hk_mp_filter(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, counts), "filter kernel");
+    }
+    {
+      ProfScope ps(ctx, "k_scan");
+      HIPCHK(hk_scan(X.st, counts, offsets, m, tmp, res->d_count), "prefix sum");
+    }
+    {
+      ProfScope ps(ctx, "k_mp_project");
+      HIPCHK(hk_mp_project(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, offsets, res->d_count, nact,
+                           out, n), "projection kernel");
+    }
+  } else {
+    const int64_t inst = ctx->num_cus;  // one pipeline instance per compute unit
+    int64_t chunk = (n + inst - 1) / inst;
+    chunk = (chunk + 63) / 64 * 64;
+    int64_t region, nregions;
+    if (v->mem == HAWK_COALESCED) {
+      region = chunk + 1;
+      nregions = inst;
+    } else {
+      region = chunk / 64 + 1;
+      nregions = inst * 64;
+    }
+    int64_t* tmp[HK_MAX_PROJ] = {};
+    for (int c = 0; c < P.nproj; ++c) ALLOC(tmp[c], int64_t*, static_cast<size_t>(region * nregions) * 8, false);
+    uint32_t *counts, *offsets, *stmp;
+    ALLOC(counts, uint32_t*, static_cast<size_t>(nregions) * 4, false);
+    ALLOC(offsets, uint32_t*, static_cast<size_t>(nregions) * 4, false);
+    ALLOC(stmp, uint32_t*, static_cast<size_t>(hk_scan_tmp_words(nregions)) * 4, false);
+    {
+      ProfScope ps(ctx, "k_sp");
+      HIPCHK(hk_sp(X.st, P, v->mem, v->pred, v->ht, v->hash, inst, tmp, region, counts), "single-pass kernel");
+    }
+    {
+      ProfScope ps(ctx, "k_scan");
+      HIPCHK(hk_scan(X.st, counts, offsets, nregions, stmp, res->d_count), "prefix sum");
+    }
+    {
+      ProfScope ps(ctx, "k_sp_concat");
+      HIPCHK(hk_sp_concat(X.st, tmp, P.nproj, region, nregions, counts, offsets, out), "concatenation");
+    }
+  }
+  return HAWK_OK;
+}
+
+void identity_words(const HkPlan& P, bool grouped, uint64_t* w) {
+  w[0] = grouped ? HK_EMPTY : 0ull;
+  w[1] = 0;
+  for (int a = 0; a < P.naggs; ++a) {
+    const HkAgg& A = P.aggs[a];
+    if (A.fn == HK_COUNT) continue;
+    w[A.word] = A.fn == HK_MIN ? static_cast<uint64_t>(INT64_MAX) : A.fn == HK_MAX ? static_cast<uint64_t>(INT64_MIN) : 0ull;
+    if (A.wide) w[A.word + 1] = 0;
+  }
+}
+
+hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
+  hawk_ctx* ctx = X.ctx;
+  const hawk_variant* v = X.v;
+  hawk_result* res = X.res;
+  const bool grouped = P.ngroup > 0;
+  const int W = P.slot_words;
+  uint64_t ident[2 + 2 * HK_MAX_AGGS] = {};
+  identity_words(P, grouped, ident);
+  HkAggTable T;
+  T.slot_words = W;
+  int64_t nslots;
+  if (grouped) {
+    T.log2cap = std::max<uint32_t>(6, ceil_log2(static_cast<uint64_t>(X.q->groups_hint) * 2)) + grow;
+    if (T.log2cap > 31) return set_error(ctx, HAWK_E_CAPACITY, "aggregation table beyond 2^31 slots");
+    nslots = (int64_t(1) << T.log2cap) + 1;  // + side slot for the all-ones key
+  } else {
+    T.log2cap = 0;
+    nslots = 1;
+  }
+  ALLOC(T.words, uint64_t*, static_cast<size_t>(nslots * W) * 8, false);
+  {
+    ProfScope ps(ctx, "k_init_aggtable");
+    HIPCHK(hk_init_aggtable(X.st, T.words, nslots, ident, W), "init table");
+  }
+  const int32_t wg = static_cast<int32_t>(v->wg_size);
+  if (wg < 1 || wg > 1024) return set_error(ctx, HAWK_E_ARG, "wg_size must be in [1, 1024]");
+  int64_t groups;
+  if (v->agg_strategy == HAWK_LOCAL) groups = static_cast<int64_t>(v->thread_mult) * ctx->num_cus;  // N tables
+  else groups = static_cast<int64_t>(ctx->num_cus) * std::max(1, 2048 / wg);                      // fill the device
+  if (groups < 1 || groups > 0x7FFFFFFF) return set_error(ctx, HAWK_E_ARG, "thread_mult out of range");
+  if (grouped) {
+    uint32_t llog2 = 0;
+    if (v->agg_strategy == HAWK_LOCAL) {
+      uint32_t want = std::max<uint32_t>(4, ceil_log2(static_cast<uint64_t>(X.q->groups_hint) * 2));
+      uint32_t fit = 0;
+      while ((int64_t(2) << fit) * W * 8 <= kLdsBudget) ++fit;
+      llog2 = std::min(want, fit);
+      if ((int64_t(1) << llog2) * W * 8 > ctx->lds_bytes)
+        return set_error(ctx, HAWK_E_INFEASIBLE, "local table does not fit in LDS");
+    }
+    ProfScope ps(ctx, "k_agg");
+    HIPCHK(hk_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, llog2, ident, W,
+                  res->d_err), "aggregation kernel");
+  } else {
+    ProfScope ps(ctx, "k_scalar_agg");
+    HIPCHK(hk_scalar_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, ident, W,
+                         res->d_err), "aggregation kernel");
+  }
+  // result columns: groups, aggregates, count
+  const int64_t cap = nslots;
+  int64_t* gcols[2] = {};
+  for (int g = 0; g < P.ngroup; ++g) {
+    ALLOC(gcols[g], int64_t*, static_cast<size_t>(cap) * 8, true);
+    res->cols.push_back({HAWK_RES_I64, gcols[g]});
+  }
+  void* acols[HK_MAX_AGGS] = {};
+  for (int a = 0; a < P.naggs; ++a) {
+    const int kind = X.q->res_kinds[a];
+    ALLOC(acols[a], void*, static_cast<size_t>(cap) * (kind == HAWK_RES_I128 ? 16 : 8), true);
+    res->cols.push_back({kind, acols[a]});
+  }
+  int64_t* cnt;
+  ALLOC(cnt, int64_t*, static_cast<size_t>(cap) * 8, true);
+  res->cols.push_back({HAWK_RES_I64, cnt});
+  {
+    ProfScope ps(ctx, "k_finalize");
+    HIPCHK(hk_finalize(X.st, P, T, nslots, gcols, acols, cnt, res->d_count, grouped ? 0 : 1), "finalize");
+  }
+  return HAWK_OK;
+}
+
+hawk_status execute_once(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v, int attempt, int grow,
+                         hawk_result** out) {
+  if (ctx->device < 0) return set_error(ctx, HAWK_E_DEVICE, "planning context cannot execute");
+  hawk_result* res = new hawk_result();
+  res->ctx = ctx;
+  res->kind = q->kind;
+  Exec X{ctx, q, v, res, {}, attempt, ctx->stream};
+  auto fail = [&](hawk_status st) {
+    result_release(res);
+    delete res;
+    return st;
+  };
+  if (v->mem > 1 || v->pred > 1 || v->ht > 1 || v->hash > 1 || v->agg_strategy > 1 || v->proj_strategy > 1 ||
+      v->thread_mult < 1)
+    return fail(set_error(ctx, HAWK_E_ARG, "variant value out of range"));
+  res->d_count = static_cast<uint64_t*>(X.get(16, true));
+  res->d_err = reinterpret_cast<int*>(res->d_count + 1);
+  if (!res->d_count) return fail(set_error(ctx, HAWK_E_OOM, "device allocation failed"));
+  hipError_t e = hk_fill_u64(ctx->stream, res->d_count, 2, 0);
+  if (e != hipSuccess) return fail(hip_error(ctx, e, "clear flags"));
+  HkPlan P = q->main;
+  P.hash = make_hash(ctx, v, attempt);
+  hawk_status st = run_builds(X, P, P.hash, grow);
+  if (!st) st = q->kind == 1 ? run_projection(X, P) : run_aggregation(X, P, grow);
+  if (st) return fail(st);
+  *out = res;
+  return HAWK_OK;
+}
+
+}  // namespace
+
+extern "C" hawk_status hawk_execute_async(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v, hawk_result** out) {
+  if (!ctx) return HAWK_E_ARG;
+  if (!q || !v || !out) return set_error(ctx, HAWK_E_ARG, "null argument");
+  *out = nullptr;
+  return execute_once(ctx, q, v, 0, 0, out);
+}
+
+extern "C" hawk_status hawk_execute(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v, hawk_result** out) {
+  if (!ctx) return HAWK_E_ARG;
+  if (!q || !v || !out) return set_error(ctx, HAWK_E_ARG, "null argument");
+  *out = nullptr;
+  int grow = 0;
+  for (int attempt = 0; attempt < kMaxAttempts; ++attempt) {
+    hawk_result* r = nullptr;
+    hawk_status st = execute_once(ctx, q, v, attempt, grow, &r);
+    if (st) return st;
+    st = result_check(r);
+    if (st == HAWK_OK) {
+      *out = r;
+      return HAWK_OK;
+    }
+    const int bits = r->err_bits;
+    hawk_result_free(r);
+    if (st != HAWK_E_CAPACITY) return st;
+    // a full linear-probing table doubles; a failed cuckoo chain first gets new
+    // hash seeds (the next attempt), then more room
+    if (bits & HK_ERR_CAPACITY) grow += 1;
+    else if (attempt >= 1) grow += 1;
+  }
+  return set_error(ctx, HAWK_E_CAPACITY, "hash table overflow after retries");
+}
+
+// ------------------------------------------------------------------ timing
+extern "C" hawk_status hawk_time_variant(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v, int32_t reps,
+                                         double limit_ms, double* median_ms) {
+  if (!ctx) return HAWK_E_ARG;
+  if (!q || !v || !median_ms || reps < 1) return set_error(ctx, HAWK_E_ARG, "bad argument");
+  if (ctx->device < 0) return set_error(ctx, HAWK_E_DEVICE, "planning context cannot execute");
+  hawk_result* r = nullptr;
+  // untimed first run: checks the variant end to end (retries included)
+  hipError_t e = hipEventRecord(ctx->ev0, ctx->stream);
+  if (e != hipSuccess) return hip_error(ctx, e, "event");
+  hawk_status st = hawk_execute(ctx, q, v, &r);
+  if (st) return st;
+  hawk_result_free(r);
+  (void)hipEventRecord(ctx->ev1, ctx->stream);
+  (void)hipEventSynchronize(ctx->ev1);
+  float first = 0.f;
+  (void)hipEventElapsedTime(&first, ctx->ev0, ctx->ev1);
+  if (limit_ms > 0 && first > limit_ms) {
+    *median_ms = first;
+    return set_error(ctx, HAWK_E_TIMEOUT, "variant slower than the time limit");
+  }
+  std::vector<double> t;
+  for (int32_t i = 0; i < reps; ++i) {
+    (void)hipEventRecord(ctx->ev0, ctx->stream);
+    st = hawk_execute_async(ctx, q, v, &r);
+    if (st) return st;
+    (void)hipEventRecord(ctx->ev1, ctx->stream);
+    e = hipEventSynchronize(ctx->ev1);
+    if (e != hipSuccess) {
+      hawk_result_free(r);
+      return hip_error(ctx, e, "event synchronize");
+    }
+    st = result_check(r);
+    hawk_result_free(r);
+    if (st) return st;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    t.push_back(ms);
+    if (limit_ms > 0 && ms > limit_ms) {
+      *median_ms = ms;
+      return set_error(ctx, HAWK_E_TIMEOUT, "variant slower than the time limit");
+    }
+  }
+  std::sort(t.begin(), t.end());
+  *median_ms = t[t.size() / 2];
+  return HAWK_OK;
+}

@@ -1,0 +1,436 @@
+// Device-side building blocks shared by the kernel files: column loads, the
+// two hash functions, atomics (LDS and device scope, exact 128-bit sums),
+// join-table probe/insert, per-row pipeline evaluation, aggregation-table
+// slot lookup and updates.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "hawk_plan.h"
+
+typedef long long v16i64 __attribute__((ext_vector_type(16)));
+
+#define WAVE 64
+
+// ------------------------------------------------------------------ small helpers
+__device__ __forceinline__ int64_t load_col(const HkCol& c, int64_t row) {
+  if (c.dtype == HK_T_I32) return static_cast<const int32_t*>(c.ptr)[row];
+  if (c.dtype == HK_T_I64) return static_cast<const int64_t*>(c.ptr)[row];
+  return static_cast<const int8_t*>(c.ptr)[row];
+}
+
+// Murmur3 64-bit finaliser (Appleby, public domain).
+__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+// slot of `key` under hash function with parameter a, table of 2^log2cap slots
+template <int HASH>
+__device__ __forceinline__ uint32_t hslot(uint64_t key, uint64_t a, uint32_t log2cap) {
+  if (HASH == HK_MURMUR) return static_cast<uint32_t>(fmix64(key ^ a) & ((1ull << log2cap) - 1));
+  // multiply-shift (Dietzfelbinger et al.): top log2cap bits of a*key mod 2^64, a odd
+  return static_cast<uint32_t>((key * a) >> (64 - log2cap));
+}
+
+template <bool LDS>
+__device__ __forceinline__ void at_add(uint64_t* p, uint64_t v) {
+  if (LDS) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <bool LDS>
+__device__ __forceinline__ uint64_t at_add_ret(uint64_t* p, uint64_t v) {
+  if (LDS) return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <bool LDS>
+__device__ __forceinline__ void at_min(uint64_t* p, int64_t v) {
+  int64_t* q = reinterpret_cast<int64_t*>(p);
+  if (LDS) __hip_atomic_fetch_min(q, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else __hip_atomic_fetch_min(q, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <bool LDS>
+__device__ __forceinline__ void at_max(uint64_t* p, int64_t v) {
+  int64_t* q = reinterpret_cast<int64_t*>(p);
+  if (LDS) __hip_atomic_fetch_max(q, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else __hip_atomic_fetch_max(q, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <bool LDS>
+__device__ __forceinline__ uint64_t at_cas(uint64_t* p, uint64_t expected, uint64_t desired) {
+  if (LDS)
+    __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+  else
+    __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+  return expected;  // the value found in memory
+}
+__device__ __forceinline__ uint64_t at_xchg(uint64_t* p, uint64_t v) {
+  return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void set_err(int* err, int bit) {
+  __hip_atomic_fetch_or(err, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exact 128-bit accumulation without 128-bit atomics: the low word takes the
+// value modulo 2^64; the high word takes the carry out of the low word minus
+// the sign (a negative v is (uint64)v - 2^64).
+template <bool LDS>
+__device__ __forceinline__ void at_add128(uint64_t* lo, uint64_t* hi, int64_t v) {
+  uint64_t u = static_cast<uint64_t>(v);
+  uint64_t old = at_add_ret<LDS>(lo, u);
+  int64_t d = static_cast<int64_t>(old + u < old) - static_cast<int64_t>(v < 0);
+  if (d != 0) at_add<LDS>(hi, static_cast<uint64_t>(d));
+}
+// adds a 128-bit partial (l, h)
+template <bool LDS>
+__device__ __forceinline__ void at_add128_pair(uint64_t* lo, uint64_t* hi, uint64_t l, int64_t h) {
+  uint64_t old = at_add_ret<LDS>(lo, l);
+  int64_t d = h + static_cast<int64_t>(old + l < old);
+  if (d != 0) at_add<LDS>(hi, static_cast<uint64_t>(d));
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  return (1ull << __lane_id()) - 1ull;
+}
+
+// ------------------------------------------------------------------ join tables
+// slot word: key (high 32 bits) | payload (low 32 bits); all-ones = empty;
+// key -1 would look empty and lives in the side word (bit 32 = present)
+template <int HT, int HASH>
+__device__ __forceinline__ bool join_lookup(const HkJoinTable& t, const HkHash& h, int32_t key, int32_t& pay) {
+  if (key == -1) {
+    uint64_t s = *t.side;
+    pay = static_cast<int32_t>(static_cast<uint32_t>(s));
+    return (s >> 32) != 0;
+  }
+  const uint64_t k64 = static_cast<uint32_t>(key);
+  if (HT == HK_LIN) {
+    const uint32_t mask = (1u << t.log2cap) - 1u;
+    uint32_t s = hslot<HASH>(k64, h.a[0], t.log2cap);
+    for (uint32_t i = 0; i <= mask; ++i) {
+      uint64_t w = t.slots[s];
+      if (w == HK_EMPTY) return false;
+      if (static_cast<uint32_t>(w >> 32) == static_cast<uint32_t>(key)) {
+        pay = static_cast<int32_t>(static_cast<uint32_t>(w));
+        return true;
+      }
+      s = (s + 1) & mask;
+    }
+    return false;
+  } else {
+#pragma unroll
+    for (int i = 0; i < HK_CUCKOO_D; ++i) {
+      uint64_t w = t.slots[hslot<HASH>(k64, h.a[i], t.log2cap)];
+      if (w != HK_EMPTY && static_cast<uint32_t>(w >> 32) == static_cast<uint32_t>(key)) {
+        pay = static_cast<int32_t>(static_cast<uint32_t>(w));
+        return true;
+      }
+    }
+    return false;
+  }
+}
+
+template <int HT, int HASH>
+__device__ __forceinline__ void join_insert(const HkJoinTable& t, const HkHash& h, int32_t key, int32_t pay,
+                                            int* err) {
+  if (key == -1) {
+    uint64_t v = (1ull << 32) | static_cast<uint32_t>(pay);
+    if (at_cas<false>(t.side, 0ull, v) != 0ull) set_err(err, HK_ERR_DUPKEY);
+    return;
+  }
+  const uint64_t w = (static_cast<uint64_t>(static_cast<uint32_t>(key)) << 32) | static_cast<uint32_t>(pay);
+  if (HT == HK_LIN) {
+    const uint32_t mask = (1u << t.log2cap) - 1u;
+    uint32_t s = hslot<HASH>(static_cast<uint32_t>(key), h.a[0], t.log2cap);
+    for (uint32_t i = 0; i <= mask; ++i) {
+      uint64_t cur = t.slots[s];
+      if (cur == HK_EMPTY) {
+        cur = at_cas<false>(&t.slots[s], HK_EMPTY, w);
+        if (cur == HK_EMPTY) return;
+      }
+      if (static_cast<uint32_t>(cur >> 32) == static_cast<uint32_t>(key)) {
+        set_err(err, HK_ERR_DUPKEY);
+        return;
+      }
+      s = (s + 1) & mask;
+    }
+    set_err(err, HK_ERR_CAPACITY);
+  } else {
+    // cuckoo insert: exchange into the current choice, the evicted entry moves
+    // on to its next choice; bounded chain
+    uint64_t cur = w;
+    int i = 0;
+    for (int step = 0; step < HK_CUCKOO_MAX_EVICT; ++step) {
+      const uint64_t k = cur >> 32;
+      const uint32_t s = hslot<HASH>(k, h.a[i], t.log2cap);
+      const uint64_t old = at_xchg(&t.slots[s], cur);
+      if (old == HK_EMPTY) return;
+      if ((old >> 32) == k) {  // another entry with the same key
+        set_err(err, HK_ERR_DUPKEY);
+        return;
+      }
+      cur = old;
+      int j = 0;
+#pragma unroll
+      for (int jj = HK_CUCKOO_D - 1; jj >= 0; --jj)
+        if (hslot<HASH>(old >> 32, h.a[jj], t.log2cap) == s) j = jj;
+      i = (j + 1) % HK_CUCKOO_D;
+    }
+    set_err(err, HK_ERR_CUCKOO);
+  }
+}
+
+// ------------------------------------------------------------------ row evaluation
+// Pushes one row through LOOP's loads, FILTER, HASH_PROBE and (if VALUES)
+// ARITHMETIC. Branched: returns false as soon as the row is dropped.
+// Predicated: evaluates everything and returns the result_increment.
+template <int PRED, int HT, int HASH, bool VALUES>
+__device__ __forceinline__ bool eval_row(const HkPlan& P, int64_t row, v16i64& r) {
+#pragma unroll
+  for (int c = 0; c < HK_MAX_COLS_A; ++c)
+    if (c < P.ncolA) r[P.colA[c].reg] = load_col(P.colA[c], row);
+  bool pass = true;
+  for (int f = 0; f < P.nfilters; ++f) {
+    const int64_t x = r[P.filters[f].reg];
+    pass = pass & (x >= P.filters[f].lo) & (x <= P.filters[f].hi);
+  }
+  if (PRED == HK_BR && !pass) return false;
+#pragma unroll
+  for (int c = 0; c < HK_MAX_COLS_B; ++c)
+    if (c < P.ncolB) r[P.colB[c].reg] = load_col(P.colB[c], row);
+  for (int p = 0; p < P.nprobes; ++p) {
+    int32_t pay = 0;
+    const bool found = join_lookup<HT, HASH>(P.probes[p].t, P.hash, static_cast<int32_t>(r[P.probes[p].fk_reg]), pay);
+    if (PRED == HK_BR && !found) return false;
+    pass = pass & found;
+    r[P.probes[p].pay_reg] = pay;
+  }
+  if (!VALUES) return pass;
+#pragma unroll
+  for (int c = 0; c < HK_MAX_COLS_C; ++c)
+    if (c < P.ncolC) r[P.colC[c].reg] = load_col(P.colC[c], row);
+  for (int k = 0; k < P.narith; ++k) {
+    const HkArith& A = P.arith[k];
+    const uint64_t x = A.xc ? static_cast<uint64_t>(A.cx) : static_cast<uint64_t>(r[A.x]);
+    const uint64_t y = A.yc ? static_cast<uint64_t>(A.cy) : static_cast<uint64_t>(r[A.y]);
+    const uint64_t v = A.op == HK_ADD ? x + y : (A.op == HK_SUB ? x - y : x * y);
+    r[A.dst] = static_cast<long long>(v);
+  }
+  return pass;
+}
+
+// row range of thread `t` out of `T` for sequential access, chunks rounded to `align`
+__device__ __forceinline__ void seq_range(int64_t n, int64_t t, int64_t T, int64_t align, int64_t& b, int64_t& e) {
+  int64_t chunk = (n + T - 1) / T;
+  chunk = (chunk + align - 1) / align * align;
+  b = t * chunk;
+  e = b + chunk < n ? b + chunk : n;
+  if (b > n) b = n;
+}
+
+// ------------------------------------------------------------------ structs passed to kernels
+struct HkIdent { uint64_t w[2 + 2 * HK_MAX_AGGS]; int32_t nw; };
+struct HkOut { int64_t* col[HK_MAX_PROJ]; int64_t dump; };
+struct HkBuild {
+  HkPlan p;              // LOOP + FILTER part (colA filter columns), nrows
+  HkCol key, payload;
+  HkJoinTable t;
+};
+struct HkResOut {
+  int64_t* gcol[2];
+  void* acol[HK_MAX_AGGS];
+  int64_t* count;
+  unsigned long long* nrows;
+  int32_t keep_empty;  // AGGREGATE without groups keeps its single row
+};
+
+
+__device__ __forceinline__ void write_proj(const HkPlan& P, const HkOut& O, int64_t pos, const v16i64& r) {
+#pragma unroll
+  for (int c = 0; c < HK_MAX_PROJ; ++c)
+    if (c < P.nproj) O.col[c][pos] = r[P.preg[c]];
+}
+
+// ------------------------------------------------------------------ aggregation (Section 4.2)
+// Global table: AoS slots [key, count, aggregate words...], linear probing or
+// cuckoo (keys inserted by k_agg_keys before aggregation). Local strategy:
+// each workgroup owns an LDS table of the same word layout (SoA), merged into
+// the global table at the end; a row whose key finds no LDS slot within the
+// probe bound goes straight to the global table.
+
+template <int HASH>
+__device__ __forceinline__ uint64_t* gslot_linear(const HkAggTable& T, const HkHash& h, uint64_t key, int* err) {
+  const int64_t W = T.slot_words;
+  if (key == HK_EMPTY) return T.words + (static_cast<int64_t>(1) << T.log2cap) * W;  // side slot
+  const uint32_t mask = (1u << T.log2cap) - 1u;
+  uint32_t s = hslot<HASH>(key, h.a[0], T.log2cap);
+  for (uint32_t i = 0; i <= mask; ++i) {
+    uint64_t* p = T.words + static_cast<int64_t>(s) * W;
+    uint64_t cur = *p;
+    if (cur == key) return p;
+    if (cur == HK_EMPTY) {
+      cur = at_cas<false>(p, HK_EMPTY, key);
+      if (cur == HK_EMPTY || cur == key) return p;
+    }
+    s = (s + 1) & mask;
+  }
+  set_err(err, HK_ERR_CAPACITY);
+  return nullptr;
+}
+
+template <int HASH>
+__device__ __forceinline__ uint64_t* gslot_cuckoo(const HkAggTable& T, const HkHash& h, uint64_t key, int* err) {
+  const int64_t W = T.slot_words;
+  if (key == HK_EMPTY) return T.words + (static_cast<int64_t>(1) << T.log2cap) * W;
+#pragma unroll
+  for (int i = 0; i < HK_CUCKOO_D; ++i) {
+    uint64_t* p = T.words + static_cast<int64_t>(hslot<HASH>(key, h.a[i], T.log2cap)) * W;
+    if (*p == key) return p;
+  }
+  set_err(err, HK_ERR_CUCKOO);
+  return nullptr;
+}
+
+template <int HT, int HASH>
+__device__ __forceinline__ uint64_t* gslot(const HkAggTable& T, const HkHash& h, uint64_t key, int* err) {
+  if (HT == HK_LIN) return gslot_linear<HASH>(T, h, key, err);
+  return gslot_cuckoo<HASH>(T, h, key, err);
+}
+
+// cuckoo phase 1: key insertion with evictions (no aggregates yet)
+template <int HASH>
+__device__ __forceinline__ void gkey_cuckoo_insert(const HkAggTable& T, const HkHash& h, uint64_t key, int* err) {
+  if (key == HK_EMPTY) return;
+  const int64_t W = T.slot_words;
+#pragma unroll
+  for (int i = 0; i < HK_CUCKOO_D; ++i)
+    if (T.words[static_cast<int64_t>(hslot<HASH>(key, h.a[i], T.log2cap)) * W] == key) return;
+  uint64_t cur = key;
+  int i = 0;
+  for (int step = 0; step < HK_CUCKOO_MAX_EVICT; ++step) {
+    const uint32_t s = hslot<HASH>(cur, h.a[i], T.log2cap);
+    const uint64_t old = at_xchg(T.words + static_cast<int64_t>(s) * W, cur);
+    if (old == HK_EMPTY || old == cur) return;
+    cur = old;
+    int j = 0;
+#pragma unroll
+    for (int jj = HK_CUCKOO_D - 1; jj >= 0; --jj)
+      if (hslot<HASH>(old, h.a[jj], T.log2cap) == s) j = jj;
+    i = (j + 1) % HK_CUCKOO_D;
+  }
+  set_err(err, HK_ERR_CUCKOO);
+}
+
+// group key of the row: one or two 32-bit attributes packed into 64 bits
+__device__ __forceinline__ uint64_t group_key(const HkPlan& P, const v16i64& r) {
+  if (P.ngroup == 0) return 0ull;
+  const uint64_t g0 = static_cast<uint32_t>(static_cast<int32_t>(r[P.greg[0]]));
+  if (P.ngroup == 1) return g0;
+  return (g0 << 32) | static_cast<uint32_t>(static_cast<int32_t>(r[P.greg[1]]));
+}
+
+// applies one row to the slot whose word j lives at base[j * stride]
+template <int PRED, bool LDS>
+__device__ __forceinline__ void agg_apply(uint64_t* base, int64_t stride, const HkPlan& P, const v16i64& r, bool pass) {
+  at_add<LDS>(base + stride, PRED == HK_PRED ? static_cast<uint64_t>(pass) : 1ull);
+#pragma unroll
+  for (int a = 0; a < HK_MAX_AGGS; ++a) {
+    if (a >= P.naggs) break;
+    const HkAgg& A = P.aggs[a];
+    if (A.fn == HK_COUNT) continue;
+    const int64_t x = r[A.reg];
+    uint64_t* w = base + A.word * stride;
+    if (A.fn == HK_SUM || A.fn == HK_AVG) {
+      // software predication: a dropped row contributes 0 (x * result_increment)
+      const int64_t v = PRED == HK_PRED ? (pass ? x : 0) : x;
+      if (A.wide) at_add128<LDS>(w, w + stride, v);
+      else at_add<LDS>(w, static_cast<uint64_t>(v));
+    } else if (A.fn == HK_MIN) {
+      at_min<LDS>(w, PRED == HK_PRED ? (pass ? x : INT64_MAX) : x);
+    } else {
+      at_max<LDS>(w, PRED == HK_PRED ? (pass ? x : INT64_MIN) : x);
+    }
+  }
+}
+
+// merges an LDS slot (word j at l[j * stride]) into a global slot g
+__device__ __forceinline__ void agg_merge(uint64_t* g, const uint64_t* l, int64_t stride, const HkPlan& P) {
+  at_add<false>(g + 1, l[stride]);
+#pragma unroll
+  for (int a = 0; a < HK_MAX_AGGS; ++a) {
+    if (a >= P.naggs) break;
+    const HkAgg& A = P.aggs[a];
+    if (A.fn == HK_COUNT) continue;
+    const uint64_t x = l[A.word * stride];
+    if (A.fn == HK_SUM || A.fn == HK_AVG) {
+      if (A.wide) at_add128_pair<false>(g + A.word, g + A.word + 1, x, static_cast<int64_t>(l[(A.word + 1) * stride]));
+      else at_add<false>(g + A.word, x);
+    } else if (A.fn == HK_MIN) {
+      at_min<false>(g + A.word, static_cast<int64_t>(x));
+    } else {
+      at_max<false>(g + A.word, static_cast<int64_t>(x));
+    }
+  }
+}
+
+// LDS slot lookup/insert for the local strategy; -1 = no slot within bound
+template <int HT, int HASH>
+__device__ __forceinline__ int32_t lslot(uint64_t* lkeys, uint32_t llog2, const HkHash& h, uint64_t key) {
+  if (HT == HK_LIN) {
+    const uint32_t mask = (1u << llog2) - 1u;
+    uint32_t s = hslot<HASH>(key, h.a[0], llog2);
+    for (int i = 0; i < HK_LOCAL_PROBES; ++i) {
+      uint64_t cur = lkeys[s];
+      if (cur == key) return static_cast<int32_t>(s);
+      if (cur == HK_EMPTY) {
+        cur = at_cas<true>(&lkeys[s], HK_EMPTY, key);
+        if (cur == HK_EMPTY || cur == key) return static_cast<int32_t>(s);
+      }
+      s = (s + 1) & mask;
+    }
+    return -1;
+  } else {
+    // cuckoo placement without eviction: the first free or matching choice
+#pragma unroll
+    for (int i = 0; i < HK_CUCKOO_D; ++i) {
+      const uint32_t s = hslot<HASH>(key, h.a[i], llog2);
+      uint64_t cur = lkeys[s];
+      if (cur == key) return static_cast<int32_t>(s);
+      if (cur == HK_EMPTY) {
+        cur = at_cas<true>(&lkeys[s], HK_EMPTY, key);
+        if (cur == HK_EMPTY || cur == key) return static_cast<int32_t>(s);
+      }
+    }
+    return -1;
+  }
+}
+
+
+__device__ __forceinline__ double i128_to_f64(uint64_t lo, int64_t hi) {
+  const int64_t slo = static_cast<int64_t>(lo);
+  if ((hi == 0 && slo >= 0) || (hi == -1 && slo < 0)) return static_cast<double>(slo);
+  return static_cast<double>(hi) * 18446744073709551616.0 + static_cast<double>(lo);
+}
+
+
+// ------------------------------------------------------------------ host-side launch helpers
+#define DISPATCH2(v, NAME, ...) \
+  do {                          \
+    if (v) {                    \
+      constexpr int NAME = 1;   \
+      __VA_ARGS__;              \
+    } else {                    \
+      constexpr int NAME = 0;   \
+      __VA_ARGS__;              \
+    }                           \
+  } while (0)
+
+static inline int64_t hk_grid_for(int64_t work, int64_t block, int64_t cap) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  return g < cap ? g : cap;
+}

@@ -1,0 +1,276 @@
+// Variant exploration (Section 8): Algorithm 1 (feature-wise learning),
+// exhaustive search ("backtracking", Section 9.3.2) as its judge, the pruning
+// rule of Section 9.1 (variants above a time limit count as infinitely slow),
+// a memo of measured configurations and an append-only timing log. Also the
+// query/variant feature vector used by the learned cost model.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "hawk.h"
+#include "hawk_internal.h"
+
+namespace {
+
+const double kInf = std::numeric_limits<double>::infinity();
+const uint32_t kMults[7] = {1, 8, 64, 256, 1024, 16384, 65536};
+const uint32_t kWgs[7] = {16, 32, 64, 128, 256, 512, 1024};
+
+}  // namespace
+
+// ------------------------------------------------------------------ Algorithm 1
+extern "C" hawk_status hawk_learn_feature_wise(const int32_t* dim_sizes, int32_t ndims, const int32_t* order, int32_t q,
+                                               hawk_cost_fn cost, void* user, int32_t* best_cfg, int64_t* n_calls) {
+  if (!dim_sizes || ndims < 1 || !cost || !best_cfg || q < 1) return HAWK_E_ARG;
+  for (int32_t i = 0; i < ndims; ++i)
+    if (dim_sizes[i] < 1) return HAWK_E_ARG;
+  std::vector<int32_t> ord(static_cast<size_t>(ndims));
+  for (int32_t i = 0; i < ndims; ++i) ord[i] = order ? order[i] : i;
+  std::vector<char> seen(static_cast<size_t>(ndims), 0);
+  for (int32_t i : ord) {
+    if (i < 0 || i >= ndims || seen[i]) return HAWK_E_ARG;
+    seen[i] = 1;
+  }
+  std::map<std::vector<int32_t>, double> memo;
+  int64_t calls = 0;
+  auto eval = [&](const std::vector<int32_t>& c) {
+    auto it = memo.find(c);
+    if (it != memo.end()) return it->second;
+    ++calls;
+    double t = cost(c.data(), ndims, user);
+    if (std::isnan(t)) t = kInf;
+    memo[c] = t;
+    return t;
+  };
+  // start from the first value of every dimension
+  std::vector<int32_t> v(static_cast<size_t>(ndims), 0);
+  for (int32_t iter = 0; iter < q; ++iter) {
+    const std::vector<int32_t> last = v;
+    for (int32_t i : ord) {
+      // vary dimension i only; keep the value with the lowest time (a strictly
+      // lower time replaces the incumbent, so ties keep the earlier value)
+      double best_t = kInf;
+      int32_t best_d = -1;
+      for (int32_t d = 0; d < dim_sizes[i]; ++d) {
+        std::vector<int32_t> w = v;
+        w[i] = d;
+        const double t = eval(w);
+        if (t < best_t) {
+          best_t = t;
+          best_d = d;
+        }
+      }
+      if (best_d >= 0) v[i] = best_d;  // every value infeasible: keep the current one
+    }
+    if (v == last) break;  // fixed point: no faster configuration found in this sweep
+  }
+  std::memcpy(best_cfg, v.data(), sizeof(int32_t) * ndims);
+  if (n_calls) *n_calls = calls;
+  return HAWK_OK;
+}
+
+// ------------------------------------------------------------------ features
+static double log2p1(double x) { return std::log2(x + 1.0); }
+
+hawk_status query_features(const hawk_query* q, const hawk_variant* v, int num_cus, float* f) {
+  const HkPlan& P = q->main;
+  int bytes = 0;
+  auto w = [](int32_t t) { return t == HK_T_I8 ? 1 : t == HK_T_I32 ? 4 : 8; };
+  for (int i = 0; i < P.ncolA; ++i) bytes += w(P.colA[i].dtype);
+  for (int i = 0; i < P.ncolB; ++i) bytes += w(P.colB[i].dtype);
+  for (int i = 0; i < P.ncolC; ++i) bytes += w(P.colC[i].dtype);
+  f[0] = static_cast<float>(log2p1(static_cast<double>(P.nrows)));
+  f[1] = static_cast<float>(q->stat_selectivity);
+  f[2] = static_cast<float>(q->kind == 2 ? log2p1(static_cast<double>(q->groups_hint)) : 0.0);
+  f[3] = static_cast<float>(bytes);
+  f[4] = static_cast<float>(P.nprobes);
+  f[5] = static_cast<float>(q->kind == 1 ? 8 * P.nproj : 8 * P.slot_words);
+  double threads, wg, strat;
+  if (q->kind == 1) {
+    strat = v->proj_strategy;
+    threads = v->proj_strategy ? static_cast<double>(v->thread_mult) * num_cus : static_cast<double>(num_cus) * 64;
+    wg = v->proj_strategy ? 256 : 64;
+  } else {
+    strat = v->agg_strategy;
+    const double wgs = v->wg_size ? v->wg_size : 256;
+    threads = v->agg_strategy == HAWK_LOCAL ? static_cast<double>(v->thread_mult) * num_cus * wgs
+                                            : static_cast<double>(num_cus) * std::max(1.0, std::floor(2048.0 / wgs)) * wgs;
+    wg = wgs;
+  }
+  f[6] = static_cast<float>(strat);
+  f[7] = static_cast<float>(std::log2(threads));
+  f[8] = static_cast<float>(std::log2(wg));
+  f[9] = static_cast<float>(v->pred);
+  f[10] = static_cast<float>(v->mem);
+  f[11] = static_cast<float>(q->has_table ? v->ht * 2 + v->hash : 0);
+  return HAWK_OK;
+}
+
+extern "C" hawk_status hawk_features(const hawk_query* q, const hawk_variant* v, float* out12) {
+  if (!q || !v || !out12) return HAWK_E_ARG;
+  return query_features(q, v, q->ctx->num_cus, out12);
+}
+
+extern "C" hawk_status hawk_query_set_stats(hawk_query* q, double selectivity) {
+  if (!q || !(selectivity >= 0.0 && selectivity <= 1.0)) return HAWK_E_ARG;
+  q->stat_selectivity = selectivity;
+  return HAWK_OK;
+}
+
+// ------------------------------------------------------------------ workload exploration
+namespace {
+
+// dimensions explored for a workload of one pipeline kind, in feature order
+// (strategy, threads, memory access first; Section 8.2)
+struct Space {
+  int kind;
+  bool table;
+  std::vector<int32_t> sizes;
+  hawk_variant at(const std::vector<int32_t>& c) const {
+    hawk_variant v;
+    std::memset(&v, 0, sizeof(v));
+    if (kind == 1) {
+      v.proj_strategy = static_cast<uint8_t>(c[0]);
+      v.thread_mult = v.proj_strategy ? kMults[c[1]] : 1;  // single-pass: one instance per CU
+      v.mem = static_cast<uint8_t>(c[2]);
+      v.pred = static_cast<uint8_t>(c[3]);
+      v.wg_size = v.proj_strategy ? 256 : 64;
+      if (table) {
+        v.ht = static_cast<uint8_t>(c[4]);
+        v.hash = static_cast<uint8_t>(c[5]);
+      }
+      v.agg_strategy = 0;
+    } else {
+      v.proj_strategy = 1;
+      v.agg_strategy = static_cast<uint8_t>(c[0]);
+      v.thread_mult = v.agg_strategy == HAWK_LOCAL ? kMults[c[1]] : 1;  // global: one table
+      v.wg_size = kWgs[c[2]];
+      v.mem = static_cast<uint8_t>(c[3]);
+      v.pred = static_cast<uint8_t>(c[4]);
+      if (table) {
+        v.ht = static_cast<uint8_t>(c[5]);
+        v.hash = static_cast<uint8_t>(c[6]);
+      }
+    }
+    return v;
+  }
+};
+
+std::string vkey(const hawk_variant& v) {
+  char buf[160];
+  hawk_variant_format(&v, buf, sizeof(buf));
+  return buf;
+}
+
+struct Explorer {
+  hawk_ctx* ctx;
+  hawk_query* const* W;
+  int32_t k;
+  const hawk_explore_opts* opts;
+  Space space;
+  std::map<std::string, double> memo;
+  int64_t evaluated = 0, pruned = 0;
+  FILE* db = nullptr;
+
+  double workload_time(const hawk_variant& v) {
+    const std::string key = vkey(v);
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+    double total = 0;
+    bool bad = false;
+    for (int32_t i = 0; i < k && !bad; ++i) {
+      double ms = 0;
+      hawk_status st = hawk_time_variant(ctx, W[i], &v, opts->reps > 0 ? opts->reps : 3, opts->limit_ms, &ms);
+      float f[12];
+      query_features(W[i], &v, ctx->num_cus, f);
+      if (db) {
+        std::fprintf(db, "%d", i);
+        for (float x : f) std::fprintf(db, "\t%.6g", x);
+        std::fprintf(db, "\t%s\t%.6f\t%d\n", key.c_str(), st == HAWK_OK ? ms : -1.0, st);
+      }
+      if (st != HAWK_OK) bad = true;
+      else total += ms;
+    }
+    ++evaluated;
+    if (bad) {
+      ++pruned;
+      total = kInf;
+      ctx->err.clear();
+    }
+    memo[key] = total;
+    return total;
+  }
+};
+
+double explorer_cost(const int32_t* cfg, int32_t ndims, void* user) {
+  Explorer* E = static_cast<Explorer*>(user);
+  std::vector<int32_t> c(cfg, cfg + ndims);
+  return E->workload_time(E->space.at(c));
+}
+
+}  // namespace
+
+extern "C" hawk_status hawk_explore(hawk_ctx* ctx, hawk_query* const* W, int32_t k, int32_t mode,
+                                    const hawk_explore_opts* opts, hawk_variant* best, hawk_explore_report* rep) {
+  if (!ctx) return HAWK_E_ARG;
+  if (!W || k < 1 || !opts || !best) return set_error(ctx, HAWK_E_ARG, "null argument");
+  const auto t0 = std::chrono::steady_clock::now();
+  Explorer E{ctx, W, k, opts, {}, {}, 0, 0, nullptr};
+  E.space.kind = W[0]->kind;
+  E.space.table = false;
+  for (int32_t i = 0; i < k; ++i) {
+    if (!W[i] || W[i]->kind != E.space.kind) return set_error(ctx, HAWK_E_ARG, "workload mixes pipeline kinds");
+    E.space.table = E.space.table || W[i]->has_table;
+  }
+  if (E.space.kind == 1) E.space.sizes = {2, 7, 2, 2};
+  else E.space.sizes = {2, 7, 7, 2, 2};
+  if (E.space.table) {
+    E.space.sizes.push_back(2);
+    E.space.sizes.push_back(2);
+  }
+  if (opts->timing_db) E.db = std::fopen(opts->timing_db, "a");
+  std::vector<int32_t> cfg(E.space.sizes.size(), 0);
+  hawk_status st = HAWK_OK;
+  if (mode == HAWK_EXPLORE_FEATURE_WISE) {
+    int64_t calls = 0;
+    st = hawk_learn_feature_wise(E.space.sizes.data(), static_cast<int32_t>(E.space.sizes.size()), nullptr,
+                                 opts->max_iters > 0 ? opts->max_iters : 5, explorer_cost, &E, cfg.data(), &calls);
+  } else if (mode == HAWK_EXPLORE_EXHAUSTIVE) {
+    double bt = kInf;
+    std::vector<int32_t> c(E.space.sizes.size(), 0);
+    for (;;) {
+      const double t = E.workload_time(E.space.at(c));
+      if (t < bt) {
+        bt = t;
+        cfg = c;
+      }
+      size_t d = c.size();
+      while (d > 0) {
+        --d;
+        if (++c[d] < E.space.sizes[d]) break;
+        c[d] = 0;
+        if (d == 0) { d = c.size() + 1; break; }
+      }
+      if (d == c.size() + 1) break;
+    }
+  } else {
+    st = set_error(ctx, HAWK_E_ARG, "unknown exploration mode");
+  }
+  if (E.db) std::fclose(E.db);
+  if (st) return st;
+  *best = E.space.at(cfg);
+  if (rep) {
+    rep->evaluated = E.evaluated;
+    rep->pruned = E.pruned;
+    rep->best_ms = E.workload_time(*best);
+    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return HAWK_OK;
+}

@@ -1,0 +1,89 @@
+// Host-side state behind the opaque handles of hawk.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "hawk.h"
+#include "hawk_plan.h"
+
+// Device memory pool of the context: blocks are hipMalloc'ed once and reused
+// (stream order makes reuse safe; nothing is returned to the driver before
+// hawk_ctx_destroy), so steady-state execution allocates nothing.
+struct DevicePool {
+  struct Block { void* p; size_t bytes; bool used; };
+  std::vector<Block> blocks;
+  void* get(size_t bytes);
+  void put(void* p);
+  void release_all();
+};
+
+struct ColReg { std::string name; int32_t dtype; int32_t scale; const void* ptr; };
+struct TableReg { std::string name; int64_t nrows; std::vector<ColReg> cols; bool live; };
+
+// one profiled kernel launch: HIP events around it on the context stream
+struct ProfRec { std::string name; hipEvent_t a, b; };
+
+struct hawk_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cus = 0;
+  int64_t lds_bytes = 0;
+  uint64_t seed = 0;
+  std::string err;
+  std::vector<TableReg> tables;
+  DevicePool pool;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool prof_on = false;
+  std::vector<ProfRec> prof;           // launches recorded since profiling was enabled
+  std::vector<hipEvent_t> prof_free;   // recycled events
+};
+
+// brackets one launch with events when profiling is on
+struct ProfScope {
+  hawk_ctx* ctx;
+  size_t idx;
+  ProfScope(hawk_ctx* c, const char* name);
+  ~ProfScope();
+};
+
+// a lowered build pipeline (LOOP, FILTER*, HASH_PUT)
+struct QueryBuild {
+  HkPlan plan;  // filter part
+  HkCol key, payload;
+  int32_t payload_dtype = 0;
+  int32_t ht_id = 0;
+  int64_t nrows = 0;
+};
+
+struct hawk_query {
+  hawk_ctx* ctx = nullptr;
+  int kind = 0;                      // 1 projection, 2 aggregation
+  std::vector<QueryBuild> builds;
+  std::vector<int> probe_build;      // build index of each probe of the main pipeline
+  HkPlan main;                       // lowered main pipeline (tables and hash seeds filled per execution)
+  std::vector<int> res_kinds;        // result kind of each aggregate
+  int64_t groups_hint = 1;
+  double stat_selectivity = 1.0;     // catalog statistic: fraction of rows reaching the sink
+  bool has_table = false;            // probes or grouping: hash-table dimensions apply
+};
+
+struct ResCol { int32_t kind; void* ptr; };
+
+struct hawk_result {
+  hawk_ctx* ctx = nullptr;
+  int kind = 0;
+  uint64_t* d_count = nullptr;       // rows of the result (device)
+  int* d_err = nullptr;              // kernel error flags (device)
+  std::vector<ResCol> cols;
+  std::vector<void*> owned;          // pool blocks released by hawk_result_free
+  bool checked = false;
+  int err_bits = 0;
+  hawk_status status = HAWK_OK;
+  int64_t nrows = -1;
+};
+
+hawk_status set_error(hawk_ctx* ctx, hawk_status st, const std::string& msg);
+std::vector<hawk_variant> variant_space(const hawk_query* q);
+hawk_status query_features(const hawk_query* q, const hawk_variant* v, int num_cus, float* f);

@@ -1,0 +1,72 @@
+// Internal plan representation shared by the host dispatcher and the gfx950
+// kernels. A validated pipeline program (Section 3.1) is lowered into a
+// fixed-size, by-value kernel argument: column loads into a 16-entry register
+// file of 64-bit values, filter predicates, probe descriptors, arithmetic
+// steps and the sink (projection or aggregation). Every variant dimension of
+// Section 9.2 is a template parameter of the kernels; everything the query
+// itself decides is data in this struct.
+#pragma once
+#include <stdint.h>
+
+#define HK_NREG 16
+#define HK_MAX_COLS_A 6          // columns loaded before the filters
+#define HK_MAX_COLS_B 4          // join-key columns loaded before the probes
+#define HK_MAX_COLS_C 8          // value columns loaded before the arithmetic
+#define HK_MAX_FILTERS 6
+#define HK_MAX_PROBES 4
+#define HK_MAX_ARITH 8
+#define HK_MAX_AGGS 8
+#define HK_MAX_PROJ 4
+#define HK_CUCKOO_D 3            // number of hash functions of the cuckoo table
+#define HK_CUCKOO_MAX_EVICT 64   // eviction chain bound before the insert fails
+#define HK_LOCAL_PROBES 8        // LDS linear probing bound before a row overflows to the global table
+
+#define HK_EMPTY 0xFFFFFFFFFFFFFFFFull
+
+enum { HK_SEQ = 0, HK_COAL = 1 };
+enum { HK_BR = 0, HK_PRED = 1 };
+enum { HK_LIN = 0, HK_CUCKOO = 1 };
+enum { HK_MURMUR = 0, HK_MULSHIFT = 1 };
+enum { HK_LOCAL = 0, HK_GLOBAL = 1 };
+
+enum { HK_T_I8 = 1, HK_T_I32 = 2, HK_T_I64 = 3 };
+enum { HK_ADD = 1, HK_SUB = 2, HK_MUL = 3 };
+enum { HK_COUNT = 1, HK_SUM = 2, HK_MIN = 3, HK_MAX = 4, HK_AVG = 5 };
+
+// error flag bits written by kernels
+enum { HK_ERR_CAPACITY = 1, HK_ERR_DUPKEY = 2, HK_ERR_CUCKOO = 4 };
+
+struct HkCol { const void* ptr; int32_t dtype; int32_t reg; };
+struct HkFilter { int64_t lo, hi; int32_t reg; int32_t pad; };
+// hash functions of one query: murmur xor keys or multiply-shift odd multipliers
+struct HkHash { uint64_t a[HK_CUCKOO_D]; };
+// a join hash table: 64-bit slots (key << 32 | payload), plus a side word for key -1
+struct HkJoinTable { uint64_t* slots; uint64_t* side; uint32_t log2cap; int32_t pad; };
+struct HkProbe { HkJoinTable t; int32_t fk_reg; int32_t pay_reg; };
+struct HkArith { int64_t cx, cy; int8_t op, dst, x, y, xc, yc, pad0, pad1; };
+struct HkAgg { int8_t fn, wide, reg, pad; int32_t word; };
+
+struct HkPlan {
+  int64_t nrows;
+  HkHash hash;
+  // column loads into registers: colA before the filters, colB (join keys)
+  // before the probes, colC before the arithmetic
+  int32_t ncolA, ncolB, ncolC, nfilters;
+  HkCol colA[HK_MAX_COLS_A];
+  HkCol colB[HK_MAX_COLS_B];
+  HkCol colC[HK_MAX_COLS_C];
+  HkFilter filters[HK_MAX_FILTERS];
+  int32_t nprobes, narith, ngroup, naggs;
+  HkProbe probes[HK_MAX_PROBES];
+  HkArith arith[HK_MAX_ARITH];
+  int32_t greg[2];
+  HkAgg aggs[HK_MAX_AGGS];
+  int32_t nproj;
+  int32_t preg[HK_MAX_PROJ];
+  // aggregation table: AoS slots of slot_words 64-bit words:
+  // [key, count, aggregate words...]; wide sums take two words (lo, hi)
+  int32_t slot_words;
+};
+
+// an aggregation hash table in HBM (plus one side slot for the sentinel key)
+struct HkAggTable { uint64_t* words; uint32_t log2cap; int32_t slot_words; };

@@ -1,0 +1,64 @@
+// Grouped aggregation (HASH_AGGREGATE, Section 4.2), local hash-table strategy.
+#include <hip/hip_runtime.h>
+
+#include "hawk_device.h"
+#include "hawk_launch.h"
+
+#define HK_CHECK_LAUNCH() return hipGetLastError()
+
+hipError_t hk_agg_local(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
+                        int64_t groups, int32_t wg, uint32_t llog2, const HkIdent& id, int* err);
+hipError_t hk_agg_global(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
+                         int64_t groups, int32_t wg, uint32_t llog2, const HkIdent& id, int* err);
+
+template <int MEM, int PRED, int HT, int HASH, int STRAT>
+__global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t llog2, HkIdent id, int* err) {
+  extern __shared__ uint64_t lds[];
+  const int64_t LC = STRAT == HK_LOCAL ? (static_cast<int64_t>(1) << llog2) : 0;
+  if (STRAT == HK_LOCAL) {
+    for (int w = 0; w < id.nw; ++w)
+      for (int64_t i = threadIdx.x; i < LC; i += blockDim.x) lds[w * LC + i] = id.w[w];
+    __syncthreads();
+  }
+  v16i64 r = {};
+  const int64_t n = P.nrows;
+  const int64_t Tn = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t b, e, step;
+  if (MEM == HK_COAL) { b = gt; e = n; step = Tn; }
+  else { seq_range(n, gt, Tn, 1, b, e); step = 1; }
+  for (int64_t row = b; row < e; row += step) {
+    const bool pass = eval_row<PRED, HT, HASH, true>(P, row, r);
+    if (PRED == HK_BR && !pass) continue;
+    const uint64_t key = group_key(P, r);
+    if (STRAT == HK_LOCAL && key != HK_EMPTY) {
+      const int32_t s = lslot<HT, HASH>(lds, llog2, P.hash, key);
+      if (s >= 0) {
+        agg_apply<PRED, true>(lds + s, LC, P, r, pass);
+        continue;
+      }
+    }
+    uint64_t* g = gslot<HT, HASH>(T, P.hash, key, err);
+    if (g) agg_apply<PRED, false>(g, 1, P, r, pass);
+  }
+  if (STRAT == HK_LOCAL) {
+    __syncthreads();
+    for (int64_t s = threadIdx.x; s < LC; s += blockDim.x) {
+      const uint64_t key = lds[s];
+      if (key == HK_EMPTY || lds[LC + s] == 0) continue;
+      uint64_t* g = gslot<HT, HASH>(T, P.hash, key, err);
+      if (g) agg_merge(g, lds + s, LC, P);
+    }
+  }
+}
+
+
+hipError_t hk_agg_local(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
+                      int64_t groups, int32_t wg, uint32_t llog2, const HkIdent& id, int* err) {
+  const dim3 g(static_cast<uint32_t>(groups)), b(static_cast<uint32_t>(wg));
+  const size_t lds = (static_cast<size_t>(1) << llog2) * id.nw * sizeof(uint64_t);
+  DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS,
+            hipLaunchKernelGGL((k_agg<M, PR, HT, HS, 0>), g, b, lds, st, P, T, llog2, id, err)))));
+  HK_CHECK_LAUNCH();
+}
+

@@ -1,0 +1,277 @@
+// Kernels shared by every pipeline kind: table initialisation, build
+// pipelines (HASH_PUT), the exclusive scan of the multi-pass strategy, the
+// concatenation of single-pass regions and aggregation result extraction.
+#include <hip/hip_runtime.h>
+
+#include "hawk_device.h"
+#include "hawk_launch.h"
+
+#define HK_CHECK_LAUNCH() return hipGetLastError()
+
+// ------------------------------------------------------------------ fill / init
+__global__ void __launch_bounds__(256) k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void __launch_bounds__(256) k_init_aggtable(uint64_t* words, int64_t nslots, HkIdent id) {
+  __shared__ uint64_t w[2 + 2 * HK_MAX_AGGS];
+  if (threadIdx.x == 0)
+    for (int j = 0; j < id.nw; ++j) w[j] = id.w[j];
+  __syncthreads();
+  const int64_t total = nslots * id.nw;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+    words[i] = w[i % id.nw];
+}
+
+template <int HT, int HASH>
+__global__ void __launch_bounds__(256) k_build(HkBuild B, int* err) {
+  v16i64 r = {};
+  const int64_t T = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < B.p.nrows; row += T) {
+    if (!eval_row<HK_BR, HT, HASH, false>(B.p, row, r)) continue;
+    join_insert<HT, HASH>(B.t, B.p.hash, static_cast<int32_t>(load_col(B.key, row)),
+                          static_cast<int32_t>(load_col(B.payload, row)), err);
+  }
+}
+
+// a cuckoo table may hold two copies of a key inserted twice; count copies
+template <int HASH>
+__global__ void __launch_bounds__(256) k_build_verify(HkBuild B, int* err) {
+  v16i64 r = {};
+  const int64_t T = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < B.p.nrows; row += T) {
+    if (!eval_row<HK_BR, HK_CUCKOO, HASH, false>(B.p, row, r)) continue;
+    const int32_t key = static_cast<int32_t>(load_col(B.key, row));
+    if (key == -1) continue;
+    uint32_t pos[HK_CUCKOO_D];
+    int copies = 0;
+#pragma unroll
+    for (int i = 0; i < HK_CUCKOO_D; ++i) {
+      pos[i] = hslot<HASH>(static_cast<uint32_t>(key), B.p.hash.a[i], B.t.log2cap);
+      bool seen = false;
+#pragma unroll
+      for (int j = 0; j < i; ++j) seen = seen || pos[j] == pos[i];
+      const uint64_t w = B.t.slots[pos[i]];
+      if (!seen && w != HK_EMPTY && static_cast<uint32_t>(w >> 32) == static_cast<uint32_t>(key)) ++copies;
+    }
+    if (copies > 1) set_err(err, HK_ERR_DUPKEY);
+    if (copies == 0) set_err(err, HK_ERR_CUCKOO);
+  }
+}
+
+// ------------------------------------------------------------------ exclusive scan (u32 counts -> u32 offsets)
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint32_t t = __shfl_up(v, d, WAVE);
+    if (__lane_id() >= d) v += t;
+  }
+  return v;
+}
+// exclusive scan of one value per thread over a 1024-thread block; returns the block total in *tot
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* tot) {
+  const int lane = __lane_id(), wid = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  const uint32_t inc = wave_incl_scan(v);
+  if (lane == WAVE - 1) sh[wid] = inc;
+  __syncthreads();
+  if (wid == 0) {
+    const uint32_t x = lane < nw ? sh[lane] : 0u;
+    const uint32_t xs = wave_incl_scan(x);
+    if (lane < nw) sh[lane] = xs - x;
+    if (lane == nw - 1) sh[WAVE] = xs;
+  }
+  __syncthreads();
+  const uint32_t res = sh[wid] + inc - v;
+  *tot = sh[WAVE];
+  __syncthreads();
+  return res;
+}
+
+#define SCAN_ITEMS 8
+#define SCAN_TILE (1024 * SCAN_ITEMS)
+
+// one block scans `m` entries tile by tile
+__global__ void __launch_bounds__(1024) k_scan_single(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                      int64_t m, const uint32_t* __restrict__ base, uint64_t* total) {
+  __shared__ uint32_t sh[WAVE + 1];
+  uint32_t carry = base ? *base : 0u;
+  for (int64_t t0 = 0; t0 < m; t0 += SCAN_TILE) {
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+      const int64_t j = t0 + threadIdx.x * SCAN_ITEMS + i;
+      v[i] = j < m ? in[j] : 0u;
+      s += v[i];
+    }
+    uint32_t tot;
+    uint32_t pre = block_excl_scan(s, sh, &tot) + carry;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+      const int64_t j = t0 + threadIdx.x * SCAN_ITEMS + i;
+      if (j < m) out[j] = pre;
+      pre += v[i];
+    }
+    carry += tot;
+  }
+  if (total && threadIdx.x == 0) *total = carry;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_reduce(const uint32_t* __restrict__ in, int64_t m, uint32_t* __restrict__ sums) {
+  __shared__ uint32_t sh[WAVE + 1];
+  const int64_t t0 = blockIdx.x * (int64_t)SCAN_TILE;
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    const int64_t j = t0 + threadIdx.x * SCAN_ITEMS + i;
+    s += j < m ? in[j] : 0u;
+  }
+  uint32_t tot;
+  block_excl_scan(s, sh, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_apply(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t m,
+                                                     const uint32_t* __restrict__ tile_off) {
+  __shared__ uint32_t sh[WAVE + 1];
+  const int64_t t0 = blockIdx.x * (int64_t)SCAN_TILE;
+  uint32_t v[SCAN_ITEMS];
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    const int64_t j = t0 + threadIdx.x * SCAN_ITEMS + i;
+    v[i] = j < m ? in[j] : 0u;
+    s += v[i];
+  }
+  uint32_t tot;
+  uint32_t pre = block_excl_scan(s, sh, &tot) + tile_off[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    const int64_t j = t0 + threadIdx.x * SCAN_ITEMS + i;
+    if (j < m) out[j] = pre;
+    pre += v[i];
+  }
+}
+
+// concatenation of the single-pass regions: one wave per region
+__global__ void __launch_bounds__(256) k_sp_concat(HkOut tmp, int32_t nproj, int64_t region, int64_t nregions,
+                                                   const uint32_t* __restrict__ counts,
+                                                   const uint32_t* __restrict__ offsets, HkOut out) {
+  const int64_t waves = (int64_t)gridDim.x * blockDim.x / WAVE;
+  for (int64_t g = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE; g < nregions; g += waves) {
+    const int64_t c = counts[g], o = offsets[g];
+    for (int64_t i = __lane_id(); i < c; i += WAVE)
+      for (int k = 0; k < HK_MAX_PROJ; ++k)
+        if (k < nproj) out.col[k][o + i] = tmp.col[k][g * region + i];
+  }
+}
+
+// ------------------------------------------------------------------ finalize
+__global__ void __launch_bounds__(256) k_finalize(HkPlan P, HkAggTable T, int64_t nslots, HkResOut O) {
+  const int64_t W = T.slot_words;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x + threadIdx.x - __lane_id(); base < nslots;
+       base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = base + __lane_id();
+    const uint64_t* p = T.words + s * W;
+    const bool live = s < nslots && (p[1] != 0 || O.keep_empty);
+    const uint64_t m = __ballot(live);
+    if (m == 0) continue;
+    unsigned long long start = 0;
+    if (__lane_id() == 0) start = atomicAdd(O.nrows, static_cast<unsigned long long>(__popcll(m)));
+    start = __shfl(start, 0, WAVE);
+    if (!live) continue;
+    const int64_t pos = static_cast<int64_t>(start) + __popcll(m & lanemask_lt());
+    const uint64_t key = p[0];  // the side slot keeps the all-ones key
+    if (P.ngroup == 1) O.gcol[0][pos] = static_cast<int32_t>(static_cast<uint32_t>(key));
+    if (P.ngroup == 2) {
+      O.gcol[0][pos] = static_cast<int32_t>(static_cast<uint32_t>(key >> 32));
+      O.gcol[1][pos] = static_cast<int32_t>(static_cast<uint32_t>(key));
+    }
+    const uint64_t cnt = p[1];
+    O.count[pos] = static_cast<int64_t>(cnt);
+    for (int a = 0; a < P.naggs; ++a) {
+      const HkAgg& A = P.aggs[a];
+      if (A.fn == HK_COUNT) {
+        static_cast<int64_t*>(O.acol[a])[pos] = static_cast<int64_t>(cnt);
+      } else if (A.fn == HK_AVG) {
+        const double sum = A.wide ? i128_to_f64(p[A.word], static_cast<int64_t>(p[A.word + 1]))
+                                  : static_cast<double>(static_cast<int64_t>(p[A.word]));
+        static_cast<double*>(O.acol[a])[pos] = sum / static_cast<double>(cnt);
+      } else if (A.fn == HK_SUM && A.wide) {
+        static_cast<uint64_t*>(O.acol[a])[2 * pos] = p[A.word];
+        static_cast<uint64_t*>(O.acol[a])[2 * pos + 1] = p[A.word + 1];
+      } else {
+        static_cast<int64_t*>(O.acol[a])[pos] = static_cast<int64_t>(p[A.word]);
+      }
+    }
+  }
+}
+
+
+// ================================================================== host launchers
+hipError_t hk_fill_u64(hipStream_t st, uint64_t* p, int64_t n, uint64_t v) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3(hk_grid_for(n, 256, 8192)), dim3(256), 0, st, p, n, v);
+  HK_CHECK_LAUNCH();
+}
+
+hipError_t hk_init_aggtable(hipStream_t st, uint64_t* words, int64_t nslots, const uint64_t* ident, int32_t nw) {
+  HkIdent id = {};
+  for (int i = 0; i < nw; ++i) id.w[i] = ident[i];
+  id.nw = nw;
+  hipLaunchKernelGGL(k_init_aggtable, dim3(hk_grid_for(nslots * nw, 256, 8192)), dim3(256), 0, st, words, nslots, id);
+  HK_CHECK_LAUNCH();
+}
+
+hipError_t hk_build(hipStream_t st, const HkPlan& p, const HkCol& key, const HkCol& pay, const HkJoinTable& t,
+                    int ht, int hash, int* err) {
+  HkBuild B;
+  B.p = p;
+  B.key = key;
+  B.payload = pay;
+  B.t = t;
+  const dim3 g(hk_grid_for(p.nrows, 256, 4096)), b(256);
+  DISPATCH2(ht, HT, DISPATCH2(hash, HS, hipLaunchKernelGGL((k_build<HT, HS>), g, b, 0, st, B, err)));
+  if (ht == HK_CUCKOO) {
+    DISPATCH2(hash, HS, hipLaunchKernelGGL((k_build_verify<HS>), g, b, 0, st, B, err));
+  }
+  HK_CHECK_LAUNCH();
+}
+
+hipError_t hk_sp_concat(hipStream_t st, int64_t* const* tmp, int32_t nproj, int64_t region, int64_t nregions,
+                        const uint32_t* counts, const uint32_t* offsets, int64_t* const* out) {
+  HkOut T = {}, O = {};
+  for (int c = 0; c < nproj; ++c) { T.col[c] = tmp[c]; O.col[c] = out[c]; }
+  hipLaunchKernelGGL(k_sp_concat, dim3(hk_grid_for(nregions * WAVE, 256, 4096)), dim3(256), 0, st, T, nproj, region,
+                     nregions, counts, offsets, O);
+  HK_CHECK_LAUNCH();
+}
+
+int64_t hk_scan_tmp_words(int64_t m) { return (m + SCAN_TILE - 1) / SCAN_TILE * 2 + 2; }
+
+hipError_t hk_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t m, uint32_t* tmp, uint64_t* total) {
+  if (m <= 8 * SCAN_TILE) {
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, in, out, m, nullptr, total);
+    HK_CHECK_LAUNCH();
+  }
+  const int64_t tiles = (m + SCAN_TILE - 1) / SCAN_TILE;
+  uint32_t* sums = tmp;
+  uint32_t* offs = tmp + tiles + 1;
+  hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(1024), 0, st, in, m, sums);
+  hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, sums, offs, tiles, nullptr, total);
+  hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(1024), 0, st, in, out, m, offs);
+  HK_CHECK_LAUNCH();
+}
+
+hipError_t hk_finalize(hipStream_t st, const HkPlan& P, const HkAggTable& T, int64_t nslots, int64_t* const* gcols,
+                       void* const* acols, int64_t* count, uint64_t* nrows, int keep_empty) {
+  HkResOut O = {};
+  for (int g = 0; g < P.ngroup; ++g) O.gcol[g] = gcols[g];
+  for (int a = 0; a < P.naggs; ++a) O.acol[a] = acols[a];
+  O.count = count;
+  O.nrows = reinterpret_cast<unsigned long long*>(nrows);
+  O.keep_empty = keep_empty;
+  hipLaunchKernelGGL(k_finalize, dim3(hk_grid_for(nslots, 256, 8192)), dim3(256), 0, st, P, T, nslots, O);
+  HK_CHECK_LAUNCH();
+}

@@ -1,0 +1,181 @@
+"""GPU parity: every variant of the HIP path against the CPU oracle, through
+the C ABI, on seeded inputs that span several tiles and a ragged tail, plus
+the degenerate cases of the method."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import compare, run_variants, sample, say
+from paper_1709_00700_amd import datagen as dg
+from paper_1709_00700_amd import hawk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = hawk.Context(0)
+    yield c
+    c.close()
+
+
+def all_variants(ctx, tables, spec):
+    p = hawk.PlanningContext()
+    p.register_shapes({t: {c: a[:1] for c, a in cols.items()} for t, cols in tables.items()})
+    vs = hawk.variant_space(hawk.build_query(p, spec))
+    p.close()
+    return vs
+
+
+# ------------------------------------------------------------------ projection
+@pytest.mark.parametrize("n", [100_003])
+def test_c1_all_32_variants(ctx, n):
+    tables, spec = dg.c1_projection(n=n)
+    vs = all_variants(ctx, tables, spec)
+    assert len(vs) == 32
+    say("c1 n", n)
+    run_variants(ctx, tables, spec, vs, label="c1")
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 4097])
+def test_c1_small_and_ragged(ctx, n):
+    tables, spec = dg.c1_projection(n=n)
+    say("c1 ragged n", n)
+    run_variants(ctx, tables, spec, all_variants(ctx, tables, spec), label=f"c1 n={n}")
+
+
+@pytest.mark.parametrize("which", ["all", "none"])
+def test_c1_all_or_none_selected(ctx, which):
+    tables, spec = dg.c1_projection(n=20_000)
+    spec["main"]["filters"] = [("a", 0, 999)] if which == "all" else [("a", 5000, 6000)]
+    say("c1", which)
+    run_variants(ctx, tables, spec, all_variants(ctx, tables, spec), label=f"c1 {which}")
+
+
+def test_projection_with_join_probe(ctx):
+    tables, spec = dg.c3_star_join(n=30_000, dims=(50, 400, 60, 160), sel=(60, 50, 60, 40))
+    spec["main"] = {"table": "f", "filters": [("rev", 0, 700_000)],
+                    "probes": [("fk0", 0, "p0"), ("fk2", 2, "p2")],
+                    "arith": [("x", "mul", "p0", "rev"), ("y", "sub", "x", "p2")],
+                    "project": ["y", "fk0", "p2"]}
+    spec["builds"] = [spec["builds"][0], spec["builds"][1], spec["builds"][2]]
+    vs = all_variants(ctx, tables, spec)
+    assert len(vs) == 128
+    say("projection with probes")
+    run_variants(ctx, tables, spec, vs, label="proj-join")
+
+
+# ------------------------------------------------------------------ grouped aggregation
+def test_c2_uniform_all_896_variants(ctx):
+    tables, spec = dg.c2_aggregation(n=50_003, dist="uniform")
+    vs = all_variants(ctx, tables, spec)
+    assert len(vs) == 896
+    say("c2 uniform, 896 variants")
+    run_variants(ctx, tables, spec, vs, label="c2u")
+
+
+def test_c2_zipf_sampled_variants(ctx):
+    tables, spec = dg.c2_aggregation(n=300_007, dist="zipf", nranks=200_000)
+    vs = sample(all_variants(ctx, tables, spec), 96, seed=1)
+    say("c2 zipf, 96 variants")
+    run_variants(ctx, tables, spec, vs, label="c2z")
+
+
+def test_c3_star_join_sampled_variants(ctx):
+    tables, spec = dg.c3_star_join(n=200_000, dims=(250, 2000, 300, 800), sel=(60, 50, 60, 40))
+    vs = sample(all_variants(ctx, tables, spec), 128, seed=2)
+    say("c3, 128 variants")
+    run_variants(ctx, tables, spec, vs, label="c3")
+
+
+def test_c4_wide_sampled_variants(ctx):
+    tables, spec = dg.c4_wide(n=100_003, price_hi=1 << 40)
+    vs = sample(all_variants(ctx, tables, spec), 96, seed=3)
+    say("c4, 96 variants")
+    _, ref = run_variants(ctx, tables, spec, vs, label="c4")
+    assert max(int(x) for x in ref["aggs"][4]) > (1 << 63)   # the wide sum really needs 128 bits
+
+
+def test_scalar_aggregate_all_variants(ctx):
+    tables, spec = dg.c4_wide(n=70_001)
+    spec["main"]["group_by"] = []
+    spec["main"]["filters"] = [("qty", 10, 40)]
+    vs = all_variants(ctx, tables, spec)
+    assert len(vs) == 224
+    say("aggregate without groups, 224 variants")
+    run_variants(ctx, tables, spec, vs, label="agg")
+
+
+def test_scalar_aggregate_empty_input(ctx):
+    tables, spec = dg.c4_wide(n=1000)
+    spec["main"]["group_by"] = []
+    spec["main"]["filters"] = [("qty", 100, 200)]     # nothing qualifies
+    run_variants(ctx, tables, spec, sample(all_variants(ctx, tables, spec), 16), label="agg-empty")
+
+
+def test_negative_and_overflowing_sums(ctx):
+    rng = np.random.default_rng(11)
+    n = 40_000
+    t = {"g1": rng.integers(-2, 2, size=n).astype(np.int8),
+         "g2": rng.integers(-3, 1, size=n).astype(np.int32),
+         "v": rng.integers(-(1 << 62), 1 << 62, size=n, dtype=np.int64) * 2 + 1,
+         "f": rng.integers(0, 10, size=n).astype(np.int32)}
+    spec = {"builds": [], "main": {"table": "t", "filters": [("f", 2, 8)], "probes": [],
+                                   "arith": [("w", "sub", 0, "v")],
+                                   "group_by": ["g1", "g2"],
+                                   "aggs": [("sum", "v", True), ("sum", "w", True), ("sum", "v", False),
+                                            ("min", "v", False), ("max", "w", False), ("avg", "v", True),
+                                            ("count", None, False)],
+                                   "groups_hint": 16}}
+    vs = sample(all_variants(ctx, {"t": t}, spec), 96, seed=4)
+    # the group (-1, -1) packs to the all-ones key and takes the side slot
+    say("sentinel groups + 128-bit sums")
+    _, ref = run_variants(ctx, {"t": t}, spec, vs, label="wide")
+    assert any(k0 == -1 and k1 == -1 for k0, k1 in zip(ref["keys"][0], ref["keys"][1]))
+
+
+def test_join_key_minus_one_and_sparse_keys(ctx):
+    d = {"key": np.array([-1, 5, -(1 << 31), (1 << 31) - 1, 7, 0], np.int32),
+         "g": np.array([10, 20, 30, 40, 50, -1], np.int32)}
+    rng = np.random.default_rng(5)
+    f = {"fk": rng.choice(np.array([-1, 5, -(1 << 31), (1 << 31) - 1, 7, 0, 3, -2], np.int32), size=5000),
+         "v": rng.integers(0, 100, size=5000).astype(np.int64)}
+    spec = {"builds": [{"table": "d", "filters": [], "key": "key", "payload": "g"}],
+            "main": {"table": "f", "filters": [], "probes": [("fk", 0, "p")], "arith": [],
+                     "group_by": ["p"], "aggs": [("sum", "v", False), ("count", None, False)], "groups_hint": 8}}
+    vs = sample(all_variants(ctx, {"d": d, "f": f}, spec), 64, seed=6)
+    run_variants(ctx, {"d": d, "f": f}, spec, vs, label="keys")
+
+
+@pytest.mark.parametrize("ht", [0, 1])
+def test_duplicate_build_key_is_reported(ctx, ht):
+    d = {"key": np.array([3, 9, 3, 4], np.int32), "g": np.array([1, 2, 3, 4], np.int32)}
+    f = {"fk": np.array([3, 4, 9], np.int32)}
+    spec = {"builds": [{"table": "d", "filters": [], "key": "key", "payload": "g"}],
+            "main": {"table": "f", "filters": [], "probes": [("fk", 0, "p")], "arith": [], "project": ["p"]}}
+    ctx.register_numpy({"d": d, "f": f})
+    q = hawk.build_query(ctx, spec)
+    with pytest.raises(hawk.HawkError) as e:
+        hawk.execute(ctx, q, hawk.variant(ht=ht))
+    assert e.value.code == hawk.HAWK_E_DUPKEY
+
+
+def test_undersized_group_hint_retries(ctx):
+    tables, spec = dg.c2_aggregation(n=60_000, dist="uniform", groups=3000)
+    spec["main"]["groups_hint"] = 40          # table for 80 slots, 3000 groups arrive
+    vs = [hawk.variant(agg_strategy=s, ht=h, hash=x, mem=1, thread_mult=8, wg_size=256)
+          for s in (0, 1) for h in (0, 1) for x in (0, 1)]
+    run_variants(ctx, tables, spec, vs, label="hint")
+
+
+def test_async_execution_matches(ctx):
+    tables, spec = dg.c2_aggregation(n=100_000, dist="zipf", nranks=5000)
+    ref = oracle.run(tables, spec)
+    ctx.register_numpy(tables)
+    q = hawk.build_query(ctx, spec)
+    rs = [hawk.execute(ctx, q, hawk.variant(agg_strategy=i % 2, ht=i // 2 % 2), sync=False) for i in range(4)]
+    for r in rs:
+        compare(r.to_numpy(spec), ref, spec, "async")
+        r.free()
