@@ -139,7 +139,8 @@ extern "C" hawk_status hawk_mlp_grad_dev(hawk_model* M, const float* dX, const f
   float* partial = static_cast<float*>(B.get(static_cast<size_t>(rows) * MLP_NPARAMS * 4));
   float* ploss = static_cast<float*>(B.get(static_cast<size_t>(rows) * 4));
   if (!partial || !ploss) return set_error(M->ctx, HAWK_E_OOM, "gradient scratch");
-  CK(hk_mlp_grad(M->ctx->stream, M->p, M->mu, M->sd, dX, dy, nullptr, m, partial, ploss, dgrad, dloss), "gradient");
+  CK(hk_mlp_grad(M->ctx->stream, M->p, M->mu, M->sd, dX, dy, nullptr, m, partial, ploss, rows, dgrad, dloss),
+     "gradient");
   return HAWK_OK;
 }
 
@@ -166,7 +167,8 @@ extern "C" hawk_status hawk_model_train(hawk_model* M, const float* X, const flo
   CK(hipMemcpy(M->sd, sd.data(), MLP_IN * 4, hipMemcpyHostToDevice), "upload sd");
   DevBuf B(ctx);
   const int64_t batch = std::min<int64_t>(o->batch, m);
-  const int64_t rows = hk_mlp_grad_rows(batch);
+  // partial rows for the largest gradient launch: the batches and the final full pass
+  const int64_t rows = std::max(hk_mlp_grad_rows(batch), hk_mlp_grad_rows(m));
   float* dX = static_cast<float*>(B.get(static_cast<size_t>(m) * MLP_IN * 4));
   float* dy = static_cast<float*>(B.get(static_cast<size_t>(m) * 4));
   int32_t* didx = static_cast<int32_t*>(B.get(static_cast<size_t>(m) * 4 * o->epochs));
@@ -190,8 +192,8 @@ extern "C" hawk_status hawk_model_train(hawk_model* M, const float* X, const flo
   for (int32_t e = 0; e < o->epochs; ++e) {
     for (int64_t b0 = 0; b0 < m; b0 += batch) {
       const int64_t nb = std::min(batch, m - b0);
-      CK(hk_mlp_grad(st, M->p, M->mu, M->sd, dX, dy, didx + static_cast<size_t>(e) * m + b0, nb, partial, ploss, grad,
-                     dloss), "gradient");
+      CK(hk_mlp_grad(st, M->p, M->mu, M->sd, dX, dy, didx + static_cast<size_t>(e) * m + b0, nb, partial, ploss, rows,
+                     grad, dloss), "gradient");
       ++M->step;
       const float c1 = 1.f - std::pow(b1, static_cast<float>(M->step));
       const float c2 = 1.f - std::pow(b2, static_cast<float>(M->step));
@@ -199,7 +201,7 @@ extern "C" hawk_status hawk_model_train(hawk_model* M, const float* X, const flo
     }
   }
   if (final_loss) {
-    CK(hk_mlp_grad(st, M->p, M->mu, M->sd, dX, dy, nullptr, m, partial, ploss, grad, dloss), "final loss");
+    CK(hk_mlp_grad(st, M->p, M->mu, M->sd, dX, dy, nullptr, m, partial, ploss, rows, grad, dloss), "final loss");
     CK(hipMemcpyAsync(final_loss, dloss, 4, hipMemcpyDeviceToHost, st), "read loss");
   }
   CK(hipStreamSynchronize(st), "synchronize");

@@ -207,8 +207,10 @@ hipError_t hk_mlp_forward(hipStream_t st, const float* p, const float* mu, const
 int64_t hk_mlp_grad_rows(int64_t m) { return hk_grid_for(m, 16, 256) * 4; }
 
 hipError_t hk_mlp_grad(hipStream_t st, const float* p, const float* mu, const float* sd, const float* X, const float* y,
-                       const int32_t* idx, int64_t m, float* partial, float* partial_loss, float* grad, float* loss) {
+                       const int32_t* idx, int64_t m, float* partial, float* partial_loss, int64_t partial_cap_rows,
+                       float* grad, float* loss) {
   const int64_t rows = hk_mlp_grad_rows(m);   // waves, 4 per block
+  if (rows > partial_cap_rows) return hipErrorInvalidValue;  // scratch too small for this batch
   const int64_t per = (m + rows - 1) / rows;
   const float scale = m > 0 ? 2.0f / static_cast<float>(m) : 0.f;
   hipLaunchKernelGGL(k_mlp_grad, dim3(rows / 4), dim3(256), 0, st, p, mu, sd, X, y, idx, m, per, scale, partial,
