@@ -429,6 +429,13 @@ __device__ __forceinline__ double i128_to_f64(uint64_t lo, int64_t hi) {
     }                           \
   } while (0)
 
+// grid of `nwg` workgroups: 1-D up to 65536, else 2-D (x = 65536); the kernel
+// linearises blockIdx and lets workgroups past nwg leave at once
+static inline dim3 hk_wg_grid(int64_t nwg) {
+  if (nwg <= 65536) return dim3(static_cast<uint32_t>(nwg));
+  return dim3(65536u, static_cast<uint32_t>((nwg + 65535) / 65536));
+}
+
 static inline int64_t hk_grid_for(int64_t work, int64_t block, int64_t cap) {
   int64_t g = (work + block - 1) / block;
   if (g < 1) g = 1;

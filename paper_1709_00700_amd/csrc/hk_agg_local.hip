@@ -12,7 +12,11 @@ hipError_t hk_agg_global(hipStream_t st, const HkPlan& P, const HkAggTable& T, i
                          int64_t groups, int32_t wg, uint32_t llog2, const HkIdent& id, int* err);
 
 template <int MEM, int PRED, int HT, int HASH, int STRAT>
-__global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t llog2, HkIdent id, int* err) {
+__global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t llog2, HkIdent id, int64_t nwg,
+                                              int* err) {
+  // workgroups may come as a 2-D grid (HSA counts grid sizes in work-items as 32-bit values)
+  const int64_t wgid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  if (wgid >= nwg) return;  // padding workgroup: leaves before any barrier
   extern __shared__ uint64_t lds[];
   const int64_t LC = STRAT == HK_LOCAL ? (static_cast<int64_t>(1) << llog2) : 0;
   if (STRAT == HK_LOCAL) {
@@ -22,8 +26,8 @@ __global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t l
   }
   v16i64 r = {};
   const int64_t n = P.nrows;
-  const int64_t Tn = (int64_t)gridDim.x * blockDim.x;
-  const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t Tn = nwg * blockDim.x;
+  const int64_t gt = wgid * blockDim.x + threadIdx.x;
   int64_t b, e, step;
   if (MEM == HK_COAL) { b = gt; e = n; step = Tn; }
   else { seq_range(n, gt, Tn, 1, b, e); step = 1; }
@@ -55,10 +59,10 @@ __global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t l
 
 hipError_t hk_agg_local(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
                       int64_t groups, int32_t wg, uint32_t llog2, const HkIdent& id, int* err) {
-  const dim3 g(static_cast<uint32_t>(groups)), b(static_cast<uint32_t>(wg));
+  const dim3 g = hk_wg_grid(groups), b(static_cast<uint32_t>(wg));
   const size_t lds = (static_cast<size_t>(1) << llog2) * id.nw * sizeof(uint64_t);
   DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS,
-            hipLaunchKernelGGL((k_agg<M, PR, HT, HS, 0>), g, b, lds, st, P, T, llog2, id, err)))));
+            hipLaunchKernelGGL((k_agg<M, PR, HT, HS, 0>), g, b, lds, st, P, T, llog2, id, groups, err)))));
   HK_CHECK_LAUNCH();
 }
 

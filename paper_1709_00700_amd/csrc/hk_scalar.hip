@@ -30,7 +30,9 @@ __device__ __forceinline__ void merge_partial(uint64_t* tgt, const HkPlan& P, ui
 }
 
 template <int MEM, int PRED, int HT, int HASH, int STRAT>
-__global__ void __launch_bounds__(1024) k_scalar_agg(HkPlan P, HkAggTable T, HkIdent id) {
+__global__ void __launch_bounds__(1024) k_scalar_agg(HkPlan P, HkAggTable T, HkIdent id, int64_t nwg) {
+  const int64_t wgid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  if (wgid >= nwg) return;  // padding workgroup of a 2-D grid
   __shared__ uint64_t lw[2 + 2 * HK_MAX_AGGS];
   if (STRAT == HK_LOCAL) {
     if (threadIdx.x == 0)
@@ -48,8 +50,8 @@ __global__ void __launch_bounds__(1024) k_scalar_agg(HkPlan P, HkAggTable T, HkI
   }
   v16i64 r = {};
   const int64_t n = P.nrows;
-  const int64_t Tn = (int64_t)gridDim.x * blockDim.x;
-  const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t Tn = nwg * blockDim.x;
+  const int64_t gt = wgid * blockDim.x + threadIdx.x;
   int64_t b, e, step;
   if (MEM == HK_COAL) { b = gt; e = n; step = Tn; }
   else { seq_range(n, gt, Tn, 1, b, e); step = 1; }
@@ -92,8 +94,8 @@ hipError_t hk_scalar_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, i
   HkIdent id = {};
   for (int i = 0; i < nw; ++i) id.w[i] = ident[i];
   id.nw = nw;
-  const dim3 g(static_cast<uint32_t>(groups)), b(static_cast<uint32_t>(wg));
+  const dim3 g = hk_wg_grid(groups), b(static_cast<uint32_t>(wg));
   DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS, DISPATCH2(strat, SG,
-            hipLaunchKernelGGL((k_scalar_agg<M, PR, HT, HS, SG>), g, b, 0, st, P, T, id))))));
+            hipLaunchKernelGGL((k_scalar_agg<M, PR, HT, HS, SG>), g, b, 0, st, P, T, id, groups))))));
   return hipGetLastError();
 }
