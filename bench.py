@@ -35,8 +35,8 @@ METRIC = "input rows/s + HBM GB/s per pipeline; learned-pick vs best-variant run
 # variant optimizer on this device; see the design doc for how they were found)
 DEFAULT_VARIANTS = {
     "c1": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=1024, wg_size=256),
-    "c2u": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=8, wg_size=256),
-    "c2z": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=8, wg_size=256),
+    "c2u": dict(proj_strategy=1, mem=1, pred=1, ht=0, hash=1, agg_strategy=0, thread_mult=8, wg_size=512),
+    "c2z": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=8, wg_size=512),
     "c3": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=8, wg_size=256),
     "c4": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=8, wg_size=256),
 }

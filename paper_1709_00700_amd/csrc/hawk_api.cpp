@@ -493,7 +493,20 @@ extern "C" hawk_status hawk_query_create(hawk_ctx* ctx, const hawk_pipeline* pip
   return HAWK_OK;
 }
 
-extern "C" void hawk_query_free(hawk_query* q) { delete q; }
+extern "C" void hawk_query_free(hawk_query* q) {
+  if (!q) return;
+  if (q->ctx && q->ctx->device >= 0 && (q->d_plans || !q->jt.empty())) {
+    (void)hipStreamSynchronize(q->ctx->stream);
+    for (auto& t : q->jt) {
+      if (t.slots) (void)hipFree(t.slots);
+      if (t.side) (void)hipFree(t.side);
+    }
+    if (q->d_plans) (void)hipFree(q->d_plans);
+    if (q->h_stage) (void)hipHostFree(q->h_stage);
+    if (q->up_ev) (void)hipEventDestroy(q->up_ev);
+  }
+  delete q;
+}
 
 extern "C" hawk_status hawk_query_kind(const hawk_query* q, int32_t* kind) {
   if (!q || !kind) return HAWK_E_ARG;
@@ -671,27 +684,77 @@ HkHash make_hash(hawk_ctx* ctx, const hawk_variant* v, int attempt) {
   return h;
 }
 
-hawk_status run_builds(Exec& X, HkPlan& main, const HkHash& h, int grow) {
-  const hawk_query* q = X.q;
-  std::vector<HkJoinTable> tabs;
-  for (const QueryBuild& B : q->builds) {
-    HkJoinTable t;
-    t.log2cap = std::max<uint32_t>(4, ceil_log2(static_cast<uint64_t>(std::max<int64_t>(1, B.nrows)) * 2)) + grow;
-    if (t.log2cap > 31) return set_error(X.ctx, HAWK_E_CAPACITY, "join table beyond 2^31 slots");
-    t.pad = 0;
-    ALLOC(t.slots, uint64_t*, (static_cast<size_t>(1) << t.log2cap) * 8, false);
-    ALLOC(t.side, uint64_t*, 8, false);
-    HIPCHK(hk_fill_u64(X.st, t.slots, int64_t(1) << t.log2cap, HK_EMPTY), "fill join table");
-    HIPCHK(hk_fill_u64(X.st, t.side, 1, 0), "fill side slot");
-    HkPlan bp = B.plan;
-    bp.hash = h;
-    {
-      ProfScope ps(X.ctx, "k_build");
-      HIPCHK(hk_build(X.st, bp, B.key, B.payload, t, X.v->ht, X.v->hash, X.res->d_err), "build");
-    }
-    tabs.push_back(t);
+// Uploads the main plan and the build plans to the query's device buffer when
+// they differ from the last upload (new hash seeds or tables); the copy is
+// ordered on the context stream from a pinned staging buffer.
+hawk_status upload_plans(Exec& X, const HkPlan& main, const std::vector<HkBuild>& builds) {
+  hawk_query* q = const_cast<hawk_query*>(X.q);
+  const size_t bytes = sizeof(HkPlan) + builds.size() * sizeof(HkBuild);
+  std::vector<char> now(bytes);
+  std::memcpy(now.data(), &main, sizeof(HkPlan));
+  if (!builds.empty()) std::memcpy(now.data() + sizeof(HkPlan), builds.data(), builds.size() * sizeof(HkBuild));
+  if (!q->d_plans) {
+    if (hipMalloc(&q->d_plans, bytes) != hipSuccess) return set_error(X.ctx, HAWK_E_OOM, "plan buffer");
+    if (hipHostMalloc(&q->h_stage, bytes, hipHostMallocDefault) != hipSuccess)
+      return set_error(X.ctx, HAWK_E_OOM, "plan staging buffer");
+    if (hipEventCreateWithFlags(&q->up_ev, hipEventDisableTiming) != hipSuccess)
+      return set_error(X.ctx, HAWK_E_DEVICE, "plan upload event");
   }
-  for (int i = 0; i < main.nprobes; ++i) main.probes[i].t = tabs[q->probe_build[i]];
+  if (now == q->uploaded) return HAWK_OK;
+  if (q->up_pending) HIPCHK(hipEventSynchronize(q->up_ev), "plan upload wait");
+  std::memcpy(q->h_stage, now.data(), bytes);
+  HIPCHK(hipMemcpyAsync(q->d_plans, q->h_stage, bytes, hipMemcpyHostToDevice, X.st), "plan upload");
+  HIPCHK(hipEventRecord(q->up_ev, X.st), "plan upload event");
+  q->up_pending = true;
+  q->uploaded.swap(now);
+  return HAWK_OK;
+}
+
+const HkPlan* dev_main(const hawk_query* q) { return static_cast<const HkPlan*>(q->d_plans); }
+const HkBuild* dev_build(const hawk_query* q, size_t i) {
+  return reinterpret_cast<const HkBuild*>(static_cast<const char*>(q->d_plans) + sizeof(HkPlan)) + i;
+}
+
+hawk_status run_builds(Exec& X, HkPlan& main, const HkHash& h, int grow) {
+  hawk_query* q = const_cast<hawk_query*>(X.q);
+  if (q->jt.size() != q->builds.size()) q->jt.resize(q->builds.size());
+  std::vector<HkBuild> bs;
+  for (size_t i = 0; i < q->builds.size(); ++i) {
+    const QueryBuild& B = q->builds[i];
+    JoinTableMem& m = q->jt[i];
+    const uint32_t l2 = std::max<uint32_t>(4, ceil_log2(static_cast<uint64_t>(std::max<int64_t>(1, B.nrows)) * 2)) + grow;
+    if (l2 > 31) return set_error(X.ctx, HAWK_E_CAPACITY, "join table beyond 2^31 slots");
+    if (!m.slots || m.log2cap != l2) {
+      if (m.slots) {
+        HIPCHK(hipStreamSynchronize(X.st), "synchronize");
+        (void)hipFree(m.slots);
+        (void)hipFree(m.side);
+        m.slots = m.side = nullptr;
+      }
+      if (hipMalloc(&m.slots, (static_cast<size_t>(1) << l2) * 8) != hipSuccess || hipMalloc(&m.side, 8) != hipSuccess)
+        return set_error(X.ctx, HAWK_E_OOM, "join table allocation failed");
+      m.log2cap = l2;
+    }
+    HkBuild b;
+    std::memset(&b, 0, sizeof(b));
+    b.p = B.plan;
+    b.p.hash = h;
+    b.key = B.key;
+    b.payload = B.payload;
+    b.t.slots = m.slots;
+    b.t.side = m.side;
+    b.t.log2cap = l2;
+    bs.push_back(b);
+  }
+  for (int i = 0; i < main.nprobes; ++i) main.probes[i].t = bs[q->probe_build[i]].t;
+  hawk_status st = upload_plans(X, main, bs);
+  if (st) return st;
+  for (size_t i = 0; i < bs.size(); ++i) {
+    HIPCHK(hk_fill_u64(X.st, bs[i].t.slots, int64_t(1) << bs[i].t.log2cap, HK_EMPTY), "fill join table");
+    HIPCHK(hk_fill_u64(X.st, bs[i].t.side, 1, 0), "fill side slot");
+    ProfScope ps(X.ctx, "k_build");
+    HIPCHK(hk_build(X.st, bs[i], dev_build(q, i), X.v->ht, X.v->hash, X.res->d_err), "build");
+  }
   return HAWK_OK;
 }
 
@@ -726,7 +789,7 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
     ALLOC(tmp, uint32_t*, static_cast<size_t>(hk_scan_tmp_words(m)) * 4, false);
     {
       ProfScope ps(ctx, "k_mp_filter");
-      HIPCHK(hk_mp_filter(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, counts), "filter kernel");
+      HIPCHK(hk_mp_filter(X.st, P, dev_main(X.q), v->mem, v->pred, v->ht, v->hash, threads, masks, counts), "filter kernel");
     }
     {
       ProfScope ps(ctx, "k_scan");
@@ -734,7 +797,7 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
     }
     {
       ProfScope ps(ctx, "k_mp_project");
-      HIPCHK(hk_mp_project(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, offsets, res->d_count, nact,
+      HIPCHK(hk_mp_project(X.st, P, dev_main(X.q), v->mem, v->pred, v->ht, v->hash, threads, masks, offsets, res->d_count, nact,
                            out, n), "projection kernel");
     }
   } else {
@@ -757,7 +820,7 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
     ALLOC(stmp, uint32_t*, static_cast<size_t>(hk_scan_tmp_words(nregions)) * 4, false);
     {
       ProfScope ps(ctx, "k_sp");
-      HIPCHK(hk_sp(X.st, P, v->mem, v->pred, v->ht, v->hash, inst, tmp, region, counts), "single-pass kernel");
+      HIPCHK(hk_sp(X.st, P, dev_main(X.q), v->mem, v->pred, v->ht, v->hash, inst, tmp, region, counts), "single-pass kernel");
     }
     {
       ProfScope ps(ctx, "k_scan");
@@ -823,11 +886,11 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
         return set_error(ctx, HAWK_E_INFEASIBLE, "local table does not fit in LDS");
     }
     ProfScope ps(ctx, "k_agg");
-    HIPCHK(hk_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, llog2, ident, W,
+    HIPCHK(hk_agg(X.st, P, dev_main(X.q), T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, llog2, ident, W,
                   res->d_err), "aggregation kernel");
   } else {
     ProfScope ps(ctx, "k_scalar_agg");
-    HIPCHK(hk_scalar_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, ident, W,
+    HIPCHK(hk_scalar_agg(X.st, P, dev_main(X.q), T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, ident, W,
                          res->d_err), "aggregation kernel");
   }
   // result columns: groups, aggregates, count
@@ -848,7 +911,7 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
   res->cols.push_back({HAWK_RES_I64, cnt});
   {
     ProfScope ps(ctx, "k_finalize");
-    HIPCHK(hk_finalize(X.st, P, T, nslots, gcols, acols, cnt, res->d_count, grouped ? 0 : 1), "finalize");
+    HIPCHK(hk_finalize(X.st, P, dev_main(X.q), T, nslots, gcols, acols, cnt, res->d_count, grouped ? 0 : 1), "finalize");
   }
   return HAWK_OK;
 }

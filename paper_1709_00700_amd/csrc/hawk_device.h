@@ -190,18 +190,28 @@ __device__ __forceinline__ void join_insert(const HkJoinTable& t, const HkHash& 
 // Predicated: evaluates everything and returns the result_increment.
 template <int PRED, int HT, int HASH, bool VALUES>
 __device__ __forceinline__ bool eval_row(const HkPlan& P, int64_t row, v16i64& r) {
+  // all loads of a phase are issued before any is consumed, so their
+  // latencies overlap
+  int64_t la[HK_MAX_COLS_A];
 #pragma unroll
   for (int c = 0; c < HK_MAX_COLS_A; ++c)
-    if (c < P.ncolA) r[P.colA[c].reg] = load_col(P.colA[c], row);
+    if (c < P.ncolA) la[c] = load_col(P.colA[c], row);
+#pragma unroll
+  for (int c = 0; c < HK_MAX_COLS_A; ++c)
+    if (c < P.ncolA) r[P.colA[c].reg] = la[c];
   bool pass = true;
   for (int f = 0; f < P.nfilters; ++f) {
     const int64_t x = r[P.filters[f].reg];
     pass = pass & (x >= P.filters[f].lo) & (x <= P.filters[f].hi);
   }
   if (PRED == HK_BR && !pass) return false;
+  int64_t lb[HK_MAX_COLS_B];
 #pragma unroll
   for (int c = 0; c < HK_MAX_COLS_B; ++c)
-    if (c < P.ncolB) r[P.colB[c].reg] = load_col(P.colB[c], row);
+    if (c < P.ncolB) lb[c] = load_col(P.colB[c], row);
+#pragma unroll
+  for (int c = 0; c < HK_MAX_COLS_B; ++c)
+    if (c < P.ncolB) r[P.colB[c].reg] = lb[c];
   for (int p = 0; p < P.nprobes; ++p) {
     int32_t pay = 0;
     const bool found = join_lookup<HT, HASH>(P.probes[p].t, P.hash, static_cast<int32_t>(r[P.probes[p].fk_reg]), pay);
@@ -210,9 +220,13 @@ __device__ __forceinline__ bool eval_row(const HkPlan& P, int64_t row, v16i64& r
     r[P.probes[p].pay_reg] = pay;
   }
   if (!VALUES) return pass;
+  int64_t lc[HK_MAX_COLS_C];
 #pragma unroll
   for (int c = 0; c < HK_MAX_COLS_C; ++c)
-    if (c < P.ncolC) r[P.colC[c].reg] = load_col(P.colC[c], row);
+    if (c < P.ncolC) lc[c] = load_col(P.colC[c], row);
+#pragma unroll
+  for (int c = 0; c < HK_MAX_COLS_C; ++c)
+    if (c < P.ncolC) r[P.colC[c].reg] = lc[c];
   for (int k = 0; k < P.narith; ++k) {
     const HkArith& A = P.arith[k];
     const uint64_t x = A.xc ? static_cast<uint64_t>(A.cx) : static_cast<uint64_t>(r[A.x]);
@@ -235,11 +249,6 @@ __device__ __forceinline__ void seq_range(int64_t n, int64_t t, int64_t T, int64
 // ------------------------------------------------------------------ structs passed to kernels
 struct HkIdent { uint64_t w[2 + 2 * HK_MAX_AGGS]; int32_t nw; };
 struct HkOut { int64_t* col[HK_MAX_PROJ]; int64_t dump; };
-struct HkBuild {
-  HkPlan p;              // LOOP + FILTER part (colA filter columns), nrows
-  HkCol key, payload;
-  HkJoinTable t;
-};
 struct HkResOut {
   int64_t* gcol[2];
   void* acol[HK_MAX_AGGS];

@@ -57,8 +57,18 @@ struct QueryBuild {
   int64_t nrows = 0;
 };
 
+// a join table owned by a query (kept across executions)
+struct JoinTableMem { uint64_t* slots = nullptr; uint64_t* side = nullptr; uint32_t log2cap = 0; };
+
 struct hawk_query {
   hawk_ctx* ctx = nullptr;
+  // device copies of the lowered plans read by the kernels: [main HkPlan][HkBuild x builds]
+  void* d_plans = nullptr;
+  void* h_stage = nullptr;           // pinned staging buffer of the upload
+  hipEvent_t up_ev = nullptr;        // completes when the last upload has been read
+  bool up_pending = false;
+  std::vector<char> uploaded;        // bytes of the last upload
+  std::vector<JoinTableMem> jt;      // one per build pipeline
   int kind = 0;                      // 1 projection, 2 aggregation
   std::vector<QueryBuild> builds;
   std::vector<int> probe_build;      // build index of each probe of the main pipeline

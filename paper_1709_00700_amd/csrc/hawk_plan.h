@@ -68,5 +68,12 @@ struct HkPlan {
   int32_t slot_words;
 };
 
+// a build pipeline (LOOP, FILTER, HASH_PUT): filter part, key and payload columns, target table
+struct HkBuild {
+  HkPlan p;              // LOOP + FILTER part (colA filter columns), nrows, hash functions
+  HkCol key, payload;
+  HkJoinTable t;
+};
+
 // an aggregation hash table in HBM (plus one side slot for the sentinel key)
 struct HkAggTable { uint64_t* words; uint32_t log2cap; int32_t slot_words; };

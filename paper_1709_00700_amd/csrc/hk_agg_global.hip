@@ -6,14 +6,15 @@
 
 #define HK_CHECK_LAUNCH() return hipGetLastError()
 
-hipError_t hk_agg_local(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
+hipError_t hk_agg_local(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int mem, int pred, int ht, int hash,
                         int64_t groups, int32_t wg, uint32_t llog2, const HkIdent& id, int* err);
-hipError_t hk_agg_global(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
+hipError_t hk_agg_global(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int mem, int pred, int ht, int hash,
                          int64_t groups, int32_t wg, uint32_t llog2, const HkIdent& id, int* err);
 
 template <int MEM, int PRED, int HT, int HASH, int STRAT>
-__global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t llog2, HkIdent id, int64_t nwg,
+__global__ void __launch_bounds__(1024) k_agg(const HkPlan* Pp, HkAggTable T, uint32_t llog2, HkIdent id, int64_t nwg,
                                               int* err) {
+  const HkPlan& P = *Pp;  // plan in device memory, read where used
   // workgroups may come as a 2-D grid (HSA counts grid sizes in work-items as 32-bit values)
   const int64_t wgid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   if (wgid >= nwg) return;  // padding workgroup: leaves before any barrier
@@ -57,18 +58,19 @@ __global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t l
 }
 
 
-hipError_t hk_agg_global(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
+hipError_t hk_agg_global(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int mem, int pred, int ht, int hash,
                       int64_t groups, int32_t wg, uint32_t llog2, const HkIdent& id, int* err) {
   const dim3 g = hk_wg_grid(groups), b(static_cast<uint32_t>(wg));
   const size_t lds = 0;
   DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS,
-            hipLaunchKernelGGL((k_agg<M, PR, HT, HS, 1>), g, b, lds, st, P, T, llog2, id, groups, err)))));
+            hipLaunchKernelGGL((k_agg<M, PR, HT, HS, 1>), g, b, lds, st, dP, T, llog2, id, groups, err)))));
   HK_CHECK_LAUNCH();
 }
 
 // cuckoo aggregation, phase 1: insert every group key that reaches the sink
 template <int MEM, int PRED, int HASH>
-__global__ void __launch_bounds__(256) k_agg_keys(HkPlan P, HkAggTable T, int* err) {
+__global__ void __launch_bounds__(256) k_agg_keys(const HkPlan* Pp, HkAggTable T, int* err) {
+  const HkPlan& P = *Pp;  // plan in device memory, read where used
   v16i64 r = {};
   const int64_t n = P.nrows;
   const int64_t Tn = (int64_t)gridDim.x * blockDim.x;
@@ -83,22 +85,22 @@ __global__ void __launch_bounds__(256) k_agg_keys(HkPlan P, HkAggTable T, int* e
   }
 }
 
-hipError_t hk_agg_keys(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int hash, int* err) {
+hipError_t hk_agg_keys(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int mem, int pred, int hash, int* err) {
   const dim3 gk(hk_grid_for(P.nrows, 256, 8192)), bk(256);
   DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(hash, HS,
-            hipLaunchKernelGGL((k_agg_keys<M, PR, HS>), gk, bk, 0, st, P, T, err))));
+            hipLaunchKernelGGL((k_agg_keys<M, PR, HS>), gk, bk, 0, st, dP, T, err))));
   HK_CHECK_LAUNCH();
 }
 
-hipError_t hk_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
+hipError_t hk_agg(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int mem, int pred, int ht, int hash,
                   int strat, int64_t groups, int32_t wg, uint32_t llog2, const uint64_t* ident, int32_t nw, int* err) {
   HkIdent id = {};
   for (int i = 0; i < nw; ++i) id.w[i] = ident[i];
   id.nw = nw;
   if (ht == HK_CUCKOO) {
-    hipError_t e = hk_agg_keys(st, P, T, mem, pred, hash, err);
+    hipError_t e = hk_agg_keys(st, P, dP, T, mem, pred, hash, err);
     if (e != hipSuccess) return e;
   }
-  if (strat == HK_LOCAL) return hk_agg_local(st, P, T, mem, pred, ht, hash, groups, wg, llog2, id, err);
-  return hk_agg_global(st, P, T, mem, pred, ht, hash, groups, wg, llog2, id, err);
+  if (strat == HK_LOCAL) return hk_agg_local(st, P, dP, T, mem, pred, ht, hash, groups, wg, llog2, id, err);
+  return hk_agg_global(st, P, dP, T, mem, pred, ht, hash, groups, wg, llog2, id, err);
 }

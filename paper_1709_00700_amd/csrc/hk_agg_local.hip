@@ -6,14 +6,15 @@
 
 #define HK_CHECK_LAUNCH() return hipGetLastError()
 
-hipError_t hk_agg_local(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
+hipError_t hk_agg_local(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int mem, int pred, int ht, int hash,
                         int64_t groups, int32_t wg, uint32_t llog2, const HkIdent& id, int* err);
-hipError_t hk_agg_global(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
+hipError_t hk_agg_global(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int mem, int pred, int ht, int hash,
                          int64_t groups, int32_t wg, uint32_t llog2, const HkIdent& id, int* err);
 
 template <int MEM, int PRED, int HT, int HASH, int STRAT>
-__global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t llog2, HkIdent id, int64_t nwg,
+__global__ void __launch_bounds__(1024) k_agg(const HkPlan* Pp, HkAggTable T, uint32_t llog2, HkIdent id, int64_t nwg,
                                               int* err) {
+  const HkPlan& P = *Pp;  // plan in device memory, read where used
   // workgroups may come as a 2-D grid (HSA counts grid sizes in work-items as 32-bit values)
   const int64_t wgid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   if (wgid >= nwg) return;  // padding workgroup: leaves before any barrier
@@ -57,12 +58,12 @@ __global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t l
 }
 
 
-hipError_t hk_agg_local(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
+hipError_t hk_agg_local(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int mem, int pred, int ht, int hash,
                       int64_t groups, int32_t wg, uint32_t llog2, const HkIdent& id, int* err) {
   const dim3 g = hk_wg_grid(groups), b(static_cast<uint32_t>(wg));
   const size_t lds = (static_cast<size_t>(1) << llog2) * id.nw * sizeof(uint64_t);
   DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS,
-            hipLaunchKernelGGL((k_agg<M, PR, HT, HS, 0>), g, b, lds, st, P, T, llog2, id, groups, err)))));
+            hipLaunchKernelGGL((k_agg<M, PR, HT, HS, 0>), g, b, lds, st, dP, T, llog2, id, groups, err)))));
   HK_CHECK_LAUNCH();
 }
 

@@ -25,7 +25,8 @@ __global__ void __launch_bounds__(256) k_init_aggtable(uint64_t* words, int64_t 
 }
 
 template <int HT, int HASH>
-__global__ void __launch_bounds__(256) k_build(HkBuild B, int* err) {
+__global__ void __launch_bounds__(256) k_build(const HkBuild* Bp, int* err) {
+  const HkBuild& B = *Bp;  // build plan in device memory
   v16i64 r = {};
   const int64_t T = (int64_t)gridDim.x * blockDim.x;
   for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < B.p.nrows; row += T) {
@@ -37,7 +38,8 @@ __global__ void __launch_bounds__(256) k_build(HkBuild B, int* err) {
 
 // a cuckoo table may hold two copies of a key inserted twice; count copies
 template <int HASH>
-__global__ void __launch_bounds__(256) k_build_verify(HkBuild B, int* err) {
+__global__ void __launch_bounds__(256) k_build_verify(const HkBuild* Bp, int* err) {
+  const HkBuild& B = *Bp;  // build plan in device memory
   v16i64 r = {};
   const int64_t T = (int64_t)gridDim.x * blockDim.x;
   for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < B.p.nrows; row += T) {
@@ -168,7 +170,8 @@ __global__ void __launch_bounds__(256) k_sp_concat(HkOut tmp, int32_t nproj, int
 }
 
 // ------------------------------------------------------------------ finalize
-__global__ void __launch_bounds__(256) k_finalize(HkPlan P, HkAggTable T, int64_t nslots, HkResOut O) {
+__global__ void __launch_bounds__(256) k_finalize(const HkPlan* Pp, HkAggTable T, int64_t nslots, HkResOut O) {
+  const HkPlan& P = *Pp;  // plan in device memory, read where used
   const int64_t W = T.slot_words;
   for (int64_t base = blockIdx.x * (int64_t)blockDim.x + threadIdx.x - __lane_id(); base < nslots;
        base += (int64_t)gridDim.x * blockDim.x) {
@@ -224,17 +227,11 @@ hipError_t hk_init_aggtable(hipStream_t st, uint64_t* words, int64_t nslots, con
   HK_CHECK_LAUNCH();
 }
 
-hipError_t hk_build(hipStream_t st, const HkPlan& p, const HkCol& key, const HkCol& pay, const HkJoinTable& t,
-                    int ht, int hash, int* err) {
-  HkBuild B;
-  B.p = p;
-  B.key = key;
-  B.payload = pay;
-  B.t = t;
-  const dim3 g(hk_grid_for(p.nrows, 256, 4096)), b(256);
-  DISPATCH2(ht, HT, DISPATCH2(hash, HS, hipLaunchKernelGGL((k_build<HT, HS>), g, b, 0, st, B, err)));
+hipError_t hk_build(hipStream_t st, const HkBuild& B, const HkBuild* dB, int ht, int hash, int* err) {
+  const dim3 g(hk_grid_for(B.p.nrows, 256, 4096)), b(256);
+  DISPATCH2(ht, HT, DISPATCH2(hash, HS, hipLaunchKernelGGL((k_build<HT, HS>), g, b, 0, st, dB, err)));
   if (ht == HK_CUCKOO) {
-    DISPATCH2(hash, HS, hipLaunchKernelGGL((k_build_verify<HS>), g, b, 0, st, B, err));
+    DISPATCH2(hash, HS, hipLaunchKernelGGL((k_build_verify<HS>), g, b, 0, st, dB, err));
   }
   HK_CHECK_LAUNCH();
 }
@@ -264,7 +261,7 @@ hipError_t hk_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t m,
   HK_CHECK_LAUNCH();
 }
 
-hipError_t hk_finalize(hipStream_t st, const HkPlan& P, const HkAggTable& T, int64_t nslots, int64_t* const* gcols,
+hipError_t hk_finalize(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int64_t nslots, int64_t* const* gcols,
                        void* const* acols, int64_t* count, uint64_t* nrows, int keep_empty) {
   HkResOut O = {};
   for (int g = 0; g < P.ngroup; ++g) O.gcol[g] = gcols[g];
@@ -272,6 +269,6 @@ hipError_t hk_finalize(hipStream_t st, const HkPlan& P, const HkAggTable& T, int
   O.count = count;
   O.nrows = reinterpret_cast<unsigned long long*>(nrows);
   O.keep_empty = keep_empty;
-  hipLaunchKernelGGL(k_finalize, dim3(hk_grid_for(nslots, 256, 8192)), dim3(256), 0, st, P, T, nslots, O);
+  hipLaunchKernelGGL(k_finalize, dim3(hk_grid_for(nslots, 256, 8192)), dim3(256), 0, st, dP, T, nslots, O);
   HK_CHECK_LAUNCH();
 }

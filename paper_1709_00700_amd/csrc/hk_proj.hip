@@ -14,7 +14,8 @@
 // per scan unit (a 64-row block for coalesced access, a thread's chunk for
 // sequential access).
 template <int MEM, int PRED, int HT, int HASH>
-__global__ void __launch_bounds__(256) k_mp_filter(HkPlan P, uint64_t* __restrict__ masks, uint32_t* __restrict__ counts) {
+__global__ void __launch_bounds__(256) k_mp_filter(const HkPlan* Pp, uint64_t* __restrict__ masks, uint32_t* __restrict__ counts) {
+  const HkPlan& P = *Pp;  // plan in device memory, read where used
   v16i64 r = {};
   const int64_t n = P.nrows;
   const int64_t T = (int64_t)gridDim.x * blockDim.x;
@@ -54,9 +55,10 @@ __global__ void __launch_bounds__(256) k_mp_filter(HkPlan P, uint64_t* __restric
 // Phase 3, projection kernel: repeats the probes to get the payloads, computes
 // the arithmetic and writes each qualifying row at its scanned position.
 template <int MEM, int PRED, int HT, int HASH>
-__global__ void __launch_bounds__(256) k_mp_project(HkPlan P, const uint64_t* __restrict__ masks,
+__global__ void __launch_bounds__(256) k_mp_project(const HkPlan* Pp, const uint64_t* __restrict__ masks,
                                                     const uint32_t* __restrict__ offsets, const uint64_t* total,
                                                     int64_t nact, HkOut O) {
+  const HkPlan& P = *Pp;  // plan in device memory, read where used
   v16i64 r = {};
   const int64_t n = P.nrows;
   const int64_t T = (int64_t)gridDim.x * blockDim.x;
@@ -114,7 +116,8 @@ __global__ void __launch_bounds__(256) k_mp_project(HkPlan P, const uint64_t* __
 //   coalesced: the wave walks its chunk 64 rows at a time; ballot + mbcnt keep row order
 //   sequential: each lane walks a sub-chunk and owns a region of sub + 1 slots
 template <int MEM, int PRED, int HT, int HASH>
-__global__ void __launch_bounds__(64) k_sp(HkPlan P, HkOut tmp, int64_t region, uint32_t* __restrict__ counts) {
+__global__ void __launch_bounds__(64) k_sp(const HkPlan* Pp, HkOut tmp, int64_t region, uint32_t* __restrict__ counts) {
+  const HkPlan& P = *Pp;  // plan in device memory, read where used
   v16i64 r = {};
   const int64_t n = P.nrows;
   const int64_t inst = blockIdx.x;
@@ -162,15 +165,15 @@ __global__ void __launch_bounds__(64) k_sp(HkPlan P, HkOut tmp, int64_t region, 
 
 
 // ================================================================== host launchers
-hipError_t hk_mp_filter(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t threads,
+hipError_t hk_mp_filter(hipStream_t st, const HkPlan& P, const HkPlan* dP, int mem, int pred, int ht, int hash, int64_t threads,
                         uint64_t* masks, uint32_t* counts) {
   const dim3 g(static_cast<uint32_t>((threads + 255) / 256)), b(256);
   DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS,
-            hipLaunchKernelGGL((k_mp_filter<M, PR, HT, HS>), g, b, 0, st, P, masks, counts)))));
+            hipLaunchKernelGGL((k_mp_filter<M, PR, HT, HS>), g, b, 0, st, dP, masks, counts)))));
   HK_CHECK_LAUNCH();
 }
 
-hipError_t hk_mp_project(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t threads,
+hipError_t hk_mp_project(hipStream_t st, const HkPlan& P, const HkPlan* dP, int mem, int pred, int ht, int hash, int64_t threads,
                          const uint64_t* masks, const uint32_t* offsets, const uint64_t* total, int64_t nact,
                          int64_t* const* out, int64_t dump) {
   HkOut O = {};
@@ -178,17 +181,17 @@ hipError_t hk_mp_project(hipStream_t st, const HkPlan& P, int mem, int pred, int
   O.dump = dump;
   const dim3 g(static_cast<uint32_t>((threads + 255) / 256)), b(256);
   DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS,
-            hipLaunchKernelGGL((k_mp_project<M, PR, HT, HS>), g, b, 0, st, P, masks, offsets, total, nact, O)))));
+            hipLaunchKernelGGL((k_mp_project<M, PR, HT, HS>), g, b, 0, st, dP, masks, offsets, total, nact, O)))));
   HK_CHECK_LAUNCH();
 }
 
-hipError_t hk_sp(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t instances,
+hipError_t hk_sp(hipStream_t st, const HkPlan& P, const HkPlan* dP, int mem, int pred, int ht, int hash, int64_t instances,
                  int64_t* const* tmp, int64_t region, uint32_t* counts) {
   HkOut O = {};
   for (int c = 0; c < P.nproj; ++c) O.col[c] = tmp[c];
   const dim3 g(static_cast<uint32_t>(instances)), b(WAVE);
   DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS,
-            hipLaunchKernelGGL((k_sp<M, PR, HT, HS>), g, b, 0, st, P, O, region, counts)))));
+            hipLaunchKernelGGL((k_sp<M, PR, HT, HS>), g, b, 0, st, dP, O, region, counts)))));
   HK_CHECK_LAUNCH();
 }
 

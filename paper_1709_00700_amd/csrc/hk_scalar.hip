@@ -30,7 +30,8 @@ __device__ __forceinline__ void merge_partial(uint64_t* tgt, const HkPlan& P, ui
 }
 
 template <int MEM, int PRED, int HT, int HASH, int STRAT>
-__global__ void __launch_bounds__(1024) k_scalar_agg(HkPlan P, HkAggTable T, HkIdent id, int64_t nwg) {
+__global__ void __launch_bounds__(1024) k_scalar_agg(const HkPlan* Pp, HkAggTable T, HkIdent id, int64_t nwg) {
+  const HkPlan& P = *Pp;  // plan in device memory, read where used
   const int64_t wgid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   if (wgid >= nwg) return;  // padding workgroup of a 2-D grid
   __shared__ uint64_t lw[2 + 2 * HK_MAX_AGGS];
@@ -88,7 +89,7 @@ __global__ void __launch_bounds__(1024) k_scalar_agg(HkPlan P, HkAggTable T, HkI
   }
 }
 
-hipError_t hk_scalar_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
+hipError_t hk_scalar_agg(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int mem, int pred, int ht, int hash,
                          int strat, int64_t groups, int32_t wg, const uint64_t* ident, int32_t nw, int* err) {
   (void)err;
   HkIdent id = {};
@@ -96,6 +97,6 @@ hipError_t hk_scalar_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, i
   id.nw = nw;
   const dim3 g = hk_wg_grid(groups), b(static_cast<uint32_t>(wg));
   DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS, DISPATCH2(strat, SG,
-            hipLaunchKernelGGL((k_scalar_agg<M, PR, HT, HS, SG>), g, b, 0, st, P, T, id, groups))))));
+            hipLaunchKernelGGL((k_scalar_agg<M, PR, HT, HS, SG>), g, b, 0, st, dP, T, id, groups))))));
   return hipGetLastError();
 }
