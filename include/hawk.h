@@ -65,7 +65,10 @@ typedef struct hawk_batch hawk_batch;
    features work; every execution entry point returns HAWK_E_DEVICE.
    Errors: HAWK_E_DEVICE (no such device), HAWK_E_ARG. */
 hawk_status hawk_ctx_create(int32_t device, void* hip_stream, hawk_ctx** out);
-/* Synchronises the stream and frees every device buffer the context owns. */
+/* Synchronises the stream and frees every device buffer the context owns,
+   including those of queries, results and models still alive: such handles
+   become orphaned, their *_free only releases host memory and every other
+   call on them returns HAWK_E_ARG. */
 void hawk_ctx_destroy(hawk_ctx* ctx);
 const char* hawk_last_error(const hawk_ctx* ctx);
 /* Device facts used by the variant space: compute units ("maximal compute

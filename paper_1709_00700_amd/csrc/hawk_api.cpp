@@ -194,12 +194,23 @@ extern "C" hawk_status hawk_ctx_create(int32_t device, void* hip_stream, hawk_ct
 
 extern "C" void hawk_ctx_destroy(hawk_ctx* ctx) {
   if (!ctx) return;
+  if (ctx->device >= 0) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+  }
+  for (hawk_query* q : ctx->queries) {
+    query_release_device(q);
+    q->ctx = nullptr;
+  }
+  for (hawk_result* r : ctx->results) {
+    r->owned.clear();  // the pool below returns their blocks
+    r->ctx = nullptr;
+  }
+  for (hawk_model* m : ctx->models) model_release_device(m);
   if (ctx->device < 0) {
     delete ctx;
     return;
   }
-  (void)hipSetDevice(ctx->device);
-  (void)hipStreamSynchronize(ctx->stream);
   ctx->pool.release_all();
   prof_clear(ctx);
   for (hipEvent_t e : ctx->prof_free) (void)hipEventDestroy(e);
@@ -489,21 +500,31 @@ extern "C" hawk_status hawk_query_create(hawk_ctx* ctx, const hawk_pipeline* pip
   if (st) { delete q; return st; }
   q->main = L.P;
   q->has_table = L.P.nprobes > 0 || L.P.ngroup > 0;
+  ctx->queries.insert(q);
   *out = q;
   return HAWK_OK;
 }
 
+void query_release_device(hawk_query* q) {
+  if (!q->ctx || q->ctx->device < 0) return;
+  if (q->d_plans || !q->jt.empty()) (void)hipStreamSynchronize(q->ctx->stream);
+  for (auto& t : q->jt) {
+    if (t.slots) (void)hipFree(t.slots);
+    if (t.side) (void)hipFree(t.side);
+  }
+  q->jt.clear();
+  if (q->d_plans) (void)hipFree(q->d_plans);
+  if (q->h_stage) (void)hipHostFree(q->h_stage);
+  if (q->up_ev) (void)hipEventDestroy(q->up_ev);
+  q->d_plans = q->h_stage = nullptr;
+  q->up_ev = nullptr;
+}
+
 extern "C" void hawk_query_free(hawk_query* q) {
   if (!q) return;
-  if (q->ctx && q->ctx->device >= 0 && (q->d_plans || !q->jt.empty())) {
-    (void)hipStreamSynchronize(q->ctx->stream);
-    for (auto& t : q->jt) {
-      if (t.slots) (void)hipFree(t.slots);
-      if (t.side) (void)hipFree(t.side);
-    }
-    if (q->d_plans) (void)hipFree(q->d_plans);
-    if (q->h_stage) (void)hipHostFree(q->h_stage);
-    if (q->up_ev) (void)hipEventDestroy(q->up_ev);
+  if (q->ctx) {
+    query_release_device(q);
+    q->ctx->queries.erase(q);
   }
   delete q;
 }
@@ -589,13 +610,17 @@ static void result_release(hawk_result* r) {
 
 extern "C" void hawk_result_free(hawk_result* r) {
   if (!r) return;
-  result_release(r);
+  if (r->ctx) {
+    result_release(r);
+    r->ctx->results.erase(r);
+  }
   delete r;
 }
 
 static hawk_status result_check(hawk_result* r) {
   if (r->checked) return r->status;
   hawk_ctx* ctx = r->ctx;
+  if (!ctx) return HAWK_E_ARG;  // its context was destroyed
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_error(ctx, e, "stream synchronize");
   int err = 0;
@@ -622,6 +647,7 @@ extern "C" hawk_status hawk_result_info(hawk_result* r, int64_t* nrows, int32_t*
 
 extern "C" hawk_status hawk_result_column(hawk_result* r, int32_t col, int32_t* elem_kind, const void** dev_ptr) {
   if (!r) return HAWK_E_ARG;
+  if (!r->ctx) return HAWK_E_ARG;
   if (col < 0 || col >= static_cast<int32_t>(r->cols.size())) return set_error(r->ctx, HAWK_E_ARG, "bad column index");
   if (elem_kind) *elem_kind = r->cols[col].kind;
   if (dev_ptr) *dev_ptr = r->cols[col].ptr;
@@ -919,13 +945,14 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
 hawk_status execute_once(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v, int attempt, int grow,
                          hawk_result** out) {
   if (ctx->device < 0) return set_error(ctx, HAWK_E_DEVICE, "planning context cannot execute");
+  if (q->ctx != ctx) return set_error(ctx, HAWK_E_ARG, "query of another context");
   hawk_result* res = new hawk_result();
   res->ctx = ctx;
   res->kind = q->kind;
+  ctx->results.insert(res);
   Exec X{ctx, q, v, res, {}, attempt, ctx->stream};
   auto fail = [&](hawk_status st) {
-    result_release(res);
-    delete res;
+    hawk_result_free(res);
     return st;
   };
   if (v->mem > 1 || v->pred > 1 || v->ht > 1 || v->hash > 1 || v->agg_strategy > 1 || v->proj_strategy > 1 ||

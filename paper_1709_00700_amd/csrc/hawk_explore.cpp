@@ -114,7 +114,7 @@ hawk_status query_features(const hawk_query* q, const hawk_variant* v, int num_c
 }
 
 extern "C" hawk_status hawk_features(const hawk_query* q, const hawk_variant* v, float* out12) {
-  if (!q || !v || !out12) return HAWK_E_ARG;
+  if (!q || !v || !out12 || !q->ctx) return HAWK_E_ARG;
   return query_features(q, v, q->ctx->num_cus, out12);
 }
 
@@ -226,7 +226,8 @@ extern "C" hawk_status hawk_explore(hawk_ctx* ctx, hawk_query* const* W, int32_t
   E.space.kind = W[0]->kind;
   E.space.table = false;
   for (int32_t i = 0; i < k; ++i) {
-    if (!W[i] || W[i]->kind != E.space.kind) return set_error(ctx, HAWK_E_ARG, "workload mixes pipeline kinds");
+    if (!W[i] || W[i]->ctx != ctx) return set_error(ctx, HAWK_E_ARG, "query of another context");
+    if (W[i]->kind != E.space.kind) return set_error(ctx, HAWK_E_ARG, "workload mixes pipeline kinds");
     E.space.table = E.space.table || W[i]->has_table;
   }
   if (E.space.kind == 1) E.space.sizes = {2, 7, 2, 2};

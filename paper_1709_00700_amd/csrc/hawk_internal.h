@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <set>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,11 @@ struct hawk_ctx {
   std::vector<TableReg> tables;
   DevicePool pool;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // live handles; destroying the context releases their device state and
+  // orphans them (their *_free then only releases host memory)
+  std::set<struct hawk_query*> queries;
+  std::set<struct hawk_result*> results;
+  std::set<struct hawk_model*> models;
   bool prof_on = false;
   std::vector<ProfRec> prof;           // launches recorded since profiling was enabled
   std::vector<hipEvent_t> prof_free;   // recycled events
@@ -95,5 +101,7 @@ struct hawk_result {
 };
 
 hawk_status set_error(hawk_ctx* ctx, hawk_status st, const std::string& msg);
+void query_release_device(hawk_query* q);
+void model_release_device(struct hawk_model* m);
 std::vector<hawk_variant> variant_space(const hawk_query* q);
 hawk_status query_features(const hawk_query* q, const hawk_variant* v, int num_cus, float* f);

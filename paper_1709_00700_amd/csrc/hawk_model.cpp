@@ -70,6 +70,7 @@ extern "C" hawk_status hawk_model_create(hawk_ctx* ctx, uint64_t seed, hawk_mode
   if (ctx->device < 0) return set_error(ctx, HAWK_E_DEVICE, "planning context cannot execute");
   hawk_model* M = new hawk_model();
   M->ctx = ctx;
+  ctx->models.insert(M);
   const size_t bytes = MLP_NPARAMS * sizeof(float);
   if (hipMalloc(&M->p, bytes) != hipSuccess || hipMalloc(&M->m1, bytes) != hipSuccess ||
       hipMalloc(&M->m2, bytes) != hipSuccess || hipMalloc(&M->mu, MLP_IN * 4) != hipSuccess ||
@@ -95,16 +96,26 @@ extern "C" hawk_status hawk_model_create(hawk_ctx* ctx, uint64_t seed, hawk_mode
   return HAWK_OK;
 }
 
-extern "C" void hawk_model_free(hawk_model* M) {
-  if (!M) return;
+void model_release_device(hawk_model* M) {
+  if (!M->ctx) return;
   (void)hipStreamSynchronize(M->ctx->stream);
   for (float* p : {M->p, M->m1, M->m2, M->mu, M->sd})
     if (p) (void)hipFree(p);
+  M->p = M->m1 = M->m2 = M->mu = M->sd = nullptr;
+  M->ctx = nullptr;
+}
+
+extern "C" void hawk_model_free(hawk_model* M) {
+  if (!M) return;
+  if (M->ctx) {
+    M->ctx->models.erase(M);
+    model_release_device(M);
+  }
   delete M;
 }
 
 extern "C" hawk_status hawk_model_set_params(hawk_model* M, const float* params, const float* mu, const float* sd) {
-  if (!M || !params || !mu || !sd) return HAWK_E_ARG;
+  if (!M || !M->ctx || !params || !mu || !sd) return HAWK_E_ARG;
   for (int k = 0; k < MLP_IN; ++k)
     if (!(sd[k] > 0.f)) return set_error(M->ctx, HAWK_E_ARG, "feature scale must be positive");
   CK(hipMemcpy(M->p, params, MLP_NPARAMS * 4, hipMemcpyHostToDevice), "upload params");
@@ -117,7 +128,7 @@ extern "C" hawk_status hawk_model_set_params(hawk_model* M, const float* params,
 }
 
 extern "C" hawk_status hawk_model_get_params(hawk_model* M, float* params, float* mu, float* sd) {
-  if (!M) return HAWK_E_ARG;
+  if (!M || !M->ctx) return HAWK_E_ARG;
   CK(hipStreamSynchronize(M->ctx->stream), "synchronize");
   if (params) CK(hipMemcpy(params, M->p, MLP_NPARAMS * 4, hipMemcpyDeviceToHost), "read params");
   if (mu) CK(hipMemcpy(mu, M->mu, MLP_IN * 4, hipMemcpyDeviceToHost), "read mu");
@@ -126,14 +137,14 @@ extern "C" hawk_status hawk_model_get_params(hawk_model* M, float* params, float
 }
 
 extern "C" hawk_status hawk_mlp_forward_dev(hawk_model* M, const float* dX, int64_t m, float* dout) {
-  if (!M || m < 0 || (m > 0 && (!dX || !dout))) return HAWK_E_ARG;
+  if (!M || !M->ctx || m < 0 || (m > 0 && (!dX || !dout))) return HAWK_E_ARG;
   CK(hk_mlp_forward(M->ctx->stream, M->p, M->mu, M->sd, dX, m, dout), "forward");
   return HAWK_OK;
 }
 
 extern "C" hawk_status hawk_mlp_grad_dev(hawk_model* M, const float* dX, const float* dy, int64_t m, float* dgrad,
                                          float* dloss) {
-  if (!M || m < 1 || !dX || !dy || !dgrad) return HAWK_E_ARG;
+  if (!M || !M->ctx || m < 1 || !dX || !dy || !dgrad) return HAWK_E_ARG;
   DevBuf B(M->ctx);
   const int64_t rows = hk_mlp_grad_rows(m);
   float* partial = static_cast<float*>(B.get(static_cast<size_t>(rows) * MLP_NPARAMS * 4));
@@ -146,8 +157,9 @@ extern "C" hawk_status hawk_mlp_grad_dev(hawk_model* M, const float* dX, const f
 
 extern "C" hawk_status hawk_model_train(hawk_model* M, const float* X, const float* y, int64_t m,
                                         const hawk_train_opts* o, float* final_loss) {
-  if (!M || !X || !y || m < 1 || !o || o->epochs < 1 || o->batch < 1 || !(o->lr > 0.f))
-    return M ? set_error(M->ctx, HAWK_E_ARG, "bad training arguments") : HAWK_E_ARG;
+  if (!M || !M->ctx) return HAWK_E_ARG;
+  if (!X || !y || m < 1 || !o || o->epochs < 1 || o->batch < 1 || !(o->lr > 0.f))
+    return set_error(M->ctx, HAWK_E_ARG, "bad training arguments");
   hawk_ctx* ctx = M->ctx;
   hipStream_t st = ctx->stream;
   // feature standardisation from the training set
@@ -209,7 +221,7 @@ extern "C" hawk_status hawk_model_train(hawk_model* M, const float* X, const flo
 }
 
 extern "C" hawk_status hawk_model_predict(hawk_model* M, const float* X, int64_t m, float* out) {
-  if (!M || m < 0 || (m > 0 && (!X || !out))) return HAWK_E_ARG;
+  if (!M || !M->ctx || m < 0 || (m > 0 && (!X || !out))) return HAWK_E_ARG;
   if (m == 0) return HAWK_OK;
   DevBuf B(M->ctx);
   float* dX = static_cast<float*>(B.get(static_cast<size_t>(m) * MLP_IN * 4));
@@ -225,12 +237,12 @@ extern "C" hawk_status hawk_model_predict(hawk_model* M, const float* X, int64_t
 
 extern "C" hawk_status hawk_model_pick(hawk_model* M, hawk_query* const* qs, int32_t n, hawk_variant* out,
                                        float* predicted_ms) {
-  if (!M || !qs || n < 1 || !out) return HAWK_E_ARG;
+  if (!M || !M->ctx || !qs || n < 1 || !out) return HAWK_E_ARG;
   // every query's variant space, featurised on the host (plan metadata), scored on the device
   std::vector<std::vector<hawk_variant>> spaces;
   int64_t cols = 0;
   for (int32_t i = 0; i < n; ++i) {
-    if (!qs[i]) return set_error(M->ctx, HAWK_E_ARG, "null query");
+    if (!qs[i] || qs[i]->ctx != M->ctx) return set_error(M->ctx, HAWK_E_ARG, "query of another context");
     spaces.push_back(variant_space(qs[i]));
     cols = std::max<int64_t>(cols, static_cast<int64_t>(spaces.back().size()));
   }

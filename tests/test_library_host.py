@@ -203,3 +203,16 @@ def test_alg1_fixed_point_is_coordinatewise_optimal(seed):
             w = list(cfg)
             w[i] = d
             assert table[tuple(w)] >= table[cfg]
+
+
+def test_handles_outliving_their_context_are_orphaned():
+    import ctypes
+    c = hawk.PlanningContext()
+    tables, spec = dg.workload("c2u", n=10)
+    c.register_shapes(tables)
+    q = hawk.build_query(c, spec)
+    c.close()                      # the query's context is gone
+    f = (ctypes.c_float * 12)()
+    assert hawk.L().hawk_features(q.handle, ctypes.byref(hawk.variant()), f) == hawk.HAWK_E_ARG
+    hawk.L().hawk_query_free(q.handle)   # only host memory is released; no crash
+    q.handle = None
