@@ -13,8 +13,10 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhawk.so")
 
-SOURCES = ["hk_common.hip", "hk_proj.hip", "hk_agg_local.hip", "hk_agg_global.hip", "hk_scalar.hip",
-           "hk_mlp.hip", "hawk_api.cpp", "hawk_explore.cpp", "hawk_model.cpp"]
+SOURCES = ["hk_common.hip", "hk_dispatch.hip", "hk_mlp.hip", "hawk_api.cpp", "hawk_explore.cpp", "hawk_model.cpp"]
+# kernel families compiled once per shape class (see HkShape in hawk_plan.h)
+SHAPED = ["hk_agg.hip", "hk_proj.hip", "hk_scalar.hip"]
+SHAPES = ["A", "F", "J", "W", "G"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off (no fp32 math on the hot path needs them)
@@ -22,10 +24,12 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+def _compile(job) -> str:
+    src, shape = job if isinstance(job, tuple) else (job, None)
+    stem = os.path.splitext(src)[0] + (f"_{shape}" if shape else "")
+    obj = os.path.join(OBJ, stem + ".o")
     path = os.path.join(CSRC, src)
-    cmd = [HIPCC] + FLAGS + ["-c", path, "-o", obj]
+    cmd = [HIPCC] + FLAGS + (["-DHK_SHAPE_CLASS=HkShape" + shape] if shape else []) + ["-c", path, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -36,9 +40,9 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+    jobs = [(s, sh) for s in SHAPED for sh in SHAPES] + list(SOURCES)
+    with ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, 16, len(jobs))) as ex:
+        objs = list(ex.map(_compile, jobs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -815,7 +815,7 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
     ALLOC(tmp, uint32_t*, static_cast<size_t>(hk_scan_tmp_words(m)) * 4, false);
     {
       ProfScope ps(ctx, "k_mp_filter");
-      HIPCHK(hk_mp_filter(X.st, P, dev_main(X.q), v->mem, v->pred, v->ht, v->hash, threads, masks, counts), "filter kernel");
+      HIPCHK(hk_mp_filter(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, counts), "filter kernel");
     }
     {
       ProfScope ps(ctx, "k_scan");
@@ -823,7 +823,7 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
     }
     {
       ProfScope ps(ctx, "k_mp_project");
-      HIPCHK(hk_mp_project(X.st, P, dev_main(X.q), v->mem, v->pred, v->ht, v->hash, threads, masks, offsets, res->d_count, nact,
+      HIPCHK(hk_mp_project(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, offsets, res->d_count, nact,
                            out, n), "projection kernel");
     }
   } else {
@@ -846,7 +846,7 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
     ALLOC(stmp, uint32_t*, static_cast<size_t>(hk_scan_tmp_words(nregions)) * 4, false);
     {
       ProfScope ps(ctx, "k_sp");
-      HIPCHK(hk_sp(X.st, P, dev_main(X.q), v->mem, v->pred, v->ht, v->hash, inst, tmp, region, counts), "single-pass kernel");
+      HIPCHK(hk_sp(X.st, P, v->mem, v->pred, v->ht, v->hash, inst, tmp, region, counts), "single-pass kernel");
     }
     {
       ProfScope ps(ctx, "k_scan");
@@ -912,11 +912,11 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
         return set_error(ctx, HAWK_E_INFEASIBLE, "local table does not fit in LDS");
     }
     ProfScope ps(ctx, "k_agg");
-    HIPCHK(hk_agg(X.st, P, dev_main(X.q), T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, llog2, ident, W,
+    HIPCHK(hk_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, llog2, ident, W,
                   res->d_err), "aggregation kernel");
   } else {
     ProfScope ps(ctx, "k_scalar_agg");
-    HIPCHK(hk_scalar_agg(X.st, P, dev_main(X.q), T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, ident, W,
+    HIPCHK(hk_scalar_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, ident, W,
                          res->d_err), "aggregation kernel");
   }
   // result columns: groups, aggregates, count

@@ -188,31 +188,37 @@ __device__ __forceinline__ void join_insert(const HkJoinTable& t, const HkHash& 
 // Pushes one row through LOOP's loads, FILTER, HASH_PROBE and (if VALUES)
 // ARITHMETIC. Branched: returns false as soon as the row is dropped.
 // Predicated: evaluates everything and returns the result_increment.
-template <int PRED, int HT, int HASH, bool VALUES>
+template <int PRED, int HT, int HASH, bool VALUES, class S>
 __device__ __forceinline__ bool eval_row(const HkPlan& P, int64_t row, v16i64& r) {
   // all loads of a phase are issued before any is consumed, so their
   // latencies overlap
-  int64_t la[HK_MAX_COLS_A];
+  int64_t la[S::colA > 0 ? S::colA : 1];
 #pragma unroll
-  for (int c = 0; c < HK_MAX_COLS_A; ++c)
+  for (int c = 0; c < S::colA; ++c)
     if (c < P.ncolA) la[c] = load_col(P.colA[c], row);
 #pragma unroll
-  for (int c = 0; c < HK_MAX_COLS_A; ++c)
+  for (int c = 0; c < S::colA; ++c)
     if (c < P.ncolA) r[P.colA[c].reg] = la[c];
   bool pass = true;
-  for (int f = 0; f < P.nfilters; ++f) {
+#pragma unroll
+  for (int f = 0; f < S::filters; ++f) {
+    if (f >= P.nfilters) break;
     const int64_t x = r[P.filters[f].reg];
     pass = pass & (x >= P.filters[f].lo) & (x <= P.filters[f].hi);
   }
   if (PRED == HK_BR && !pass) return false;
-  int64_t lb[HK_MAX_COLS_B];
+  if (S::colB > 0) {
+    int64_t lb[S::colB > 0 ? S::colB : 1];
 #pragma unroll
-  for (int c = 0; c < HK_MAX_COLS_B; ++c)
-    if (c < P.ncolB) lb[c] = load_col(P.colB[c], row);
+    for (int c = 0; c < S::colB; ++c)
+      if (c < P.ncolB) lb[c] = load_col(P.colB[c], row);
 #pragma unroll
-  for (int c = 0; c < HK_MAX_COLS_B; ++c)
-    if (c < P.ncolB) r[P.colB[c].reg] = lb[c];
-  for (int p = 0; p < P.nprobes; ++p) {
+    for (int c = 0; c < S::colB; ++c)
+      if (c < P.ncolB) r[P.colB[c].reg] = lb[c];
+  }
+#pragma unroll
+  for (int p = 0; p < S::probes; ++p) {
+    if (p >= P.nprobes) break;
     int32_t pay = 0;
     const bool found = join_lookup<HT, HASH>(P.probes[p].t, P.hash, static_cast<int32_t>(r[P.probes[p].fk_reg]), pay);
     if (PRED == HK_BR && !found) return false;
@@ -220,14 +226,16 @@ __device__ __forceinline__ bool eval_row(const HkPlan& P, int64_t row, v16i64& r
     r[P.probes[p].pay_reg] = pay;
   }
   if (!VALUES) return pass;
-  int64_t lc[HK_MAX_COLS_C];
+  int64_t lc[S::colC > 0 ? S::colC : 1];
 #pragma unroll
-  for (int c = 0; c < HK_MAX_COLS_C; ++c)
+  for (int c = 0; c < S::colC; ++c)
     if (c < P.ncolC) lc[c] = load_col(P.colC[c], row);
 #pragma unroll
-  for (int c = 0; c < HK_MAX_COLS_C; ++c)
+  for (int c = 0; c < S::colC; ++c)
     if (c < P.ncolC) r[P.colC[c].reg] = lc[c];
-  for (int k = 0; k < P.narith; ++k) {
+#pragma unroll
+  for (int k = 0; k < S::arith; ++k) {
+    if (k >= P.narith) break;
     const HkArith& A = P.arith[k];
     const uint64_t x = A.xc ? static_cast<uint64_t>(A.cx) : static_cast<uint64_t>(r[A.x]);
     const uint64_t y = A.yc ? static_cast<uint64_t>(A.cy) : static_cast<uint64_t>(r[A.y]);
@@ -258,9 +266,10 @@ struct HkResOut {
 };
 
 
+template <class S>
 __device__ __forceinline__ void write_proj(const HkPlan& P, const HkOut& O, int64_t pos, const v16i64& r) {
 #pragma unroll
-  for (int c = 0; c < HK_MAX_PROJ; ++c)
+  for (int c = 0; c < S::proj; ++c)
     if (c < P.nproj) O.col[c][pos] = r[P.preg[c]];
 }
 
@@ -343,11 +352,11 @@ __device__ __forceinline__ uint64_t group_key(const HkPlan& P, const v16i64& r) 
 }
 
 // applies one row to the slot whose word j lives at base[j * stride]
-template <int PRED, bool LDS>
+template <int PRED, bool LDS, class S>
 __device__ __forceinline__ void agg_apply(uint64_t* base, int64_t stride, const HkPlan& P, const v16i64& r, bool pass) {
   at_add<LDS>(base + stride, PRED == HK_PRED ? static_cast<uint64_t>(pass) : 1ull);
 #pragma unroll
-  for (int a = 0; a < HK_MAX_AGGS; ++a) {
+  for (int a = 0; a < S::aggs; ++a) {
     if (a >= P.naggs) break;
     const HkAgg& A = P.aggs[a];
     if (A.fn == HK_COUNT) continue;
@@ -367,10 +376,11 @@ __device__ __forceinline__ void agg_apply(uint64_t* base, int64_t stride, const 
 }
 
 // merges an LDS slot (word j at l[j * stride]) into a global slot g
+template <class S>
 __device__ __forceinline__ void agg_merge(uint64_t* g, const uint64_t* l, int64_t stride, const HkPlan& P) {
   at_add<false>(g + 1, l[stride]);
 #pragma unroll
-  for (int a = 0; a < HK_MAX_AGGS; ++a) {
+  for (int a = 0; a < S::aggs; ++a) {
     if (a >= P.naggs) break;
     const HkAgg& A = P.aggs[a];
     if (A.fn == HK_COUNT) continue;

@@ -7,8 +7,9 @@
 
 #include "hawk_plan.h"
 
-// Every launcher takes the plan twice: P, the host copy (sizes, counts), and
-// dP, the identical struct in device memory that the kernels read.
+// Pipeline kernels take the lowered plan by value (a kernel argument); each
+// launcher picks the shape class that holds the plan. Build and finalize
+// kernels read the copy the query keeps in device memory (dB / dP).
 
 hipError_t hk_fill_u64(hipStream_t st, uint64_t* p, int64_t n, uint64_t v);
 hipError_t hk_init_aggtable(hipStream_t st, uint64_t* words, int64_t nslots, const uint64_t* ident, int32_t nw);
@@ -18,14 +19,14 @@ hipError_t hk_init_aggtable(hipStream_t st, uint64_t* words, int64_t nslots, con
 hipError_t hk_build(hipStream_t st, const HkBuild& B, const HkBuild* dB, int ht, int hash, int* err);
 
 // multi-pass projection: filter kernel, scan, projection kernel
-hipError_t hk_mp_filter(hipStream_t st, const HkPlan& P, const HkPlan* dP, int mem, int pred, int ht, int hash, int64_t threads,
+hipError_t hk_mp_filter(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t threads,
                         uint64_t* masks, uint32_t* counts);
-hipError_t hk_mp_project(hipStream_t st, const HkPlan& P, const HkPlan* dP, int mem, int pred, int ht, int hash, int64_t threads,
+hipError_t hk_mp_project(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t threads,
                          const uint64_t* masks, const uint32_t* offsets, const uint64_t* total, int64_t nact,
                          int64_t* const* out, int64_t dump);
 
 // single-pass projection into per-instance regions, then in-order concatenation
-hipError_t hk_sp(hipStream_t st, const HkPlan& P, const HkPlan* dP, int mem, int pred, int ht, int hash, int64_t instances,
+hipError_t hk_sp(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t instances,
                  int64_t* const* tmp, int64_t region, uint32_t* counts);
 hipError_t hk_sp_concat(hipStream_t st, int64_t* const* tmp, int32_t nproj, int64_t region, int64_t nregions,
                         const uint32_t* counts, const uint32_t* offsets, int64_t* const* out);
@@ -35,9 +36,9 @@ int64_t hk_scan_tmp_words(int64_t m);
 hipError_t hk_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t m, uint32_t* tmp, uint64_t* total);
 
 // grouped aggregation (cuckoo: key phase first), non-grouped aggregation, result extraction
-hipError_t hk_agg(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int mem, int pred, int ht, int hash,
+hipError_t hk_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
                   int strat, int64_t groups, int32_t wg, uint32_t llog2, const uint64_t* ident, int32_t nw, int* err);
-hipError_t hk_scalar_agg(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int mem, int pred, int ht, int hash,
+hipError_t hk_scalar_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
                          int strat, int64_t groups, int32_t wg, const uint64_t* ident, int32_t nw, int* err);
 hipError_t hk_finalize(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int64_t nslots, int64_t* const* gcols,
                        void* const* acols, int64_t* count, uint64_t* nrows, int keep_empty);

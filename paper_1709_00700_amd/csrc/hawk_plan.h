@@ -75,5 +75,34 @@ struct HkBuild {
   HkJoinTable t;
 };
 
+// Shape classes: compile-time bounds of the per-row loops. A kernel
+// instantiated for a class touches only the plan fields that class can use,
+// so those fields stay in scalar registers for the whole row loop. The
+// dispatcher picks the smallest class that holds the plan (hk_shape_of).
+template <int A, int F, int B, int PR, int C, int AR, int AG, int PJ>
+struct HkShape {
+  static constexpr int colA = A, filters = F, colB = B, probes = PR, colC = C, arith = AR, aggs = AG, proj = PJ;
+};
+using HkShapeA = HkShape<0, 0, 0, 0, 2, 0, 4, 0>;   // group-aggregate of value columns (no filters, joins, arithmetic)
+using HkShapeF = HkShape<2, 2, 0, 0, 3, 2, 4, 2>;   // filters, a little arithmetic, projection or aggregation
+using HkShapeJ = HkShape<0, 0, 4, 4, 1, 0, 2, 2>;   // joins: up to 4 probes
+using HkShapeW = HkShape<0, 0, 0, 0, 6, 4, 8, 2>;   // wide: many value columns, arithmetic steps, aggregates
+using HkShapeG = HkShape<HK_MAX_COLS_A, HK_MAX_FILTERS, HK_MAX_COLS_B, HK_MAX_PROBES, HK_MAX_COLS_C, HK_MAX_ARITH,
+                         HK_MAX_AGGS, HK_MAX_PROJ>;   // anything the plan format allows
+enum { HK_SHAPE_A = 0, HK_SHAPE_F = 1, HK_SHAPE_J = 2, HK_SHAPE_W = 3, HK_SHAPE_G = 4 };
+
+template <class S>
+inline bool hk_fits(const HkPlan& P) {
+  return P.ncolA <= S::colA && P.nfilters <= S::filters && P.ncolB <= S::colB && P.nprobes <= S::probes &&
+         P.ncolC <= S::colC && P.narith <= S::arith && P.naggs <= S::aggs && P.nproj <= S::proj;
+}
+inline int hk_shape_of(const HkPlan& P) {
+  if (hk_fits<HkShapeA>(P)) return HK_SHAPE_A;
+  if (hk_fits<HkShapeF>(P)) return HK_SHAPE_F;
+  if (hk_fits<HkShapeJ>(P)) return HK_SHAPE_J;
+  if (hk_fits<HkShapeW>(P)) return HK_SHAPE_W;
+  return HK_SHAPE_G;
+}
+
 // an aggregation hash table in HBM (plus one side slot for the sentinel key)
 struct HkAggTable { uint64_t* words; uint32_t log2cap; int32_t slot_words; };

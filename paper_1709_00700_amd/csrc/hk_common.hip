@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(256) k_build(const HkBuild* Bp, int* err) {
   v16i64 r = {};
   const int64_t T = (int64_t)gridDim.x * blockDim.x;
   for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < B.p.nrows; row += T) {
-    if (!eval_row<HK_BR, HT, HASH, false>(B.p, row, r)) continue;
+    if (!eval_row<HK_BR, HT, HASH, false, HkShapeG>(B.p, row, r)) continue;
     join_insert<HT, HASH>(B.t, B.p.hash, static_cast<int32_t>(load_col(B.key, row)),
                           static_cast<int32_t>(load_col(B.payload, row)), err);
   }
@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(256) k_build_verify(const HkBuild* Bp, int* er
   v16i64 r = {};
   const int64_t T = (int64_t)gridDim.x * blockDim.x;
   for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < B.p.nrows; row += T) {
-    if (!eval_row<HK_BR, HK_CUCKOO, HASH, false>(B.p, row, r)) continue;
+    if (!eval_row<HK_BR, HK_CUCKOO, HASH, false, HkShapeG>(B.p, row, r)) continue;
     const int32_t key = static_cast<int32_t>(load_col(B.key, row));
     if (key == -1) continue;
     uint32_t pos[HK_CUCKOO_D];

@@ -1,21 +1,23 @@
 // Projection pipelines (Section 4.1): the multi-pass (fine-grained) strategy
 // with its filter and projection kernels, and the single-pass (coarse-grained)
-// strategy with one pipeline instance per compute unit.
+// strategy with one pipeline instance per compute unit. Compiled once per
+// shape class (-DHK_SHAPE_CLASS=HkShapeX).
 #include <hip/hip_runtime.h>
 
 #include "hawk_device.h"
 #include "hawk_launch.h"
 
-#define HK_CHECK_LAUNCH() return hipGetLastError()
+#ifndef HK_SHAPE_CLASS
+#error "compile once per shape class with -DHK_SHAPE_CLASS=HkShapeX"
+#endif
 
 // ------------------------------------------------------------------ projection: multi-pass (Section 4.1)
 // Phase 1, filter kernel: evaluates filters and probes and records one flag
 // bit per row (64-bit words, one per 64-row block) plus the number of flags
 // per scan unit (a 64-row block for coalesced access, a thread's chunk for
 // sequential access).
-template <int MEM, int PRED, int HT, int HASH>
-__global__ void __launch_bounds__(256) k_mp_filter(const HkPlan* Pp, uint64_t* __restrict__ masks, uint32_t* __restrict__ counts) {
-  const HkPlan& P = *Pp;  // plan in device memory, read where used
+template <int MEM, int PRED, int HT, int HASH, class S>
+__global__ void __launch_bounds__(256) k_mp_filter(HkPlan P, uint64_t* __restrict__ masks, uint32_t* __restrict__ counts) {
   v16i64 r = {};
   const int64_t n = P.nrows;
   const int64_t T = (int64_t)gridDim.x * blockDim.x;
@@ -25,7 +27,7 @@ __global__ void __launch_bounds__(256) k_mp_filter(const HkPlan* Pp, uint64_t* _
     for (int64_t base = gt - __lane_id(); base < n; base += T) {
       const int64_t row = base + __lane_id();
       bool pass = false;
-      if (row < n) pass = eval_row<PRED, HT, HASH, false>(P, row, r);
+      if (row < n) pass = eval_row<PRED, HT, HASH, false, S>(P, row, r);
       const uint64_t m = __ballot(pass);
       if (__lane_id() == 0) {
         masks[base >> 6] = m;
@@ -41,7 +43,7 @@ __global__ void __launch_bounds__(256) k_mp_filter(const HkPlan* Pp, uint64_t* _
       uint64_t m = 0;
       const int64_t we = w0 + WAVE < e ? w0 + WAVE : e;
       for (int64_t row = w0; row < we; ++row) {
-        const bool pass = eval_row<PRED, HT, HASH, false>(P, row, r);
+        const bool pass = eval_row<PRED, HT, HASH, false, S>(P, row, r);
         if (PRED == HK_PRED) m |= static_cast<uint64_t>(pass) << (row - w0);
         else if (pass) m |= 1ull << (row - w0);
       }
@@ -54,11 +56,10 @@ __global__ void __launch_bounds__(256) k_mp_filter(const HkPlan* Pp, uint64_t* _
 
 // Phase 3, projection kernel: repeats the probes to get the payloads, computes
 // the arithmetic and writes each qualifying row at its scanned position.
-template <int MEM, int PRED, int HT, int HASH>
-__global__ void __launch_bounds__(256) k_mp_project(const HkPlan* Pp, const uint64_t* __restrict__ masks,
+template <int MEM, int PRED, int HT, int HASH, class S>
+__global__ void __launch_bounds__(256) k_mp_project(HkPlan P, const uint64_t* __restrict__ masks,
                                                     const uint32_t* __restrict__ offsets, const uint64_t* total,
                                                     int64_t nact, HkOut O) {
-  const HkPlan& P = *Pp;  // plan in device memory, read where used
   v16i64 r = {};
   const int64_t n = P.nrows;
   const int64_t T = (int64_t)gridDim.x * blockDim.x;
@@ -72,12 +73,12 @@ __global__ void __launch_bounds__(256) k_mp_project(const HkPlan* Pp, const uint
       const int64_t pos = offsets[base >> 6] + __popcll(m & lanemask_lt());
       if (PRED == HK_BR) {
         if (pass) {
-          eval_row<HK_BR, HT, HASH, true>(P, row, r);
-          write_proj(P, O, pos, r);
+          eval_row<HK_BR, HT, HASH, true, S>(P, row, r);
+          write_proj<S>(P, O, pos, r);
         }
       } else if (row < n) {
-        eval_row<HK_PRED, HT, HASH, true>(P, row, r);
-        write_proj(P, O, pass ? pos : O.dump, r);
+        eval_row<HK_PRED, HT, HASH, true, S>(P, row, r);
+        write_proj<S>(P, O, pass ? pos : O.dump, r);
       }
     }
   } else {
@@ -91,8 +92,8 @@ __global__ void __launch_bounds__(256) k_mp_project(const HkPlan* Pp, const uint
         while (m) {
           const int bit = __ffsll(static_cast<unsigned long long>(m)) - 1;
           m &= m - 1;
-          eval_row<HK_BR, HT, HASH, true>(P, w0 + bit, r);
-          write_proj(P, O, pos++, r);
+          eval_row<HK_BR, HT, HASH, true, S>(P, w0 + bit, r);
+          write_proj<S>(P, O, pos++, r);
         }
       }
     } else {
@@ -101,8 +102,8 @@ __global__ void __launch_bounds__(256) k_mp_project(const HkPlan* Pp, const uint
       const int64_t end = gt + 1 < nact ? static_cast<int64_t>(offsets[gt + 1]) : static_cast<int64_t>(*total);
       for (int64_t row = b; row < e; ++row) {
         const bool pass = (masks[row >> 6] >> (row & 63)) & 1ull;
-        eval_row<HK_PRED, HT, HASH, true>(P, row, r);
-        write_proj(P, O, pos < end ? pos : O.dump, r);
+        eval_row<HK_PRED, HT, HASH, true, S>(P, row, r);
+        write_proj<S>(P, O, pos < end ? pos : O.dump, r);
         pos += pass;
       }
     }
@@ -115,9 +116,8 @@ __global__ void __launch_bounds__(256) k_mp_project(const HkPlan* Pp, const uint
 // own region; the regions are concatenated in order afterwards.
 //   coalesced: the wave walks its chunk 64 rows at a time; ballot + mbcnt keep row order
 //   sequential: each lane walks a sub-chunk and owns a region of sub + 1 slots
-template <int MEM, int PRED, int HT, int HASH>
-__global__ void __launch_bounds__(64) k_sp(const HkPlan* Pp, HkOut tmp, int64_t region, uint32_t* __restrict__ counts) {
-  const HkPlan& P = *Pp;  // plan in device memory, read where used
+template <int MEM, int PRED, int HT, int HASH, class S>
+__global__ void __launch_bounds__(64) k_sp(HkPlan P, HkOut tmp, int64_t region, uint32_t* __restrict__ counts) {
   v16i64 r = {};
   const int64_t n = P.nrows;
   const int64_t inst = blockIdx.x;
@@ -130,15 +130,15 @@ __global__ void __launch_bounds__(64) k_sp(const HkPlan* Pp, HkOut tmp, int64_t 
       const int64_t row = base + __lane_id();
       if (PRED == HK_BR) {
         bool pass = false;
-        if (row < e) pass = eval_row<HK_BR, HT, HASH, true>(P, row, r);
+        if (row < e) pass = eval_row<HK_BR, HT, HASH, true, S>(P, row, r);
         const uint64_t m = __ballot(pass);
-        if (pass) write_proj(P, tmp, rs + wpos + __popcll(m & lanemask_lt()), r);
+        if (pass) write_proj<S>(P, tmp, rs + wpos + __popcll(m & lanemask_lt()), r);
         wpos += __popcll(m);
       } else {
         bool pass = false;
-        if (row < e) pass = eval_row<HK_PRED, HT, HASH, true>(P, row, r);
+        if (row < e) pass = eval_row<HK_PRED, HT, HASH, true, S>(P, row, r);
         const uint64_t m = __ballot(pass);
-        if (row < e) write_proj(P, tmp, pass ? rs + wpos + __popcll(m & lanemask_lt()) : rs + region - 1, r);
+        if (row < e) write_proj<S>(P, tmp, pass ? rs + wpos + __popcll(m & lanemask_lt()) : rs + region - 1, r);
         wpos += __popcll(m);
       }
     }
@@ -152,10 +152,10 @@ __global__ void __launch_bounds__(64) k_sp(const HkPlan* Pp, HkOut tmp, int64_t 
     int64_t pos = 0;
     for (int64_t row = lb; row < le; ++row) {
       if (PRED == HK_BR) {
-        if (eval_row<HK_BR, HT, HASH, true>(P, row, r)) write_proj(P, tmp, rs + pos++, r);
+        if (eval_row<HK_BR, HT, HASH, true, S>(P, row, r)) write_proj<S>(P, tmp, rs + pos++, r);
       } else {
-        const bool pass = eval_row<HK_PRED, HT, HASH, true>(P, row, r);
-        write_proj(P, tmp, rs + pos, r);
+        const bool pass = eval_row<HK_PRED, HT, HASH, true, S>(P, row, r);
+        write_proj<S>(P, tmp, rs + pos, r);
         pos += pass;
       }
     }
@@ -164,34 +164,39 @@ __global__ void __launch_bounds__(64) k_sp(const HkPlan* Pp, HkOut tmp, int64_t 
 }
 
 
-// ================================================================== host launchers
-hipError_t hk_mp_filter(hipStream_t st, const HkPlan& P, const HkPlan* dP, int mem, int pred, int ht, int hash, int64_t threads,
-                        uint64_t* masks, uint32_t* counts) {
+// ================================================================== launchers for one shape class
+template <class S>
+hipError_t hk_mp_filter_shape(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t threads,
+                              uint64_t* masks, uint32_t* counts) {
   const dim3 g(static_cast<uint32_t>((threads + 255) / 256)), b(256);
   DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS,
-            hipLaunchKernelGGL((k_mp_filter<M, PR, HT, HS>), g, b, 0, st, dP, masks, counts)))));
-  HK_CHECK_LAUNCH();
+            hipLaunchKernelGGL((k_mp_filter<M, PR, HT, HS, S>), g, b, 0, st, P, masks, counts)))));
+  return hipGetLastError();
 }
 
-hipError_t hk_mp_project(hipStream_t st, const HkPlan& P, const HkPlan* dP, int mem, int pred, int ht, int hash, int64_t threads,
-                         const uint64_t* masks, const uint32_t* offsets, const uint64_t* total, int64_t nact,
-                         int64_t* const* out, int64_t dump) {
-  HkOut O = {};
-  for (int c = 0; c < P.nproj; ++c) O.col[c] = out[c];
-  O.dump = dump;
+template <class S>
+hipError_t hk_mp_project_shape(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t threads,
+                               const uint64_t* masks, const uint32_t* offsets, const uint64_t* total, int64_t nact,
+                               const HkOut& O) {
   const dim3 g(static_cast<uint32_t>((threads + 255) / 256)), b(256);
   DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS,
-            hipLaunchKernelGGL((k_mp_project<M, PR, HT, HS>), g, b, 0, st, dP, masks, offsets, total, nact, O)))));
-  HK_CHECK_LAUNCH();
+            hipLaunchKernelGGL((k_mp_project<M, PR, HT, HS, S>), g, b, 0, st, P, masks, offsets, total, nact, O)))));
+  return hipGetLastError();
 }
 
-hipError_t hk_sp(hipStream_t st, const HkPlan& P, const HkPlan* dP, int mem, int pred, int ht, int hash, int64_t instances,
-                 int64_t* const* tmp, int64_t region, uint32_t* counts) {
-  HkOut O = {};
-  for (int c = 0; c < P.nproj; ++c) O.col[c] = tmp[c];
+template <class S>
+hipError_t hk_sp_shape(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t instances,
+                       const HkOut& O, int64_t region, uint32_t* counts) {
   const dim3 g(static_cast<uint32_t>(instances)), b(WAVE);
   DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS,
-            hipLaunchKernelGGL((k_sp<M, PR, HT, HS>), g, b, 0, st, dP, O, region, counts)))));
-  HK_CHECK_LAUNCH();
+            hipLaunchKernelGGL((k_sp<M, PR, HT, HS, S>), g, b, 0, st, P, O, region, counts)))));
+  return hipGetLastError();
 }
 
+template hipError_t hk_mp_filter_shape<HK_SHAPE_CLASS>(hipStream_t, const HkPlan&, int, int, int, int, int64_t,
+                                                       uint64_t*, uint32_t*);
+template hipError_t hk_mp_project_shape<HK_SHAPE_CLASS>(hipStream_t, const HkPlan&, int, int, int, int, int64_t,
+                                                        const uint64_t*, const uint32_t*, const uint64_t*, int64_t,
+                                                        const HkOut&);
+template hipError_t hk_sp_shape<HK_SHAPE_CLASS>(hipStream_t, const HkPlan&, int, int, int, int, int64_t, const HkOut&,
+                                                int64_t, uint32_t*);

@@ -1,4 +1,4 @@
-// AGGREGATE without grouping attributes (Table 1). As in the paper's
+// AGGREGATE without grouping attributes (Table 1), compiled once per shape class. As in the paper's
 // AGGREGATE fragment (Section 7.4), every thread keeps its own running
 // aggregates in registers while it walks its rows; at the end each thread
 // merges them once, into its workgroup's LDS slot (local strategy, then one
@@ -8,6 +8,10 @@
 
 #include "hawk_device.h"
 #include "hawk_launch.h"
+
+#ifndef HK_SHAPE_CLASS
+#error "compile once per shape class with -DHK_SHAPE_CLASS=HkShapeX"
+#endif
 
 template <bool LDS>
 __device__ __forceinline__ void merge_partial(uint64_t* tgt, const HkPlan& P, uint64_t cnt, const uint64_t* lo,
@@ -29,9 +33,8 @@ __device__ __forceinline__ void merge_partial(uint64_t* tgt, const HkPlan& P, ui
   }
 }
 
-template <int MEM, int PRED, int HT, int HASH, int STRAT>
-__global__ void __launch_bounds__(1024) k_scalar_agg(const HkPlan* Pp, HkAggTable T, HkIdent id, int64_t nwg) {
-  const HkPlan& P = *Pp;  // plan in device memory, read where used
+template <int MEM, int PRED, int HT, int HASH, int STRAT, class S>
+__global__ void __launch_bounds__(1024) k_scalar_agg(HkPlan P, HkAggTable T, HkIdent id, int64_t nwg) {
   const int64_t wgid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   if (wgid >= nwg) return;  // padding workgroup of a 2-D grid
   __shared__ uint64_t lw[2 + 2 * HK_MAX_AGGS];
@@ -57,11 +60,11 @@ __global__ void __launch_bounds__(1024) k_scalar_agg(const HkPlan* Pp, HkAggTabl
   if (MEM == HK_COAL) { b = gt; e = n; step = Tn; }
   else { seq_range(n, gt, Tn, 1, b, e); step = 1; }
   for (int64_t row = b; row < e; row += step) {
-    const bool pass = eval_row<PRED, HT, HASH, true>(P, row, r);
+    const bool pass = eval_row<PRED, HT, HASH, true, S>(P, row, r);
     if (PRED == HK_BR && !pass) continue;
     cnt += PRED == HK_PRED ? static_cast<uint64_t>(pass) : 1ull;
 #pragma unroll
-    for (int a = 0; a < HK_MAX_AGGS; ++a) {
+    for (int a = 0; a < S::aggs; ++a) {
       if (a >= P.naggs) break;
       const HkAgg& A = P.aggs[a];
       const int64_t x = r[A.reg];
@@ -83,20 +86,20 @@ __global__ void __launch_bounds__(1024) k_scalar_agg(const HkPlan* Pp, HkAggTabl
   if (STRAT == HK_LOCAL) {
     merge_partial<true>(lw, P, cnt, lo, hi);
     __syncthreads();
-    if (threadIdx.x == 0) agg_merge(T.words, lw, 1, P);
+    if (threadIdx.x == 0) agg_merge<S>(T.words, lw, 1, P);
   } else {
     merge_partial<false>(T.words, P, cnt, lo, hi);
   }
 }
 
-hipError_t hk_scalar_agg(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int mem, int pred, int ht, int hash,
-                         int strat, int64_t groups, int32_t wg, const uint64_t* ident, int32_t nw, int* err) {
-  (void)err;
-  HkIdent id = {};
-  for (int i = 0; i < nw; ++i) id.w[i] = ident[i];
-  id.nw = nw;
+template <class S>
+hipError_t hk_scalar_shape(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
+                           int strat, int64_t groups, int32_t wg, const HkIdent& id) {
   const dim3 g = hk_wg_grid(groups), b(static_cast<uint32_t>(wg));
   DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS, DISPATCH2(strat, SG,
-            hipLaunchKernelGGL((k_scalar_agg<M, PR, HT, HS, SG>), g, b, 0, st, dP, T, id, groups))))));
+            hipLaunchKernelGGL((k_scalar_agg<M, PR, HT, HS, SG, S>), g, b, 0, st, P, T, id, groups))))));
   return hipGetLastError();
 }
+
+template hipError_t hk_scalar_shape<HK_SHAPE_CLASS>(hipStream_t, const HkPlan&, const HkAggTable&, int, int, int, int, int,
+                                                    int64_t, int32_t, const HkIdent&);

@@ -237,3 +237,96 @@ def workload(name: str, **kw):
     if name == "c4":
         return c4_wide(**kw)
     raise ValueError(name)
+
+
+# ---------------------------------------------------------------- C5: mixed workload of many pipelines
+# key cardinalities available in the grouping pool (groups are snapped to the nearest level)
+C5_GROUP_LEVELS = (1, 16, 256, 4096, 65536, 1 << 20, 4_000_000)
+
+
+def c5_pools(pool_rows, seed=MASTER_SEED + 5):
+    """Shared column pools; every C5 pipeline scans a window of one of them.
+
+    kind 1 (projection): a, b, c, d int32 uniform [0, 10^6)
+    kind 2 (aggregation): f int32 uniform [0, 10^6) (selectivity filter),
+        k<i> int32 keys uniform over C5_GROUP_LEVELS[i] sparse values, v int64 [0, 10^6)
+    kind 3 (star join): fact fk0..fk3 into four dimensions of 2.5k/200k/30k/80k rows,
+        rev int64 [0, 10^6); dims carry key, f (uniform [0, 10^6)) and g
+    """
+    n = int(pool_rows)
+    p1 = {c: uniform(seed, _stream(5, j), n, 0, 1_000_000, np.int32) for j, c in enumerate("abcd")}
+    p2 = {"f": uniform(seed, _stream(5, 8), n, 0, 1_000_000, np.int32),
+          "v": uniform(seed, _stream(5, 9), n, 0, 1_000_000, np.int64)}
+    sc = lib().hg_scramble32
+    for i, g in enumerate(C5_GROUP_LEVELS):
+        ranks = uniform(seed, _stream(5, 16 + i), n, 0, g, np.int32)
+        if g <= 1 << 16:
+            key_of = np.array([sc(r, 0x51 + i) for r in range(g)], dtype=np.uint32).view(np.int32)
+            p2[f"k{i}"] = key_of[ranks]
+        else:
+            p2[f"k{i}"] = ranks   # dense keys for the large levels
+    dims = {}
+    ngroups = (7, 50, 250, 25)
+    for j, nd in enumerate(C3_DIMS):
+        dims[f"d{j}"] = {"key": sparse_keys(seed, _stream(5, 32 + j), nd),
+                         "f": uniform(seed, _stream(5, 40 + j), nd, 0, 1_000_000, np.int32),
+                         "g": uniform(seed, _stream(5, 48 + j), nd, 0, ngroups[j], np.int32)}
+    p3 = {f"fk{j}": foreign_keys(seed, _stream(5, 56 + j), _stream(5, 32 + j), n, nd) for j, nd in enumerate(C3_DIMS)}
+    p3["rev"] = uniform(seed, _stream(5, 60), n, 0, 1_000_000, np.int64)
+    return {"p1": p1, "p2": p2, "p3": p3, **dims}
+
+
+def c5_queries(nq=256, pool_rows=200_000_000, seed=MASTER_SEED + 5, min_rows=1_000_000, max_rows=200_000_000):
+    """Seeded list of C5 pipelines: dicts with kind, window (offset, rows), target
+    selectivity, groups and the neutral spec (table names refer to windows)."""
+    u = unit_f64(seed, _stream(5, 100), 8 * nq).reshape(nq, 8)
+    lo, hi = np.log(min_rows), np.log(max_rows)
+    mu, sigma = 0.5 * (lo + hi), (np.log(max_rows / min_rows)) / 4.0
+    out = []
+    for i in range(nq):
+        kind = 1 + int(u[i, 0] * 3)
+        # ln rows ~ N(mu, sigma) by Box-Muller, clipped to [min_rows, max_rows] and the pool
+        z = np.sqrt(-2.0 * np.log(max(u[i, 1], 1e-300))) * np.cos(2 * np.pi * u[i, 2])
+        rows = int(np.clip(np.exp(mu + sigma * z), min_rows, max_rows))
+        rows = min(rows, int(pool_rows))
+        sel = float(np.exp(np.log(1e-3) + u[i, 3] * (np.log(0.5) - np.log(1e-3))))
+        groups_t = float(np.exp(u[i, 4] * np.log(4e6)))
+        level = int(np.argmin([abs(np.log(max(groups_t, 1)) - np.log(g)) for g in C5_GROUP_LEVELS]))
+        off = int(u[i, 5] * (int(pool_rows) - rows + 1))
+        thr = int(round(sel * 1_000_000)) - 1
+        win = f"w{i}"
+        if kind == 1:
+            spec = {"builds": [], "main": {"table": win, "filters": [("a", 0, thr)], "probes": [],
+                                           "arith": [("cd", "mul", "c", "d"), ("out", "add", "cd", "b")],
+                                           "project": ["out"]}}
+            pool = "p1"
+        elif kind == 2:
+            spec = {"builds": [], "main": {"table": win, "filters": [("f", 0, thr)], "probes": [], "arith": [],
+                                           "group_by": [f"k{level}"] if C5_GROUP_LEVELS[level] > 1 else [],
+                                           "aggs": [("count", None, False), ("sum", "v", False),
+                                                    ("min", "v", False), ("max", "v", False)],
+                                           "groups_hint": int(C5_GROUP_LEVELS[level])}}
+            pool = "p2"
+        else:
+            # four dimension filters whose product is about the target selectivity
+            per = sel ** 0.25
+            dthr = int(round(per * 1_000_000)) - 1
+            spec = {"builds": [{"table": f"d{j}", "filters": [("f", 0, dthr)], "key": "key", "payload": "g"}
+                               for j in range(4)],
+                    "main": {"table": win, "filters": [], "probes": [(f"fk{j}", j, f"p{j}") for j in range(4)],
+                             "arith": [], "group_by": ["p0", "p2"], "aggs": [("sum", "rev", False)],
+                             "groups_hint": 7 * 250}}
+            pool = "p3"
+        out.append({"kind": kind, "pool": pool, "offset": off, "rows": rows, "selectivity": sel,
+                    "groups": int(C5_GROUP_LEVELS[level]) if kind == 2 else (1750 if kind == 3 else 0),
+                    "window": win, "spec": spec})
+    return out
+
+
+def c5_window_tables(pools, q):
+    """numpy views of the tables a C5 pipeline reads (its window, plus dimensions)."""
+    pool = pools[q["pool"]]
+    t = {q["window"]: {c: a[q["offset"]:q["offset"] + q["rows"]] for c, a in pool.items()}}
+    for b in q["spec"]["builds"]:
+        t[b["table"]] = pools[b["table"]]
+    return t
