@@ -285,6 +285,55 @@ hawk_status hawk_mlp_grad_dev(hawk_model* m, const float* dX, const float* dy, i
    predicted time (first on ties); predicted_ms may be NULL. */
 hawk_status hawk_model_pick(hawk_model* m, hawk_query* const* qs, int32_t n, hawk_variant* out, float* predicted_ms);
 
+/* ------------------------------------------------------------ batched execution */
+/* Many queries as one captured HIP graph of persistent kernels. Section 8
+   tunes one variant per workload and the paper leaves per-query work
+   distribution open (Section 9.5); a batch instead runs every query of a
+   mixed workload in one launch sequence: a fill kernel resets the batch's
+   tables and counters, a persistent kernel runs the tiles of every build
+   pipeline (HASH_PUT, Table 1), one persistent kernel per plan shape runs
+   the main pipelines' tiles (LOOP, FILTER, HASH_PROBE, ARITHMETIC, then
+   HASH_AGGREGATE/AGGREGATE or order-preserving PROJECT), and a persistent
+   kernel writes every aggregation's result rows. Workgroups take
+   (query, tile) items from an atomic counter. Inside a batch every query uses
+   one fixed variant: coalesced access, branched evaluation, linear probing
+   with Murmur hashing, local (LDS) pre-aggregation; projections keep input
+   order with a single-pass look-back over tile counts.
+   Schedule options: tile_rows_log2 in [14, 18] (rows per work item),
+   wgs_per_cu in [1, 32] (persistent workgroups per compute unit), order 0
+   (submission order) or 1 (largest query first); reserved must be 0.
+   NULL opts = {16, 2, 1, 0}. */
+typedef struct { int32_t tile_rows_log2; int32_t wgs_per_cu; int32_t order; int32_t reserved; } hawk_batch_opts;
+/* Creates a batch of n queries of ctx (borrowed: they must outlive the batch;
+   their tables must stay registered and unmodified). Allocates the batch's
+   device memory (tables sized from the queries' row counts and group hints,
+   outputs sized for every input row) and captures the graph. Errors:
+   HAWK_E_ARG, HAWK_E_DEVICE (planning context, HIP error), HAWK_E_OOM,
+   HAWK_E_INFEASIBLE (tile does not fit in LDS). */
+hawk_status hawk_batch_create(hawk_ctx* ctx, hawk_query* const* qs, int32_t n, const hawk_batch_opts* opts,
+                              hawk_batch** out);
+/* Releases the batch's device memory (synchronises the context stream);
+   its result views are orphaned (every call on them returns HAWK_E_ARG). */
+void hawk_batch_free(hawk_batch* b);
+/* Replays the graph once on the context stream (asynchronous). */
+hawk_status hawk_batch_run(hawk_batch* b);
+/* One untimed and `reps` timed replays with HIP events on the context
+   stream; *median_ms is the median. Returns HAWK_E_CAPACITY when a hash table
+   of the batch overflowed (group hint or join size too small). */
+hawk_status hawk_batch_time(hawk_batch* b, int32_t reps, double* median_ms);
+/* Times every schedule of the grid tile_rows_log2 14..18 x wgs_per_cu
+   {1, 2, 4, 8} x order {0, 1} (`reps` timed replays each), keeps the fastest
+   (first on ties) and re-captures the graph with it. best/best_ms may be NULL. */
+hawk_status hawk_batch_autotune(hawk_batch* b, int32_t reps, hawk_batch_opts* best, double* best_ms);
+hawk_status hawk_batch_opts_get(const hawk_batch* b, hawk_batch_opts* out);
+/* A view of query i's result after the latest run, read with the result
+   calls above (same column layout as hawk_execute). The view owns no memory:
+   the next hawk_batch_run overwrites what it shows, and hawk_batch_free
+   orphans it; release it with hawk_result_free. Errors as the result calls;
+   HAWK_E_CAPACITY or HAWK_E_DUPKEY when the run's hash tables failed (no
+   retry inside a batch). */
+hawk_status hawk_batch_result(hawk_batch* b, int32_t i, hawk_result** out);
+
 #ifdef __cplusplus
 }
 #endif

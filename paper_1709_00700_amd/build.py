@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhawk.so")
 
-SOURCES = ["hk_common.hip", "hk_dispatch.hip", "hk_mlp.hip", "hawk_api.cpp", "hawk_explore.cpp", "hawk_model.cpp"]
+SOURCES = ["hk_batch.hip", "hk_common.hip", "hk_dispatch.hip", "hk_mlp.hip", "hawk_api.cpp", "hawk_explore.cpp", "hawk_model.cpp", "hawk_batch.cpp"]
 # kernel families compiled once per shape class (see HkShape in hawk_plan.h)
 SHAPED = ["hk_agg.hip", "hk_proj.hip", "hk_scalar.hip"]
 SHAPES = ["A", "F", "J", "W", "G"]
@@ -40,7 +40,7 @@ def _compile(job) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
-    jobs = [(s, sh) for s in SHAPED for sh in SHAPES] + list(SOURCES)
+    jobs = SOURCES[:1] + [(s, sh) for s in SHAPED for sh in SHAPES] + SOURCES[1:]  # longest first
     with ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, 16, len(jobs))) as ex:
         objs = list(ex.map(_compile, jobs))
     tmp = LIB + ".tmp"

@@ -207,6 +207,7 @@ extern "C" void hawk_ctx_destroy(hawk_ctx* ctx) {
     r->ctx = nullptr;
   }
   for (hawk_model* m : ctx->models) model_release_device(m);
+  for (hawk_batch* b : ctx->batches) batch_release_device(b);
   if (ctx->device < 0) {
     delete ctx;
     return;
@@ -610,6 +611,7 @@ static void result_release(hawk_result* r) {
 
 extern "C" void hawk_result_free(hawk_result* r) {
   if (!r) return;
+  if (r->batch) batch_forget_view(r->batch, r);
   if (r->ctx) {
     result_release(r);
     r->ctx->results.erase(r);

@@ -255,15 +255,6 @@ __device__ __forceinline__ void seq_range(int64_t n, int64_t t, int64_t T, int64
 }
 
 // ------------------------------------------------------------------ structs passed to kernels
-struct HkIdent { uint64_t w[2 + 2 * HK_MAX_AGGS]; int32_t nw; };
-struct HkOut { int64_t* col[HK_MAX_PROJ]; int64_t dump; };
-struct HkResOut {
-  int64_t* gcol[2];
-  void* acol[HK_MAX_AGGS];
-  int64_t* count;
-  unsigned long long* nrows;
-  int32_t keep_empty;  // AGGREGATE without groups keeps its single row
-};
 
 
 template <class S>
@@ -435,6 +426,33 @@ __device__ __forceinline__ double i128_to_f64(uint64_t lo, int64_t hi) {
   return static_cast<double>(hi) * 18446744073709551616.0 + static_cast<double>(lo);
 }
 
+
+// writes the group row of slot words p (key, count, aggregates) at row pos of the result columns
+__device__ __forceinline__ void write_group_row(const HkPlan& P, const uint64_t* p, int64_t pos, const HkResOut& O) {
+  const uint64_t key = p[0];  // the side slot keeps the all-ones key
+  if (P.ngroup == 1) O.gcol[0][pos] = static_cast<int32_t>(static_cast<uint32_t>(key));
+  if (P.ngroup == 2) {
+    O.gcol[0][pos] = static_cast<int32_t>(static_cast<uint32_t>(key >> 32));
+    O.gcol[1][pos] = static_cast<int32_t>(static_cast<uint32_t>(key));
+  }
+  const uint64_t cnt = p[1];
+  O.count[pos] = static_cast<int64_t>(cnt);
+  for (int a = 0; a < P.naggs; ++a) {
+    const HkAgg& A = P.aggs[a];
+    if (A.fn == HK_COUNT) {
+      static_cast<int64_t*>(O.acol[a])[pos] = static_cast<int64_t>(cnt);
+    } else if (A.fn == HK_AVG) {
+      const double sum = A.wide ? i128_to_f64(p[A.word], static_cast<int64_t>(p[A.word + 1]))
+                                : static_cast<double>(static_cast<int64_t>(p[A.word]));
+      static_cast<double*>(O.acol[a])[pos] = sum / static_cast<double>(cnt);
+    } else if (A.fn == HK_SUM && A.wide) {
+      static_cast<uint64_t*>(O.acol[a])[2 * pos] = p[A.word];
+      static_cast<uint64_t*>(O.acol[a])[2 * pos + 1] = p[A.word + 1];
+    } else {
+      static_cast<int64_t*>(O.acol[a])[pos] = static_cast<int64_t>(p[A.word]);
+    }
+  }
+}
 
 // ------------------------------------------------------------------ host-side launch helpers
 #define DISPATCH2(v, NAME, ...) \

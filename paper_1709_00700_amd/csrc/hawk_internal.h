@@ -41,6 +41,7 @@ struct hawk_ctx {
   std::set<struct hawk_query*> queries;
   std::set<struct hawk_result*> results;
   std::set<struct hawk_model*> models;
+  std::set<struct hawk_batch*> batches;
   bool prof_on = false;
   std::vector<ProfRec> prof;           // launches recorded since profiling was enabled
   std::vector<hipEvent_t> prof_free;   // recycled events
@@ -98,10 +99,13 @@ struct hawk_result {
   int err_bits = 0;
   hawk_status status = HAWK_OK;
   int64_t nrows = -1;
+  struct hawk_batch* batch = nullptr;  // set for a view of a batch's result (owns nothing)
 };
 
 hawk_status set_error(hawk_ctx* ctx, hawk_status st, const std::string& msg);
 void query_release_device(hawk_query* q);
 void model_release_device(struct hawk_model* m);
+void batch_release_device(struct hawk_batch* b);
+void batch_forget_view(struct hawk_batch* b, hawk_result* r);
 std::vector<hawk_variant> variant_space(const hawk_query* q);
 hawk_status query_features(const hawk_query* q, const hawk_variant* v, int num_cus, float* f);

@@ -104,5 +104,18 @@ inline int hk_shape_of(const HkPlan& P) {
   return HK_SHAPE_G;
 }
 
+// identity words of an aggregation slot [key, count, aggregates...]
+struct HkIdent { uint64_t w[2 + 2 * HK_MAX_AGGS]; int32_t nw; };
+// projection outputs (int64 per projected attribute) and the dump slot
+struct HkOut { int64_t* col[HK_MAX_PROJ]; int64_t dump; };
+// aggregation result columns
+struct HkResOut {
+  int64_t* gcol[2];
+  void* acol[HK_MAX_AGGS];
+  int64_t* count;
+  unsigned long long* nrows;
+  int32_t keep_empty;  // AGGREGATE without groups keeps its single row
+};
+
 // an aggregation hash table in HBM (plus one side slot for the sentinel key)
 struct HkAggTable { uint64_t* words; uint32_t log2cap; int32_t slot_words; };

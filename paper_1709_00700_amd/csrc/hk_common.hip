@@ -185,29 +185,7 @@ __global__ void __launch_bounds__(256) k_finalize(const HkPlan* Pp, HkAggTable T
     start = __shfl(start, 0, WAVE);
     if (!live) continue;
     const int64_t pos = static_cast<int64_t>(start) + __popcll(m & lanemask_lt());
-    const uint64_t key = p[0];  // the side slot keeps the all-ones key
-    if (P.ngroup == 1) O.gcol[0][pos] = static_cast<int32_t>(static_cast<uint32_t>(key));
-    if (P.ngroup == 2) {
-      O.gcol[0][pos] = static_cast<int32_t>(static_cast<uint32_t>(key >> 32));
-      O.gcol[1][pos] = static_cast<int32_t>(static_cast<uint32_t>(key));
-    }
-    const uint64_t cnt = p[1];
-    O.count[pos] = static_cast<int64_t>(cnt);
-    for (int a = 0; a < P.naggs; ++a) {
-      const HkAgg& A = P.aggs[a];
-      if (A.fn == HK_COUNT) {
-        static_cast<int64_t*>(O.acol[a])[pos] = static_cast<int64_t>(cnt);
-      } else if (A.fn == HK_AVG) {
-        const double sum = A.wide ? i128_to_f64(p[A.word], static_cast<int64_t>(p[A.word + 1]))
-                                  : static_cast<double>(static_cast<int64_t>(p[A.word]));
-        static_cast<double*>(O.acol[a])[pos] = sum / static_cast<double>(cnt);
-      } else if (A.fn == HK_SUM && A.wide) {
-        static_cast<uint64_t*>(O.acol[a])[2 * pos] = p[A.word];
-        static_cast<uint64_t*>(O.acol[a])[2 * pos + 1] = p[A.word + 1];
-      } else {
-        static_cast<int64_t*>(O.acol[a])[pos] = static_cast<int64_t>(p[A.word]);
-      }
-    }
+    write_group_row(P, p, pos, O);
   }
 }
 

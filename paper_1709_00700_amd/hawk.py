@@ -43,6 +43,8 @@ EXPORTS = [
     "hawk_profile_enable", "hawk_profile_read",
     "hawk_model_create", "hawk_model_free", "hawk_model_set_params", "hawk_model_get_params",
     "hawk_model_train", "hawk_model_predict", "hawk_mlp_forward_dev", "hawk_mlp_grad_dev", "hawk_model_pick",
+    "hawk_batch_create", "hawk_batch_free", "hawk_batch_run", "hawk_batch_time", "hawk_batch_autotune",
+    "hawk_batch_opts_get", "hawk_batch_result",
 ]
 
 
@@ -96,6 +98,14 @@ class hawk_explore_opts(ctypes.Structure):
 class hawk_train_opts(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
                 ("seed", ctypes.c_uint64)]
+
+
+class hawk_batch_opts(ctypes.Structure):
+    _fields_ = [("tile_rows_log2", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"tile_rows_log2": self.tile_rows_log2, "wgs_per_cu": self.wgs_per_cu, "order": self.order}
 
 
 class hawk_explore_report(ctypes.Structure):
@@ -152,6 +162,13 @@ def L():
             "hawk_model_pick": ([vp, P(vp), i32, P(hawk_variant), P(ctypes.c_float)], i32),
             "hawk_profile_enable": ([vp, i32], i32),
             "hawk_profile_read": ([vp, ctypes.c_char_p, P(ctypes.c_double), P(i64)], i32),
+            "hawk_batch_create": ([vp, P(vp), i32, P(hawk_batch_opts), P(vp)], i32),
+            "hawk_batch_free": ([vp], None),
+            "hawk_batch_run": ([vp], i32),
+            "hawk_batch_time": ([vp, i32, P(ctypes.c_double)], i32),
+            "hawk_batch_autotune": ([vp, i32, P(hawk_batch_opts), P(ctypes.c_double)], i32),
+            "hawk_batch_opts_get": ([vp, P(hawk_batch_opts)], i32),
+            "hawk_batch_result": ([vp, i32, P(vp)], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -518,3 +535,51 @@ class Model:
         pred = np.empty(len(queries), np.float32)
         check(L().hawk_model_pick(self.handle, W, len(queries), out, _fptr(pred)), self.ctx.handle)
         return list(out), pred
+
+
+# ---------------------------------------------------------------- batched execution
+class Batch:
+    """Many queries replayed as one captured graph of persistent kernels (see hawk.h, batched execution)."""
+
+    def __init__(self, ctx: Context, queries: list, tile_rows_log2=16, wgs_per_cu=2, order=1):
+        self.ctx = ctx
+        self.queries = list(queries)  # the batch borrows them
+        W = (ctypes.c_void_p * len(queries))(*[q.handle.value for q in queries])
+        o = hawk_batch_opts(tile_rows_log2, wgs_per_cu, order, 0)
+        h = ctypes.c_void_p()
+        check(L().hawk_batch_create(ctx.handle, W, len(queries), ctypes.byref(o), ctypes.byref(h)), ctx.handle)
+        self.handle = h
+
+    def free(self):
+        if self.handle:
+            L().hawk_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def run(self):
+        check(L().hawk_batch_run(self.handle), self.ctx.handle)
+
+    def time(self, reps=5) -> float:
+        ms = ctypes.c_double()
+        check(L().hawk_batch_time(self.handle, reps, ctypes.byref(ms)), self.ctx.handle)
+        return ms.value
+
+    def autotune(self, reps=3):
+        o, ms = hawk_batch_opts(), ctypes.c_double()
+        check(L().hawk_batch_autotune(self.handle, reps, ctypes.byref(o), ctypes.byref(ms)), self.ctx.handle)
+        return o.as_dict(), ms.value
+
+    def opts(self) -> dict:
+        o = hawk_batch_opts()
+        check(L().hawk_batch_opts_get(self.handle, ctypes.byref(o)), self.ctx.handle)
+        return o.as_dict()
+
+    def result(self, i: int) -> Result:
+        h = ctypes.c_void_p()
+        check(L().hawk_batch_result(self.handle, i, ctypes.byref(h)), self.ctx.handle)
+        return Result(self.ctx, h)

@@ -1,0 +1,108 @@
+"""GPU parity of batched execution: a mixed workload of projection,
+aggregation and star-join pipelines replayed as one captured graph of
+persistent kernels, every query's result against the oracle, over several
+replays, schedules and the autotuner's re-capture."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import compare, say
+from paper_1709_00700_amd import datagen as dg
+from paper_1709_00700_amd import hawk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = hawk.Context(0)
+    yield c
+    c.close()
+
+
+def c5_setup(ctx, nq, pool_rows, min_rows, max_rows, seed=dg.MASTER_SEED + 5):
+    """Registers the pools once on the device and every query's window as a
+    table of views into them; returns (queries, handles, oracle answers)."""
+    import torch
+    pools = dg.c5_pools(pool_rows, seed)
+    qs = dg.c5_queries(nq, pool_rows, seed, min_rows=min_rows, max_rows=max_rows)
+    dev = {p: {c: torch.from_numpy(np.ascontiguousarray(a)).to("cuda") for c, a in cols.items()}
+           for p, cols in pools.items()}
+    for j in range(4):
+        ctx.register(f"d{j}", dev[f"d{j}"])
+    handles, refs = [], []
+    for q in qs:
+        o, n = q["offset"], q["rows"]
+        ctx.register(q["window"], {c: t[o:o + n] for c, t in dev[q["pool"]].items()})
+        handles.append(hawk.build_query(ctx, q["spec"]))
+        refs.append(oracle.run(dg.c5_window_tables(pools, q), q["spec"]))
+    ctx._keep.append(dev)
+    return qs, handles, refs
+
+
+def check_batch(b, qs, refs, label):
+    for i, (q, ref) in enumerate(zip(qs, refs)):
+        r = b.result(i)
+        got = r.to_numpy(q["spec"])
+        r.free()
+        compare(got, ref, q["spec"], f"{label} query {i} kind {q['kind']} rows {q['rows']}")
+
+
+def test_batch_mixed_workload_two_replays(ctx):
+    say("batch: 24 mixed queries, up to 400k rows each")
+    qs, hs, refs = c5_setup(ctx, 24, 400_000, 1000, 400_000)
+    assert {q["kind"] for q in qs} == {1, 2, 3}
+    b = hawk.Batch(ctx, hs)
+    for rep in range(2):
+        b.run()
+        check_batch(b, qs, refs, f"replay {rep}")
+    b.free()
+
+
+@pytest.mark.parametrize("tile,wgs,order", [(14, 1, 0), (18, 8, 1), (15, 3, 0)])
+def test_batch_schedules(ctx, tile, wgs, order):
+    say("batch schedule", tile, wgs, order)
+    qs, hs, refs = c5_setup(ctx, 12, 300_000, 1000, 300_000, seed=dg.MASTER_SEED + 55)
+    b = hawk.Batch(ctx, hs, tile_rows_log2=tile, wgs_per_cu=wgs, order=order)
+    assert b.opts() == {"tile_rows_log2": tile, "wgs_per_cu": wgs, "order": order}
+    b.run()
+    check_batch(b, qs, refs, f"tile {tile} wgs {wgs} order {order}")
+    b.free()
+
+
+def test_batch_tiny_ragged_queries(ctx):
+    # windows of 1..5000 rows: single partial tiles, empty selections, one-row groups
+    say("batch: 32 tiny queries")
+    qs, hs, refs = c5_setup(ctx, 32, 50_000, 1, 5000, seed=dg.MASTER_SEED + 56)
+    b = hawk.Batch(ctx, hs, tile_rows_log2=14, wgs_per_cu=2)
+    b.run()
+    b.run()
+    check_batch(b, qs, refs, "tiny")
+    b.free()
+
+
+def test_batch_autotune_recaptures(ctx):
+    say("batch autotune")
+    qs, hs, refs = c5_setup(ctx, 8, 200_000, 1000, 200_000, seed=dg.MASTER_SEED + 57)
+    b = hawk.Batch(ctx, hs)
+    best, ms = b.autotune(reps=1)
+    assert b.opts() == best and ms > 0
+    say("best", best, ms)
+    b.run()
+    check_batch(b, qs, refs, f"tuned {best}")
+    assert b.time(reps=3) > 0
+    b.free()
+
+
+def test_batch_view_orphaned_by_free(ctx):
+    qs, hs, refs = c5_setup(ctx, 3, 20_000, 1000, 20_000, seed=dg.MASTER_SEED + 58)
+    b = hawk.Batch(ctx, hs)
+    b.run()
+    r = b.result(0)
+    r.info()
+    b.free()
+    with pytest.raises(hawk.HawkError):
+        r.info()
+    r.free()
