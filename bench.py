@@ -31,8 +31,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "input rows/s + HBM GB/s per pipeline; learned-pick vs best-variant runtime ratio"
 
-# variants used by the timed steps, per workload pipeline (chosen by the
-# variant optimizer on this device; see the design doc for how they were found)
+# variants used by the timed steps, per workload pipeline: the exhaustive
+# search's best on MI355X (python bench.py --workload W --explore exhaustive)
 DEFAULT_VARIANTS = {
     "c1": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=1024, wg_size=256),
     "c2u": dict(proj_strategy=1, mem=1, pred=1, ht=0, hash=1, agg_strategy=0, thread_mult=8, wg_size=512),
@@ -44,6 +44,8 @@ DEFAULT_VARIANTS = {
 # algorithmic bytes read per input row of each pipeline (columns the
 # pipeline must read once), plus the kernel family that dominates it
 ALGO_BYTES_PER_ROW = {"c1": None, "c2u": 12, "c2z": 12, "c3": 24, "c4": 22}
+KERNEL_FAMILIES = ["k_agg", "k_scalar_agg", "k_mp_filter", "k_mp_project", "k_sp", "k_build", "k_finalize",
+                   "k_init_aggtable", "k_scan", "k_sp_concat"]
 WORKLOADS = {
     "c1": ["c1"],
     "c2": ["c2u", "c2z"],
@@ -78,6 +80,57 @@ def make_pipelines(workload, rows):
     return out
 
 
+# HBM traffic of the dominant kernel, from two rocprofv3 --pmc runs (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch) of this script's default workload, each
+# scaled by the ratio of known bytes to the counter's reading for a plain
+# device copy (--copy-calibration). Valid only for the kernel sources it was
+# measured on: bench.py reports null when their hash differs.
+TRAFFIC = {}
+
+
+def kernel_sources_sha(kernel):
+    import hashlib
+    files = {"k_agg": ["hk_agg.hip", "hawk_device.h", "hawk_plan.h"]}.get(kernel, [])
+    if not files:
+        return None
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1709_00700_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, workload):
+    t = TRAFFIC.get((kernel, workload))
+    if not t or t["sources_sha"] != kernel_sources_sha(kernel):
+        return None
+    return t["bytes_per_launch"]
+
+
+def copy_calibration(nbytes):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = nbytes // 8
+    src = torch.arange(n, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 8, "copies": 4}), flush=True)
+
+
+def explore(ctx, pipes, mode, timing_db):
+    from paper_1709_00700_amd import hawk
+    m = hawk.HAWK_EXPLORE_EXHAUSTIVE if mode == "exhaustive" else hawk.HAWK_EXPLORE_FEATURE_WISE
+    for name, q, v, nrows in pipes:
+        log(f"[bench] exploring {name} ({mode})")
+        best, rep = hawk.explore(ctx, [q], m, reps=3, max_iters=5, limit_ms=1000.0, timing_db=timing_db)
+        print(json.dumps({"explore": name, "mode": mode, "rows": nrows, "best": hawk.format_variant(best),
+                          "best_variant": best.as_dict(), **rep}), flush=True)
+
+
 def cpu_baseline(workload, budget_s=20.0):
     """The oracle as it stands, single-threaded, on a bounded sample of the workload."""
     import oracle
@@ -108,16 +161,24 @@ def main():
     ap.add_argument("--rows", type=int, default=None, help="override the input rows per pipeline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--explore", choices=["exhaustive", "feature_wise"], default=None,
+                    help="run the variant optimizer on each pipeline instead of the timed steps")
+    ap.add_argument("--timing-db", default=None, help="append every exploration measurement to this file")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build does not run across several GPUs "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+              "(every pipeline would shard by row ranges of its scanned table)", file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_1709_00700_amd import hawk
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     ctx = hawk.Context(0)
     ncu, _ = ctx.device_info()
     pipes = []
@@ -132,6 +193,10 @@ def main():
         pipes.append((name, q, v, nrows))
         del tables
     stream = ctx.stream
+    if args.explore:
+        explore(ctx, pipes, args.explore, args.timing_db)
+        ctx.close()
+        return
 
     def step():
         for _, q, v, _ in pipes:
@@ -147,6 +212,9 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # the library brackets each of its launches with HIP events on its own
+    # stream while the timed steps run: the roofline's kernel durations
+    hawk.profile_enable(ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
@@ -157,6 +225,8 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = e0.elapsed_time(e1) / args.steps
     value = total_rows / (ms_per_step / 1e3)
+    timed = {f: hawk.profile_read(ctx, f) for f in KERNEL_FAMILIES}
+    hawk.profile_enable(ctx, False)
 
     # per-pipeline times and the dominant kernel, timed with events on the library stream
     per = []
@@ -166,9 +236,7 @@ def main():
         hawk.profile_enable(ctx, True)
         for _ in range(max(5, args.steps // 2)):
             hawk.execute(ctx, q, v, sync=False).free()
-        fams = ["k_agg", "k_scalar_agg", "k_mp_filter", "k_mp_project", "k_sp", "k_build", "k_finalize",
-                "k_init_aggtable", "k_scan", "k_sp_concat"]
-        stats = {f: hawk.profile_read(ctx, f) for f in fams}
+        stats = {f: hawk.profile_read(ctx, f) for f in KERNEL_FAMILIES}
         hawk.profile_enable(ctx, False)
         stats = {f: (t / n, n) for f, (t, n) in stats.items() if n}
         dom = max(stats, key=lambda f: stats[f][0])
@@ -181,15 +249,18 @@ def main():
             entry["kernel_algo_gb_per_s"] = nrows * bpr / (stats[dom][0] / 1e3) / 1e9
         per.append(entry)
         kern_stats.setdefault(dom, []).append((stats[dom][0], nrows * (bpr or 0)))
-    # roofline of the dominant kernel over the step: algorithmic bytes per launch / average launch duration
-    dom = max(kern_stats, key=lambda f: sum(t for t, _ in kern_stats[f]))
-    launches = kern_stats[dom]
-    avg_ms = sum(t for t, _ in launches) / len(launches)
-    avg_bytes = sum(b for _, b in launches) / len(launches)
+    # roofline of the dominant kernel of the timed steps: algorithmic bytes
+    # per launch (the pipelines' launches are equally many) / the average
+    # launch duration recorded during the timed region
+    dom = max(timed, key=lambda f: timed[f][0])
+    tot_ms, nl = timed[dom]
+    avg_ms = tot_ms / nl
+    launches = [b for _, b in kern_stats.get(dom, [])]
+    avg_bytes = sum(launches) / len(launches) if launches else 0.0
     achieved = avg_bytes / (avg_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "algo_bytes_per_launch": avg_bytes, "avg_launch_ms": round(avg_ms, 4)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom, args.workload),
+                "algo_bytes_per_launch": avg_bytes, "avg_launch_ms": round(avg_ms, 4), "launches_timed": nl}
 
     out = {"metric": METRIC, "value": value, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",

@@ -639,7 +639,7 @@ static hawk_status result_check(hawk_result* r) {
 }
 
 extern "C" hawk_status hawk_result_info(hawk_result* r, int64_t* nrows, int32_t* ncols) {
-  if (!r) return HAWK_E_ARG;
+  if (!r || !r->ctx) return HAWK_E_ARG;  // orphaned: its memory is gone
   hawk_status st = result_check(r);
   if (st) return st;
   if (nrows) *nrows = r->nrows;
@@ -657,7 +657,7 @@ extern "C" hawk_status hawk_result_column(hawk_result* r, int32_t col, int32_t* 
 }
 
 extern "C" hawk_status hawk_result_copy_column(hawk_result* r, int32_t col, void* host_dst, int64_t cap_bytes) {
-  if (!r) return HAWK_E_ARG;
+  if (!r || !r->ctx) return HAWK_E_ARG;
   hawk_status st = result_check(r);
   if (st) return st;
   if (col < 0 || col >= static_cast<int32_t>(r->cols.size())) return set_error(r->ctx, HAWK_E_ARG, "bad column index");
