@@ -45,7 +45,7 @@ DEFAULT_VARIANTS = {
 # pipeline must read once), plus the kernel family that dominates it
 ALGO_BYTES_PER_ROW = {"c1": None, "c2u": 12, "c2z": 12, "c3": 24, "c4": 22}
 KERNEL_FAMILIES = ["k_agg", "k_scalar_agg", "k_mp_filter", "k_mp_project", "k_sp", "k_build", "k_finalize",
-                   "k_init_aggtable", "k_scan", "k_sp_concat"]
+                   "k_init_aggtable", "k_scan", "k_sp_concat", "k_spill_scatter", "k_spill_agg"]
 WORKLOADS = {
     "c1": ["c1"],
     "c2": ["c2u", "c2z"],

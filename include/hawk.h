@@ -86,8 +86,9 @@ typedef struct {
 } hawk_column;
 
 /* Registers a table under `name`; names and column names are copied.
-   nrows must be < 2^32. Errors: HAWK_E_ARG (duplicate table/column name,
-   bad dtype, null pointer with nrows > 0). */
+   nrows must be < 2^32; each column must be aligned to its element size.
+   Errors: HAWK_E_ARG (duplicate table/column name, bad dtype, null pointer
+   with nrows > 0, misaligned column). */
 hawk_status hawk_table_register(hawk_ctx* ctx, const char* name, int64_t nrows,
                                 const hawk_column* cols, int32_t ncols, int32_t* table_id);
 hawk_status hawk_table_unregister(hawk_ctx* ctx, int32_t table_id);
@@ -240,7 +241,9 @@ hawk_status hawk_profile_enable(hawk_ctx* ctx, int32_t on);
 /* Sum of the recorded durations and number of launches of one kernel family:
    "k_agg" (grouped aggregation, including the cuckoo key phase), "k_scalar_agg",
    "k_mp_filter", "k_scan", "k_mp_project", "k_sp", "k_sp_concat", "k_build",
-   "k_init_aggtable", "k_finalize". Synchronises the stream. */
+   "k_init_aggtable", "k_finalize", "k_spill_scatter" and "k_spill_agg"
+   (regrouping by table region, then aggregation, of the rows a local table
+   could not hold). Synchronises the stream. */
 hawk_status hawk_profile_read(hawk_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
 
 /* ------------------------------------------------------------ cost-model features */

@@ -22,6 +22,7 @@ namespace {
 
 const uint32_t kMults[7] = {1, 8, 64, 256, 1024, 16384, 65536};  // Section 9.2
 const uint32_t kWgs[7] = {16, 32, 64, 128, 256, 512, 1024};       // Section 9.2
+const int64_t kSpillLds = 65536;  // LDS bytes of a spill region / of a table plus its histogram
 const int64_t kLdsBudget = 32768;  // bytes of LDS per workgroup for a local table
 const int kMaxAttempts = 12;
 
@@ -184,7 +185,9 @@ extern "C" hawk_status hawk_ctx_create(int32_t device, void* hip_stream, hawk_ct
   c->num_cus = prop.multiProcessorCount;
   c->lds_bytes = static_cast<int64_t>(prop.sharedMemPerBlock);
   c->seed = 0x48415748ull;  // fixed: results never depend on it, timings stay reproducible
-  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+      hipMalloc(&c->dummy, 256) != hipSuccess || hipMemset(c->dummy, 0, 256) != hipSuccess) {
+    if (c->dummy) (void)hipFree(c->dummy);
     delete c;
     return HAWK_E_DEVICE;
   }
@@ -217,6 +220,7 @@ extern "C" void hawk_ctx_destroy(hawk_ctx* ctx) {
   for (hipEvent_t e : ctx->prof_free) (void)hipEventDestroy(e);
   (void)hipEventDestroy(ctx->ev0);
   (void)hipEventDestroy(ctx->ev1);
+  (void)hipFree(ctx->dummy);
   delete ctx;
 }
 
@@ -246,6 +250,9 @@ extern "C" hawk_status hawk_table_register(hawk_ctx* ctx, const char* name, int6
     if (cols[i].dtype != HAWK_I8 && cols[i].dtype != HAWK_I32 && cols[i].dtype != HAWK_I64)
       return set_error(ctx, HAWK_E_ARG, std::string("bad dtype of column ") + cols[i].name);
     if (!cols[i].dev_ptr && nrows > 0) return set_error(ctx, HAWK_E_ARG, std::string("null column ") + cols[i].name);
+    const uintptr_t esize = cols[i].dtype == HAWK_I64 ? 8 : (cols[i].dtype == HAWK_I32 ? 4 : 1);
+    if (reinterpret_cast<uintptr_t>(cols[i].dev_ptr) % esize != 0)
+      return set_error(ctx, HAWK_E_ARG, std::string("column not aligned to its element size: ") + cols[i].name);
     for (const auto& c : t.cols)
       if (c.name == cols[i].name) return set_error(ctx, HAWK_E_ARG, std::string("duplicate column ") + cols[i].name);
     t.cols.push_back({cols[i].name, cols[i].dtype, cols[i].scale, cols[i].dev_ptr});
@@ -499,6 +506,11 @@ extern "C" hawk_status hawk_query_create(hawk_ctx* ctx, const hawk_pipeline* pip
   }
   if (!st && stage != 3) st = set_error(ctx, HAWK_E_PLAN, "main pipeline has no PROJECT/AGGREGATE/HASH_AGGREGATE");
   if (st) { delete q; return st; }
+  // unused column slots read the context's zero block, so kernels may load
+  // every slot of their shape class without a per-slot condition
+  for (int c = L.P.ncolA; c < HK_MAX_COLS_A; ++c) L.P.colA[c] = HkCol{ctx->dummy, HK_T_I64, 0};
+  for (int c = L.P.ncolB; c < HK_MAX_COLS_B; ++c) L.P.colB[c] = HkCol{ctx->dummy, HK_T_I64, 0};
+  for (int c = L.P.ncolC; c < HK_MAX_COLS_C; ++c) L.P.colC[c] = HkCol{ctx->dummy, HK_T_I64, 0};
   q->main = L.P;
   q->has_table = L.P.nprobes > 0 || L.P.ngroup > 0;
   ctx->queries.insert(q);
@@ -888,8 +900,10 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
     T.log2cap = std::max<uint32_t>(6, ceil_log2(static_cast<uint64_t>(X.q->groups_hint) * 2)) + grow;
     if (T.log2cap > 31) return set_error(ctx, HAWK_E_CAPACITY, "aggregation table beyond 2^31 slots");
     nslots = (int64_t(1) << T.log2cap) + 1;  // + side slot for the all-ones key
+    T.rlog2 = T.log2cap;
   } else {
     T.log2cap = 0;
+    T.rlog2 = 0;
     nslots = 1;
   }
   ALLOC(T.words, uint64_t*, static_cast<size_t>(nslots * W) * 8, false);
@@ -913,9 +927,64 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
       if ((int64_t(1) << llog2) * W * 8 > ctx->lds_bytes)
         return set_error(ctx, HAWK_E_INFEASIBLE, "local table does not fit in LDS");
     }
-    ProfScope ps(ctx, "k_agg");
-    HIPCHK(hk_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, llog2, ident, W,
-                  res->d_err), "aggregation kernel");
+    // Overflow partitioning: with the local strategy and linear probing, when
+    // the LDS table cannot hold every group, rows that miss it are spilled
+    // and aggregated per table region by the region's owner workgroup
+    // instead of each updating the table with device-scope atomics.
+    HkSpill sp;
+    std::memset(&sp, 0, sizeof(sp));
+    // a region (aggregated in LDS by its owner) takes at most 64 KB; the
+    // partition histogram of a workgroup sits beside its LDS table
+    uint32_t rlog2 = 0;
+    while ((int64_t(2) << rlog2) * W * 8 <= kSpillLds) ++rlog2;
+    const int64_t nparts = T.log2cap > rlog2 ? int64_t(1) << (T.log2cap - rlog2) : 1;
+    const bool spill = v->agg_strategy == HAWK_LOCAL && v->ht == HAWK_LINEAR_PROBING && T.log2cap > llog2 &&
+                       rlog2 >= 6 && nparts >= 2 && (int64_t(1) << llog2) * W * 8 + nparts * 4 <= kSpillLds &&
+                       nparts * groups <= (int64_t(1) << 26) && P.nrows > 0 && ctx->lds_bytes >= kSpillLds;
+    if (spill) {
+      T.rlog2 = rlog2;
+      sp.nparts = static_cast<int32_t>(nparts);
+      for (int a = 0; a < P.naggs; ++a) {
+        if (P.aggs[a].fn == HK_COUNT) continue;
+        bool seen = false;
+        for (int j = 0; j < sp.ncols; ++j) seen = seen || sp.reg[j] == P.aggs[a].reg;
+        if (!seen) sp.reg[sp.ncols++] = P.aggs[a].reg;
+      }
+      sp.ew = 1 + sp.ncols;
+      const int64_t threads = groups * wg;
+      sp.region = (P.nrows + threads - 1) / threads * wg;
+      const int64_t m = nparts * groups;
+      uint32_t *offs, *stmp;
+      uint64_t *total, *part;
+      ALLOC(sp.buf, uint64_t*, static_cast<size_t>(groups * sp.region * sp.ew) * 8, false);
+      ALLOC(sp.hist, uint32_t*, static_cast<size_t>(m) * 4, false);
+      ALLOC(sp.cnt, uint32_t*, static_cast<size_t>(groups) * 4, false);
+      ALLOC(offs, uint32_t*, static_cast<size_t>(m) * 4, false);
+      ALLOC(stmp, uint32_t*, static_cast<size_t>(hk_scan_tmp_words(m)) * 4, false);
+      ALLOC(total, uint64_t*, 8, false);
+      ALLOC(part, uint64_t*, static_cast<size_t>(P.nrows * sp.ew) * 8, false);
+      {
+        ProfScope ps(ctx, "k_agg");
+        HIPCHK(hk_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, llog2, ident, W,
+                      res->d_err, &sp), "aggregation kernel");
+      }
+      {
+        ProfScope ps(ctx, "k_scan");
+        HIPCHK(hk_scan(X.st, sp.hist, offs, m, stmp, total), "spill offsets");
+      }
+      {
+        ProfScope ps(ctx, "k_spill_scatter");
+        HIPCHK(hk_spill(X.st, 0, P, T, v->hash, sp, offs, total, groups, part, res->d_err), "spill regrouping");
+      }
+      {
+        ProfScope ps(ctx, "k_spill_agg");
+        HIPCHK(hk_spill(X.st, 1, P, T, v->hash, sp, offs, total, groups, part, res->d_err), "spill aggregation");
+      }
+    } else {
+      ProfScope ps(ctx, "k_agg");
+      HIPCHK(hk_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, llog2, ident, W,
+                    res->d_err), "aggregation kernel");
+    }
   } else {
     ProfScope ps(ctx, "k_scalar_agg");
     HIPCHK(hk_scalar_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, ident, W,

@@ -177,13 +177,14 @@ hawk_status setup_memory(hawk_batch* B) {
         Q.ident.w[A.word] = A.fn == HK_MIN ? static_cast<uint64_t>(INT64_MAX)
                             : A.fn == HK_MAX ? static_cast<uint64_t>(INT64_MIN) : 0ull;
       }
-      Q.table.slot_words = W;
+      Q.table.slot_words = W;  // rlog2 below: one region (whole-table probing)
       if (grouped) {
         // a pipeline cannot produce more groups than it scans rows
         const uint64_t groups = static_cast<uint64_t>(std::max<int64_t>(1, std::min<int64_t>(q->groups_hint, n)));
         Q.table.log2cap = std::max<uint32_t>(6, clog2(groups * 2));
         if (Q.table.log2cap > 31) return berr(B, HAWK_E_CAPACITY, "aggregation table beyond 2^31 slots");
         Q.nslots = (int64_t(1) << Q.table.log2cap) + 1;  // + side slot for the all-ones key
+        Q.table.rlog2 = Q.table.log2cap;
         uint32_t want = std::max<uint32_t>(4, clog2(groups * 2)), fit = 0;
         while ((int64_t(2) << fit) * W * 8 <= kLdsBudget) ++fit;
         Q.llog2 = std::min(want, fit);

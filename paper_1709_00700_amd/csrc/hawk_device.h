@@ -18,6 +18,29 @@ __device__ __forceinline__ int64_t load_col(const HkCol& c, int64_t row) {
   return static_cast<const int8_t*>(c.ptr)[row];
 }
 
+// A column value as loaded: the aligned 8-byte block that holds the element.
+// Every element type then takes one branch-free 64-bit load, so all loads of
+// a phase (or of several rows) can be in flight at once; the element is
+// shifted out and sign-extended when it is first used. An element is
+// naturally aligned (checked at registration), so its 8-aligned block lies
+// in the element's own page: the load never touches an unmapped address.
+struct HkRaw { uint64_t w; };
+typedef const __attribute__((address_space(1))) uint64_t hk_global_u64;  // a global (not flat) load
+__device__ __forceinline__ uint32_t col_lg(int32_t dtype) {
+  return dtype == HK_T_I64 ? 3u : (dtype == HK_T_I32 ? 2u : 0u);
+}
+__device__ __forceinline__ void load_raw(const HkCol& c, int64_t row, HkRaw& v) {
+  const uint64_t a = reinterpret_cast<uint64_t>(c.ptr) + (static_cast<uint64_t>(row) << col_lg(c.dtype));
+  v.w = *reinterpret_cast<hk_global_u64*>(a & ~7ull);
+}
+__device__ __forceinline__ int64_t raw_value(const HkCol& c, int64_t row, const HkRaw& v) {
+  const uint32_t lg = col_lg(c.dtype);
+  const uint64_t a = reinterpret_cast<uint64_t>(c.ptr) + (static_cast<uint64_t>(row) << lg);
+  const uint32_t sh = static_cast<uint32_t>(a & 7ull) * 8u;
+  const uint32_t top = 64u - (8u << lg);
+  return static_cast<int64_t>((v.w >> sh) << top) >> top;
+}
+
 // Murmur3 64-bit finaliser (Appleby, public domain).
 __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
   k ^= k >> 33;
@@ -185,36 +208,70 @@ __device__ __forceinline__ void join_insert(const HkJoinTable& t, const HkHash& 
 }
 
 // ------------------------------------------------------------------ row evaluation
+// The first load phase of a row: the columns read before anything can drop
+// the row (FILTER columns; probe keys when there is no filter; value columns
+// when there is neither filter nor probe). Kernels that scan several rows
+// per thread fetch this phase for all of them before evaluating any.
+template <class S>
+struct HkFirst {
+  static constexpr int A = S::colA;
+  static constexpr int B = S::filters == 0 ? S::colB : 0;
+  static constexpr int C = (S::filters == 0 && S::probes == 0) ? S::colC : 0;
+  HkRaw a[A > 0 ? A : 1], b[B > 0 ? B : 1], c[C > 0 ? C : 1];
+};
+
+// Issues the same number of loads whatever the plan (unused slots read the
+// context's zero block at row 0), so the wait for a row's loads can leave
+// the loads issued after them in flight.
+template <class S>
+__device__ __forceinline__ void fetch_first(const HkPlan& P, int64_t row, HkFirst<S>& f) {
+#pragma unroll
+  for (int c = 0; c < HkFirst<S>::A; ++c) load_raw(P.colA[c], c < P.ncolA ? row : 0, f.a[c]);
+#pragma unroll
+  for (int c = 0; c < HkFirst<S>::B; ++c) load_raw(P.colB[c], c < P.ncolB ? row : 0, f.b[c]);
+#pragma unroll
+  for (int c = 0; c < HkFirst<S>::C; ++c) load_raw(P.colC[c], c < P.ncolC ? row : 0, f.c[c]);
+}
+
 // Pushes one row through LOOP's loads, FILTER, HASH_PROBE and (if VALUES)
 // ARITHMETIC. Branched: returns false as soon as the row is dropped.
 // Predicated: evaluates everything and returns the result_increment.
-template <int PRED, int HT, int HASH, bool VALUES, class S>
-__device__ __forceinline__ bool eval_row(const HkPlan& P, int64_t row, v16i64& r) {
-  // all loads of a phase are issued before any is consumed, so their
+// PRE: the first load phase comes from `f` (fetched earlier) instead of memory.
+template <int PRED, int HT, int HASH, bool VALUES, class S, bool PRE>
+__device__ __forceinline__ bool eval_row_f(const HkPlan& P, int64_t row, const HkFirst<S>& f, v16i64& r) {
+  // every load of a phase is issued before any is widened, so their
   // latencies overlap
-  int64_t la[S::colA > 0 ? S::colA : 1];
+  {
+    HkRaw la[S::colA > 0 ? S::colA : 1];
 #pragma unroll
-  for (int c = 0; c < S::colA; ++c)
-    if (c < P.ncolA) la[c] = load_col(P.colA[c], row);
+    for (int c = 0; c < S::colA; ++c)
+      if (c < P.ncolA) {
+        if (PRE) la[c] = f.a[c];
+        else load_raw(P.colA[c], row, la[c]);
+      }
 #pragma unroll
-  for (int c = 0; c < S::colA; ++c)
-    if (c < P.ncolA) r[P.colA[c].reg] = la[c];
+    for (int c = 0; c < S::colA; ++c)
+      if (c < P.ncolA) r[P.colA[c].reg] = raw_value(P.colA[c], row, la[c]);
+  }
   bool pass = true;
 #pragma unroll
-  for (int f = 0; f < S::filters; ++f) {
-    if (f >= P.nfilters) break;
-    const int64_t x = r[P.filters[f].reg];
-    pass = pass & (x >= P.filters[f].lo) & (x <= P.filters[f].hi);
+  for (int f2 = 0; f2 < S::filters; ++f2) {
+    if (f2 >= P.nfilters) break;
+    const int64_t x = r[P.filters[f2].reg];
+    pass = pass & (x >= P.filters[f2].lo) & (x <= P.filters[f2].hi);
   }
   if (PRED == HK_BR && !pass) return false;
   if (S::colB > 0) {
-    int64_t lb[S::colB > 0 ? S::colB : 1];
+    HkRaw lb[S::colB > 0 ? S::colB : 1];
 #pragma unroll
     for (int c = 0; c < S::colB; ++c)
-      if (c < P.ncolB) lb[c] = load_col(P.colB[c], row);
+      if (c < P.ncolB) {
+        if (PRE && c < HkFirst<S>::B) lb[c] = f.b[c < HkFirst<S>::B ? c : 0];
+        else load_raw(P.colB[c], row, lb[c]);
+      }
 #pragma unroll
     for (int c = 0; c < S::colB; ++c)
-      if (c < P.ncolB) r[P.colB[c].reg] = lb[c];
+      if (c < P.ncolB) r[P.colB[c].reg] = raw_value(P.colB[c], row, lb[c]);
   }
 #pragma unroll
   for (int p = 0; p < S::probes; ++p) {
@@ -226,13 +283,18 @@ __device__ __forceinline__ bool eval_row(const HkPlan& P, int64_t row, v16i64& r
     r[P.probes[p].pay_reg] = pay;
   }
   if (!VALUES) return pass;
-  int64_t lc[S::colC > 0 ? S::colC : 1];
+  {
+    HkRaw lc[S::colC > 0 ? S::colC : 1];
 #pragma unroll
-  for (int c = 0; c < S::colC; ++c)
-    if (c < P.ncolC) lc[c] = load_col(P.colC[c], row);
+    for (int c = 0; c < S::colC; ++c)
+      if (c < P.ncolC) {
+        if (PRE && c < HkFirst<S>::C) lc[c] = f.c[c < HkFirst<S>::C ? c : 0];
+        else load_raw(P.colC[c], row, lc[c]);
+      }
 #pragma unroll
-  for (int c = 0; c < S::colC; ++c)
-    if (c < P.ncolC) r[P.colC[c].reg] = lc[c];
+    for (int c = 0; c < S::colC; ++c)
+      if (c < P.ncolC) r[P.colC[c].reg] = raw_value(P.colC[c], row, lc[c]);
+  }
 #pragma unroll
   for (int k = 0; k < S::arith; ++k) {
     if (k >= P.narith) break;
@@ -243,6 +305,12 @@ __device__ __forceinline__ bool eval_row(const HkPlan& P, int64_t row, v16i64& r
     r[A.dst] = static_cast<long long>(v);
   }
   return pass;
+}
+
+template <int PRED, int HT, int HASH, bool VALUES, class S>
+__device__ __forceinline__ bool eval_row(const HkPlan& P, int64_t row, v16i64& r) {
+  const HkFirst<S> none{};
+  return eval_row_f<PRED, HT, HASH, VALUES, S, false>(P, row, none, r);
 }
 
 // row range of thread `t` out of `T` for sequential access, chunks rounded to `align`
@@ -271,21 +339,24 @@ __device__ __forceinline__ void write_proj(const HkPlan& P, const HkOut& O, int6
 // the global table at the end; a row whose key finds no LDS slot within the
 // probe bound goes straight to the global table.
 
-template <int HASH>
+// WGS: the caller's workgroup owns the key's region for the whole kernel, so
+// workgroup-scope atomics suffice (performed in this XCD's L2)
+template <int HASH, bool WGS = false>
 __device__ __forceinline__ uint64_t* gslot_linear(const HkAggTable& T, const HkHash& h, uint64_t key, int* err) {
   const int64_t W = T.slot_words;
   if (key == HK_EMPTY) return T.words + (static_cast<int64_t>(1) << T.log2cap) * W;  // side slot
-  const uint32_t mask = (1u << T.log2cap) - 1u;
+  const uint32_t rmask = (1u << T.rlog2) - 1u;
   uint32_t s = hslot<HASH>(key, h.a[0], T.log2cap);
-  for (uint32_t i = 0; i <= mask; ++i) {
+  const uint32_t base = s & ~rmask;
+  for (uint32_t i = 0; i <= rmask; ++i) {
     uint64_t* p = T.words + static_cast<int64_t>(s) * W;
     uint64_t cur = *p;
     if (cur == key) return p;
     if (cur == HK_EMPTY) {
-      cur = at_cas<false>(p, HK_EMPTY, key);
+      cur = at_cas<WGS>(p, HK_EMPTY, key);
       if (cur == HK_EMPTY || cur == key) return p;
     }
-    s = (s + 1) & mask;
+    s = base | ((s + 1) & rmask);
   }
   set_err(err, HK_ERR_CAPACITY);
   return nullptr;

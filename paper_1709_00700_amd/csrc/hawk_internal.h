@@ -36,6 +36,7 @@ struct hawk_ctx {
   std::vector<TableReg> tables;
   DevicePool pool;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  void* dummy = nullptr;  // 256 zero bytes in device memory: the column of a plan's unused column slots
   // live handles; destroying the context releases their device state and
   // orphans them (their *_free then only releases host memory)
   std::set<struct hawk_query*> queries;

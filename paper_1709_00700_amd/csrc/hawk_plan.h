@@ -117,5 +117,24 @@ struct HkResOut {
   int32_t keep_empty;  // AGGREGATE without groups keeps its single row
 };
 
-// an aggregation hash table in HBM (plus one side slot for the sentinel key)
-struct HkAggTable { uint64_t* words; uint32_t log2cap; int32_t slot_words; };
+// an aggregation hash table in HBM (plus one side slot for the sentinel key);
+// linear probing stays inside the aligned region of 2^rlog2 slots that holds
+// the key's hash slot (rlog2 == log2cap: the whole table is one region)
+struct HkAggTable { uint64_t* words; uint32_t log2cap; int32_t slot_words; uint32_t rlog2; int32_t pad; };
+
+// Overflow partitioning of the local strategy. A row whose key finds no slot
+// in its workgroup's LDS table is appended to the workgroup's spill region as
+// an entry [key, input values...]; the entries are then regrouped by table
+// region (partition = hash slot >> rlog2) and each region is aggregated by
+// the one workgroup that owns it, so no row touches the table with
+// device-scope atomics.
+struct HkSpill {
+  uint64_t* buf;              // nwg regions of `region` entries of `ew` words
+  int64_t region;             // entries per workgroup region (rows the workgroup scans, at most)
+  uint32_t* hist;             // entry counts per (partition, workgroup), partition-major
+  uint32_t* cnt;              // entries per workgroup
+  int32_t nparts;             // table regions: 2^(log2cap - rlog2)
+  int32_t ncols;              // input values per entry
+  int32_t ew;                 // words per entry: 1 + ncols
+  int32_t reg[HK_MAX_AGGS];   // register of each input value
+};

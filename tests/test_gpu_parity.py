@@ -83,6 +83,39 @@ def test_c2_zipf_sampled_variants(ctx):
     run_variants(ctx, tables, spec, vs, label="c2z")
 
 
+def local_linear(vs):
+    return [v for v in vs if v.agg_strategy == 0 and v.ht == 0]
+
+
+def test_overflow_partitioning_all_local_linear_variants(ctx):
+    # 60k zipf ranks: far more groups than an LDS table holds, so every local
+    # linear-probing variant spills its LDS misses and aggregates them per region
+    tables, spec = dg.c2_aggregation(n=150_001, dist="zipf", nranks=60_000)
+    vs = local_linear(all_variants(ctx, tables, spec))
+    assert len(vs) == 392
+    say("overflow partitioning, 392 variants")
+    run_variants(ctx, tables, spec, vs, label="spill")
+
+
+def test_overflow_partitioning_wide_sums_two_keys(ctx):
+    rng = np.random.default_rng(12)
+    n = 120_000
+    t = {"g1": rng.integers(-300, 300, size=n).astype(np.int32),
+         "g2": rng.integers(-1, 40, size=n).astype(np.int32),
+         "v": rng.integers(-(1 << 62), 1 << 62, size=n, dtype=np.int64),
+         "f": rng.integers(0, 10, size=n).astype(np.int32)}
+    spec = {"builds": [], "main": {"table": "t", "filters": [("f", 1, 8)], "probes": [],
+                                   "arith": [("w", "sub", 0, "v")],
+                                   "group_by": ["g1", "g2"],
+                                   "aggs": [("sum", "v", True), ("sum", "w", True), ("min", "v", False),
+                                            ("max", "w", False), ("avg", "v", True), ("count", None, False)],
+                                   "groups_hint": 24_600}}
+    vs = sample(local_linear(all_variants(ctx, {"t": t}, spec)), 64, seed=7)
+    say("overflow partitioning: two keys, 128-bit sums, AVG")
+    _, ref = run_variants(ctx, {"t": t}, spec, vs, label="spill-wide")
+    assert ref["rows"] > 20_000
+
+
 def test_c3_star_join_sampled_variants(ctx):
     tables, spec = dg.c3_star_join(n=200_000, dims=(250, 2000, 300, 800), sel=(60, 50, 60, 40))
     vs = sample(all_variants(ctx, tables, spec), 128, seed=2)

@@ -1,6 +1,7 @@
 """Host-side checks of libhawk.so that need no GPU: exported symbols, plan
 validation, the variant space of Section 9.2, features, and Algorithm 1
 against its oracle under fake timing backends."""
+import ctypes
 import itertools
 import math
 import os
@@ -121,6 +122,17 @@ def test_plan_validation_errors(plan_ctx):
     with pytest.raises(hawk.HawkError) as e:
         hawk.execute(plan_ctx, q, hawk.variant())
     assert e.value.code == hawk.HAWK_E_DEVICE
+
+
+@pytest.mark.parametrize("dtype,addr,ok", [(1, 0x1001, True), (2, 0x1002, False), (2, 0x1004, True),
+                                           (3, 0x1004, False), (3, 0x1008, True)])
+def test_columns_must_be_aligned_to_their_element_size(plan_ctx, dtype, addr, ok):
+    col = (hawk.hawk_column * 1)(hawk.hawk_column(b"c", dtype, 0, ctypes.c_void_p(addr)))
+    tid = ctypes.c_int32()
+    st = hawk.L().hawk_table_register(plan_ctx.handle, f"t{dtype}_{addr}".encode(), 10, col, 1, ctypes.byref(tid))
+    assert (st == hawk.HAWK_OK) == ok
+    if not ok:
+        assert st == hawk.HAWK_E_ARG
 
 
 def test_features_follow_their_definition(plan_ctx):
