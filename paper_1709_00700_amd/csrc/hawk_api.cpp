@@ -919,6 +919,7 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
   if (groups < 1 || groups > 0x7FFFFFFF) return set_error(ctx, HAWK_E_ARG, "thread_mult out of range");
   if (grouped) {
     uint32_t llog2 = 0;
+    int32_t reps = 1;
     if (v->agg_strategy == HAWK_LOCAL) {
       uint32_t want = std::max<uint32_t>(4, ceil_log2(static_cast<uint64_t>(X.q->groups_hint) * 2));
       uint32_t fit = 0;
@@ -926,6 +927,9 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
       llog2 = std::min(want, fit);
       if ((int64_t(1) << llog2) * W * 8 > ctx->lds_bytes)
         return set_error(ctx, HAWK_E_INFEASIBLE, "local table does not fit in LDS");
+      // copies of the aggregate words while they fit the budget (up to 16)
+      const int64_t LC = int64_t(1) << llog2;
+      while (reps < 16 && (LC + (W - 1) * (2 * reps) * (LC + 1)) * 8 <= kLdsBudget) reps *= 2;
     }
     // Overflow partitioning: with the local strategy and linear probing, when
     // the LDS table cannot hold every group, rows that miss it are spilled
@@ -939,7 +943,8 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
     while ((int64_t(2) << rlog2) * W * 8 <= kSpillLds) ++rlog2;
     const int64_t nparts = T.log2cap > rlog2 ? int64_t(1) << (T.log2cap - rlog2) : 1;
     const bool spill = v->agg_strategy == HAWK_LOCAL && v->ht == HAWK_LINEAR_PROBING && T.log2cap > llog2 &&
-                       rlog2 >= 6 && nparts >= 2 && (int64_t(1) << llog2) * W * 8 + nparts * 4 <= kSpillLds &&
+                       rlog2 >= 6 && nparts >= 2 &&
+                       ((int64_t(1) << llog2) + (W - 1) * reps * (reps > 1 ? (int64_t(1) << llog2) + 1 : (int64_t(1) << llog2))) * 8 + nparts * 4 <= kSpillLds &&
                        nparts * groups <= (int64_t(1) << 26) && P.nrows > 0 && ctx->lds_bytes >= kSpillLds;
     if (spill) {
       T.rlog2 = rlog2;
@@ -966,7 +971,7 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
       {
         ProfScope ps(ctx, "k_agg");
         HIPCHK(hk_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, llog2, ident, W,
-                      res->d_err, &sp), "aggregation kernel");
+                      res->d_err, &sp, reps), "aggregation kernel");
       }
       {
         ProfScope ps(ctx, "k_scan");
@@ -983,7 +988,7 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
     } else {
       ProfScope ps(ctx, "k_agg");
       HIPCHK(hk_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, llog2, ident, W,
-                    res->d_err), "aggregation kernel");
+                    res->d_err, nullptr, reps), "aggregation kernel");
     }
   } else {
     ProfScope ps(ctx, "k_scalar_agg");

@@ -413,17 +413,18 @@ __device__ __forceinline__ uint64_t group_key(const HkPlan& P, const v16i64& r) 
   return (g0 << 32) | static_cast<uint32_t>(static_cast<int32_t>(r[P.greg[1]]));
 }
 
-// applies one row to the slot whose word j lives at base[j * stride]
+// applies one row to the slot whose word j >= 1 (count, aggregates) lives at
+// w1[(j - 1) * stride]
 template <int PRED, bool LDS, class S>
-__device__ __forceinline__ void agg_apply(uint64_t* base, int64_t stride, const HkPlan& P, const v16i64& r, bool pass) {
-  at_add<LDS>(base + stride, PRED == HK_PRED ? static_cast<uint64_t>(pass) : 1ull);
+__device__ __forceinline__ void agg_apply_w1(uint64_t* w1, int64_t stride, const HkPlan& P, const v16i64& r, bool pass) {
+  at_add<LDS>(w1, PRED == HK_PRED ? static_cast<uint64_t>(pass) : 1ull);
 #pragma unroll
   for (int a = 0; a < S::aggs; ++a) {
     if (a >= P.naggs) break;
     const HkAgg& A = P.aggs[a];
     if (A.fn == HK_COUNT) continue;
     const int64_t x = r[A.reg];
-    uint64_t* w = base + A.word * stride;
+    uint64_t* w = w1 + (A.word - 1) * stride;
     if (A.fn == HK_SUM || A.fn == HK_AVG) {
       // software predication: a dropped row contributes 0 (x * result_increment)
       const int64_t v = PRED == HK_PRED ? (pass ? x : 0) : x;
@@ -437,18 +438,52 @@ __device__ __forceinline__ void agg_apply(uint64_t* base, int64_t stride, const 
   }
 }
 
-// merges an LDS slot (word j at l[j * stride]) into a global slot g
+// applies one row to the slot whose word j lives at base[j * stride]
+template <int PRED, bool LDS, class S>
+__device__ __forceinline__ void agg_apply(uint64_t* base, int64_t stride, const HkPlan& P, const v16i64& r, bool pass) {
+  agg_apply_w1<PRED, LDS, S>(base + stride, stride, P, r, pass);
+}
+
+// folds the words j >= 1 of slot copy b (word j at b[(j - 1) * stride]) into
+// copy a (same layout); both belong to the calling thread
 template <class S>
-__device__ __forceinline__ void agg_merge(uint64_t* g, const uint64_t* l, int64_t stride, const HkPlan& P) {
-  at_add<false>(g + 1, l[stride]);
+__device__ __forceinline__ void agg_fold_w1(uint64_t* a, const uint64_t* b, int64_t stride, const HkPlan& P) {
+  a[0] += b[0];
+#pragma unroll
+  for (int k = 0; k < S::aggs; ++k) {
+    if (k >= P.naggs) break;
+    const HkAgg& A = P.aggs[k];
+    if (A.fn == HK_COUNT) continue;
+    uint64_t* x = a + (A.word - 1) * stride;
+    const uint64_t y = b[(A.word - 1) * stride];
+    if (A.fn == HK_SUM || A.fn == HK_AVG) {
+      if (A.wide) {
+        const uint64_t lo = *x + y;
+        x[stride] += b[A.word * stride] + static_cast<uint64_t>(lo < y);
+        *x = lo;
+      } else {
+        *x += y;
+      }
+    } else if (A.fn == HK_MIN) {
+      *x = static_cast<int64_t>(y) < static_cast<int64_t>(*x) ? y : *x;
+    } else {
+      *x = static_cast<int64_t>(y) > static_cast<int64_t>(*x) ? y : *x;
+    }
+  }
+}
+
+// merges an LDS slot (word j >= 1 at l1[(j - 1) * stride]) into a global slot g
+template <class S>
+__device__ __forceinline__ void agg_merge_w1(uint64_t* g, const uint64_t* l1, int64_t stride, const HkPlan& P) {
+  at_add<false>(g + 1, l1[0]);
 #pragma unroll
   for (int a = 0; a < S::aggs; ++a) {
     if (a >= P.naggs) break;
     const HkAgg& A = P.aggs[a];
     if (A.fn == HK_COUNT) continue;
-    const uint64_t x = l[A.word * stride];
+    const uint64_t x = l1[(A.word - 1) * stride];
     if (A.fn == HK_SUM || A.fn == HK_AVG) {
-      if (A.wide) at_add128_pair<false>(g + A.word, g + A.word + 1, x, static_cast<int64_t>(l[(A.word + 1) * stride]));
+      if (A.wide) at_add128_pair<false>(g + A.word, g + A.word + 1, x, static_cast<int64_t>(l1[A.word * stride]));
       else at_add<false>(g + A.word, x);
     } else if (A.fn == HK_MIN) {
       at_min<false>(g + A.word, static_cast<int64_t>(x));
@@ -456,6 +491,12 @@ __device__ __forceinline__ void agg_merge(uint64_t* g, const uint64_t* l, int64_
       at_max<false>(g + A.word, static_cast<int64_t>(x));
     }
   }
+}
+
+// merges an LDS slot (word j at l[j * stride]) into a global slot g
+template <class S>
+__device__ __forceinline__ void agg_merge(uint64_t* g, const uint64_t* l, int64_t stride, const HkPlan& P) {
+  agg_merge_w1<S>(g, l + stride, stride, P);
 }
 
 // LDS slot lookup/insert for the local strategy; -1 = no slot within bound

@@ -35,7 +35,8 @@ hipError_t hk_sp_concat(hipStream_t st, int64_t* const* tmp, int32_t nproj, int6
 int64_t hk_scan_tmp_words(int64_t m);
 hipError_t hk_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t m, uint32_t* tmp, uint64_t* total);
 
-// grouped aggregation (cuckoo: key phase first), non-grouped aggregation, result extraction
+// grouped aggregation (cuckoo: key phase first; reps: copies of the aggregate
+// words of the LDS table, a power of two), non-grouped aggregation, result extraction
 // sp != null: spill mode of the local strategy with linear probing (LDS misses
 // are appended to sp's regions instead of updating the table); hk_spill step 0
 // then regroups the entries by table region (offs = exclusive scan of sp.hist,
@@ -43,7 +44,7 @@ hipError_t hk_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t m,
 // region of 2^T.rlog2 slots must fit in the launch's LDS)
 hipError_t hk_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
                   int strat, int64_t groups, int32_t wg, uint32_t llog2, const uint64_t* ident, int32_t nw, int* err,
-                  const HkSpill* sp = nullptr);
+                  const HkSpill* sp = nullptr, int32_t reps = 1);
 hipError_t hk_spill(hipStream_t st, int step, const HkPlan& P, const HkAggTable& T, int hash, const HkSpill& sp,
                     const uint32_t* offs, const uint64_t* total, int64_t nwg, uint64_t* part, int* err);
 hipError_t hk_scalar_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,

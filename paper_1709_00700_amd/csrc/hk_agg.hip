@@ -14,21 +14,32 @@
 #error "compile once per shape class with -DHK_SHAPE_CLASS=HkShapeX"
 #endif
 
+// The local table in LDS: keys[LC], then for each word j >= 1 (count,
+// aggregates) `reps` copies of the LC slots, RS words apart (padded by one
+// word when reps > 1 so the copies of a slot sit in different banks). Lane l
+// updates copy l % reps: lanes of one instruction that hit the same group
+// then mostly hit different addresses. The copies are folded before the
+// table is merged into the global table.
 template <int MEM, int PRED, int HT, int HASH, int STRAT, class S, bool SPILL>
 __global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t llog2, HkIdent id, int64_t nwg,
-                                              int* err, HkSpill sp) {
+                                              int* err, HkSpill sp, int32_t reps) {
   // workgroups may come as a 2-D grid (HSA counts grid sizes in work-items as 32-bit values)
   const int64_t wgid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   if (wgid >= nwg) return;  // padding workgroup: leaves before any barrier
   extern __shared__ uint64_t lds[];
   __shared__ uint32_t spill_cursor;
   const int64_t LC = STRAT == HK_LOCAL ? (static_cast<int64_t>(1) << llog2) : 0;
+  const int64_t RS = reps > 1 ? LC + 1 : LC;
+  const int64_t WS = reps * RS;  // from word j to word j + 1 of one copy
+  uint64_t* lw1 = lds + LC;      // word 1 of copy 0 of slot 0
+  const int64_t q = __lane_id() & (reps - 1);
   // spill mode: the partition histogram follows the LDS table
-  uint32_t* hist = reinterpret_cast<uint32_t*>(lds + LC * id.nw);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(lds + LC + (id.nw - 1) * WS);
   uint32_t* cursor = &spill_cursor;
   if (STRAT == HK_LOCAL) {
-    for (int w = 0; w < id.nw; ++w)
-      for (int64_t i = threadIdx.x; i < LC; i += blockDim.x) lds[w * LC + i] = id.w[w];
+    for (int64_t i = threadIdx.x; i < LC; i += blockDim.x) lds[i] = id.w[0];
+    for (int w = 1; w < id.nw; ++w)
+      for (int64_t i = threadIdx.x; i < WS; i += blockDim.x) lw1[(w - 1) * WS + i] = id.w[w];
     if (SPILL) {
       for (int i = threadIdx.x; i < sp.nparts; i += blockDim.x) hist[i] = 0;
       if (threadIdx.x == 0) *cursor = 0;
@@ -53,7 +64,7 @@ __global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t l
       if (STRAT == HK_LOCAL && key != HK_EMPTY) {
         const int32_t s = lslot<HT, HASH>(lds, llog2, P.hash, key);
         if (s >= 0) {
-          agg_apply<PRED, true, S>(lds + s, LC, P, r, pass);
+          agg_apply_w1<PRED, true, S>(lw1 + q * RS + s, WS, P, r, pass);
           done = true;
         }
       }
@@ -119,9 +130,12 @@ __global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t l
     __syncthreads();
     for (int64_t s = threadIdx.x; s < LC; s += blockDim.x) {
       const uint64_t key = lds[s];
-      if (key == HK_EMPTY || lds[LC + s] == 0) continue;
+      if (key == HK_EMPTY) continue;
+      uint64_t* c0 = lw1 + s;
+      for (int32_t c = 1; c < reps; ++c) agg_fold_w1<S>(c0, c0 + c * RS, WS, P);
+      if (c0[0] == 0) continue;  // only predicated rows that did not pass reached this group
       uint64_t* g = gslot<HT, HASH>(T, P.hash, key, err);
-      if (g) agg_merge<S>(g, lds + s, LC, P);
+      if (g) agg_merge_w1<S>(g, c0, WS, P);
     }
     if (SPILL) {
       for (int p = threadIdx.x; p < sp.nparts; p += blockDim.x) sp.hist[static_cast<int64_t>(p) * nwg + wgid] = hist[p];
@@ -218,7 +232,8 @@ __global__ void __launch_bounds__(256) k_agg_keys(HkPlan P, HkAggTable T, int* e
 template <class S>
 hipError_t hk_agg_shape(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
                         int strat, int64_t groups, int32_t wg, uint32_t llog2, const HkIdent& id, int* err,
-                        const HkSpill* sp) {
+                        const HkSpill* sp, int32_t reps) {
+  if (reps < 1 || reps > 64 || (reps & (reps - 1)) != 0) return hipErrorInvalidValue;
   if (ht == HK_CUCKOO) {
     const dim3 gk(hk_grid_for(P.nrows, 256, 8192)), bk(256);
     DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(hash, HS,
@@ -227,7 +242,11 @@ hipError_t hk_agg_shape(hipStream_t st, const HkPlan& P, const HkAggTable& T, in
     if (e != hipSuccess) return e;
   }
   const dim3 g = hk_wg_grid(groups), b(static_cast<uint32_t>(wg));
-  size_t lds = strat == HK_LOCAL ? (static_cast<size_t>(1) << llog2) * id.nw * sizeof(uint64_t) : 0;
+  size_t lds = 0;
+  if (strat == HK_LOCAL) {
+    const size_t LC = static_cast<size_t>(1) << llog2;
+    lds = (LC + (id.nw - 1) * reps * (reps > 1 ? LC + 1 : LC)) * sizeof(uint64_t);
+  }
   if (sp) {
     // spill mode exists for the local strategy with linear probing
     if (strat != HK_LOCAL || ht != HK_LIN) return hipErrorInvalidValue;
@@ -235,14 +254,14 @@ hipError_t hk_agg_shape(hipStream_t st, const HkPlan& P, const HkAggTable& T, in
     const HkSpill S1 = *sp;
     DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(hash, HS,
               hipLaunchKernelGGL((k_agg<M, PR, HK_LIN, HS, HK_LOCAL, S, true>), g, b, lds, st, P, T, llog2, id,
-                                 groups, err, S1))));
+                                 groups, err, S1, reps))));
     return hipGetLastError();
   }
   HkSpill none;
   std::memset(&none, 0, sizeof(none));
   DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS, DISPATCH2(strat, SG,
             hipLaunchKernelGGL((k_agg<M, PR, HT, HS, SG, S, false>), g, b, lds, st, P, T, llog2, id, groups, err,
-                               none))))));
+                               none, reps))))));
   return hipGetLastError();
 }
 
@@ -262,6 +281,7 @@ hipError_t hk_spill_shape(hipStream_t st, int step, const HkPlan& P, const HkAgg
 }
 
 template hipError_t hk_agg_shape<HK_SHAPE_CLASS>(hipStream_t, const HkPlan&, const HkAggTable&, int, int, int, int, int,
-                                                 int64_t, int32_t, uint32_t, const HkIdent&, int*, const HkSpill*);
+                                                 int64_t, int32_t, uint32_t, const HkIdent&, int*, const HkSpill*,
+                                                 int32_t);
 template hipError_t hk_spill_shape<HK_SHAPE_CLASS>(hipStream_t, int, const HkPlan&, const HkAggTable&, int, const HkSpill&,
                                                    const uint32_t*, const uint64_t*, int64_t, uint64_t*, int*);

@@ -3,6 +3,8 @@
 // concatenation of single-pass regions and aggregation result extraction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "hawk_device.h"
 #include "hawk_launch.h"
 
@@ -170,22 +172,45 @@ __global__ void __launch_bounds__(256) k_sp_concat(HkOut tmp, int32_t nproj, int
 }
 
 // ------------------------------------------------------------------ finalize
-__global__ void __launch_bounds__(256) k_finalize(const HkPlan* Pp, HkAggTable T, int64_t nslots, HkResOut O) {
+// Each workgroup takes a contiguous chunk of slots: it counts the chunk's
+// live slots, reserves their result rows with one atomic, then writes them
+// in slot order (wave offsets from a per-round prefix in LDS).
+__global__ void __launch_bounds__(256) k_finalize(const HkPlan* Pp, HkAggTable T, int64_t nslots, int64_t chunk,
+                                                  HkResOut O) {
   const HkPlan& P = *Pp;  // plan in device memory, read where used
   const int64_t W = T.slot_words;
-  for (int64_t base = blockIdx.x * (int64_t)blockDim.x + threadIdx.x - __lane_id(); base < nslots;
-       base += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s = base + __lane_id();
+  const int64_t s0 = blockIdx.x * chunk;
+  const int64_t s1 = s0 + chunk < nslots ? s0 + chunk : nslots;
+  __shared__ uint32_t wcount[256 / WAVE];
+  __shared__ unsigned long long base;
+  const int wave = threadIdx.x / WAVE, nwaves = blockDim.x / WAVE;
+  uint32_t mine = 0;
+  for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) mine += (T.words[s * W + 1] != 0 || O.keep_empty) ? 1u : 0u;
+  for (int off = WAVE / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off, WAVE);
+  if (__lane_id() == 0) wcount[wave] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tot = 0;
+    for (int w = 0; w < nwaves; ++w) tot += wcount[w];
+    base = tot ? atomicAdd(O.nrows, tot) : 0ull;
+  }
+  __syncthreads();
+  unsigned long long pos0 = base;
+  for (int64_t r0 = s0; r0 < s1; r0 += blockDim.x) {
+    const int64_t s = r0 + threadIdx.x;
     const uint64_t* p = T.words + s * W;
-    const bool live = s < nslots && (p[1] != 0 || O.keep_empty);
+    const bool live = s < s1 && (p[1] != 0 || O.keep_empty);
     const uint64_t m = __ballot(live);
-    if (m == 0) continue;
-    unsigned long long start = 0;
-    if (__lane_id() == 0) start = atomicAdd(O.nrows, static_cast<unsigned long long>(__popcll(m)));
-    start = __shfl(start, 0, WAVE);
-    if (!live) continue;
-    const int64_t pos = static_cast<int64_t>(start) + __popcll(m & lanemask_lt());
-    write_group_row(P, p, pos, O);
+    __syncthreads();  // the previous round's offsets are read
+    if (__lane_id() == 0) wcount[wave] = static_cast<uint32_t>(__popcll(m));
+    __syncthreads();
+    unsigned long long before = 0, round = 0;
+    for (int w = 0; w < nwaves; ++w) {
+      if (w < wave) before += wcount[w];
+      round += wcount[w];
+    }
+    if (live) write_group_row(P, p, static_cast<int64_t>(pos0 + before) + __popcll(m & lanemask_lt()), O);
+    pos0 += round;
   }
 }
 
@@ -247,6 +272,9 @@ hipError_t hk_finalize(hipStream_t st, const HkPlan& P, const HkPlan* dP, const 
   O.count = count;
   O.nrows = reinterpret_cast<unsigned long long*>(nrows);
   O.keep_empty = keep_empty;
-  hipLaunchKernelGGL(k_finalize, dim3(hk_grid_for(nslots, 256, 8192)), dim3(256), 0, st, dP, T, nslots, O);
+  if (nslots <= 0) return hipSuccess;
+  const int64_t nwg = std::min<int64_t>(1024, (nslots + 2047) / 2048);
+  const int64_t chunk = (nslots + nwg - 1) / nwg;
+  hipLaunchKernelGGL(k_finalize, dim3(static_cast<uint32_t>(nwg)), dim3(256), 0, st, dP, T, nslots, chunk, O);
   HK_CHECK_LAUNCH();
 }

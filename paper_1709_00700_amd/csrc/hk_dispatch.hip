@@ -10,7 +10,7 @@
 template <class S>
 hipError_t hk_agg_shape(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
                         int strat, int64_t groups, int32_t wg, uint32_t llog2, const HkIdent& id, int* err,
-                        const HkSpill* sp);
+                        const HkSpill* sp, int32_t reps);
 template <class S>
 hipError_t hk_spill_shape(hipStream_t st, int step, const HkPlan& P, const HkAggTable& T, int hash, const HkSpill& sp,
                           const uint32_t* offs, const uint64_t* total, int64_t nwg, uint64_t* part, int* err);
@@ -46,9 +46,9 @@ static HkIdent make_ident(const uint64_t* ident, int32_t nw) {
 
 hipError_t hk_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash, int strat,
                   int64_t groups, int32_t wg, uint32_t llog2, const uint64_t* ident, int32_t nw, int* err,
-                  const HkSpill* sp) {
+                  const HkSpill* sp, int32_t reps) {
   const HkIdent id = make_ident(ident, nw);
-  BY_SHAPE(P, hk_agg_shape<S>(st, P, T, mem, pred, ht, hash, strat, groups, wg, llog2, id, err, sp));
+  BY_SHAPE(P, hk_agg_shape<S>(st, P, T, mem, pred, ht, hash, strat, groups, wg, llog2, id, err, sp, reps));
 }
 
 hipError_t hk_spill(hipStream_t st, int step, const HkPlan& P, const HkAggTable& T, int hash, const HkSpill& sp,
