@@ -51,12 +51,15 @@ WORKLOADS = {
     "c2": ["c2u", "c2z"],
     "c3": ["c3"],
     "c4": ["c4"],
+    "c5": [],
 }
 DESCRIPTION = {
     "c1": "selection+projection: 1M rows, 4 int32 cols uniform [0,1000), a<100 AND 200<=b<700, out int64 c*d+a in row order",
     "c2": "grouped aggregation: 64M rows int32 key + int64 value uniform [0,1e6); 16 uniform groups and zipf(1.1) over 1M ranks; COUNT/SUM/MIN/MAX",
     "c3": "star join: 120M-row fact, 4 int32 FKs into dims 2.5k/200k/30k/80k filtered 20/5/20/1 %, SUM(int64 rev) by (d0.g, d2.g)",
     "c4": "wide scan-aggregate: 600M rows, 6 skewed groups, 8 aggregates incl. exact 128-bit SUM(price*(100-disc)*(100+tax))",
+    "c5": "mixed workload: 256 projection / aggregation / star-join pipelines over windows of 200M-row pools, "
+          "lognormal rows in [1M, 200M], one batched graph launch",
 }
 
 
@@ -131,6 +134,102 @@ def explore(ctx, pipes, mode, timing_db):
                           "best_variant": best.as_dict(), **rep}), flush=True)
 
 
+def run_c5(args):
+    """Mixed workload: every pipeline in one batched graph launch (rows/s of the
+    whole batch); with --pick-quality also the learned per-query picks against
+    exhaustive search and Algorithm 1, on a smaller seeded instance."""
+    import torch
+    from paper_1709_00700_amd import datagen as dg
+    from paper_1709_00700_amd import hawk, optimizer
+
+    pool_rows = args.rows or 200_000_000
+    nq = args.c5_queries
+    ctx = hawk.Context(0)
+    ncu, _ = ctx.device_info()
+    log(f"[bench] c5: generating pools of {pool_rows} rows, {nq} pipelines")
+    pools = dg.c5_pools(pool_rows)
+    qs = dg.c5_queries(nq, pool_rows, min_rows=min(1_000_000, pool_rows), max_rows=pool_rows)
+    hs = optimizer.register_c5(ctx, pools, qs)
+    del pools
+    total_rows = sum(q["rows"] for q in qs)
+    log("[bench] c5: capturing the batch")
+    b = hawk.Batch(ctx, hs)
+    if args.autotune:
+        best, ms = b.autotune(reps=2)
+        log(f"[bench] c5: autotuned schedule {best} ({ms:.3f} ms)")
+    b.run()
+    r = b.result(0)
+    r.info()  # raises if any hash table of the batch overflowed
+    r.free()
+    for _ in range(args.warmup):
+        b.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(ctx.stream)
+    for _ in range(args.steps):
+        b.run()
+    e1.record(ctx.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    out = {"metric": METRIC, "value": total_rows / (ms / 1e3), "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": DESCRIPTION["c5"], "pipelines": nq, "rows_per_step": total_rows,
+                      "pool_rows": pool_rows, "schedule": b.opts(), "compute_units": ncu,
+                      "kinds": {k: sum(1 for q in qs if q["kind"] == k) for k in (1, 2, 3)}},
+           "wall_s_timed": wall}
+    b.free()
+    if args.pick_quality:
+        out["pick_quality"] = c5_pick_quality(ctx, args)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def c5_pick_quality(ctx, args):
+    """Train the cost model on sampled-variant timings of one seeded C5 instance,
+    then compare its per-query picks and Algorithm 1's per-kind variant with the
+    exhaustive best of each query of another instance."""
+    from paper_1709_00700_amd import datagen as dg
+    from paper_1709_00700_amd import hawk, optimizer
+
+    pool = args.pq_pool_rows
+    lim = args.pq_limit_ms
+    seed_train, seed_test = dg.MASTER_SEED + 1005, dg.MASTER_SEED + 5
+    log(f"[bench] pick quality: pools of {pool} rows, {args.pq_train} training / {args.pq_test} test pipelines")
+    tr_pools = dg.c5_pools(pool, seed_train)
+    tr = dg.c5_queries(args.pq_train, pool, seed_train, min_rows=min(10_000, pool), max_rows=pool)
+    tr_h = optimizer.register_c5(ctx, tr_pools, tr, prefix="train_")
+    del tr_pools
+    te_pools = dg.c5_pools(pool, seed_test)
+    te = dg.c5_queries(args.pq_test, pool, seed_test, min_rows=min(10_000, pool), max_rows=pool)
+    te_h = optimizer.register_c5(ctx, te_pools, te, prefix="test_")
+    del te_pools
+    t0 = time.perf_counter()
+    X, y = optimizer.training_set(ctx, tr_h, args.pq_per_query, reps=3, limit_ms=lim, seed=7,
+                                  progress=lambda m: log("[bench] " + m))
+    t_collect = time.perf_counter() - t0
+    log(f"[bench] pick quality: {len(y)} training samples in {t_collect:.1f} s")
+    m = hawk.Model(ctx, seed=1)
+    t0 = time.perf_counter()
+    loss = m.train(X, y, epochs=300, batch=512, lr=3e-3, seed=2)
+    t_train = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    alg1 = optimizer.alg1_per_kind(ctx, te_h, reps=3, limit_ms=lim)
+    t_alg1 = time.perf_counter() - t0
+    log("[bench] pick quality: exhaustive search of the test pipelines")
+    t0 = time.perf_counter()
+    pq = optimizer.pick_quality(ctx, te_h, m, reps=3, limit_ms=lim, alg1=alg1, progress=lambda m: log("[bench] " + m))
+    t_ex = time.perf_counter() - t0
+    pq.update({"training_samples": int(len(y)), "train_mse": loss, "collect_s": t_collect, "train_s": t_train,
+               "alg1_s": t_alg1, "exhaustive_s": t_ex, "pool_rows": pool,
+               "alg1_variants": {str(k): hawk.format_variant(v) for k, (v, _) in alg1.items()},
+               "alg1_evaluated": {str(k): r["evaluated"] for k, (_, r) in alg1.items()}})
+    m.free()
+    return pq
+
+
 def cpu_baseline(workload, budget_s=20.0):
     """The oracle as it stands, single-threaded, on a bounded sample of the workload."""
     import oracle
@@ -166,6 +265,14 @@ def main():
     ap.add_argument("--timing-db", default=None, help="append every exploration measurement to this file")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration)")
+    ap.add_argument("--c5-queries", type=int, default=256)
+    ap.add_argument("--autotune", action="store_true", help="c5: autotune the batch schedule first")
+    ap.add_argument("--pick-quality", action="store_true", help="c5: also evaluate the learned per-query picks")
+    ap.add_argument("--pq-pool-rows", type=int, default=4_000_000)
+    ap.add_argument("--pq-train", type=int, default=64)
+    ap.add_argument("--pq-test", type=int, default=32)
+    ap.add_argument("--pq-per-query", type=int, default=96)
+    ap.add_argument("--pq-limit-ms", type=float, default=100.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build does not run across several GPUs "
@@ -178,6 +285,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.workload == "c5":
+        run_c5(args)
         return
     ctx = hawk.Context(0)
     ncu, _ = ctx.device_info()
