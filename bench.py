@@ -207,7 +207,7 @@ def c5_pick_quality(ctx, args):
     te_h = optimizer.register_c5(ctx, te_pools, te, prefix="test_")
     del te_pools
     t0 = time.perf_counter()
-    X, y = optimizer.training_set(ctx, tr_h, args.pq_per_query, reps=3, limit_ms=lim, seed=7,
+    X, y = optimizer.training_set(ctx, tr_h, args.pq_per_query, reps=2, limit_ms=lim, seed=7,
                                   progress=lambda m: log("[bench] " + m))
     t_collect = time.perf_counter() - t0
     log(f"[bench] pick quality: {len(y)} training samples in {t_collect:.1f} s")
@@ -216,11 +216,11 @@ def c5_pick_quality(ctx, args):
     loss = m.train(X, y, epochs=300, batch=512, lr=3e-3, seed=2)
     t_train = time.perf_counter() - t0
     t0 = time.perf_counter()
-    alg1 = optimizer.alg1_per_kind(ctx, te_h, reps=3, limit_ms=lim)
+    alg1 = optimizer.alg1_per_kind(ctx, te_h, reps=2, limit_ms=lim)
     t_alg1 = time.perf_counter() - t0
     log("[bench] pick quality: exhaustive search of the test pipelines")
     t0 = time.perf_counter()
-    pq = optimizer.pick_quality(ctx, te_h, m, reps=3, limit_ms=lim, alg1=alg1, progress=lambda m: log("[bench] " + m))
+    pq = optimizer.pick_quality(ctx, te_h, m, reps=2, limit_ms=lim, alg1=alg1, progress=lambda m: log("[bench] " + m))
     t_ex = time.perf_counter() - t0
     pq.update({"training_samples": int(len(y)), "train_mse": loss, "collect_s": t_collect, "train_s": t_train,
                "alg1_s": t_alg1, "exhaustive_s": t_ex, "pool_rows": pool,
@@ -268,11 +268,11 @@ def main():
     ap.add_argument("--c5-queries", type=int, default=256)
     ap.add_argument("--autotune", action="store_true", help="c5: autotune the batch schedule first")
     ap.add_argument("--pick-quality", action="store_true", help="c5: also evaluate the learned per-query picks")
-    ap.add_argument("--pq-pool-rows", type=int, default=4_000_000)
-    ap.add_argument("--pq-train", type=int, default=64)
-    ap.add_argument("--pq-test", type=int, default=32)
-    ap.add_argument("--pq-per-query", type=int, default=96)
-    ap.add_argument("--pq-limit-ms", type=float, default=100.0)
+    ap.add_argument("--pq-pool-rows", type=int, default=2_000_000)
+    ap.add_argument("--pq-train", type=int, default=48)
+    ap.add_argument("--pq-test", type=int, default=24)
+    ap.add_argument("--pq-per-query", type=int, default=64)
+    ap.add_argument("--pq-limit-ms", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build does not run across several GPUs "

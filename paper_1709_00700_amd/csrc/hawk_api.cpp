@@ -956,12 +956,13 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
         if (!seen) sp.reg[sp.ncols++] = P.aggs[a].reg;
       }
       sp.ew = 1 + sp.ncols;
-      const int64_t threads = groups * wg;
-      sp.region = (P.nrows + threads - 1) / threads * wg;
+      sp.nrows = P.nrows;
+      sp.bs = wg;
+      sp.coal = v->mem == HAWK_COALESCED ? 1 : 0;
       const int64_t m = nparts * groups;
       uint32_t *offs, *stmp;
       uint64_t *total, *part;
-      ALLOC(sp.buf, uint64_t*, static_cast<size_t>(groups * sp.region * sp.ew) * 8, false);
+      ALLOC(sp.buf, uint64_t*, static_cast<size_t>(P.nrows * sp.ew) * 8, false);
       ALLOC(sp.hist, uint32_t*, static_cast<size_t>(m) * 4, false);
       ALLOC(sp.cnt, uint32_t*, static_cast<size_t>(groups) * 4, false);
       ALLOC(offs, uint32_t*, static_cast<size_t>(m) * 4, false);

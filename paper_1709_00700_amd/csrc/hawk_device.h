@@ -313,6 +313,31 @@ __device__ __forceinline__ bool eval_row(const HkPlan& P, int64_t row, v16i64& r
   return eval_row_f<PRED, HT, HASH, VALUES, S, false>(P, row, none, r);
 }
 
+// true when workgroup `wgid` (nwg workgroups of `bs` threads) owns no row of
+// n under the row mapping of MEM (uniform over the workgroup: it may leave
+// before any barrier)
+template <int MEM>
+__device__ __forceinline__ bool wg_without_rows(int64_t n, int64_t wgid, int64_t nwg, int64_t bs) {
+  const int64_t first = wgid * bs;  // its first thread
+  if (MEM == HK_COAL) return first >= n;
+  const int64_t T = nwg * bs;
+  const int64_t chunk = (n + T - 1) / T;
+  return first * chunk >= n;
+}
+
+// first spill entry of workgroup w: the rows scanned by workgroups before it
+// (closed form of the coalesced and the sequential row mapping), so regions
+// hold exactly the scan's rows in all
+__device__ __forceinline__ int64_t spill_region_start(const HkSpill& sp, int64_t nwg, int64_t w) {
+  const int64_t bs = sp.bs, T = nwg * bs, n = sp.nrows;
+  if (sp.coal) {
+    const int64_t K = n / T, rem = n - K * T;
+    return w * bs * K + (rem < w * bs ? rem : w * bs);
+  }
+  const int64_t chunk = (n + T - 1) / T;
+  return w * bs * chunk < n ? w * bs * chunk : n;
+}
+
 // row range of thread `t` out of `T` for sequential access, chunks rounded to `align`
 __device__ __forceinline__ void seq_range(int64_t n, int64_t t, int64_t T, int64_t align, int64_t& b, int64_t& e) {
   int64_t chunk = (n + T - 1) / T;

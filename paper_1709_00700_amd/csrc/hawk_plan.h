@@ -129,8 +129,10 @@ struct HkAggTable { uint64_t* words; uint32_t log2cap; int32_t slot_words; uint3
 // the one workgroup that owns it, so no row touches the table with
 // device-scope atomics.
 struct HkSpill {
-  uint64_t* buf;              // nwg regions of `region` entries of `ew` words
-  int64_t region;             // entries per workgroup region (rows the workgroup scans, at most)
+  uint64_t* buf;              // one region per workgroup, as many entries as rows it scans (nrows in all)
+  int64_t nrows;              // rows of the scan
+  int32_t bs;                 // threads per workgroup
+  int32_t coal;               // row mapping: 1 coalesced (thread-strided), 0 sequential (chunks)
   uint32_t* hist;             // entry counts per (partition, workgroup), partition-major
   uint32_t* cnt;              // entries per workgroup
   int32_t nparts;             // table regions: 2^(log2cap - rlog2)

@@ -26,6 +26,15 @@ __global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t l
   // workgroups may come as a 2-D grid (HSA counts grid sizes in work-items as 32-bit values)
   const int64_t wgid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   if (wgid >= nwg) return;  // padding workgroup: leaves before any barrier
+  // a workgroup without rows has nothing to aggregate (spill mode: its
+  // histogram column and count are still written, as zeros)
+  if (wg_without_rows<MEM>(P.nrows, wgid, nwg, blockDim.x)) {
+    if (SPILL) {
+      for (int p = threadIdx.x; p < sp.nparts; p += blockDim.x) sp.hist[static_cast<int64_t>(p) * nwg + wgid] = 0;
+      if (threadIdx.x == 0) sp.cnt[wgid] = 0;
+    }
+    return;
+  }
   extern __shared__ uint64_t lds[];
   __shared__ uint32_t spill_cursor;
   const int64_t LC = STRAT == HK_LOCAL ? (static_cast<int64_t>(1) << llog2) : 0;
@@ -53,7 +62,13 @@ __global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t l
   int64_t b, e, step;
   if (MEM == HK_COAL) { b = gt; e = n; step = Tn; }
   else { seq_range(n, gt, Tn, 1, b, e); step = 1; }
-  uint64_t* region = SPILL ? sp.buf + wgid * sp.region * sp.ew : nullptr;
+  int64_t rcap = 0;
+  uint64_t* region = nullptr;
+  if (SPILL) {
+    const int64_t r0 = spill_region_start(sp, nwg, wgid);
+    rcap = spill_region_start(sp, nwg, wgid + 1) - r0;
+    region = sp.buf + r0 * sp.ew;
+  }
   auto row_step = [&](int64_t row, const HkFirst<S>& f) {
     const bool pass = eval_row_f<PRED, HT, HASH, true, S, true>(P, row, f, r);
     bool spill = false;
@@ -90,7 +105,7 @@ __global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t l
         base = __shfl(base, leader, WAVE);
         if (spill) {
           const int64_t pos = static_cast<int64_t>(base) + __popcll(m & lanemask_lt());
-          if (pos < sp.region) {
+          if (pos < rcap) {
             uint64_t* ent = region + pos * sp.ew;
             ent[0] = key;
             for (int j = 0; j < sp.ncols; ++j) ent[1 + j] = static_cast<uint64_t>(r[sp.reg[j]]);
@@ -139,7 +154,7 @@ __global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t l
     }
     if (SPILL) {
       for (int p = threadIdx.x; p < sp.nparts; p += blockDim.x) sp.hist[static_cast<int64_t>(p) * nwg + wgid] = hist[p];
-      if (threadIdx.x == 0) sp.cnt[wgid] = *cursor < sp.region ? *cursor : static_cast<uint32_t>(sp.region);
+      if (threadIdx.x == 0) sp.cnt[wgid] = *cursor < rcap ? *cursor : static_cast<uint32_t>(rcap);
     }
   }
 }
@@ -156,7 +171,7 @@ __global__ void __launch_bounds__(256) k_spill_scatter(HkSpill sp, const uint32_
   for (int p = threadIdx.x; p < sp.nparts; p += blockDim.x) cur[p] = offs[static_cast<int64_t>(p) * nwg + wgid];
   __syncthreads();
   const int64_t cnt = sp.cnt[wgid];
-  const uint64_t* region = sp.buf + wgid * sp.region * sp.ew;
+  const uint64_t* region = sp.buf + spill_region_start(sp, nwg, wgid) * sp.ew;
   for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
     const uint64_t* ent = region + i * sp.ew;
     const uint64_t key = ent[0];

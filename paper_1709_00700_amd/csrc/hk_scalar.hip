@@ -37,6 +37,7 @@ template <int MEM, int PRED, int HT, int HASH, int STRAT, class S>
 __global__ void __launch_bounds__(1024) k_scalar_agg(HkPlan P, HkAggTable T, HkIdent id, int64_t nwg) {
   const int64_t wgid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   if (wgid >= nwg) return;  // padding workgroup of a 2-D grid
+  if (wg_without_rows<MEM>(P.nrows, wgid, nwg, blockDim.x)) return;  // nothing to fold
   __shared__ uint64_t lw[2 + 2 * HK_MAX_AGGS];
   if (STRAT == HK_LOCAL) {
     if (threadIdx.x == 0)

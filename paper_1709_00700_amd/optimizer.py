@@ -90,8 +90,8 @@ def exhaustive(ctx, q, reps: int, limit_ms: float) -> dict:
 def alg1_per_kind(ctx, queries: list, reps: int, limit_ms: float, max_iters: int = 5) -> dict:
     """Algorithm 1 over each kind's sub-workload: {kind: (variant, report)}."""
     out = {}
-    for kind in sorted({q.kind() for q in queries}):
-        W = [q for q in queries if q.kind() == kind]
+    for kind in sorted({q.kind for q in queries}):
+        W = [q for q in queries if q.kind == kind]
         v, rep = hawk.explore(ctx, W, hawk.HAWK_EXPLORE_FEATURE_WISE, reps=reps, max_iters=max_iters,
                               limit_ms=limit_ms)
         out[kind] = (v, rep)
@@ -115,7 +115,7 @@ def pick_quality(ctx, queries: list, model, reps: int, limit_ms: float, alg1: di
         t_pick = table.get(variant_key(q, pv))
         if t_pick is None:
             t_pick = timed(ctx, q, pv, reps, limit_ms)
-        av = alg1[q.kind()][0]
+        av = alg1[q.kind][0]
         t_alg1 = table.get(variant_key(q, av))
         if t_alg1 is None:
             t_alg1 = timed(ctx, q, av, reps, limit_ms)

@@ -1,0 +1,48 @@
+"""GPU check of the learned cost model as a per-query optimizer: trained on
+sampled-variant timings of one seeded mixed workload, its picks on another
+workload's pipelines are compared with each pipeline's exhaustive best and
+with the one variant per kind that Algorithm 1 learns for the workload."""
+import json
+
+import pytest
+
+from gpu_common import say
+from paper_1709_00700_amd import datagen as dg
+from paper_1709_00700_amd import hawk, optimizer
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = hawk.Context(0)
+    yield c
+    c.close()
+
+
+def test_learned_picks_beat_algorithm1_per_workload(ctx):
+    pool, lim = 2_000_000, 10.0
+    seed_train, seed_test = dg.MASTER_SEED + 1005, dg.MASTER_SEED + 5
+    tr_pools = dg.c5_pools(pool, seed_train)
+    tr = dg.c5_queries(40, pool, seed_train, min_rows=10_000, max_rows=pool)
+    tr_h = optimizer.register_c5(ctx, tr_pools, tr, prefix="train_")
+    te_pools = dg.c5_pools(pool, seed_test)
+    te = dg.c5_queries(16, pool, seed_test, min_rows=10_000, max_rows=pool)
+    te_h = optimizer.register_c5(ctx, te_pools, te, prefix="test_")
+    say("collecting training timings")
+    X, y = optimizer.training_set(ctx, tr_h, 64, reps=2, limit_ms=lim, seed=7, progress=say)
+    m = hawk.Model(ctx, seed=1)
+    loss = m.train(X, y, epochs=300, batch=512, lr=3e-3, seed=2)
+    say("training mse", loss)
+    alg1 = optimizer.alg1_per_kind(ctx, te_h, reps=2, limit_ms=lim)
+    pq = optimizer.pick_quality(ctx, te_h, m, reps=2, limit_ms=lim, alg1=alg1, progress=say)
+    say(json.dumps({k: pq[k] for k in ("model", "alg1")}))
+    assert pq["model"]["pruned_picks"] == 0
+    # per-query picks from the model are closer to each pipeline's best than
+    # one learned variant per kind, on the geometric mean and in total
+    assert pq["model"]["geomean_ratio"] < pq["alg1"]["geomean_ratio"]
+    assert pq["model"]["total_ratio"] < pq["alg1"]["total_ratio"]
+    assert pq["model"]["geomean_ratio"] < 1.3
+    m.free()
