@@ -36,9 +36,9 @@ METRIC = "input rows/s + HBM GB/s per pipeline; learned-pick vs best-variant run
 DEFAULT_VARIANTS = {
     "c1": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=1024, wg_size=256),
     "c2u": dict(proj_strategy=1, mem=1, pred=1, ht=0, hash=1, agg_strategy=0, thread_mult=8, wg_size=512),
-    "c2z": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=8, wg_size=512),
-    "c3": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=8, wg_size=256),
-    "c4": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=8, wg_size=256),
+    "c2z": dict(proj_strategy=1, mem=1, pred=1, ht=0, hash=1, agg_strategy=0, thread_mult=1, wg_size=1024),
+    "c3": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=1, agg_strategy=0, thread_mult=8, wg_size=512),
+    "c4": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=1, agg_strategy=0, thread_mult=64, wg_size=256),
 }
 
 # algorithmic bytes read per input row of each pipeline (columns the
@@ -124,12 +124,12 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_calibration_bytes": n * 8, "copies": 4}), flush=True)
 
 
-def explore(ctx, pipes, mode, timing_db):
+def explore(ctx, pipes, mode, timing_db, args_limit_ms):
     from paper_1709_00700_amd import hawk
     m = hawk.HAWK_EXPLORE_EXHAUSTIVE if mode == "exhaustive" else hawk.HAWK_EXPLORE_FEATURE_WISE
     for name, q, v, nrows in pipes:
         log(f"[bench] exploring {name} ({mode})")
-        best, rep = hawk.explore(ctx, [q], m, reps=3, max_iters=5, limit_ms=1000.0, timing_db=timing_db)
+        best, rep = hawk.explore(ctx, [q], m, reps=2, max_iters=5, limit_ms=args_limit_ms, timing_db=timing_db)
         print(json.dumps({"explore": name, "mode": mode, "rows": nrows, "best": hawk.format_variant(best),
                           "best_variant": best.as_dict(), **rep}), flush=True)
 
@@ -263,6 +263,7 @@ def main():
     ap.add_argument("--explore", choices=["exhaustive", "feature_wise"], default=None,
                     help="run the variant optimizer on each pipeline instead of the timed steps")
     ap.add_argument("--timing-db", default=None, help="append every exploration measurement to this file")
+    ap.add_argument("--explore-limit-ms", type=float, default=200.0, help="pruning limit of the exploration")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration)")
     ap.add_argument("--c5-queries", type=int, default=256)
@@ -304,7 +305,7 @@ def main():
         del tables
     stream = ctx.stream
     if args.explore:
-        explore(ctx, pipes, args.explore, args.timing_db)
+        explore(ctx, pipes, args.explore, args.timing_db, args.explore_limit_ms)
         ctx.close()
         return
 
