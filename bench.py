@@ -268,6 +268,7 @@ def main():
     ap.add_argument("--explore-limit-ms", type=float, default=200.0, help="pruning limit of the exploration")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration)")
+    ap.add_argument("--no-jit", action="store_true", help="use only the kernels compiled ahead of time")
     ap.add_argument("--c5-queries", type=int, default=256)
     ap.add_argument("--autotune", action="store_true", help="c5: autotune the batch schedule first")
     ap.add_argument("--pick-quality", action="store_true", help="c5: also evaluate the learned per-query picks")
@@ -293,6 +294,8 @@ def main():
         run_c5(args)
         return
     ctx = hawk.Context(0)
+    if not args.no_jit and not args.explore:
+        ctx.set_jit(True)  # aggregation kernels compiled for each plan structure during the warm-up
     ncu, _ = ctx.device_info()
     pipes = []
     total_rows = 0
@@ -379,7 +382,9 @@ def main():
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "int64", "data": "synthetic",
            "config": {"workload": DESCRIPTION[args.workload], "pipelines": [p[0] for p in pipes],
-                      "rows_per_step": total_rows, "compute_units": ncu},
+                      "rows_per_step": total_rows, "compute_units": ncu,
+                      "codegen": dict(zip(("run_time_kernels", "compile_ms"), ctx.jit_stats()),
+                                      run_time=not args.no_jit)},
            "roofline": roofline, "per_pipeline": per, "wall_s_timed": wall}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

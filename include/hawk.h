@@ -233,6 +233,24 @@ typedef struct {
 hawk_status hawk_explore(hawk_ctx* ctx, hawk_query* const* W, int32_t k, int32_t mode,
                          const hawk_explore_opts* opts, hawk_variant* best, hawk_explore_report* rep);
 
+/* ------------------------------------------------------------ run-time code generation */
+/* When on, grouped aggregation with linear probing runs a kernel compiled at
+   run time (hipRTC, gfx950) for the plan's structure: column types and
+   registers, filter and probe registers, arithmetic operators, group and
+   aggregate layout are constants of the generated code, as in the paper's
+   per-query code generation (Section 7); column pointers, filter bounds,
+   arithmetic constants, join tables, hash seeds and the row count stay
+   arguments, so queries of one structure share a kernel. The first execution
+   of a (structure, variant) pair compiles it (about a second); kernels are
+   cached in the context until hawk_ctx_destroy. Off by default: every other
+   path, and this one when off, uses the kernels compiled ahead of time.
+   Errors: HAWK_E_ARG, HAWK_E_DEVICE (planning context). A compilation
+   failure is reported by the execution as HAWK_E_DEVICE with the compiler
+   log in hawk_last_error. */
+hawk_status hawk_ctx_set_jit(hawk_ctx* ctx, int32_t on);
+/* Kernels compiled so far and their total compile time. */
+hawk_status hawk_jit_stats(const hawk_ctx* ctx, int64_t* kernels, double* compile_ms);
+
 /* ------------------------------------------------------------ kernel profiling */
 /* When on, every launch of the library's kernel families is bracketed by HIP
    events on the context stream (adds two event records per launch). Enabling

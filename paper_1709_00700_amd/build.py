@@ -13,7 +13,10 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhawk.so")
 
-SOURCES = ["hk_batch.hip", "hk_common.hip", "hk_dispatch.hip", "hk_mlp.hip", "hawk_api.cpp", "hawk_explore.cpp", "hawk_model.cpp", "hawk_batch.cpp"]
+SOURCES = ["hk_batch.hip", "hk_common.hip", "hk_dispatch.hip", "hk_mlp.hip", "hawk_api.cpp", "hawk_explore.cpp",
+           "hawk_model.cpp", "hawk_batch.cpp", "hawk_jit.cpp"]
+# device headers embedded into the library for run-time compilation (hawk_jit.cpp)
+EMBEDDED = [("kSrcPlan", "hawk_plan.h"), ("kSrcDevice", "hawk_device.h"), ("kSrcAggBody", "hk_agg_body.h")]
 # kernel families compiled once per shape class (see HkShape in hawk_plan.h)
 SHAPED = ["hk_agg.hip", "hk_proj.hip", "hk_scalar.hip"]
 SHAPES = ["A", "F", "J", "W", "G"]
@@ -21,7 +24,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off (no fp32 math on the hot path needs them)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+         "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", OBJ]
 
 
 def _compile(job) -> str:
@@ -38,13 +41,29 @@ def _compile(job) -> str:
     return obj
 
 
+def _embed_headers() -> None:
+    """Writes hk_jit_sources.inc: each embedded header as a raw string literal."""
+    out = []
+    for var, name in EMBEDDED:
+        with open(os.path.join(CSRC, name)) as f:
+            text = f.read()
+        if ')HKSRC"' in text:
+            raise RuntimeError(f"{name} contains the raw-string delimiter")
+        out.append(f'const char {var}[] = R"HKSRC({text})HKSRC";\n')
+    path = os.path.join(OBJ, "hk_jit_sources.inc")
+    with open(path + ".tmp", "w") as f:
+        f.write("".join(out))
+    os.replace(path + ".tmp", path)
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
+    _embed_headers()
     jobs = SOURCES[:1] + [(s, sh) for s in SHAPED for sh in SHAPES] + SOURCES[1:]  # longest first
     with ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, 16, len(jobs))) as ex:
         objs = list(ex.map(_compile, jobs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lhiprtc"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")

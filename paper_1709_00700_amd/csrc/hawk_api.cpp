@@ -96,7 +96,12 @@ hawk_status set_error(hawk_ctx* ctx, hawk_status st, const std::string& msg) {
 }
 
 static hawk_status hip_error(hawk_ctx* ctx, hipError_t e, const char* where) {
-  return set_error(ctx, HAWK_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+  std::string msg = std::string(where) + ": " + hipGetErrorString(e);
+  if (!ctx->jit_cache.last_error.empty()) {
+    msg += " (" + ctx->jit_cache.last_error + ")";
+    ctx->jit_cache.last_error.clear();
+  }
+  return set_error(ctx, HAWK_E_DEVICE, msg);
 }
 
 // ------------------------------------------------------------------ kernel profiling
@@ -216,6 +221,7 @@ extern "C" void hawk_ctx_destroy(hawk_ctx* ctx) {
     return;
   }
   ctx->pool.release_all();
+  ctx->jit_cache.release();
   prof_clear(ctx);
   for (hipEvent_t e : ctx->prof_free) (void)hipEventDestroy(e);
   (void)hipEventDestroy(ctx->ev0);
@@ -225,6 +231,20 @@ extern "C" void hawk_ctx_destroy(hawk_ctx* ctx) {
 }
 
 extern "C" const char* hawk_last_error(const hawk_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" hawk_status hawk_ctx_set_jit(hawk_ctx* ctx, int32_t on) {
+  if (!ctx) return HAWK_E_ARG;
+  if (ctx->device < 0 && on) return set_error(ctx, HAWK_E_DEVICE, "planning context cannot execute");
+  ctx->jit = on != 0;
+  return HAWK_OK;
+}
+
+extern "C" hawk_status hawk_jit_stats(const hawk_ctx* ctx, int64_t* kernels, double* compile_ms) {
+  if (!ctx) return HAWK_E_ARG;
+  if (kernels) *kernels = ctx->jit_cache.compiled;
+  if (compile_ms) *compile_ms = ctx->jit_cache.compile_ms;
+  return HAWK_OK;
+}
 
 extern "C" hawk_status hawk_device_info(const hawk_ctx* ctx, int32_t* num_cus, int64_t* lds_bytes) {
   if (!ctx) return HAWK_E_ARG;
@@ -885,6 +905,25 @@ void identity_words(const HkPlan& P, bool grouped, uint64_t* w) {
   }
 }
 
+// grouped-aggregation launch: the kernel specialised for the plan when the
+// context compiles at run time (linear probing), else the precompiled one
+hipError_t agg_launch(Exec& X, const HkPlan& P, const HkAggTable& T, int64_t groups, int32_t wg, uint32_t llog2,
+                      const uint64_t* ident, int32_t W, const HkSpill* sp, int32_t reps) {
+  const hawk_variant* v = X.v;
+  if (X.ctx->jit && v->ht == HAWK_LINEAR_PROBING) {
+    HkIdent id = {};
+    for (int i = 0; i < W; ++i) id.w[i] = ident[i];
+    id.nw = W;
+    std::string msg;
+    const hipError_t e = jit_agg_launch(X.ctx->jit_cache, msg, X.st, P, T, v->mem, v->pred, v->hash, v->agg_strategy,
+                                        groups, wg, llog2, id, X.res->d_err, sp, reps);
+    if (e != hipSuccess && !msg.empty()) X.ctx->jit_cache.last_error = msg;
+    return e;
+  }
+  return hk_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, llog2, ident, W,
+                X.res->d_err, sp, reps);
+}
+
 hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
   hawk_ctx* ctx = X.ctx;
   const hawk_variant* v = X.v;
@@ -971,8 +1010,7 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
       ALLOC(part, uint64_t*, static_cast<size_t>(P.nrows * sp.ew) * 8, false);
       {
         ProfScope ps(ctx, "k_agg");
-        HIPCHK(hk_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, llog2, ident, W,
-                      res->d_err, &sp, reps), "aggregation kernel");
+        HIPCHK(agg_launch(X, P, T, groups, wg, llog2, ident, W, &sp, reps), "aggregation kernel");
       }
       {
         ProfScope ps(ctx, "k_scan");
@@ -988,8 +1026,7 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
       }
     } else {
       ProfScope ps(ctx, "k_agg");
-      HIPCHK(hk_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, llog2, ident, W,
-                    res->d_err, nullptr, reps), "aggregation kernel");
+      HIPCHK(agg_launch(X, P, T, groups, wg, llog2, ident, W, nullptr, reps), "aggregation kernel");
     }
   } else {
     ProfScope ps(ctx, "k_scalar_agg");

@@ -3,7 +3,9 @@
 // join-table probe/insert, per-row pipeline evaluation, aggregation-table
 // slot lookup and updates.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 
 #include "hawk_plan.h"
 
@@ -592,6 +594,7 @@ __device__ __forceinline__ void write_group_row(const HkPlan& P, const uint64_t*
 }
 
 // ------------------------------------------------------------------ host-side launch helpers
+#ifndef __HIPCC_RTC__
 #define DISPATCH2(v, NAME, ...) \
   do {                          \
     if (v) {                    \
@@ -615,3 +618,4 @@ static inline int64_t hk_grid_for(int64_t work, int64_t block, int64_t cap) {
   if (g < 1) g = 1;
   return g < cap ? g : cap;
 }
+#endif  // __HIPCC_RTC__

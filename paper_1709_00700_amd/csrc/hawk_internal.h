@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "hawk.h"
+#include "hawk_jit.h"
 #include "hawk_plan.h"
 
 // Device memory pool of the context: blocks are hipMalloc'ed once and reused
@@ -37,6 +38,8 @@ struct hawk_ctx {
   DevicePool pool;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   void* dummy = nullptr;  // 256 zero bytes in device memory: the column of a plan's unused column slots
+  bool jit = false;       // grouped aggregation runs kernels specialised at run time for the plan
+  JitCache jit_cache;
   // live handles; destroying the context releases their device state and
   // orphans them (their *_free then only releases host memory)
   std::set<struct hawk_query*> queries;

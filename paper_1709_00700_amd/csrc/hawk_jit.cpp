@@ -1,0 +1,132 @@
+// Run-time specialisation of the grouped-aggregation kernel (see hawk_jit.h).
+#include "hawk_jit.h"
+
+#include <hip/hiprtc.h>
+
+#include <chrono>
+#include <cstring>
+#include <sstream>
+
+#include "hawk_device.h"
+#include "hawk_launch.h"
+
+namespace {
+
+// the device headers, embedded at build time (raw string literals)
+#include "hk_jit_sources.inc"
+
+void emit_col(std::ostringstream& o, const char* arr, int c, const HkCol& col) {
+  o << "  P." << arr << "[" << c << "].ptr = Prt." << arr << "[" << c << "].ptr; P." << arr << "[" << c
+    << "].dtype = " << col.dtype << "; P." << arr << "[" << c << "].reg = " << col.reg << ";\n";
+}
+
+}  // namespace
+
+void JitCache::release() {
+  for (auto& k : kernels) (void)hipModuleUnload(k.second.module);
+  kernels.clear();
+}
+
+std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash, int strat, bool spill) {
+  std::ostringstream o;
+  o << "#include \"hk_agg_body.h\"\n"
+       "extern \"C\" __global__ void __launch_bounds__(1024) hk_jit_agg(HkPlan Prt, HkAggTable T, uint32_t llog2,\n"
+       "    HkIdent id, int64_t nwg, int* err, HkSpill sp, int32_t reps) {\n"
+       "  HkPlan P;\n"
+       "  P.nrows = Prt.nrows;\n  P.hash = Prt.hash;\n";
+  o << "  P.ncolA = " << P.ncolA << "; P.ncolB = " << P.ncolB << "; P.ncolC = " << P.ncolC
+    << "; P.nfilters = " << P.nfilters << ";\n";
+  for (int c = 0; c < P.ncolA; ++c) emit_col(o, "colA", c, P.colA[c]);
+  for (int c = 0; c < P.ncolB; ++c) emit_col(o, "colB", c, P.colB[c]);
+  for (int c = 0; c < P.ncolC; ++c) emit_col(o, "colC", c, P.colC[c]);
+  for (int f = 0; f < P.nfilters; ++f)
+    o << "  P.filters[" << f << "].lo = Prt.filters[" << f << "].lo; P.filters[" << f << "].hi = Prt.filters[" << f
+      << "].hi; P.filters[" << f << "].reg = " << P.filters[f].reg << ";\n";
+  o << "  P.nprobes = " << P.nprobes << "; P.narith = " << P.narith << "; P.ngroup = " << P.ngroup
+    << "; P.naggs = " << P.naggs << ";\n";
+  for (int p = 0; p < P.nprobes; ++p)
+    o << "  P.probes[" << p << "].t = Prt.probes[" << p << "].t; P.probes[" << p << "].fk_reg = " << P.probes[p].fk_reg
+      << "; P.probes[" << p << "].pay_reg = " << P.probes[p].pay_reg << ";\n";
+  for (int k = 0; k < P.narith; ++k) {
+    const HkArith& A = P.arith[k];
+    o << "  P.arith[" << k << "].cx = Prt.arith[" << k << "].cx; P.arith[" << k << "].cy = Prt.arith[" << k
+      << "].cy; P.arith[" << k << "].op = " << int(A.op) << "; P.arith[" << k << "].dst = " << int(A.dst)
+      << "; P.arith[" << k << "].x = " << int(A.x) << "; P.arith[" << k << "].y = " << int(A.y) << "; P.arith[" << k
+      << "].xc = " << int(A.xc) << "; P.arith[" << k << "].yc = " << int(A.yc) << ";\n";
+  }
+  o << "  P.greg[0] = " << P.greg[0] << "; P.greg[1] = " << P.greg[1] << ";\n";
+  for (int a = 0; a < P.naggs; ++a) {
+    const HkAgg& A = P.aggs[a];
+    o << "  P.aggs[" << a << "].fn = " << int(A.fn) << "; P.aggs[" << a << "].wide = " << int(A.wide) << "; P.aggs["
+      << a << "].reg = " << int(A.reg) << "; P.aggs[" << a << "].word = " << A.word << ";\n";
+  }
+  o << "  P.nproj = 0;\n  P.slot_words = " << P.slot_words << ";\n";
+  o << "  agg_body<" << mem << ", " << pred << ", " << ht << ", " << hash << ", " << strat << ", HkShape<" << P.ncolA
+    << ", " << P.nfilters << ", " << P.ncolB << ", " << P.nprobes << ", " << P.ncolC << ", " << P.narith << ", "
+    << P.naggs << ", 0>, " << (spill ? "true" : "false") << ">(P, T, llog2, id, nwg, err, sp, reps);\n}\n";
+  return o.str();
+}
+
+hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P,
+                          const HkAggTable& T, int mem, int pred, int hash, int strat, int64_t groups, int32_t wg,
+                          uint32_t llog2, const HkIdent& id, int* err, const HkSpill* sp, int32_t reps) {
+  const std::string src = jit_agg_source(P, mem, pred, HK_LIN, hash, strat, sp != nullptr);
+  auto it = cache.kernels.find(src);
+  if (it == cache.kernels.end()) {
+    const auto t0 = std::chrono::steady_clock::now();
+    hiprtcProgram prog;
+    const char* hs[] = {kSrcPlan, kSrcDevice, kSrcAggBody};
+    const char* hn[] = {"hawk_plan.h", "hawk_device.h", "hk_agg_body.h"};
+    if (hiprtcCreateProgram(&prog, src.c_str(), "hk_jit_agg.hip", 3, hs, hn) != HIPRTC_SUCCESS) {
+      err_msg = "hipRTC: program creation failed";
+      return hipErrorInvalidValue;
+    }
+    const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                          "-packed-fp32-ops"};
+    const hiprtcResult r = hiprtcCompileProgram(prog, 7, opts);
+    if (r != HIPRTC_SUCCESS) {
+      size_t ls = 0;
+      (void)hiprtcGetProgramLogSize(prog, &ls);
+      std::string log(ls, '\0');
+      if (ls) (void)hiprtcGetProgramLog(prog, &log[0]);
+      (void)hiprtcDestroyProgram(&prog);
+      err_msg = std::string("hipRTC: ") + hiprtcGetErrorString(r) + ": " + log.substr(0, 2000);
+      return hipErrorInvalidValue;
+    }
+    size_t cs = 0;
+    (void)hiprtcGetCodeSize(prog, &cs);
+    std::vector<char> code(cs);
+    (void)hiprtcGetCode(prog, code.data());
+    (void)hiprtcDestroyProgram(&prog);
+    JitKernel k{};
+    hipError_t e = hipModuleLoadData(&k.module, code.data());
+    if (e != hipSuccess) {
+      err_msg = "module load of the specialised kernel failed";
+      return e;
+    }
+    e = hipModuleGetFunction(&k.fn, k.module, "hk_jit_agg");
+    if (e != hipSuccess) {
+      (void)hipModuleUnload(k.module);
+      err_msg = "specialised kernel not found in its module";
+      return e;
+    }
+    cache.compile_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    ++cache.compiled;
+    it = cache.kernels.emplace(src, k).first;
+  }
+  HkSpill none;
+  std::memset(&none, 0, sizeof(none));
+  HkPlan Pa = P;
+  HkAggTable Ta = T;
+  HkIdent ida = id;
+  HkSpill spa = sp ? *sp : none;
+  int64_t nwg = groups;
+  int* erra = err;
+  uint32_t ll = llog2;
+  int32_t rp = reps;
+  void* args[] = {&Pa, &Ta, &ll, &ida, &nwg, &erra, &spa, &rp};
+  const dim3 g = hk_wg_grid(groups);
+  const size_t lds = hk_agg_lds_bytes(strat, llog2, id.nw, reps, sp);
+  return hipModuleLaunchKernel(it->second.fn, g.x, g.y, 1, static_cast<uint32_t>(wg), 1, 1,
+                               static_cast<uint32_t>(lds), st, args, nullptr);
+}

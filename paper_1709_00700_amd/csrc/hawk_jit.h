@@ -1,0 +1,33 @@
+// Run-time specialisation of the grouped-aggregation kernel for one plan
+// structure (the variant generation of Section 7, done with hipRTC): the
+// kernel body of hk_agg_body.h is compiled with the plan's structure
+// (column types and registers, operators, aggregates, counts) as constants,
+// while data that differs between queries of one structure (column
+// pointers, filter bounds, arithmetic constants, join tables, hash seeds,
+// row count) stays a kernel argument. Kernels are cached per context by
+// their generated source.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "hawk_plan.h"
+
+struct JitKernel { hipModule_t module; hipFunction_t fn; };
+struct JitCache {
+  std::map<std::string, JitKernel> kernels;
+  int64_t compiled = 0;
+  double compile_ms = 0;
+  std::string last_error;  // compiler log of the last failed compilation
+  void release();
+};
+
+// Generated source of the specialised kernel `hk_jit_agg` for (P, variant).
+std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash, int strat, bool spill);
+// Compiles (or finds) and launches the specialised kernel; same arguments and
+// launch shape as the ahead-of-time k_agg. Linear probing only.
+hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P,
+                          const HkAggTable& T, int mem, int pred, int hash, int strat, int64_t groups, int32_t wg,
+                          uint32_t llog2, const HkIdent& id, int* err, const HkSpill* sp, int32_t reps);

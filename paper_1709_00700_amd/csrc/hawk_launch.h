@@ -45,6 +45,17 @@ hipError_t hk_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t m,
 hipError_t hk_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
                   int strat, int64_t groups, int32_t wg, uint32_t llog2, const uint64_t* ident, int32_t nw, int* err,
                   const HkSpill* sp = nullptr, int32_t reps = 1);
+// dynamic LDS bytes of one aggregation workgroup (local table, its copies,
+// the spill histogram)
+inline size_t hk_agg_lds_bytes(int strat, uint32_t llog2, int32_t nw, int32_t reps, const HkSpill* sp) {
+  size_t lds = 0;
+  if (strat == HK_LOCAL) {
+    const size_t LC = static_cast<size_t>(1) << llog2;
+    lds = (LC + static_cast<size_t>(nw - 1) * reps * (reps > 1 ? LC + 1 : LC)) * sizeof(uint64_t);
+  }
+  if (sp) lds += static_cast<size_t>(sp->nparts) * sizeof(uint32_t);
+  return lds;
+}
 hipError_t hk_spill(hipStream_t st, int step, const HkPlan& P, const HkAggTable& T, int hash, const HkSpill& sp,
                     const uint32_t* offs, const uint64_t* total, int64_t nwg, uint64_t* part, int* err);
 hipError_t hk_scalar_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,

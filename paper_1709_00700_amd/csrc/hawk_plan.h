@@ -6,7 +6,21 @@
 // Section 9.2 is a template parameter of the kernels; everything the query
 // itself decides is data in this struct.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <stdint.h>
+#else
+// compiled at run time (hipRTC): fixed-width types come from the runtime's own header
+typedef __hip_internal::int8_t int8_t;
+typedef __hip_internal::uint8_t uint8_t;
+typedef __hip_internal::int32_t int32_t;
+typedef __hip_internal::uint32_t uint32_t;
+typedef __hip_internal::int64_t int64_t;
+typedef __hip_internal::uint64_t uint64_t;
+#ifndef INT64_MAX
+#define INT64_MAX 9223372036854775807LL
+#define INT64_MIN (-INT64_MAX - 1)
+#endif
+#endif
 
 #define HK_NREG 16
 #define HK_MAX_COLS_A 6          // columns loaded before the filters

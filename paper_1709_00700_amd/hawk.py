@@ -44,7 +44,7 @@ EXPORTS = [
     "hawk_model_create", "hawk_model_free", "hawk_model_set_params", "hawk_model_get_params",
     "hawk_model_train", "hawk_model_predict", "hawk_mlp_forward_dev", "hawk_mlp_grad_dev", "hawk_model_pick",
     "hawk_batch_create", "hawk_batch_free", "hawk_batch_run", "hawk_batch_time", "hawk_batch_autotune",
-    "hawk_batch_opts_get", "hawk_batch_result",
+    "hawk_batch_opts_get", "hawk_batch_result", "hawk_ctx_set_jit", "hawk_jit_stats",
 ]
 
 
@@ -169,6 +169,8 @@ def L():
             "hawk_batch_autotune": ([vp, i32, P(hawk_batch_opts), P(ctypes.c_double)], i32),
             "hawk_batch_opts_get": ([vp, P(hawk_batch_opts)], i32),
             "hawk_batch_result": ([vp, i32, P(vp)], i32),
+            "hawk_ctx_set_jit": ([vp, i32], i32),
+            "hawk_jit_stats": ([vp, P(i64), P(ctypes.c_double)], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -232,6 +234,16 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_jit(self, on: bool = True):
+        """Run-time compiled aggregation kernels for each plan structure (see hawk.h)."""
+        check(L().hawk_ctx_set_jit(self.handle, int(on)), self.handle)
+
+    def jit_stats(self):
+        """(kernels compiled, total compile milliseconds)."""
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        check(L().hawk_jit_stats(self.handle, ctypes.byref(n), ctypes.byref(ms)), self.handle)
+        return n.value, ms.value
 
     def device_info(self):
         n, lds = ctypes.c_int32(), ctypes.c_int64()
