@@ -95,7 +95,7 @@ TRAFFIC = {
 
 def kernel_sources_sha(kernel):
     import hashlib
-    files = {"k_agg": ["hk_agg.hip", "hawk_device.h", "hawk_plan.h"]}.get(kernel, [])
+    files = {"k_agg": ["hk_agg.hip", "hk_agg_body.h", "hawk_jit.cpp", "hawk_device.h", "hawk_plan.h"]}.get(kernel, [])
     if not files:
         return None
     h = hashlib.sha256()
