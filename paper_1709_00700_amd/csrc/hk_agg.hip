@@ -22,11 +22,14 @@ __global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t l
 }
 
 // spill, step 2: each workgroup moves its region's entries to their
-// partitions (offsets = exclusive scan of the partition-major histogram)
+// partitions (offsets = exclusive scan of the partition-major histogram).
+// Each thread handles SU entries per round: their loads are all issued before
+// the first cursor update; two-word entries move as one 16-byte store.
+#define SPILL_SU 4
 template <int HASH>
-__global__ void __launch_bounds__(256) k_spill_scatter(HkSpill sp, const uint32_t* __restrict__ offs, int64_t nwg,
-                                                       HkHash h, uint32_t log2cap, uint32_t rlog2,
-                                                       uint64_t* __restrict__ out) {
+__global__ void __launch_bounds__(1024) k_spill_scatter(HkSpill sp, const uint32_t* __restrict__ offs, int64_t nwg,
+                                                        HkHash h, uint32_t log2cap, uint32_t rlog2,
+                                                        uint64_t* __restrict__ out) {
   const int64_t wgid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   if (wgid >= nwg) return;
   extern __shared__ uint32_t cur[];
@@ -34,13 +37,32 @@ __global__ void __launch_bounds__(256) k_spill_scatter(HkSpill sp, const uint32_
   __syncthreads();
   const int64_t cnt = sp.cnt[wgid];
   const uint64_t* region = sp.buf + spill_region_start(sp, nwg, wgid) * sp.ew;
+  const int64_t stride = static_cast<int64_t>(blockDim.x) * SPILL_SU;
+  if (sp.ew == 2) {
+    const ulonglong2* src = reinterpret_cast<const ulonglong2*>(region);
+    ulonglong2* dst = reinterpret_cast<ulonglong2*>(out);
+    for (int64_t i0 = threadIdx.x; i0 < cnt; i0 += stride) {
+      ulonglong2 v[SPILL_SU];
+#pragma unroll
+      for (int u = 0; u < SPILL_SU; ++u) {
+        const int64_t i = i0 + u * static_cast<int64_t>(blockDim.x);
+        if (i < cnt) v[u] = src[i];
+      }
+#pragma unroll
+      for (int u = 0; u < SPILL_SU; ++u) {
+        const int64_t i = i0 + u * static_cast<int64_t>(blockDim.x);
+        if (i < cnt) dst[atomicAdd(&cur[hslot<HASH>(v[u].x, h.a[0], log2cap) >> rlog2], 1u)] = v[u];
+      }
+    }
+    return;
+  }
   for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
     const uint64_t* ent = region + i * sp.ew;
     const uint64_t key = ent[0];
     const uint32_t pos = atomicAdd(&cur[hslot<HASH>(key, h.a[0], log2cap) >> rlog2], 1u);
-    uint64_t* dst = out + static_cast<int64_t>(pos) * sp.ew;
-    dst[0] = key;
-    for (int j = 0; j < sp.ncols; ++j) dst[1 + j] = ent[1 + j];
+    uint64_t* d = out + static_cast<int64_t>(pos) * sp.ew;
+    d[0] = key;
+    for (int j = 0; j < sp.ncols; ++j) d[1 + j] = ent[1 + j];
   }
 }
 
@@ -49,7 +71,7 @@ __global__ void __launch_bounds__(256) k_spill_scatter(HkSpill sp, const uint32_
 // atomics, probing confined to the region as in the table) and writes the
 // region back
 template <int HASH, class S>
-__global__ void __launch_bounds__(256) k_spill_agg(HkPlan P, HkAggTable T, HkSpill sp, const uint32_t* __restrict__ offs,
+__global__ void __launch_bounds__(1024) k_spill_agg(HkPlan P, HkAggTable T, HkSpill sp, const uint32_t* __restrict__ offs,
                                                    const uint64_t* total, int64_t nwg, const uint64_t* __restrict__ in,
                                                    int* err) {
   const int64_t p = blockIdx.x;
@@ -142,11 +164,11 @@ hipError_t hk_spill_shape(hipStream_t st, int step, const HkPlan& P, const HkAgg
                           const uint32_t* offs, const uint64_t* total, int64_t nwg, uint64_t* part, int* err) {
   if (step == 0) {
     const size_t lds = static_cast<size_t>(sp.nparts) * sizeof(uint32_t);
-    DISPATCH2(hash, HS, hipLaunchKernelGGL((k_spill_scatter<HS>), hk_wg_grid(nwg), dim3(256), lds, st, sp, offs, nwg,
+    DISPATCH2(hash, HS, hipLaunchKernelGGL((k_spill_scatter<HS>), hk_wg_grid(nwg), dim3(1024), lds, st, sp, offs, nwg,
                                            P.hash, T.log2cap, T.rlog2, part));
   } else {
     const size_t lds = (static_cast<size_t>(1) << T.rlog2) * T.slot_words * sizeof(uint64_t);
-    DISPATCH2(hash, HS, hipLaunchKernelGGL((k_spill_agg<HS, S>), dim3(static_cast<uint32_t>(sp.nparts)), dim3(256),
+    DISPATCH2(hash, HS, hipLaunchKernelGGL((k_spill_agg<HS, S>), dim3(static_cast<uint32_t>(sp.nparts)), dim3(512),
                                            lds, st, P, T, sp, offs, total, nwg, part, err));
   }
   return hipGetLastError();
