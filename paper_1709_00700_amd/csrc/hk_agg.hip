@@ -86,10 +86,7 @@ __global__ void __launch_bounds__(1024) k_spill_agg(HkPlan P, HkAggTable T, HkSp
   __syncthreads();
   const uint32_t rmask = static_cast<uint32_t>(R - 1);
   v16i64 r = {};
-  for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
-    const uint64_t* ent = in + i * sp.ew;
-    const uint64_t key = ent[0];
-    for (int j = 0; j < sp.ncols; ++j) r[sp.reg[j]] = static_cast<long long>(ent[1 + j]);
+  auto apply = [&](uint64_t key) {
     uint32_t s = hslot<HASH>(key, P.hash.a[0], T.log2cap) & rmask;
     int32_t found = -1;
     for (uint32_t k = 0; k <= rmask; ++k) {
@@ -103,9 +100,37 @@ __global__ void __launch_bounds__(1024) k_spill_agg(HkPlan P, HkAggTable T, HkSp
     }
     if (found < 0) {
       set_err(err, HK_ERR_CAPACITY);  // the region is full: the caller retries with a larger table
-      continue;
+      return;
     }
     agg_apply<HK_BR, true, S>(lt + found, R, P, r, true);
+  };
+  if (sp.ew == 2) {
+    // one input value per entry: SU entries per thread and round, loaded first
+    const ulonglong2* src = reinterpret_cast<const ulonglong2*>(in);
+    const int reg = sp.reg[0];
+    const int64_t stride = static_cast<int64_t>(blockDim.x) * SPILL_SU;
+    for (int64_t i0 = b + threadIdx.x; i0 < e; i0 += stride) {
+      ulonglong2 v[SPILL_SU];
+#pragma unroll
+      for (int u = 0; u < SPILL_SU; ++u) {
+        const int64_t i = i0 + u * static_cast<int64_t>(blockDim.x);
+        if (i < e) v[u] = src[i];
+      }
+#pragma unroll
+      for (int u = 0; u < SPILL_SU; ++u) {
+        const int64_t i = i0 + u * static_cast<int64_t>(blockDim.x);
+        if (i < e) {
+          r[reg] = static_cast<long long>(v[u].y);
+          apply(v[u].x);
+        }
+      }
+    }
+  } else {
+    for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+      const uint64_t* ent = in + i * sp.ew;
+      for (int j = 0; j < sp.ncols; ++j) r[sp.reg[j]] = static_cast<long long>(ent[1 + j]);
+      apply(ent[0]);
+    }
   }
   __syncthreads();
   for (int64_t i = threadIdx.x; i < R * W; i += blockDim.x) g[i] = lt[(i % W) * R + i / W];
