@@ -147,6 +147,8 @@ def run_c5(args):
     pool_rows = args.rows or 200_000_000
     nq = args.c5_queries
     ctx = hawk.Context(0)
+    if not args.no_jit:
+        ctx.set_jit(True)
     ncu, _ = ctx.device_info()
     log(f"[bench] c5: generating pools of {pool_rows} rows, {nq} pipelines")
     pools = dg.c5_pools(pool_rows)
@@ -180,6 +182,8 @@ def run_c5(args):
            "vs_baseline": None, "dtype": "int64", "data": "synthetic",
            "config": {"workload": DESCRIPTION["c5"], "pipelines": nq, "rows_per_step": total_rows,
                       "pool_rows": pool_rows, "schedule": b.opts(), "compute_units": ncu,
+                      "codegen": dict(zip(("run_time_kernels", "compile_ms"), ctx.jit_stats()),
+                                      run_time=not args.no_jit),
                       "kinds": {k: sum(1 for q in qs if q["kind"] == k) for k in (1, 2, 3)}},
            "wall_s_timed": wall}
     b.free()

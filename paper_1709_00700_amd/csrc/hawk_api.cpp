@@ -702,6 +702,76 @@ extern "C" hawk_status hawk_result_copy_column(hawk_result* r, int32_t col, void
 }
 
 // ------------------------------------------------------------------ execution
+hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int64_t groups_hint,
+                       const hawk_variant* v, int64_t groups, AggConfig& c) {
+  const int W = P.slot_words;
+  c = AggConfig{};
+  c.groups = groups;
+  c.llog2 = 0;
+  c.reps = 1;
+  c.rlog2 = T.log2cap;
+  if (v->agg_strategy == HAWK_LOCAL) {
+    const uint32_t want = std::max<uint32_t>(4, ceil_log2(static_cast<uint64_t>(groups_hint) * 2));
+    uint32_t fit = 0;
+    while ((int64_t(2) << fit) * W * 8 <= kLdsBudget) ++fit;
+    c.llog2 = std::min(want, fit);
+    if ((int64_t(1) << c.llog2) * W * 8 > ctx->lds_bytes)
+      return set_error(ctx, HAWK_E_INFEASIBLE, "local table does not fit in LDS");
+    // copies of the aggregate words while they fit the budget (up to 16)
+    const int64_t LC = int64_t(1) << c.llog2;
+    while (c.reps < 16 && (LC + (W - 1) * (2 * c.reps) * (LC + 1)) * 8 <= kLdsBudget) c.reps *= 2;
+  }
+  // Overflow partitioning: with the local strategy and linear probing, when
+  // the LDS table cannot hold every group, rows that miss it are spilled and
+  // aggregated per table region by the region's owner workgroup instead of
+  // each updating the table with device-scope atomics. A region (aggregated
+  // in LDS by its owner) takes at most 64 KB; the partition histogram of a
+  // workgroup sits beside its LDS table.
+  uint32_t rlog2 = 0;
+  while ((int64_t(2) << rlog2) * W * 8 <= kSpillLds) ++rlog2;
+  const int64_t nparts = T.log2cap > rlog2 ? int64_t(1) << (T.log2cap - rlog2) : 1;
+  const int64_t LC = int64_t(1) << c.llog2;
+  const int64_t table_bytes = (LC + (W - 1) * c.reps * (c.reps > 1 ? LC + 1 : LC)) * 8;
+  c.spill = v->agg_strategy == HAWK_LOCAL && v->ht == HAWK_LINEAR_PROBING && T.log2cap > c.llog2 && rlog2 >= 6 &&
+            nparts >= 2 && table_bytes + nparts * 4 <= kSpillLds && nparts * groups <= (int64_t(1) << 26) &&
+            P.nrows > 0 && ctx->lds_bytes >= kSpillLds;
+  if (c.spill) {
+    c.rlog2 = rlog2;
+    c.nparts = nparts;
+    HkSpill& sp = c.sp;
+    sp.nparts = static_cast<int32_t>(nparts);
+    for (int a = 0; a < P.naggs; ++a) {
+      if (P.aggs[a].fn == HK_COUNT) continue;
+      bool seen = false;
+      for (int j = 0; j < sp.ncols; ++j) seen = seen || sp.reg[j] == P.aggs[a].reg;
+      if (!seen) sp.reg[sp.ncols++] = P.aggs[a].reg;
+    }
+    sp.ew = 1 + sp.ncols;
+    sp.nrows = P.nrows;
+    sp.bs = static_cast<int32_t>(v->wg_size);
+    sp.coal = v->mem == HAWK_COALESCED ? 1 : 0;
+  }
+  return HAWK_OK;
+}
+
+hipError_t agg_kernel_launch(hawk_ctx* ctx, hipStream_t st, const hawk_variant* v, const HkPlan& P,
+                             const HkAggTable& T, const AggConfig& c, const uint64_t* ident, int32_t W, int* err,
+                             const HkSpill* sp) {
+  const int32_t wg = static_cast<int32_t>(v->wg_size);
+  if (ctx->jit && v->ht == HAWK_LINEAR_PROBING) {
+    HkIdent id = {};
+    for (int i = 0; i < W; ++i) id.w[i] = ident[i];
+    id.nw = W;
+    std::string msg;
+    const hipError_t e = jit_agg_launch(ctx->jit_cache, msg, st, P, T, v->mem, v->pred, v->hash, v->agg_strategy,
+                                        c.groups, wg, c.llog2, id, err, sp, c.reps);
+    if (e != hipSuccess && !msg.empty()) ctx->jit_cache.last_error = msg;
+    return e;
+  }
+  return hk_agg(st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, c.groups, wg, c.llog2, ident, W, err,
+                sp, c.reps);
+}
+
 namespace {
 
 struct Exec {
@@ -905,25 +975,6 @@ void identity_words(const HkPlan& P, bool grouped, uint64_t* w) {
   }
 }
 
-// grouped-aggregation launch: the kernel specialised for the plan when the
-// context compiles at run time (linear probing), else the precompiled one
-hipError_t agg_launch(Exec& X, const HkPlan& P, const HkAggTable& T, int64_t groups, int32_t wg, uint32_t llog2,
-                      const uint64_t* ident, int32_t W, const HkSpill* sp, int32_t reps) {
-  const hawk_variant* v = X.v;
-  if (X.ctx->jit && v->ht == HAWK_LINEAR_PROBING) {
-    HkIdent id = {};
-    for (int i = 0; i < W; ++i) id.w[i] = ident[i];
-    id.nw = W;
-    std::string msg;
-    const hipError_t e = jit_agg_launch(X.ctx->jit_cache, msg, X.st, P, T, v->mem, v->pred, v->hash, v->agg_strategy,
-                                        groups, wg, llog2, id, X.res->d_err, sp, reps);
-    if (e != hipSuccess && !msg.empty()) X.ctx->jit_cache.last_error = msg;
-    return e;
-  }
-  return hk_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, llog2, ident, W,
-                X.res->d_err, sp, reps);
-}
-
 hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
   hawk_ctx* ctx = X.ctx;
   const hawk_variant* v = X.v;
@@ -957,48 +1008,13 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
   else groups = static_cast<int64_t>(ctx->num_cus) * std::max(1, 2048 / wg);                      // fill the device
   if (groups < 1 || groups > 0x7FFFFFFF) return set_error(ctx, HAWK_E_ARG, "thread_mult out of range");
   if (grouped) {
-    uint32_t llog2 = 0;
-    int32_t reps = 1;
-    if (v->agg_strategy == HAWK_LOCAL) {
-      uint32_t want = std::max<uint32_t>(4, ceil_log2(static_cast<uint64_t>(X.q->groups_hint) * 2));
-      uint32_t fit = 0;
-      while ((int64_t(2) << fit) * W * 8 <= kLdsBudget) ++fit;
-      llog2 = std::min(want, fit);
-      if ((int64_t(1) << llog2) * W * 8 > ctx->lds_bytes)
-        return set_error(ctx, HAWK_E_INFEASIBLE, "local table does not fit in LDS");
-      // copies of the aggregate words while they fit the budget (up to 16)
-      const int64_t LC = int64_t(1) << llog2;
-      while (reps < 16 && (LC + (W - 1) * (2 * reps) * (LC + 1)) * 8 <= kLdsBudget) reps *= 2;
-    }
-    // Overflow partitioning: with the local strategy and linear probing, when
-    // the LDS table cannot hold every group, rows that miss it are spilled
-    // and aggregated per table region by the region's owner workgroup
-    // instead of each updating the table with device-scope atomics.
-    HkSpill sp;
-    std::memset(&sp, 0, sizeof(sp));
-    // a region (aggregated in LDS by its owner) takes at most 64 KB; the
-    // partition histogram of a workgroup sits beside its LDS table
-    uint32_t rlog2 = 0;
-    while ((int64_t(2) << rlog2) * W * 8 <= kSpillLds) ++rlog2;
-    const int64_t nparts = T.log2cap > rlog2 ? int64_t(1) << (T.log2cap - rlog2) : 1;
-    const bool spill = v->agg_strategy == HAWK_LOCAL && v->ht == HAWK_LINEAR_PROBING && T.log2cap > llog2 &&
-                       rlog2 >= 6 && nparts >= 2 &&
-                       ((int64_t(1) << llog2) + (W - 1) * reps * (reps > 1 ? (int64_t(1) << llog2) + 1 : (int64_t(1) << llog2))) * 8 + nparts * 4 <= kSpillLds &&
-                       nparts * groups <= (int64_t(1) << 26) && P.nrows > 0 && ctx->lds_bytes >= kSpillLds;
-    if (spill) {
-      T.rlog2 = rlog2;
-      sp.nparts = static_cast<int32_t>(nparts);
-      for (int a = 0; a < P.naggs; ++a) {
-        if (P.aggs[a].fn == HK_COUNT) continue;
-        bool seen = false;
-        for (int j = 0; j < sp.ncols; ++j) seen = seen || sp.reg[j] == P.aggs[a].reg;
-        if (!seen) sp.reg[sp.ncols++] = P.aggs[a].reg;
-      }
-      sp.ew = 1 + sp.ncols;
-      sp.nrows = P.nrows;
-      sp.bs = wg;
-      sp.coal = v->mem == HAWK_COALESCED ? 1 : 0;
-      const int64_t m = nparts * groups;
+    AggConfig cfg;
+    hawk_status cst = agg_config(ctx, P, T, X.q->groups_hint, v, groups, cfg);
+    if (cst) return cst;
+    T.rlog2 = cfg.rlog2;
+    if (cfg.spill) {
+      HkSpill sp = cfg.sp;
+      const int64_t m = cfg.nparts * groups;
       uint32_t *offs, *stmp;
       uint64_t *total, *part;
       ALLOC(sp.buf, uint64_t*, static_cast<size_t>(P.nrows * sp.ew) * 8, false);
@@ -1010,7 +1026,7 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
       ALLOC(part, uint64_t*, static_cast<size_t>(P.nrows * sp.ew) * 8, false);
       {
         ProfScope ps(ctx, "k_agg");
-        HIPCHK(agg_launch(X, P, T, groups, wg, llog2, ident, W, &sp, reps), "aggregation kernel");
+        HIPCHK(agg_kernel_launch(ctx, X.st, v, P, T, cfg, ident, W, res->d_err, &sp), "aggregation kernel");
       }
       {
         ProfScope ps(ctx, "k_scan");
@@ -1026,7 +1042,7 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
       }
     } else {
       ProfScope ps(ctx, "k_agg");
-      HIPCHK(agg_launch(X, P, T, groups, wg, llog2, ident, W, nullptr, reps), "aggregation kernel");
+      HIPCHK(agg_kernel_launch(ctx, X.st, v, P, T, cfg, ident, W, res->d_err, nullptr), "aggregation kernel");
     }
   } else {
     ProfScope ps(ctx, "k_scalar_agg");

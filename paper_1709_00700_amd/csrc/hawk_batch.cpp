@@ -20,6 +20,7 @@ namespace {
 
 const int64_t kBuildTile = 1 << 14;   // build rows per work item
 const int64_t kFinalTile = 1 << 16;   // table slots per finalize work item
+const int64_t kDirectRows = 1 << 22;  // grouped aggregations this large get their own launches
 const int64_t kLdsBudget = 32768;     // LDS bytes of a grouped tile's table
 enum { HEAD_BUILD = 0, HEAD_MAIN = 1, HEAD_FINAL = 6, HEAD_COUNT = 8 };
 
@@ -73,6 +74,21 @@ struct hawk_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::set<hawk_result*> views;         // live result views of this batch
+  // grouped aggregations run with their own launches inside the graph (large
+  // or high-cardinality ones): the aggregation kernel of a fixed variant and,
+  // when its LDS table cannot hold the groups, the spill kernels
+  struct Direct {
+    int32_t q;
+    hawk_variant v;
+    AggConfig cfg;
+    HkSpill sp;
+    uint32_t* offs;
+    uint32_t* stmp;
+    uint64_t* total;
+    uint64_t* part;
+  };
+  std::vector<Direct> direct;
+  std::vector<char> is_direct;
 };
 
 namespace {
@@ -194,6 +210,48 @@ hawk_status setup_memory(hawk_batch* B) {
       }
       Q.table.words = static_cast<uint64_t*>(balloc(B, static_cast<size_t>(Q.nslots * W) * 8, B->allocs));
       if (!Q.table.words) return berr(B, HAWK_E_OOM, "batch aggregation table");
+      const int64_t ghint = std::max<int64_t>(1, std::min<int64_t>(q->groups_hint, n));
+      if (grouped && (n >= kDirectRows || (int64_t(1) << Q.llog2) < 2 * ghint)) {
+        // own launches: local strategy, coalesced, linear probing with the
+        // batch's Murmur seeds (the join tables of its probes use them too)
+        hawk_batch::Direct d{};
+        d.q = static_cast<int32_t>(i);
+        d.v.proj_strategy = HAWK_MULTI_PASS;
+        d.v.mem = HAWK_COALESCED;
+        d.v.ht = HAWK_LINEAR_PROBING;
+        d.v.hash = HAWK_MURMUR;
+        d.v.agg_strategy = HAWK_LOCAL;
+        d.v.thread_mult = 8;
+        d.v.wg_size = 512;
+        hawk_status cst = agg_config(ctx, Q.plan, Q.table, ghint, &d.v, 8 * ctx->num_cus, d.cfg);
+        if (!cst && d.cfg.spill) {  // spilling pipelines do best with one large workgroup per CU
+          d.v.thread_mult = 1;
+          d.v.wg_size = 1024;
+          cst = agg_config(ctx, Q.plan, Q.table, ghint, &d.v, ctx->num_cus, d.cfg);
+        }
+        if (cst) return cst;
+        Q.table.rlog2 = d.cfg.rlog2;
+        if (d.cfg.spill) {
+          d.sp = d.cfg.sp;
+          const int64_t m = d.cfg.nparts * d.cfg.groups;
+          d.sp.buf = static_cast<uint64_t*>(balloc(B, static_cast<size_t>(n * d.sp.ew) * 8, B->allocs));
+          d.sp.hist = static_cast<uint32_t*>(balloc(B, static_cast<size_t>(m) * 4, B->allocs));
+          d.sp.cnt = static_cast<uint32_t*>(balloc(B, static_cast<size_t>(d.cfg.groups) * 4, B->allocs));
+          d.offs = static_cast<uint32_t*>(balloc(B, static_cast<size_t>(m) * 4, B->allocs));
+          d.stmp = static_cast<uint32_t*>(balloc(B, static_cast<size_t>(hk_scan_tmp_words(m)) * 4, B->allocs));
+          d.total = static_cast<uint64_t*>(balloc(B, 8, B->allocs));
+          d.part = static_cast<uint64_t*>(balloc(B, static_cast<size_t>(n * d.sp.ew) * 8, B->allocs));
+          if (!d.sp.buf || !d.sp.hist || !d.sp.cnt || !d.offs || !d.stmp || !d.total || !d.part)
+            return berr(B, HAWK_E_OOM, "batch spill buffers");
+        }
+        if (ctx->jit) {
+          std::string msg;
+          if (jit_agg_prepare(ctx->jit_cache, msg, Q.plan, d.v.mem, d.v.pred, d.v.hash, d.v.agg_strategy,
+                              d.cfg.spill) != hipSuccess)
+            return berr(B, HAWK_E_DEVICE, "run-time compilation: " + msg);
+        }
+        B->direct.push_back(d);
+      }
       add_fill(B, Q.table.words, Q.nslots * W, Q.ident.w, W);
       const int64_t cap = Q.nslots;
       for (int g = 0; g < Q.plan.ngroup; ++g) {
@@ -212,6 +270,8 @@ hawk_status setup_memory(hawk_batch* B) {
     }
     B->hq.push_back(Q);
   }
+  B->is_direct.assign(B->hq.size(), 0);
+  for (const auto& d : B->direct) B->is_direct[d.q] = 1;
   return HAWK_OK;
 }
 
@@ -259,7 +319,7 @@ hawk_status setup_schedule(hawk_batch* B, const hawk_batch_opts& o) {
     size_t lds = 64;
     for (int32_t i : order) {
       const HkBatchQuery& Q = hq[i];
-      if (Q.shape != s || Q.ntiles == 0) continue;
+      if (Q.shape != s || Q.ntiles == 0 || B->is_direct[i]) continue;
       qi.push_back(i);
       nt.push_back(Q.ntiles);
       size_t need;
@@ -315,6 +375,19 @@ hawk_status setup_schedule(hawk_batch* B, const hawk_batch_opts& o) {
     le = hk_batch_build(B->cap, std::min<int64_t>(grid, std::max<int64_t>(1, B->build_items)), B->d_builds,
                         B->d_build_bases, static_cast<int32_t>(B->hb.size()), B->build_items, kBuildTile,
                         B->d_heads + HEAD_BUILD, B->d_err);
+  for (const auto& d : B->direct) {
+    if (le != hipSuccess) break;
+    const HkBatchQuery& Q = hq[d.q];
+    le = agg_kernel_launch(ctx, B->cap, &d.v, Q.plan, Q.table, d.cfg, Q.ident.w, Q.ident.nw, B->d_err,
+                           d.cfg.spill ? &d.sp : nullptr);
+    if (le == hipSuccess && d.cfg.spill) {
+      le = hk_scan(B->cap, d.sp.hist, d.offs, d.cfg.nparts * d.cfg.groups, d.stmp, d.total);
+      if (le == hipSuccess)
+        le = hk_spill(B->cap, 0, Q.plan, Q.table, d.v.hash, d.sp, d.offs, d.total, d.cfg.groups, d.part, B->d_err);
+      if (le == hipSuccess)
+        le = hk_spill(B->cap, 1, Q.plan, Q.table, d.v.hash, d.sp, d.offs, d.total, d.cfg.groups, d.part, B->d_err);
+    }
+  }
   for (int s = 0; s < 5 && le == hipSuccess; ++s)
     le = hk_batch_main(B->cap, s, std::min<int64_t>(grid, std::max<int64_t>(1, B->items_shape[s])), 256,
                        B->lds_shape[s], B->d_qs, B->d_qidx[s], B->d_bases[s], B->nq_shape[s], B->items_shape[s],

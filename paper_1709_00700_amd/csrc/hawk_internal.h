@@ -107,6 +107,25 @@ struct hawk_result {
 };
 
 hawk_status set_error(hawk_ctx* ctx, hawk_status st, const std::string& msg);
+
+// launch configuration of a grouped aggregation: workgroups, LDS table size
+// and copies, and whether (and how) rows that miss the LDS table spill
+struct AggConfig {
+  int64_t groups;
+  uint32_t llog2;
+  int32_t reps;
+  bool spill;
+  uint32_t rlog2;   // table region (log2 slots); the whole table without spilling
+  int64_t nparts;
+  HkSpill sp;       // sizes and registers; buffers are the caller's
+};
+hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int64_t groups_hint,
+                       const hawk_variant* v, int64_t groups, AggConfig& c);
+// the aggregation kernel of variant v: compiled at run time for the plan when
+// the context does so (linear probing), else the precompiled one
+hipError_t agg_kernel_launch(hawk_ctx* ctx, hipStream_t st, const hawk_variant* v, const HkPlan& P,
+                             const HkAggTable& T, const AggConfig& c, const uint64_t* ident, int32_t W, int* err,
+                             const HkSpill* sp);
 void query_release_device(hawk_query* q);
 void model_release_device(struct hawk_model* m);
 void batch_release_device(struct hawk_batch* b);

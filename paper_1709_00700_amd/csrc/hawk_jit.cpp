@@ -67,10 +67,9 @@ std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash,
   return o.str();
 }
 
-hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P,
-                          const HkAggTable& T, int mem, int pred, int hash, int strat, int64_t groups, int32_t wg,
-                          uint32_t llog2, const HkIdent& id, int* err, const HkSpill* sp, int32_t reps) {
-  const std::string src = jit_agg_source(P, mem, pred, HK_LIN, hash, strat, sp != nullptr);
+namespace {
+
+hipError_t get_kernel(JitCache& cache, std::string& err_msg, const std::string& src, hipFunction_t& fn) {
   auto it = cache.kernels.find(src);
   if (it == cache.kernels.end()) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -114,6 +113,24 @@ hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st,
     ++cache.compiled;
     it = cache.kernels.emplace(src, k).first;
   }
+  fn = it->second.fn;
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t jit_agg_prepare(JitCache& cache, std::string& err_msg, const HkPlan& P, int mem, int pred, int hash,
+                           int strat, bool spill) {
+  hipFunction_t fn;
+  return get_kernel(cache, err_msg, jit_agg_source(P, mem, pred, HK_LIN, hash, strat, spill), fn);
+}
+
+hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P,
+                          const HkAggTable& T, int mem, int pred, int hash, int strat, int64_t groups, int32_t wg,
+                          uint32_t llog2, const HkIdent& id, int* err, const HkSpill* sp, int32_t reps) {
+  hipFunction_t fn;
+  const hipError_t ge = get_kernel(cache, err_msg, jit_agg_source(P, mem, pred, HK_LIN, hash, strat, sp != nullptr), fn);
+  if (ge != hipSuccess) return ge;
   HkSpill none;
   std::memset(&none, 0, sizeof(none));
   HkPlan Pa = P;
@@ -127,6 +144,6 @@ hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st,
   void* args[] = {&Pa, &Ta, &ll, &ida, &nwg, &erra, &spa, &rp};
   const dim3 g = hk_wg_grid(groups);
   const size_t lds = hk_agg_lds_bytes(strat, llog2, id.nw, reps, sp);
-  return hipModuleLaunchKernel(it->second.fn, g.x, g.y, 1, static_cast<uint32_t>(wg), 1, 1,
+  return hipModuleLaunchKernel(fn, g.x, g.y, 1, static_cast<uint32_t>(wg), 1, 1,
                                static_cast<uint32_t>(lds), st, args, nullptr);
 }
