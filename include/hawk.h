@@ -322,9 +322,12 @@ hawk_status hawk_model_pick(hawk_model* m, hawk_query* const* qs, int32_t n, haw
    order with a single-pass look-back over tile counts.
    Schedule options: tile_rows_log2 in [14, 18] (rows per work item),
    wgs_per_cu in [1, 32] (persistent workgroups per compute unit), order 0
-   (submission order) or 1 (largest query first); reserved must be 0.
-   NULL opts = {16, 2, 1, 0}. */
-typedef struct { int32_t tile_rows_log2; int32_t wgs_per_cu; int32_t order; int32_t reserved; } hawk_batch_opts;
+   (submission order) or 1 (largest query first); separate 1 gives grouped
+   aggregations of at least 2^20 rows with more groups than a tile's LDS
+   table holds their own launches in the graph (the spilling local strategy,
+   compiled at run time when the context does so), 0 keeps every pipeline
+   in the persistent kernels. NULL opts = {16, 2, 1, 1}. */
+typedef struct { int32_t tile_rows_log2; int32_t wgs_per_cu; int32_t order; int32_t separate; } hawk_batch_opts;
 /* Creates a batch of n queries of ctx (borrowed: they must outlive the batch;
    their tables must stay registered and unmodified). Allocates the batch's
    device memory (tables sized from the queries' row counts and group hints,

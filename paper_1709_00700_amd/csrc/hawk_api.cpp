@@ -22,8 +22,8 @@ namespace {
 
 const uint32_t kMults[7] = {1, 8, 64, 256, 1024, 16384, 65536};  // Section 9.2
 const uint32_t kWgs[7] = {16, 32, 64, 128, 256, 512, 1024};       // Section 9.2
-const int64_t kSpillLds = 65536;  // LDS bytes of a spill region / of a table plus its histogram
-const int64_t kLdsBudget = 32768;  // bytes of LDS per workgroup for a local table
+const int64_t kSpillLds = 64512;  // LDS bytes of a spill region / of a table plus its histogram
+const int64_t kLdsBudget = 64512;  // LDS bytes of a local table (64 KB with the static words: two workgroups per CU)
 const int kMaxAttempts = 12;
 
 uint64_t splitmix(uint64_t& s) {
@@ -727,8 +727,12 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
   // each updating the table with device-scope atomics. A region (aggregated
   // in LDS by its owner) takes at most 64 KB; the partition histogram of a
   // workgroup sits beside its LDS table.
+  // Regions as large as 64 KB of LDS allow, but at least 256 of them (so
+  // that the regions' owners fill the device) while they keep 64 slots.
   uint32_t rlog2 = 0;
   while ((int64_t(2) << rlog2) * W * 8 <= kSpillLds) ++rlog2;
+  if (T.log2cap >= 14 && T.log2cap - 8 < rlog2) rlog2 = T.log2cap - 8;
+  else if (T.log2cap < 14 && rlog2 > 6) rlog2 = 6;
   const int64_t nparts = T.log2cap > rlog2 ? int64_t(1) << (T.log2cap - rlog2) : 1;
   const int64_t LC = int64_t(1) << c.llog2;
   const int64_t table_bytes = (LC + (W - 1) * c.reps * (c.reps > 1 ? LC + 1 : LC)) * 8;

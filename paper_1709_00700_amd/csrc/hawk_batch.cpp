@@ -20,8 +20,10 @@ namespace {
 
 const int64_t kBuildTile = 1 << 14;   // build rows per work item
 const int64_t kFinalTile = 1 << 16;   // table slots per finalize work item
-const int64_t kDirectRows = 1 << 22;  // grouped aggregations this large get their own launches
-const int64_t kLdsBudget = 32768;     // LDS bytes of a grouped tile's table
+// grouped aggregations with more groups than a tile's LDS table holds get
+// their own launches (spilling instead of device-scope atomics) from this size on
+const int64_t kDirectRows = 1 << 20;
+const int64_t kLdsBudget = 64512;     // LDS bytes of a grouped tile's table (64 KB with the static words)
 enum { HEAD_BUILD = 0, HEAD_MAIN = 1, HEAD_FINAL = 6, HEAD_COUNT = 8 };
 
 uint32_t clog2(uint64_t x) {
@@ -211,7 +213,7 @@ hawk_status setup_memory(hawk_batch* B) {
       Q.table.words = static_cast<uint64_t*>(balloc(B, static_cast<size_t>(Q.nslots * W) * 8, B->allocs));
       if (!Q.table.words) return berr(B, HAWK_E_OOM, "batch aggregation table");
       const int64_t ghint = std::max<int64_t>(1, std::min<int64_t>(q->groups_hint, n));
-      if (grouped && (n >= kDirectRows || (int64_t(1) << Q.llog2) < 2 * ghint)) {
+      if (grouped && B->opts.separate && n >= kDirectRows && (int64_t(1) << Q.llog2) < 2 * ghint) {
         // own launches: local strategy, coalesced, linear probing with the
         // batch's Murmur seeds (the join tables of its probes use them too)
         hawk_batch::Direct d{};
@@ -221,10 +223,15 @@ hawk_status setup_memory(hawk_batch* B) {
         d.v.ht = HAWK_LINEAR_PROBING;
         d.v.hash = HAWK_MURMUR;
         d.v.agg_strategy = HAWK_LOCAL;
-        d.v.thread_mult = 8;
+        // about 64K rows or more per workgroup, up to 8 workgroups per CU
+        uint32_t tm = 1;
+        while (tm < 8 && n / (static_cast<int64_t>(ctx->num_cus) * 2 * tm) >= 65536) tm *= 2;
+        d.v.thread_mult = tm;
         d.v.wg_size = 512;
-        hawk_status cst = agg_config(ctx, Q.plan, Q.table, ghint, &d.v, 8 * ctx->num_cus, d.cfg);
-        if (!cst && d.cfg.spill) {  // spilling pipelines do best with one large workgroup per CU
+        hawk_status cst = agg_config(ctx, Q.plan, Q.table, ghint, &d.v, static_cast<int64_t>(tm) * ctx->num_cus, d.cfg);
+        if (!cst && d.cfg.spill && Q.plan.nprobes == 0) {
+          // a spilling scan without probes does best with one large workgroup
+          // per CU; probes are latency-bound and keep the wider grid
           d.v.thread_mult = 1;
           d.v.wg_size = 1024;
           cst = agg_config(ctx, Q.plan, Q.table, ghint, &d.v, ctx->num_cus, d.cfg);
@@ -406,7 +413,7 @@ hawk_status setup_schedule(hawk_batch* B, const hawk_batch_opts& o) {
 
 bool valid_opts(const hawk_batch_opts& o) {
   return o.tile_rows_log2 >= 14 && o.tile_rows_log2 <= 18 && o.wgs_per_cu >= 1 && o.wgs_per_cu <= 32 &&
-         (o.order == 0 || o.order == 1);
+         (o.order == 0 || o.order == 1) && (o.separate == 0 || o.separate == 1);
 }
 
 }  // namespace
@@ -436,7 +443,7 @@ extern "C" hawk_status hawk_batch_create(hawk_ctx* ctx, hawk_query* const* qs, i
   if (!qs || n < 1 || !out) return set_error(ctx, HAWK_E_ARG, "null argument");
   *out = nullptr;
   if (ctx->device < 0) return set_error(ctx, HAWK_E_DEVICE, "planning context cannot execute");
-  hawk_batch_opts o = opts ? *opts : hawk_batch_opts{16, 2, 1, 0};
+  hawk_batch_opts o = opts ? *opts : hawk_batch_opts{16, 2, 1, 1};
   if (!valid_opts(o)) return set_error(ctx, HAWK_E_ARG, "batch options out of range");
   hawk_batch* B = new hawk_batch();
   B->ctx = ctx;
@@ -452,6 +459,7 @@ extern "C" hawk_status hawk_batch_create(hawk_ctx* ctx, hawk_query* const* qs, i
     return set_error(ctx, HAWK_E_DEVICE, "capture stream");
   }
   ctx->batches.insert(B);
+  B->opts = o;  // setup_memory reads `separate`
   hawk_status st = setup_memory(B);
   if (!st) st = setup_schedule(B, o);
   if (st) {
@@ -513,7 +521,7 @@ extern "C" hawk_status hawk_batch_autotune(hawk_batch* B, int32_t reps, hawk_bat
   for (int order = 0; order < 2; ++order)
     for (int tl : tiles)
       for (int w : wgs) {
-        hawk_batch_opts o{tl, w, order, 0};
+        hawk_batch_opts o{tl, w, order, B->opts.separate};
         hawk_status st = setup_schedule(B, o);
         if (st) return st;
         double ms = 0;

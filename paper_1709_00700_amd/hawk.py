@@ -102,10 +102,11 @@ class hawk_train_opts(ctypes.Structure):
 
 class hawk_batch_opts(ctypes.Structure):
     _fields_ = [("tile_rows_log2", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("separate", ctypes.c_int32)]
 
     def as_dict(self):
-        return {"tile_rows_log2": self.tile_rows_log2, "wgs_per_cu": self.wgs_per_cu, "order": self.order}
+        return {"tile_rows_log2": self.tile_rows_log2, "wgs_per_cu": self.wgs_per_cu, "order": self.order,
+                "separate": self.separate}
 
 
 class hawk_explore_report(ctypes.Structure):
@@ -553,11 +554,11 @@ class Model:
 class Batch:
     """Many queries replayed as one captured graph of persistent kernels (see hawk.h, batched execution)."""
 
-    def __init__(self, ctx: Context, queries: list, tile_rows_log2=16, wgs_per_cu=2, order=1):
+    def __init__(self, ctx: Context, queries: list, tile_rows_log2=16, wgs_per_cu=2, order=1, separate=1):
         self.ctx = ctx
         self.queries = list(queries)  # the batch borrows them
         W = (ctypes.c_void_p * len(queries))(*[q.handle.value for q in queries])
-        o = hawk_batch_opts(tile_rows_log2, wgs_per_cu, order, 0)
+        o = hawk_batch_opts(tile_rows_log2, wgs_per_cu, order, separate)
         h = ctypes.c_void_p()
         check(L().hawk_batch_create(ctx.handle, W, len(queries), ctypes.byref(o), ctypes.byref(h)), ctx.handle)
         self.handle = h

@@ -66,9 +66,30 @@ def test_batch_schedules(ctx, tile, wgs, order):
     say("batch schedule", tile, wgs, order)
     qs, hs, refs = c5_setup(ctx, 12, 300_000, 1000, 300_000, seed=dg.MASTER_SEED + 55)
     b = hawk.Batch(ctx, hs, tile_rows_log2=tile, wgs_per_cu=wgs, order=order)
-    assert b.opts() == {"tile_rows_log2": tile, "wgs_per_cu": wgs, "order": order}
+    assert b.opts() == {"tile_rows_log2": tile, "wgs_per_cu": wgs, "order": order, "separate": 1}
     b.run()
     check_batch(b, qs, refs, f"tile {tile} wgs {wgs} order {order}")
+    b.free()
+
+
+def test_batch_without_separate_launches(ctx):
+    say("batch: every pipeline in the persistent kernels")
+    qs, hs, refs = c5_setup(ctx, 12, 2_000_000, 1_000_000, 2_000_000, seed=dg.MASTER_SEED + 59)
+    b = hawk.Batch(ctx, hs, separate=0)
+    b.run()
+    check_batch(b, qs, refs, "no separate launches")
+    b.free()
+
+
+def test_batch_separate_launches_large_groups(ctx):
+    # pipelines of 1M-2M rows: the high-cardinality aggregations get their own launches
+    say("batch: separate launches")
+    qs, hs, refs = c5_setup(ctx, 12, 2_000_000, 1_000_000, 2_000_000, seed=dg.MASTER_SEED + 59)
+    assert any(q["kind"] == 2 and q["groups"] >= 4096 for q in qs)
+    b = hawk.Batch(ctx, hs, separate=1)
+    for rep in range(2):
+        b.run()
+        check_batch(b, qs, refs, f"separate, replay {rep}")
     b.free()
 
 
