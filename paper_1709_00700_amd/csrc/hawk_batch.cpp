@@ -254,7 +254,7 @@ hawk_status setup_memory(hawk_batch* B) {
         if (ctx->jit) {
           std::string msg;
           if (jit_agg_prepare(ctx->jit_cache, msg, Q.plan, d.v.mem, d.v.pred, d.v.hash, d.v.agg_strategy,
-                              d.cfg.spill) != hipSuccess)
+                              d.cfg.llog2, Q.ident.nw, d.cfg.reps, d.cfg.spill ? &d.sp : nullptr) != hipSuccess)
             return berr(B, HAWK_E_DEVICE, "run-time compilation: " + msg);
         }
         B->direct.push_back(d);

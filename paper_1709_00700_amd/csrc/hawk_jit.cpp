@@ -27,11 +27,15 @@ void JitCache::release() {
   kernels.clear();
 }
 
-std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash, int strat, bool spill) {
+std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash, int strat, bool spill,
+                           size_t lds_bytes) {
   std::ostringstream o;
+  // the local table is a static LDS array of the launch's size (no dynamic LDS)
+  const size_t words = lds_bytes / 8 > 0 ? (lds_bytes + 7) / 8 : 1;
   o << "#include \"hk_agg_body.h\"\n"
        "extern \"C\" __global__ void __launch_bounds__(1024) hk_jit_agg(HkPlan Prt, HkAggTable T, uint32_t llog2,\n"
        "    HkIdent id, int64_t nwg, int* err, HkSpill sp, int32_t reps) {\n"
+       "  __shared__ uint64_t lds[" << words << "];\n"
        "  HkPlan P;\n"
        "  P.nrows = Prt.nrows;\n  P.hash = Prt.hash;\n";
   o << "  P.ncolA = " << P.ncolA << "; P.ncolB = " << P.ncolB << "; P.ncolC = " << P.ncolC
@@ -63,7 +67,7 @@ std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash,
   o << "  P.nproj = 0;\n  P.slot_words = " << P.slot_words << ";\n";
   o << "  agg_body<" << mem << ", " << pred << ", " << ht << ", " << hash << ", " << strat << ", HkShape<" << P.ncolA
     << ", " << P.nfilters << ", " << P.ncolB << ", " << P.nprobes << ", " << P.ncolC << ", " << P.narith << ", "
-    << P.naggs << ", 0>, " << (spill ? "true" : "false") << ">(P, T, llog2, id, nwg, err, sp, reps);\n}\n";
+    << P.naggs << ", 0>, " << (spill ? "true" : "false") << ">(P, T, llog2, id, nwg, err, sp, reps, lds);\n}\n";
   return o.str();
 }
 
@@ -120,16 +124,19 @@ hipError_t get_kernel(JitCache& cache, std::string& err_msg, const std::string& 
 }  // namespace
 
 hipError_t jit_agg_prepare(JitCache& cache, std::string& err_msg, const HkPlan& P, int mem, int pred, int hash,
-                           int strat, bool spill) {
+                           int strat, uint32_t llog2, int32_t nw, int32_t reps, const HkSpill* sp) {
   hipFunction_t fn;
-  return get_kernel(cache, err_msg, jit_agg_source(P, mem, pred, HK_LIN, hash, strat, spill), fn);
+  const size_t lds = hk_agg_lds_bytes(strat, llog2, nw, reps, sp);
+  return get_kernel(cache, err_msg, jit_agg_source(P, mem, pred, HK_LIN, hash, strat, sp != nullptr, lds), fn);
 }
 
 hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P,
                           const HkAggTable& T, int mem, int pred, int hash, int strat, int64_t groups, int32_t wg,
                           uint32_t llog2, const HkIdent& id, int* err, const HkSpill* sp, int32_t reps) {
   hipFunction_t fn;
-  const hipError_t ge = get_kernel(cache, err_msg, jit_agg_source(P, mem, pred, HK_LIN, hash, strat, sp != nullptr), fn);
+  const size_t lds = hk_agg_lds_bytes(strat, llog2, id.nw, reps, sp);
+  const hipError_t ge =
+      get_kernel(cache, err_msg, jit_agg_source(P, mem, pred, HK_LIN, hash, strat, sp != nullptr, lds), fn);
   if (ge != hipSuccess) return ge;
   HkSpill none;
   std::memset(&none, 0, sizeof(none));
@@ -143,7 +150,5 @@ hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st,
   int32_t rp = reps;
   void* args[] = {&Pa, &Ta, &ll, &ida, &nwg, &erra, &spa, &rp};
   const dim3 g = hk_wg_grid(groups);
-  const size_t lds = hk_agg_lds_bytes(strat, llog2, id.nw, reps, sp);
-  return hipModuleLaunchKernel(fn, g.x, g.y, 1, static_cast<uint32_t>(wg), 1, 1,
-                               static_cast<uint32_t>(lds), st, args, nullptr);
+  return hipModuleLaunchKernel(fn, g.x, g.y, 1, static_cast<uint32_t>(wg), 1, 1, 0, st, args, nullptr);
 }

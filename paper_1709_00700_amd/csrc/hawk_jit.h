@@ -4,8 +4,9 @@
 // (column types and registers, operators, aggregates, counts) as constants,
 // while data that differs between queries of one structure (column
 // pointers, filter bounds, arithmetic constants, join tables, hash seeds,
-// row count) stays a kernel argument. Kernels are cached per context by
-// their generated source.
+// row count) stays a kernel argument. The local table is a static LDS array
+// of the launch's size. Kernels are cached per context by their generated
+// source.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -25,10 +26,11 @@ struct JitCache {
 };
 
 // Generated source of the specialised kernel `hk_jit_agg` for (P, variant).
-std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash, int strat, bool spill);
+std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash, int strat, bool spill,
+                           size_t lds_bytes);
 // Compiles the specialised kernel unless the cache holds it (no GPU work).
 hipError_t jit_agg_prepare(JitCache& cache, std::string& err_msg, const HkPlan& P, int mem, int pred, int hash,
-                           int strat, bool spill);
+                           int strat, uint32_t llog2, int32_t nw, int32_t reps, const HkSpill* sp);
 // Compiles (or finds) and launches the specialised kernel; same arguments and
 // launch shape as the ahead-of-time k_agg. Linear probing only.
 hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P,

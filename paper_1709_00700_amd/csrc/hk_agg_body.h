@@ -15,7 +15,7 @@
 // table is merged into the global table.
 template <int MEM, int PRED, int HT, int HASH, int STRAT, class S, bool SPILL>
 __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, uint32_t llog2, const HkIdent& id,
-                                         int64_t nwg, int* err, const HkSpill& sp, int32_t reps) {
+                                         int64_t nwg, int* err, const HkSpill& sp, int32_t reps, uint64_t* lds) {
   // workgroups may come as a 2-D grid (HSA counts grid sizes in work-items as 32-bit values)
   const int64_t wgid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   if (wgid >= nwg) return;  // padding workgroup: leaves before any barrier
@@ -28,7 +28,6 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
     }
     return;
   }
-  extern __shared__ uint64_t lds[];
   __shared__ uint32_t spill_cursor;
   const int64_t LC = STRAT == HK_LOCAL ? (static_cast<int64_t>(1) << llog2) : 0;
   const int64_t RS = reps > 1 ? LC + 1 : LC;
