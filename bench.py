@@ -32,13 +32,14 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "input rows/s + HBM GB/s per pipeline; learned-pick vs best-variant runtime ratio"
 
 # variants used by the timed steps, per workload pipeline: the exhaustive
-# search's best on MI355X (python bench.py --workload W --explore exhaustive)
+# search's best on MI355X (python bench.py --workload W --explore exhaustive),
+# with its workgroup count and size re-swept for the run-time compiled kernels
 DEFAULT_VARIANTS = {
     "c1": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=1024, wg_size=256),
-    "c2u": dict(proj_strategy=1, mem=1, pred=1, ht=0, hash=1, agg_strategy=0, thread_mult=8, wg_size=512),
-    "c2z": dict(proj_strategy=1, mem=1, pred=1, ht=0, hash=1, agg_strategy=0, thread_mult=1, wg_size=1024),
+    "c2u": dict(proj_strategy=1, mem=1, pred=1, ht=0, hash=1, agg_strategy=0, thread_mult=1, wg_size=1024),
+    "c2z": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=1, agg_strategy=0, thread_mult=1, wg_size=1024),
     "c3": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=1, agg_strategy=0, thread_mult=8, wg_size=512),
-    "c4": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=1, agg_strategy=0, thread_mult=64, wg_size=256),
+    "c4": dict(proj_strategy=1, mem=1, pred=1, ht=0, hash=1, agg_strategy=0, thread_mult=8, wg_size=512),
 }
 
 # algorithmic bytes read per input row of each pipeline (columns the
