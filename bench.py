@@ -88,7 +88,7 @@ def make_pipelines(workload, rows):
 # then WRITE_SIZE, KiB per dispatch) of this script's default workload, each
 # scaled by the ratio of known bytes to the counter's reading for a plain
 # device copy (--copy-calibration). Valid only for the kernel sources it was
-# measured on: bench.py reports null when their hash differs.
+# measured on, with the same variants: bench.py reports null otherwise.
 TRAFFIC = {
     ("k_agg", "c2"): {"sources_sha": "feb9f327e4b42342", "bytes_per_launch": 1067726016},
 }
@@ -106,9 +106,16 @@ def kernel_sources_sha(kernel):
     return h.hexdigest()[:16]
 
 
+def variants_sha(workload):
+    import hashlib
+    return hashlib.sha256(json.dumps([DEFAULT_VARIANTS[p] for p in WORKLOADS[workload]],
+                                     sort_keys=True).encode()).hexdigest()[:16]
+
+
 def traffic_for(kernel, workload):
+    """Measured HBM bytes per launch, while the kernel sources and the workload's variants are unchanged."""
     t = TRAFFIC.get((kernel, workload))
-    if not t or t["sources_sha"] != kernel_sources_sha(kernel):
+    if not t or t["sources_sha"] != kernel_sources_sha(kernel) or t.get("variants_sha") != variants_sha(workload):
         return None
     return t["bytes_per_launch"]
 
