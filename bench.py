@@ -90,7 +90,8 @@ def make_pipelines(workload, rows):
 # device copy (--copy-calibration). Valid only for the kernel sources it was
 # measured on, with the same variants: bench.py reports null otherwise.
 TRAFFIC = {
-    ("k_agg", "c2"): {"sources_sha": "feb9f327e4b42342", "bytes_per_launch": 1067726016},
+    ("k_agg", "c2"): {"sources_sha": "feb9f327e4b42342", "variants_sha": "c62b14057a3f9b21",
+                      "bytes_per_launch": 1065128303},
 }
 
 
@@ -210,6 +211,9 @@ def c5_pick_quality(ctx, args):
 
     pool = args.pq_pool_rows
     lim = args.pq_limit_ms
+    # the optimizer measures the kernels compiled ahead of time (compiling
+    # every variant of every plan at run time would dominate the search)
+    ctx.set_jit(False)
     seed_train, seed_test = dg.MASTER_SEED + 1005, dg.MASTER_SEED + 5
     log(f"[bench] pick quality: pools of {pool} rows, {args.pq_train} training / {args.pq_test} test pipelines")
     tr_pools = dg.c5_pools(pool, seed_train)
