@@ -531,15 +531,29 @@ template <int HT, int HASH>
 __device__ __forceinline__ int32_t lslot(uint64_t* lkeys, uint32_t llog2, const HkHash& h, uint64_t key) {
   if (HT == HK_LIN) {
     const uint32_t mask = (1u << llog2) - 1u;
-    uint32_t s = hslot<HASH>(key, h.a[0], llog2);
-    for (int i = 0; i < HK_LOCAL_PROBES; ++i) {
-      uint64_t cur = lkeys[s];
+    const uint32_t s0 = hslot<HASH>(key, h.a[0], llog2);
+    uint64_t cur = lkeys[s0];
+    if (cur == key) return static_cast<int32_t>(s0);
+    if (cur == HK_EMPTY) {
+      cur = at_cas<true>(&lkeys[s0], HK_EMPTY, key);
+      if (cur == HK_EMPTY || cur == key) return static_cast<int32_t>(s0);
+    }
+    // the rest of the probe window in one round trip instead of one per slot.
+    // A slot only ever changes from empty to a key, so a key read here stays,
+    // and an empty slot read here is settled by the compare-and-swap: the
+    // outcome is that of probing the slots one by one.
+    uint64_t win[HK_LOCAL_PROBES - 1];
+#pragma unroll
+    for (int i = 1; i < HK_LOCAL_PROBES; ++i) win[i - 1] = lkeys[(s0 + i) & mask];
+#pragma unroll
+    for (int i = 1; i < HK_LOCAL_PROBES; ++i) {
+      const uint32_t s = (s0 + i) & mask;
+      cur = win[i - 1];
       if (cur == key) return static_cast<int32_t>(s);
       if (cur == HK_EMPTY) {
         cur = at_cas<true>(&lkeys[s], HK_EMPTY, key);
         if (cur == HK_EMPTY || cur == key) return static_cast<int32_t>(s);
       }
-      s = (s + 1) & mask;
     }
     return -1;
   } else {

@@ -116,6 +116,31 @@ def test_overflow_partitioning_wide_sums_two_keys(ctx):
     assert ref["rows"] > 20_000
 
 
+@pytest.mark.parametrize("aggs", [[("count", None, False), ("sum", "v", False), ("min", "v", False),
+                                   ("max", "v", False)],
+                                  [("count", None, False)]])
+def test_overflow_partitioning_one_hot_region(ctx, aggs):
+    # The first half of the rows (in scan order) cycles over 300k keys, so a
+    # workgroup's LDS table is full before the second half, which holds one
+    # key only, begins. On a coalesced grid every workgroup then spills that
+    # key's rows, so one table region receives half of all rows and its owner
+    # aggregates 1.2M entries on one slot. COUNT alone spills keys without values.
+    rng = np.random.default_rng(31)
+    n = 2_400_000
+    key = np.empty(n, np.int32)
+    key[:n // 2] = (np.arange(n // 2) % 300_000) + 1
+    key[n // 2:] = -5
+    t = {"g": key, "v": rng.integers(-(1 << 40), 1 << 40, size=n, dtype=np.int64)}
+    spec = {"builds": [], "main": {"table": "t", "filters": [], "probes": [], "arith": [],
+                                   "group_by": ["g"], "aggs": aggs, "groups_hint": 300_001}}
+    vs = [v for v in local_linear(all_variants(ctx, {"t": t}, spec))
+          if v.mem == 1 and v.thread_mult <= 2 and v.wg_size >= 256]
+    vs = sample(vs, 16, seed=9)
+    say("overflow partitioning, one hot region", len(aggs), "aggregates")
+    _, ref = run_variants(ctx, {"t": t}, spec, vs, label="spill-one-region")
+    assert ref["rows"] == 300_001
+
+
 def test_c3_star_join_sampled_variants(ctx):
     tables, spec = dg.c3_star_join(n=200_000, dims=(250, 2000, 300, 800), sel=(60, 50, 60, 40))
     vs = sample(all_variants(ctx, tables, spec), 128, seed=2)
