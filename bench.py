@@ -312,7 +312,8 @@ def main():
     ctx = hawk.Context(0)
     if not args.no_jit and not args.explore:
         ctx.set_jit(True)  # aggregation kernels compiled for each plan structure during the warm-up
-    ncu, _ = ctx.device_info()
+    ncu, lds_bytes = ctx.device_info()
+    log(f"[bench] device: {ncu} compute units, {lds_bytes} LDS bytes per workgroup")
     pipes = []
     total_rows = 0
     for name, tables, spec in make_pipelines(args.workload, args.rows):

@@ -22,7 +22,8 @@ namespace {
 
 const uint32_t kMults[7] = {1, 8, 64, 256, 1024, 16384, 65536};  // Section 9.2
 const uint32_t kWgs[7] = {16, 32, 64, 128, 256, 512, 1024};       // Section 9.2
-const int64_t kSpillLds = 64512;  // LDS bytes of a spill region / of a table plus its histogram
+const int64_t kSpillLds = 64512;    // LDS bytes of a local table plus its spill histogram (two workgroups per CU)
+const int64_t kRegionLds = 163840;  // LDS bytes of a spill region, at most
 const int64_t kLdsBudget = 64512;  // LDS bytes of a local table (64 KB with the static words: two workgroups per CU)
 const int kMaxAttempts = 12;
 
@@ -710,16 +711,22 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
   c.llog2 = 0;
   c.reps = 1;
   c.rlog2 = T.log2cap;
+  // A grid of at most one workgroup per CU lets each take the CU's LDS (less
+  // 1 KB for static words); a wider grid keeps two workgroups per CU. The
+  // table then leaves 8 KB for a spill histogram.
+  const bool whole_cu = groups <= ctx->num_cus;
+  const int64_t wg_lds = whole_cu ? std::min<int64_t>(ctx->lds_bytes, kRegionLds) - 1024 : kSpillLds;
+  const int64_t table_budget = whole_cu ? wg_lds - 8192 : kLdsBudget;
   if (v->agg_strategy == HAWK_LOCAL) {
     const uint32_t want = std::max<uint32_t>(4, ceil_log2(static_cast<uint64_t>(groups_hint) * 2));
     uint32_t fit = 0;
-    while ((int64_t(2) << fit) * W * 8 <= kLdsBudget) ++fit;
+    while ((int64_t(2) << fit) * W * 8 <= table_budget) ++fit;
     c.llog2 = std::min(want, fit);
     if ((int64_t(1) << c.llog2) * W * 8 > ctx->lds_bytes)
       return set_error(ctx, HAWK_E_INFEASIBLE, "local table does not fit in LDS");
     // copies of the aggregate words while they fit the budget (up to 16)
     const int64_t LC = int64_t(1) << c.llog2;
-    while (c.reps < 16 && (LC + (W - 1) * (2 * c.reps) * (LC + 1)) * 8 <= kLdsBudget) c.reps *= 2;
+    while (c.reps < 16 && (LC + (W - 1) * (2 * c.reps) * (LC + 1)) * 8 <= table_budget) c.reps *= 2;
   }
   // Overflow partitioning: with the local strategy and linear probing, when
   // the LDS table cannot hold every group, rows that miss it are spilled and
@@ -727,17 +734,20 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
   // each updating the table with device-scope atomics. A region (aggregated
   // in LDS by its owner) takes at most 64 KB; the partition histogram of a
   // workgroup sits beside its LDS table.
-  // Regions as large as 64 KB of LDS allow, but at least 256 of them (so
-  // that the regions' owners fill the device) while they keep 64 slots.
+  // Regions as large as one workgroup's LDS allows (up to 160 KB: fewer,
+  // larger regions spread the spilled rows over fewer buckets), but at least
+  // 256 of them (so that the regions' owners fill the device) while they
+  // keep 64 slots.
+  const int64_t region_lds = std::min<int64_t>(ctx->lds_bytes, kRegionLds);
   uint32_t rlog2 = 0;
-  while ((int64_t(2) << rlog2) * W * 8 <= kSpillLds) ++rlog2;
+  while ((int64_t(2) << rlog2) * W * 8 <= region_lds) ++rlog2;
   if (T.log2cap >= 14 && T.log2cap - 8 < rlog2) rlog2 = T.log2cap - 8;
   else if (T.log2cap < 14 && rlog2 > 6) rlog2 = 6;
   const int64_t nparts = T.log2cap > rlog2 ? int64_t(1) << (T.log2cap - rlog2) : 1;
   const int64_t LC = int64_t(1) << c.llog2;
   const int64_t table_bytes = (LC + (W - 1) * c.reps * (c.reps > 1 ? LC + 1 : LC)) * 8;
   c.spill = v->agg_strategy == HAWK_LOCAL && v->ht == HAWK_LINEAR_PROBING && T.log2cap > c.llog2 && rlog2 >= 6 &&
-            nparts >= 2 && table_bytes + nparts * 4 <= kSpillLds && nparts * groups <= (int64_t(1) << 26) &&
+            nparts >= 2 && table_bytes + nparts * 4 <= wg_lds && nparts * groups <= (int64_t(1) << 26) &&
             P.nrows > 0 && ctx->lds_bytes >= kSpillLds;
   if (c.spill) {
     c.rlog2 = rlog2;

@@ -41,7 +41,7 @@ hipError_t hk_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t m,
 // are appended to sp's regions instead of updating the table); hk_spill step 0
 // then regroups the entries by table region (offs = exclusive scan of sp.hist,
 // *total = entries) into `part`, step 1 aggregates each region in LDS (a
-// region of 2^T.rlog2 slots must fit in the launch's LDS)
+// region of 2^T.rlog2 slots must fit in one workgroup's LDS)
 hipError_t hk_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
                   int strat, int64_t groups, int32_t wg, uint32_t llog2, const uint64_t* ident, int32_t nw, int* err,
                   const HkSpill* sp = nullptr, int32_t reps = 1);

@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t l
 // partitions (offsets = exclusive scan of the partition-major histogram).
 // Each thread handles SU entries per round: their loads are all issued before
 // the first cursor update; two-word entries move as one 16-byte store.
-#define SPILL_SU 4
+#define SPILL_SU 8
 template <int HASH>
 __global__ void __launch_bounds__(1024) k_spill_scatter(HkSpill sp, const uint32_t* __restrict__ offs, int64_t nwg,
                                                         HkHash h, uint32_t log2cap, uint32_t rlog2,
@@ -193,8 +193,10 @@ hipError_t hk_spill_shape(hipStream_t st, int step, const HkPlan& P, const HkAgg
     DISPATCH2(hash, HS, hipLaunchKernelGGL((k_spill_scatter<HS>), hk_wg_grid(nwg), dim3(1024), lds, st, sp, offs, nwg,
                                            P.hash, T.log2cap, T.rlog2, part));
   } else {
+    // a region larger than half the LDS of a CU: one workgroup per CU, of 1024 threads
     const size_t lds = (static_cast<size_t>(1) << T.rlog2) * T.slot_words * sizeof(uint64_t);
-    DISPATCH2(hash, HS, hipLaunchKernelGGL((k_spill_agg<HS, S>), dim3(static_cast<uint32_t>(sp.nparts)), dim3(512),
+    const uint32_t threads = lds > 81920 ? 1024 : 512;
+    DISPATCH2(hash, HS, hipLaunchKernelGGL((k_spill_agg<HS, S>), dim3(static_cast<uint32_t>(sp.nparts)), dim3(threads),
                                            lds, st, P, T, sp, offs, total, nwg, part, err));
   }
   return hipGetLastError();
