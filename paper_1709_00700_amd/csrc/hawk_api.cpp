@@ -764,6 +764,7 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
     sp.nrows = P.nrows;
     sp.bs = static_cast<int32_t>(v->wg_size);
     sp.coal = v->mem == HAWK_COALESCED ? 1 : 0;
+    sp.fcap = static_cast<int32_t>(int64_t(1) << c.llog2);
   }
   return HAWK_OK;
 }
@@ -1038,6 +1039,8 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
       ALLOC(stmp, uint32_t*, static_cast<size_t>(hk_scan_tmp_words(m)) * 4, false);
       ALLOC(total, uint64_t*, 8, false);
       ALLOC(part, uint64_t*, static_cast<size_t>(P.nrows * sp.ew) * 8, false);
+      ALLOC(sp.flush, uint64_t*, static_cast<size_t>(groups * sp.fcap * W) * 8, false);
+      ALLOC(sp.foffs, uint32_t*, static_cast<size_t>(groups * (cfg.nparts + 1)) * 4, false);
       {
         ProfScope ps(ctx, "k_agg");
         HIPCHK(agg_kernel_launch(ctx, X.st, v, P, T, cfg, ident, W, res->d_err, &sp), "aggregation kernel");
@@ -1048,11 +1051,12 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
       }
       {
         ProfScope ps(ctx, "k_spill_scatter");
-        HIPCHK(hk_spill(X.st, 0, P, T, v->hash, sp, offs, total, groups, part, res->d_err), "spill regrouping");
+        HIPCHK(hk_spill(X.st, 0, P, T, v->hash, sp, ident, W, offs, total, groups, part, res->d_err), "spill regrouping");
       }
       {
         ProfScope ps(ctx, "k_spill_agg");
-        HIPCHK(hk_spill(X.st, 1, P, T, v->hash, sp, offs, total, groups, part, res->d_err), "spill aggregation");
+        HIPCHK(hk_spill(X.st, 1, P, T, v->hash, sp, ident, W, offs, total, groups, part, res->d_err),
+               "spill aggregation");
       }
     } else {
       ProfScope ps(ctx, "k_agg");

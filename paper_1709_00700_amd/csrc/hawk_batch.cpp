@@ -248,7 +248,12 @@ hawk_status setup_memory(hawk_batch* B) {
           d.stmp = static_cast<uint32_t*>(balloc(B, static_cast<size_t>(hk_scan_tmp_words(m)) * 4, B->allocs));
           d.total = static_cast<uint64_t*>(balloc(B, 8, B->allocs));
           d.part = static_cast<uint64_t*>(balloc(B, static_cast<size_t>(n * d.sp.ew) * 8, B->allocs));
-          if (!d.sp.buf || !d.sp.hist || !d.sp.cnt || !d.offs || !d.stmp || !d.total || !d.part)
+          d.sp.flush = static_cast<uint64_t*>(
+              balloc(B, static_cast<size_t>(d.cfg.groups * d.sp.fcap * W) * 8, B->allocs));
+          d.sp.foffs = static_cast<uint32_t*>(
+              balloc(B, static_cast<size_t>(d.cfg.groups * (d.cfg.nparts + 1)) * 4, B->allocs));
+          if (!d.sp.buf || !d.sp.hist || !d.sp.cnt || !d.offs || !d.stmp || !d.total || !d.part || !d.sp.flush ||
+              !d.sp.foffs)
             return berr(B, HAWK_E_OOM, "batch spill buffers");
         }
         if (ctx->jit) {
@@ -390,9 +395,11 @@ hawk_status setup_schedule(hawk_batch* B, const hawk_batch_opts& o) {
     if (le == hipSuccess && d.cfg.spill) {
       le = hk_scan(B->cap, d.sp.hist, d.offs, d.cfg.nparts * d.cfg.groups, d.stmp, d.total);
       if (le == hipSuccess)
-        le = hk_spill(B->cap, 0, Q.plan, Q.table, d.v.hash, d.sp, d.offs, d.total, d.cfg.groups, d.part, B->d_err);
+        le = hk_spill(B->cap, 0, Q.plan, Q.table, d.v.hash, d.sp, Q.ident.w, Q.ident.nw, d.offs, d.total, d.cfg.groups,
+                      d.part, B->d_err);
       if (le == hipSuccess)
-        le = hk_spill(B->cap, 1, Q.plan, Q.table, d.v.hash, d.sp, d.offs, d.total, d.cfg.groups, d.part, B->d_err);
+        le = hk_spill(B->cap, 1, Q.plan, Q.table, d.v.hash, d.sp, Q.ident.w, Q.ident.nw, d.offs, d.total, d.cfg.groups,
+                      d.part, B->d_err);
     }
   }
   for (int s = 0; s < 5 && le == hipSuccess; ++s)

@@ -499,25 +499,65 @@ __device__ __forceinline__ void agg_fold_w1(uint64_t* a, const uint64_t* b, int6
   }
 }
 
-// merges an LDS slot (word j >= 1 at l1[(j - 1) * stride]) into a global slot g
-template <class S>
-__device__ __forceinline__ void agg_merge_w1(uint64_t* g, const uint64_t* l1, int64_t stride, const HkPlan& P) {
-  at_add<false>(g + 1, l1[0]);
+// merges a slot's count and aggregate words (word j >= 1 at l1[(j - 1) * stride])
+// into slot d (word j at d[j * ds]); WGS: workgroup-scope atomics (LDS)
+template <bool WGS, class S>
+__device__ __forceinline__ void agg_merge_into(uint64_t* d, int64_t ds, const uint64_t* l1, int64_t stride,
+                                               const HkPlan& P) {
+  at_add<WGS>(d + ds, l1[0]);
 #pragma unroll
   for (int a = 0; a < S::aggs; ++a) {
     if (a >= P.naggs) break;
     const HkAgg& A = P.aggs[a];
     if (A.fn == HK_COUNT) continue;
     const uint64_t x = l1[(A.word - 1) * stride];
+    uint64_t* y = d + A.word * ds;
     if (A.fn == HK_SUM || A.fn == HK_AVG) {
-      if (A.wide) at_add128_pair<false>(g + A.word, g + A.word + 1, x, static_cast<int64_t>(l1[A.word * stride]));
-      else at_add<false>(g + A.word, x);
+      if (A.wide) at_add128_pair<WGS>(y, y + ds, x, static_cast<int64_t>(l1[A.word * stride]));
+      else at_add<WGS>(y, x);
     } else if (A.fn == HK_MIN) {
-      at_min<false>(g + A.word, static_cast<int64_t>(x));
+      at_min<WGS>(y, static_cast<int64_t>(x));
     } else {
-      at_max<false>(g + A.word, static_cast<int64_t>(x));
+      at_max<WGS>(y, static_cast<int64_t>(x));
     }
   }
+}
+
+// merges an LDS slot (word j >= 1 at l1[(j - 1) * stride]) into a global slot g
+template <class S>
+__device__ __forceinline__ void agg_merge_w1(uint64_t* g, const uint64_t* l1, int64_t stride, const HkPlan& P) {
+  agg_merge_into<false, S>(g, 1, l1, stride, P);
+}
+
+// exclusive prefix sum of a[0..n) (LDS) in place by the whole workgroup; the
+// prefixes also go to out[0..n), the total to out[n]. wave_tot: LDS words,
+// one per wave of the workgroup. Ends with a barrier.
+__device__ __forceinline__ void wg_exclusive_scan(uint32_t* a, int n, uint32_t* out, uint32_t* wave_tot) {
+  const int bs = blockDim.x, t = threadIdx.x;
+  const int K = (n + bs - 1) / bs;
+  const int b = t * K < n ? t * K : n;
+  const int e = b + K < n ? b + K : n;
+  uint32_t sum = 0;
+  for (int i = b; i < e; ++i) sum += a[i];
+  const int lane = __lane_id();
+  uint32_t x = sum;  // inclusive scan of the chunk sums within the wave
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, WAVE);
+    if (lane >= d) x += y;
+  }
+  const int wv = t / WAVE;
+  if (lane == WAVE - 1 || t == bs - 1) wave_tot[wv] = x;
+  __syncthreads();
+  uint32_t run = x - sum;
+  for (int j = 0; j < wv; ++j) run += wave_tot[j];
+  for (int i = b; i < e; ++i) {
+    const uint32_t v = a[i];
+    a[i] = run;
+    out[i] = run;
+    run += v;
+  }
+  if (t == bs - 1) out[n] = run;  // the last thread's chunk ends at n
+  __syncthreads();
 }
 
 // merges an LDS slot (word j at l[j * stride]) into a global slot g

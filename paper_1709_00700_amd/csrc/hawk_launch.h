@@ -38,9 +38,10 @@ hipError_t hk_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t m,
 // grouped aggregation (cuckoo: key phase first; reps: copies of the aggregate
 // words of the LDS table, a power of two), non-grouped aggregation, result extraction
 // sp != null: spill mode of the local strategy with linear probing (LDS misses
-// are appended to sp's regions instead of updating the table); hk_spill step 0
-// then regroups the entries by table region (offs = exclusive scan of sp.hist,
-// *total = entries) into `part`, step 1 aggregates each region in LDS (a
+// are appended to sp's regions instead of updating the table, and the LDS
+// tables end as merge entries in sp.flush); hk_spill step 0 then regroups the
+// entries by table region (offs = exclusive scan of sp.hist, *total = entries)
+// into `part`, step 1 aggregates each region in LDS from the identity (a
 // region of 2^T.rlog2 slots must fit in one workgroup's LDS)
 hipError_t hk_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
                   int strat, int64_t groups, int32_t wg, uint32_t llog2, const uint64_t* ident, int32_t nw, int* err,
@@ -57,7 +58,8 @@ inline size_t hk_agg_lds_bytes(int strat, uint32_t llog2, int32_t nw, int32_t re
   return lds;
 }
 hipError_t hk_spill(hipStream_t st, int step, const HkPlan& P, const HkAggTable& T, int hash, const HkSpill& sp,
-                    const uint32_t* offs, const uint64_t* total, int64_t nwg, uint64_t* part, int* err);
+                    const uint64_t* ident, int32_t nw, const uint32_t* offs, const uint64_t* total, int64_t nwg,
+                    uint64_t* part, int* err);
 hipError_t hk_scalar_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
                          int strat, int64_t groups, int32_t wg, const uint64_t* ident, int32_t nw, int* err);
 hipError_t hk_finalize(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int64_t nslots, int64_t* const* gcols,

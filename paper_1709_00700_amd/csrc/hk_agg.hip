@@ -67,43 +67,65 @@ __global__ void __launch_bounds__(1024) k_spill_scatter(HkSpill sp, const uint32
   }
 }
 
-// spill, step 3: workgroup p owns table region p for the whole kernel: it
-// copies the region into LDS, aggregates partition p's entries there (LDS
-// atomics, probing confined to the region as in the table) and writes the
-// region back
+// spill, step 3: workgroup p owns table region p for the whole kernel. No
+// other kernel writes the region's slots in spill mode, so it starts from the
+// identity in LDS, merges the workgroups' merge entries of region p, then
+// aggregates partition p's spilled entries (LDS atomics, probing confined to
+// the region as in the table) and writes the region back.
 template <int HASH, class S>
-__global__ void __launch_bounds__(1024) k_spill_agg(HkPlan P, HkAggTable T, HkSpill sp, const uint32_t* __restrict__ offs,
-                                                   const uint64_t* total, int64_t nwg, const uint64_t* __restrict__ in,
-                                                   int* err) {
+__global__ void __launch_bounds__(1024) k_spill_agg(HkPlan P, HkAggTable T, HkSpill sp, HkIdent id,
+                                                   const uint32_t* __restrict__ offs, const uint64_t* total,
+                                                   int64_t nwg, const uint64_t* __restrict__ in, int* err) {
   const int64_t p = blockIdx.x;
   const int64_t b = offs[p * nwg];
   const int64_t e = p + 1 < sp.nparts ? static_cast<int64_t>(offs[(p + 1) * nwg]) : static_cast<int64_t>(*total);
-  if (b >= e) return;  // nothing spilled here (uniform over the workgroup)
+  const int64_t fstride = sp.nparts + 1;
+  // The region may take all the LDS a workgroup can have, so this kernel
+  // holds no static LDS: the flag below is the region's first word, read
+  // before the region is initialised.
   extern __shared__ uint64_t lt[];  // word w of region slot i at lt[w * R + i]
+  uint32_t* flag = reinterpret_cast<uint32_t*>(lt);
+  if (threadIdx.x == 0) *flag = 0;
+  __syncthreads();
+  for (int64_t w = threadIdx.x; w < nwg; w += blockDim.x)
+    if (sp.foffs[w * fstride + p + 1] > sp.foffs[w * fstride + p]) atomicOr(flag, 1u);
+  __syncthreads();
+  const bool merges = *flag != 0;
+  __syncthreads();
+  // nothing spilled and no merge entries here: the region keeps its identity
+  if (!merges && b >= e) return;
   const int64_t R = static_cast<int64_t>(1) << T.rlog2;
   const int W = T.slot_words;
   uint64_t* g = T.words + p * R * W;
-  for (int64_t i = threadIdx.x; i < R * W; i += blockDim.x) lt[(i % W) * R + i / W] = g[i];
+  for (int64_t i = threadIdx.x; i < R * W; i += blockDim.x) lt[i] = id.w[i / R];
   __syncthreads();
   const uint32_t rmask = static_cast<uint32_t>(R - 1);
-  v16i64 r = {};
-  auto apply = [&](uint64_t key) {
+  // the region slot of a key (inserted if new); -1 when the region is full
+  auto find = [&](uint64_t key) -> int32_t {
     uint32_t s = hslot<HASH>(key, P.hash.a[0], T.log2cap) & rmask;
-    int32_t found = -1;
     for (uint32_t k = 0; k <= rmask; ++k) {
       uint64_t cur = lt[s];
       if (cur == HK_EMPTY) cur = at_cas<true>(&lt[s], HK_EMPTY, key);
-      if (cur == HK_EMPTY || cur == key) {
-        found = static_cast<int32_t>(s);
-        break;
-      }
+      if (cur == HK_EMPTY || cur == key) return static_cast<int32_t>(s);
       s = (s + 1) & rmask;
     }
-    if (found < 0) {
-      set_err(err, HK_ERR_CAPACITY);  // the region is full: the caller retries with a larger table
-      return;
+    set_err(err, HK_ERR_CAPACITY);  // the region is full: the caller retries with a larger table
+    return -1;
+  };
+  // merge entries: thread by source workgroup
+  for (int64_t w = threadIdx.x; w < nwg; w += blockDim.x) {
+    const int64_t mb = sp.foffs[w * fstride + p], me = sp.foffs[w * fstride + p + 1];
+    const uint64_t* src = sp.flush + w * sp.fcap * W;
+    for (int64_t i = mb; i < me; ++i) {
+      const uint64_t* ent = src + i * W;
+      const int32_t s = find(ent[0]);
+      if (s >= 0) agg_merge_into<true, S>(lt + s, R, ent + 1, 1, P);
     }
-    agg_apply<HK_BR, true, S>(lt + found, R, P, r, true);
+  }
+  v16i64 r = {};
+  auto apply = [&](uint64_t key) {
+    const int32_t found = find(key);
+    if (found >= 0) agg_apply<HK_BR, true, S>(lt + found, R, P, r, true);
   };
   if (sp.ew == 2) {
     // one input value per entry: SU entries per thread and round, loaded first
@@ -154,6 +176,19 @@ __global__ void __launch_bounds__(256) k_agg_keys(HkPlan P, HkAggTable T, int* e
   }
 }
 
+// a launch whose static plus dynamic LDS exceeds one workgroup's maximum
+// would abort the queue: such a launch is refused here instead
+template <class K>
+static hipError_t lds_fits(K kernel, size_t dyn) {
+  hipFuncAttributes a;
+  hipError_t e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kernel));
+  if (e != hipSuccess) return e;
+  int dev = 0, maxl = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&maxl, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
+  return a.sharedSizeBytes + dyn <= static_cast<size_t>(maxl) ? hipSuccess : hipErrorInvalidValue;
+}
+
 template <class S>
 hipError_t hk_agg_shape(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
                         int strat, int64_t groups, int32_t wg, uint32_t llog2, const HkIdent& id, int* err,
@@ -172,22 +207,31 @@ hipError_t hk_agg_shape(hipStream_t st, const HkPlan& P, const HkAggTable& T, in
     // spill mode exists for the local strategy with linear probing
     if (strat != HK_LOCAL || ht != HK_LIN) return hipErrorInvalidValue;
     const HkSpill S1 = *sp;
-    DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(hash, HS,
-              hipLaunchKernelGGL((k_agg<M, PR, HK_LIN, HS, HK_LOCAL, S, true>), g, b, lds, st, P, T, llog2, id,
-                                 groups, err, S1, reps))));
-    return hipGetLastError();
+    hipError_t le = hipSuccess;
+    DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(hash, HS, {
+      le = lds_fits(k_agg<M, PR, HK_LIN, HS, HK_LOCAL, S, true>, lds);
+      if (le == hipSuccess)
+        hipLaunchKernelGGL((k_agg<M, PR, HK_LIN, HS, HK_LOCAL, S, true>), g, b, lds, st, P, T, llog2, id, groups,
+                           err, S1, reps);
+    })));
+    return le != hipSuccess ? le : hipGetLastError();
   }
   HkSpill none;
   std::memset(&none, 0, sizeof(none));
-  DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS, DISPATCH2(strat, SG,
-            hipLaunchKernelGGL((k_agg<M, PR, HT, HS, SG, S, false>), g, b, lds, st, P, T, llog2, id, groups, err,
-                               none, reps))))));
-  return hipGetLastError();
+  hipError_t le = hipSuccess;
+  DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS, DISPATCH2(strat, SG, {
+    le = lds_fits(k_agg<M, PR, HT, HS, SG, S, false>, lds);
+    if (le == hipSuccess)
+      hipLaunchKernelGGL((k_agg<M, PR, HT, HS, SG, S, false>), g, b, lds, st, P, T, llog2, id, groups, err, none,
+                         reps);
+  })))));
+  return le != hipSuccess ? le : hipGetLastError();
 }
 
 template <class S>
 hipError_t hk_spill_shape(hipStream_t st, int step, const HkPlan& P, const HkAggTable& T, int hash, const HkSpill& sp,
-                          const uint32_t* offs, const uint64_t* total, int64_t nwg, uint64_t* part, int* err) {
+                          const HkIdent& id, const uint32_t* offs, const uint64_t* total, int64_t nwg, uint64_t* part,
+                          int* err) {
   if (step == 0) {
     const size_t lds = static_cast<size_t>(sp.nparts) * sizeof(uint32_t);
     DISPATCH2(hash, HS, hipLaunchKernelGGL((k_spill_scatter<HS>), hk_wg_grid(nwg), dim3(1024), lds, st, sp, offs, nwg,
@@ -196,8 +240,14 @@ hipError_t hk_spill_shape(hipStream_t st, int step, const HkPlan& P, const HkAgg
     // a region larger than half the LDS of a CU: one workgroup per CU, of 1024 threads
     const size_t lds = (static_cast<size_t>(1) << T.rlog2) * T.slot_words * sizeof(uint64_t);
     const uint32_t threads = lds > 81920 ? 1024 : 512;
-    DISPATCH2(hash, HS, hipLaunchKernelGGL((k_spill_agg<HS, S>), dim3(static_cast<uint32_t>(sp.nparts)), dim3(threads),
-                                           lds, st, P, T, sp, offs, total, nwg, part, err));
+    hipError_t le = hipSuccess;
+    DISPATCH2(hash, HS, {
+      le = lds_fits(k_spill_agg<HS, S>, lds);
+      if (le == hipSuccess)
+        hipLaunchKernelGGL((k_spill_agg<HS, S>), dim3(static_cast<uint32_t>(sp.nparts)), dim3(threads), lds, st, P, T,
+                           sp, id, offs, total, nwg, part, err);
+    });
+    if (le != hipSuccess) return le;
   }
   return hipGetLastError();
 }
@@ -206,4 +256,5 @@ template hipError_t hk_agg_shape<HK_SHAPE_CLASS>(hipStream_t, const HkPlan&, con
                                                  int64_t, int32_t, uint32_t, const HkIdent&, int*, const HkSpill*,
                                                  int32_t);
 template hipError_t hk_spill_shape<HK_SHAPE_CLASS>(hipStream_t, int, const HkPlan&, const HkAggTable&, int, const HkSpill&,
-                                                   const uint32_t*, const uint64_t*, int64_t, uint64_t*, int*);
+                                                   const HkIdent&, const uint32_t*, const uint64_t*, int64_t, uint64_t*,
+                                                   int*);

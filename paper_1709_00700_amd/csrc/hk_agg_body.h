@@ -24,11 +24,13 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
   if (wg_without_rows<MEM>(P.nrows, wgid, nwg, blockDim.x)) {
     if (SPILL) {
       for (int p = threadIdx.x; p < sp.nparts; p += blockDim.x) sp.hist[static_cast<int64_t>(p) * nwg + wgid] = 0;
+      for (int p = threadIdx.x; p <= sp.nparts; p += blockDim.x) sp.foffs[wgid * (sp.nparts + 1) + p] = 0;
       if (threadIdx.x == 0) sp.cnt[wgid] = 0;
     }
     return;
   }
   __shared__ uint32_t spill_cursor;
+  __shared__ uint32_t wave_tot[1024 / WAVE];
   const int64_t LC = STRAT == HK_LOCAL ? (static_cast<int64_t>(1) << llog2) : 0;
   const int64_t RS = reps > 1 ? LC + 1 : LC;
   const int64_t WS = reps * RS;  // from word j to word j + 1 of one copy
@@ -133,7 +135,7 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
       row_step(rk, f[k]);
     }
   }
-  if (STRAT == HK_LOCAL) {
+  if (STRAT == HK_LOCAL && !SPILL) {
     __syncthreads();
     for (int64_t s = threadIdx.x; s < LC; s += blockDim.x) {
       const uint64_t key = lds[s];
@@ -144,9 +146,37 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
       uint64_t* g = gslot<HT, HASH>(T, P.hash, key, err);
       if (g) agg_merge_w1<S>(g, c0, WS, P);
     }
-    if (SPILL) {
-      for (int p = threadIdx.x; p < sp.nparts; p += blockDim.x) sp.hist[static_cast<int64_t>(p) * nwg + wgid] = hist[p];
-      if (threadIdx.x == 0) sp.cnt[wgid] = *cursor < rcap ? *cursor : static_cast<uint32_t>(rcap);
+  }
+  if (STRAT == HK_LOCAL && SPILL) {
+    // the spill histogram goes out, then the same LDS words count this
+    // table's slots by region and, scanned, place them as merge entries
+    __syncthreads();
+    for (int p = threadIdx.x; p < sp.nparts; p += blockDim.x) sp.hist[static_cast<int64_t>(p) * nwg + wgid] = hist[p];
+    if (threadIdx.x == 0) sp.cnt[wgid] = *cursor < rcap ? *cursor : static_cast<uint32_t>(rcap);
+    __syncthreads();
+    for (int p = threadIdx.x; p < sp.nparts; p += blockDim.x) hist[p] = 0;
+    __syncthreads();
+    for (int64_t s = threadIdx.x; s < LC; s += blockDim.x) {
+      const uint64_t key = lds[s];
+      if (key == HK_EMPTY) continue;
+      uint64_t* c0 = lw1 + s;
+      for (int32_t c = 1; c < reps; ++c) agg_fold_w1<S>(c0, c0 + c * RS, WS, P);
+      if (c0[0] == 0) continue;  // only predicated rows that did not pass reached this group
+      atomicAdd(&hist[hslot<HASH>(key, P.hash.a[0], T.log2cap) >> T.rlog2], 1u);
+    }
+    __syncthreads();
+    wg_exclusive_scan(hist, sp.nparts, sp.foffs + wgid * (sp.nparts + 1), wave_tot);
+    const int W = T.slot_words;
+    uint64_t* fl = sp.flush + wgid * sp.fcap * W;
+    for (int64_t s = threadIdx.x; s < LC; s += blockDim.x) {
+      const uint64_t key = lds[s];
+      if (key == HK_EMPTY) continue;
+      const uint64_t* c0 = lw1 + s;  // folded above by this thread
+      if (c0[0] == 0) continue;
+      const uint32_t pos = atomicAdd(&hist[hslot<HASH>(key, P.hash.a[0], T.log2cap) >> T.rlog2], 1u);
+      uint64_t* ent = fl + static_cast<int64_t>(pos) * W;
+      ent[0] = key;
+      for (int j = 1; j < W; ++j) ent[j] = c0[(j - 1) * WS];
     }
   }
 }

@@ -13,7 +13,8 @@ hipError_t hk_agg_shape(hipStream_t st, const HkPlan& P, const HkAggTable& T, in
                         const HkSpill* sp, int32_t reps);
 template <class S>
 hipError_t hk_spill_shape(hipStream_t st, int step, const HkPlan& P, const HkAggTable& T, int hash, const HkSpill& sp,
-                          const uint32_t* offs, const uint64_t* total, int64_t nwg, uint64_t* part, int* err);
+                          const HkIdent& id, const uint32_t* offs, const uint64_t* total, int64_t nwg, uint64_t* part,
+                          int* err);
 template <class S>
 hipError_t hk_scalar_shape(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
                            int strat, int64_t groups, int32_t wg, const HkIdent& id);
@@ -52,8 +53,10 @@ hipError_t hk_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem,
 }
 
 hipError_t hk_spill(hipStream_t st, int step, const HkPlan& P, const HkAggTable& T, int hash, const HkSpill& sp,
-                    const uint32_t* offs, const uint64_t* total, int64_t nwg, uint64_t* part, int* err) {
-  BY_SHAPE(P, hk_spill_shape<S>(st, step, P, T, hash, sp, offs, total, nwg, part, err));
+                    const uint64_t* ident, int32_t nw, const uint32_t* offs, const uint64_t* total, int64_t nwg,
+                    uint64_t* part, int* err) {
+  const HkIdent id = make_ident(ident, nw);
+  BY_SHAPE(P, hk_spill_shape<S>(st, step, P, T, hash, sp, id, offs, total, nwg, part, err));
 }
 
 hipError_t hk_scalar_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
