@@ -229,22 +229,27 @@ def c5_pick_quality(ctx, args):
                                   progress=lambda m: log("[bench] " + m))
     t_collect = time.perf_counter() - t0
     log(f"[bench] pick quality: {len(y)} training samples in {t_collect:.1f} s")
-    m = hawk.Model(ctx, seed=1)
+    # the picks come from an ensemble of five models (mean + one standard
+    # deviation of their predictions); a single model is scored beside it
+    ens = optimizer.Ensemble(ctx, size=5, penalty=1.0, seed=1)
     t0 = time.perf_counter()
-    loss = m.train(X, y, epochs=300, batch=512, lr=3e-3, seed=2)
+    loss = ens.train(X, y, epochs=300, batch=512, lr=3e-3, seed=2)
     t_train = time.perf_counter() - t0
+    single = ens.models[0]
     t0 = time.perf_counter()
     alg1 = optimizer.alg1_per_kind(ctx, te_h, reps=2, limit_ms=lim)
     t_alg1 = time.perf_counter() - t0
     log("[bench] pick quality: exhaustive search of the test pipelines")
     t0 = time.perf_counter()
-    pq = optimizer.pick_quality(ctx, te_h, m, reps=2, limit_ms=lim, alg1=alg1, progress=lambda m: log("[bench] " + m))
+    pq = optimizer.pick_quality(ctx, te_h, ens, reps=2, limit_ms=lim, alg1=alg1,
+                                progress=lambda m: log("[bench] " + m), extra={"single_model": single})
     t_ex = time.perf_counter() - t0
     pq.update({"training_samples": int(len(y)), "train_mse": loss, "collect_s": t_collect, "train_s": t_train,
                "alg1_s": t_alg1, "exhaustive_s": t_ex, "pool_rows": pool,
                "alg1_variants": {str(k): hawk.format_variant(v) for k, (v, _) in alg1.items()},
-               "alg1_evaluated": {str(k): r["evaluated"] for k, (_, r) in alg1.items()}})
-    m.free()
+               "alg1_evaluated": {str(k): r["evaluated"] for k, (_, r) in alg1.items()},
+               "picker": "ensemble of 5 cost models, mean + 1 sd of predicted ln(ms)"})
+    ens.free()
     return pq
 
 

@@ -305,6 +305,14 @@ hawk_status hawk_mlp_grad_dev(hawk_model* m, const float* dX, const float* dy, i
 /* For each of n queries: the variant of its variant space with the lowest
    predicted time (first on ties); predicted_ms may be NULL. */
 hawk_status hawk_model_pick(hawk_model* m, hawk_query* const* qs, int32_t n, hawk_variant* out, float* predicted_ms);
+/* The same over an ensemble of nm models of one context (trained on the same
+   timings from different seeds): each variant scores the members' mean
+   predicted ln(ms) plus `penalty` (>= 0) times their standard deviation, so
+   a variant the members disagree on, far from the training timings, is not
+   picked for an optimistic error of one model. predicted_ms (may be NULL)
+   receives exp(mean) of each pick. */
+hawk_status hawk_model_pick_ensemble(hawk_model* const* ms, int32_t nm, float penalty, hawk_query* const* qs,
+                                     int32_t n, hawk_variant* out, float* predicted_ms);
 
 /* ------------------------------------------------------------ batched execution */
 /* Many queries as one captured HIP graph of persistent kernels. Section 8

@@ -235,6 +235,66 @@ extern "C" hawk_status hawk_model_predict(hawk_model* M, const float* X, int64_t
   return HAWK_OK;
 }
 
+extern "C" hawk_status hawk_model_pick_ensemble(hawk_model* const* ms, int32_t nm, float penalty,
+                                                hawk_query* const* qs, int32_t n, hawk_variant* out,
+                                                float* predicted_ms) {
+  if (!ms || nm < 1 || !ms[0] || !ms[0]->ctx || !qs || n < 1 || !out || !(penalty >= 0.f)) return HAWK_E_ARG;
+  hawk_model* M = ms[0];  // errors are reported on its context
+  hawk_ctx* ctx = M->ctx;
+  for (int32_t k = 1; k < nm; ++k)
+    if (!ms[k] || ms[k]->ctx != ctx) return set_error(ctx, HAWK_E_ARG, "models of different contexts");
+  std::vector<std::vector<hawk_variant>> spaces;
+  int64_t cols = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!qs[i] || qs[i]->ctx != ctx) return set_error(ctx, HAWK_E_ARG, "query of another context");
+    spaces.push_back(variant_space(qs[i]));
+    cols = std::max<int64_t>(cols, static_cast<int64_t>(spaces.back().size()));
+  }
+  const int64_t m = n * cols;
+  std::vector<float> X(static_cast<size_t>(m) * MLP_IN, 0.f);
+  for (int32_t i = 0; i < n; ++i)
+    for (int64_t c = 0; c < cols; ++c) {
+      const hawk_variant& v = spaces[i][std::min<int64_t>(c, static_cast<int64_t>(spaces[i].size()) - 1)];
+      query_features(qs[i], &v, ctx->num_cus, &X[static_cast<size_t>(i * cols + c) * MLP_IN]);
+    }
+  DevBuf B(ctx);
+  float* dX = static_cast<float*>(B.get(X.size() * 4));
+  float* dO = static_cast<float*>(B.get(static_cast<size_t>(m) * nm * 4));
+  if (!dX || !dO) return set_error(ctx, HAWK_E_OOM, "pick buffers");
+  hipStream_t st = ctx->stream;
+  CK(hipMemcpyAsync(dX, X.data(), X.size() * 4, hipMemcpyHostToDevice, st), "upload features");
+  for (int32_t k = 0; k < nm; ++k)
+    CK(hk_mlp_forward(st, ms[k]->p, ms[k]->mu, ms[k]->sd, dX, m, dO + k * m), "forward");
+  std::vector<float> pred(static_cast<size_t>(m) * nm);
+  CK(hipMemcpyAsync(pred.data(), dO, pred.size() * 4, hipMemcpyDeviceToHost, st), "read predictions");
+  CK(hipStreamSynchronize(st), "synchronize");
+  // score = mean + penalty * standard deviation of the members' ln(ms)
+  for (int32_t i = 0; i < n; ++i) {
+    const int64_t nv = static_cast<int64_t>(spaces[i].size());
+    int64_t best = 0;
+    double best_score = 0, best_mean = 0;
+    for (int64_t c = 0; c < nv; ++c) {
+      double s1 = 0, s2 = 0;
+      for (int32_t k = 0; k < nm; ++k) {
+        const double y = pred[static_cast<size_t>(k * m + i * cols + c)];
+        s1 += y;
+        s2 += y * y;
+      }
+      const double mean = s1 / nm;
+      const double sd = std::sqrt(std::max(0.0, s2 / nm - mean * mean));
+      const double score = mean + penalty * sd;
+      if (c == 0 || score < best_score) {
+        best = c;
+        best_score = score;
+        best_mean = mean;
+      }
+    }
+    out[i] = spaces[i][best];
+    if (predicted_ms) predicted_ms[i] = static_cast<float>(std::exp(best_mean));
+  }
+  return HAWK_OK;
+}
+
 extern "C" hawk_status hawk_model_pick(hawk_model* M, hawk_query* const* qs, int32_t n, hawk_variant* out,
                                        float* predicted_ms) {
   if (!M || !M->ctx || !qs || n < 1 || !out) return HAWK_E_ARG;

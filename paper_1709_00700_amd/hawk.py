@@ -43,6 +43,7 @@ EXPORTS = [
     "hawk_profile_enable", "hawk_profile_read",
     "hawk_model_create", "hawk_model_free", "hawk_model_set_params", "hawk_model_get_params",
     "hawk_model_train", "hawk_model_predict", "hawk_mlp_forward_dev", "hawk_mlp_grad_dev", "hawk_model_pick",
+    "hawk_model_pick_ensemble",
     "hawk_batch_create", "hawk_batch_free", "hawk_batch_run", "hawk_batch_time", "hawk_batch_autotune",
     "hawk_batch_opts_get", "hawk_batch_result", "hawk_ctx_set_jit", "hawk_jit_stats",
 ]
@@ -161,6 +162,8 @@ def L():
             "hawk_mlp_forward_dev": ([vp, vp, i64, vp], i32),
             "hawk_mlp_grad_dev": ([vp, vp, vp, i64, vp, vp], i32),
             "hawk_model_pick": ([vp, P(vp), i32, P(hawk_variant), P(ctypes.c_float)], i32),
+            "hawk_model_pick_ensemble": ([P(vp), i32, ctypes.c_float, P(vp), i32, P(hawk_variant),
+                                          P(ctypes.c_float)], i32),
             "hawk_profile_enable": ([vp, i32], i32),
             "hawk_profile_read": ([vp, ctypes.c_char_p, P(ctypes.c_double), P(i64)], i32),
             "hawk_batch_create": ([vp, P(vp), i32, P(hawk_batch_opts), P(vp)], i32),
@@ -548,6 +551,18 @@ class Model:
         pred = np.empty(len(queries), np.float32)
         check(L().hawk_model_pick(self.handle, W, len(queries), out, _fptr(pred)), self.ctx.handle)
         return list(out), pred
+
+
+def model_pick_ensemble(models: list, penalty: float, queries: list):
+    """hawk_model_pick_ensemble: per query the variant with the lowest mean + penalty * sd
+    of the models' predicted ln(ms); returns (variants, predicted ms)."""
+    M = (ctypes.c_void_p * len(models))(*[m.handle.value for m in models])
+    W = (ctypes.c_void_p * len(queries))(*[q.handle.value for q in queries])
+    out = (hawk_variant * len(queries))()
+    pred = np.empty(len(queries), np.float32)
+    check(L().hawk_model_pick_ensemble(M, len(models), float(penalty), W, len(queries), out, _fptr(pred)),
+          models[0].ctx.handle)
+    return list(out), pred
 
 
 # ---------------------------------------------------------------- batched execution

@@ -65,6 +65,28 @@ def variant_key(q, v) -> str:
     return hawk.format_variant(v)
 
 
+class Ensemble:
+    """Cost models trained on the same timings from different seeds; picks by the
+    members' mean predicted ln(ms) plus `penalty` standard deviations (their
+    disagreement marks predictions far from the training timings)."""
+
+    def __init__(self, ctx, size: int = 5, penalty: float = 1.0, seed: int = 1):
+        self.models = [hawk.Model(ctx, seed=seed + k) for k in range(size)]
+        self.penalty = penalty
+
+    def train(self, X, y, epochs=300, batch=512, lr=3e-3, seed=2) -> float:
+        """Trains every member; returns the members' mean training MSE."""
+        return float(np.mean([m.train(X, y, epochs=epochs, batch=batch, lr=lr, seed=seed + 7919 * k)
+                              for k, m in enumerate(self.models)]))
+
+    def pick(self, queries: list):
+        return hawk.model_pick_ensemble(self.models, self.penalty, queries)
+
+    def free(self):
+        for m in self.models:
+            m.free()
+
+
 def training_set(ctx, queries: list, per_query: int, reps: int, limit_ms: float, seed: int, progress=None):
     """Features and ln(ms) of up to `per_query` sampled variants of each query.
     A pruned variant enters with the limit as its time."""
@@ -99,34 +121,38 @@ def alg1_per_kind(ctx, queries: list, reps: int, limit_ms: float, max_iters: int
 
 
 def pick_quality(ctx, queries: list, model, reps: int, limit_ms: float, alg1: dict | None = None,
-                 progress=None) -> dict:
+                 progress=None, extra: dict | None = None) -> dict:
     """Runtime of the model's per-query picks and of Algorithm 1's per-workload variant,
-    relative to each query's exhaustive best: r_q = t(pick_q) / t(best_q)."""
+    relative to each query's exhaustive best: r_q = t(pick_q) / t(best_q). `extra`
+    names further pickers (objects with .pick(queries)) scored on the same search."""
     if alg1 is None:
         alg1 = alg1_per_kind(ctx, queries, reps, limit_ms)
-    picks, _ = model.pick(queries)
+    pickers = {"model": model, **(extra or {})}
+    picks = {name: p.pick(queries)[0] for name, p in pickers.items()}
     rows = []
-    for n, (q, pv) in enumerate(zip(queries, picks)):
+    for n, q in enumerate(queries):
         if progress:
             progress(f"exhaustive search: query {n + 1}/{len(queries)}")
         table = exhaustive(ctx, q, reps, limit_ms)
         best_key = min(table, key=table.get)
-        best = table[best_key]
-        t_pick = table.get(variant_key(q, pv))
-        if t_pick is None:
-            t_pick = timed(ctx, q, pv, reps, limit_ms)
-        av = alg1[q.kind][0]
-        t_alg1 = table.get(variant_key(q, av))
-        if t_alg1 is None:
-            t_alg1 = timed(ctx, q, av, reps, limit_ms)
-        rows.append({"best_ms": best, "best": best_key, "pick_ms": t_pick, "pick": variant_key(q, pv),
-                     "alg1_ms": t_alg1, "alg1": variant_key(q, av)})
+        row = {"best_ms": table[best_key], "best": best_key}
+        chosen = {name: pv[n] for name, pv in picks.items()}
+        chosen["alg1"] = alg1[q.kind][0]
+        for name, v in chosen.items():
+            t = table.get(variant_key(q, v))
+            if t is None:
+                t = timed(ctx, q, v, reps, limit_ms)
+            key = "pick" if name == "model" else name
+            row[key + "_ms"] = t
+            row[key] = variant_key(q, v)
+        rows.append(row)
 
     def ratios(k):
         return np.array([r[k] / r["best_ms"] for r in rows])
 
     out = {"queries": len(rows)}
-    for name, k in (("model", "pick_ms"), ("alg1", "alg1_ms")):
+    for name in list(pickers) + ["alg1"]:
+        k = ("pick" if name == "model" else name) + "_ms"
         r = ratios(k)
         finite = np.isfinite(r)
         out[name] = {"geomean_ratio": float(np.exp(np.mean(np.log(r[finite])))) if finite.any() else math.inf,
