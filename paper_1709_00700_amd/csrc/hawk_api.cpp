@@ -23,7 +23,7 @@ namespace {
 const uint32_t kMults[7] = {1, 8, 64, 256, 1024, 16384, 65536};  // Section 9.2
 const uint32_t kWgs[7] = {16, 32, 64, 128, 256, 512, 1024};       // Section 9.2
 const int64_t kSpillLds = 64512;    // LDS bytes of a local table plus its spill histogram (two workgroups per CU)
-const int64_t kRegionLds = 163840;  // LDS bytes of a spill region, at most
+const int64_t kCuLds = 163840;      // LDS bytes of a CU, and of a spill region at most
 const int64_t kLdsBudget = 64512;  // LDS bytes of a local table (64 KB with the static words: two workgroups per CU)
 const int kMaxAttempts = 12;
 
@@ -715,7 +715,7 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
   // 1 KB for static words); a wider grid keeps two workgroups per CU. The
   // table then leaves 8 KB for a spill histogram.
   const bool whole_cu = groups <= ctx->num_cus;
-  const int64_t wg_lds = whole_cu ? std::min<int64_t>(ctx->lds_bytes, kRegionLds) - 1024 : kSpillLds;
+  const int64_t wg_lds = whole_cu ? std::min<int64_t>(ctx->lds_bytes, kCuLds) - 1024 : kSpillLds;
   const int64_t table_budget = whole_cu ? wg_lds - 8192 : kLdsBudget;
   if (v->agg_strategy == HAWK_LOCAL) {
     const uint32_t want = std::max<uint32_t>(4, ceil_log2(static_cast<uint64_t>(groups_hint) * 2));
@@ -738,7 +738,7 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
   // larger regions spread the spilled rows over fewer buckets), but at least
   // 256 of them (so that the regions' owners fill the device) while they
   // keep 64 slots.
-  const int64_t region_lds = std::min<int64_t>(ctx->lds_bytes, kRegionLds);
+  const int64_t region_lds = std::min<int64_t>(ctx->lds_bytes, kCuLds);
   uint32_t rlog2 = 0;
   while ((int64_t(2) << rlog2) * W * 8 <= region_lds) ++rlog2;
   if (T.log2cap >= 14 && T.log2cap - 8 < rlog2) rlog2 = T.log2cap - 8;

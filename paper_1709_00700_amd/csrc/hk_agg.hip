@@ -67,6 +67,75 @@ __global__ void __launch_bounds__(1024) k_spill_scatter(HkSpill sp, const uint32
   }
 }
 
+// spill, step 2 for two-word entries: the region is moved in tiles of
+// SU * 1024 entries that are first sorted by partition in LDS (counting sort:
+// ranks from LDS atomics, offsets from a workgroup scan), so that consecutive
+// lanes store consecutive entries of one partition instead of 64 scattered
+// 16-byte stores per instruction. LDS: the tile, then per partition the
+// running output cursor, the tile counts and the tile offsets (nparts + 1),
+// then one word per wave.
+template <int HASH, int SU>
+__global__ void __launch_bounds__(1024) k_spill_scatter_lds(HkSpill sp, const uint32_t* __restrict__ offs,
+                                                            int64_t nwg, HkHash h, uint32_t log2cap, uint32_t rlog2,
+                                                            uint64_t* __restrict__ out) {
+  const int64_t wgid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  if (wgid >= nwg) return;
+  constexpr int TE = SU * 1024;
+  extern __shared__ uint64_t sm[];
+  ulonglong2* tile = reinterpret_cast<ulonglong2*>(sm);
+  const int np = sp.nparts;
+  uint32_t* gcur = reinterpret_cast<uint32_t*>(sm + 2 * TE);
+  uint32_t* tcnt = gcur + np;
+  uint32_t* toff = tcnt + np;
+  uint32_t* wave_tot = toff + np + 1;
+  const int t = threadIdx.x, bs = blockDim.x;
+  for (int p = t; p < np; p += bs) gcur[p] = offs[static_cast<int64_t>(p) * nwg + wgid];
+  const int64_t cnt = sp.cnt[wgid];
+  const ulonglong2* src = reinterpret_cast<const ulonglong2*>(sp.buf + spill_region_start(sp, nwg, wgid) * sp.ew);
+  ulonglong2* dst = reinterpret_cast<ulonglong2*>(out);
+  for (int64_t base = 0; base < cnt; base += TE) {
+    const int n = cnt - base < TE ? static_cast<int>(cnt - base) : TE;
+    for (int p = t; p < np; p += bs) tcnt[p] = 0;
+    __syncthreads();
+    ulonglong2 v[SU];
+    uint32_t pr[SU], rk[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int i = t + u * bs;
+      if (i < n) v[u] = src[base + i];
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int i = t + u * bs;
+      if (i < n) {
+        pr[u] = hslot<HASH>(v[u].x, h.a[0], log2cap) >> rlog2;
+        rk[u] = atomicAdd(&tcnt[pr[u]], 1u);
+      }
+    }
+    __syncthreads();
+    wg_exclusive_scan(tcnt, np, toff, wave_tot);  // toff[p]: first tile slot of partition p; toff[np] = n
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int i = t + u * bs;
+      if (i < n) tile[toff[pr[u]] + rk[u]] = v[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int j = t + u * bs;
+      if (j < n) {
+        const ulonglong2 e = tile[j];
+        const uint32_t p = hslot<HASH>(e.x, h.a[0], log2cap) >> rlog2;
+        dst[static_cast<int64_t>(gcur[p]) + (j - toff[p])] = e;
+      }
+    }
+    __syncthreads();
+    for (int p = t; p < np; p += bs) gcur[p] += toff[p + 1] - toff[p];
+    // the next tile's counts are cleared after this barrier
+    __syncthreads();
+  }
+}
+
 // spill, step 3: workgroup p owns table region p for the whole kernel. No
 // other kernel writes the region's slots in spill mode, so it starts from the
 // identity in LDS, merges the workgroups' merge entries of region p, then
@@ -233,9 +302,37 @@ hipError_t hk_spill_shape(hipStream_t st, int step, const HkPlan& P, const HkAgg
                           const HkIdent& id, const uint32_t* offs, const uint64_t* total, int64_t nwg, uint64_t* part,
                           int* err) {
   if (step == 0) {
-    const size_t lds = static_cast<size_t>(sp.nparts) * sizeof(uint32_t);
-    DISPATCH2(hash, HS, hipLaunchKernelGGL((k_spill_scatter<HS>), hk_wg_grid(nwg), dim3(1024), lds, st, sp, offs, nwg,
-                                           P.hash, T.log2cap, T.rlog2, part));
+    // two-word entries with 1024 threads: tiles sorted in LDS (8192 entries,
+    // else 4096, whichever fits with the partition arrays)
+    int dev = 0, maxl = 0;
+    hipError_t ae = hipGetDevice(&dev);
+    if (ae == hipSuccess) ae = hipDeviceGetAttribute(&maxl, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (ae != hipSuccess) return ae;
+    const size_t side = (3 * static_cast<size_t>(sp.nparts) + 1) * sizeof(uint32_t) + (1024 / WAVE) * sizeof(uint32_t);
+    const size_t l8 = 8192 * 16 + side, l4 = 4096 * 16 + side;
+    if (sp.ew == 2 && l8 <= static_cast<size_t>(maxl)) {
+      hipError_t le = hipSuccess;
+      DISPATCH2(hash, HS, {
+        le = lds_fits(k_spill_scatter_lds<HS, 8>, l8);
+        if (le == hipSuccess)
+          hipLaunchKernelGGL((k_spill_scatter_lds<HS, 8>), hk_wg_grid(nwg), dim3(1024), l8, st, sp, offs, nwg, P.hash,
+                             T.log2cap, T.rlog2, part);
+      });
+      if (le != hipSuccess) return le;
+    } else if (sp.ew == 2 && l4 <= static_cast<size_t>(maxl)) {
+      hipError_t le = hipSuccess;
+      DISPATCH2(hash, HS, {
+        le = lds_fits(k_spill_scatter_lds<HS, 4>, l4);
+        if (le == hipSuccess)
+          hipLaunchKernelGGL((k_spill_scatter_lds<HS, 4>), hk_wg_grid(nwg), dim3(1024), l4, st, sp, offs, nwg, P.hash,
+                             T.log2cap, T.rlog2, part);
+      });
+      if (le != hipSuccess) return le;
+    } else {
+      const size_t lds = static_cast<size_t>(sp.nparts) * sizeof(uint32_t);
+      DISPATCH2(hash, HS, hipLaunchKernelGGL((k_spill_scatter<HS>), hk_wg_grid(nwg), dim3(1024), lds, st, sp, offs,
+                                             nwg, P.hash, T.log2cap, T.rlog2, part));
+    }
   } else {
     // a region larger than half the LDS of a CU: one workgroup per CU, of 1024 threads
     const size_t lds = (static_cast<size_t>(1) << T.rlog2) * T.slot_words * sizeof(uint64_t);
