@@ -166,7 +166,8 @@ __global__ void __launch_bounds__(1024) k_spill_agg(HkPlan P, HkAggTable T, HkSp
   const int64_t R = static_cast<int64_t>(1) << T.rlog2;
   const int W = T.slot_words;
   uint64_t* g = T.words + p * R * W;
-  for (int64_t i = threadIdx.x; i < R * W; i += blockDim.x) lt[i] = id.w[i / R];
+  const uint32_t RW = static_cast<uint32_t>(R * W);  // at most the LDS words of a workgroup
+  for (uint32_t i = threadIdx.x; i < RW; i += blockDim.x) lt[i] = id.w[i >> T.rlog2];
   __syncthreads();
   const uint32_t rmask = static_cast<uint32_t>(R - 1);
   // the region slot of a key (inserted if new); -1 when the region is full
@@ -181,11 +182,14 @@ __global__ void __launch_bounds__(1024) k_spill_agg(HkPlan P, HkAggTable T, HkSp
     set_err(err, HK_ERR_CAPACITY);  // the region is full: the caller retries with a larger table
     return -1;
   };
-  // merge entries: thread by source workgroup
-  for (int64_t w = threadIdx.x; w < nwg; w += blockDim.x) {
+  // merge entries: K threads per source workgroup (one when the sources
+  // outnumber the threads), each taking every K-th of its entries
+  const int64_t K = nwg < blockDim.x ? blockDim.x / nwg : 1;
+  for (int64_t x = threadIdx.x; x < nwg * K; x += blockDim.x) {
+    const int64_t w = x % nwg;
     const int64_t mb = sp.foffs[w * fstride + p], me = sp.foffs[w * fstride + p + 1];
     const uint64_t* src = sp.flush + w * sp.fcap * W;
-    for (int64_t i = mb; i < me; ++i) {
+    for (int64_t i = mb + x / nwg; i < me; i += K) {
       const uint64_t* ent = src + i * W;
       const int32_t s = find(ent[0]);
       if (s >= 0) agg_merge_into<true, S>(lt + s, R, ent + 1, 1, P);
@@ -225,7 +229,8 @@ __global__ void __launch_bounds__(1024) k_spill_agg(HkPlan P, HkAggTable T, HkSp
     }
   }
   __syncthreads();
-  for (int64_t i = threadIdx.x; i < R * W; i += blockDim.x) g[i] = lt[(i % W) * R + i / W];
+  const uint32_t W32 = static_cast<uint32_t>(W);
+  for (uint32_t i = threadIdx.x; i < RW; i += blockDim.x) g[i] = lt[(i % W32) * R + i / W32];
 }
 
 // cuckoo aggregation, phase 1: insert every group key that reaches the sink
