@@ -1012,60 +1012,28 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
     nslots = 1;
   }
   ALLOC(T.words, uint64_t*, static_cast<size_t>(nslots * W) * 8, false);
-  {
-    ProfScope ps(ctx, "k_init_aggtable");
-    HIPCHK(hk_init_aggtable(X.st, T.words, nslots, ident, W), "init table");
-  }
   const int32_t wg = static_cast<int32_t>(v->wg_size);
   if (wg < 1 || wg > 1024) return set_error(ctx, HAWK_E_ARG, "wg_size must be in [1, 1024]");
   int64_t groups;
   if (v->agg_strategy == HAWK_LOCAL) groups = static_cast<int64_t>(v->thread_mult) * ctx->num_cus;  // N tables
   else groups = static_cast<int64_t>(ctx->num_cus) * std::max(1, 2048 / wg);                      // fill the device
   if (groups < 1 || groups > 0x7FFFFFFF) return set_error(ctx, HAWK_E_ARG, "thread_mult out of range");
+  AggConfig cfg{};
   if (grouped) {
-    AggConfig cfg;
     hawk_status cst = agg_config(ctx, P, T, X.q->groups_hint, v, groups, cfg);
     if (cst) return cst;
     T.rlog2 = cfg.rlog2;
-    if (cfg.spill) {
-      HkSpill sp = cfg.sp;
-      const int64_t m = cfg.nparts * groups;
-      uint32_t *offs, *stmp;
-      uint64_t *total, *part;
-      ALLOC(sp.buf, uint64_t*, static_cast<size_t>(P.nrows * sp.ew) * 8, false);
-      ALLOC(sp.hist, uint32_t*, static_cast<size_t>(m) * 4, false);
-      ALLOC(sp.cnt, uint32_t*, static_cast<size_t>(groups) * 4, false);
-      ALLOC(offs, uint32_t*, static_cast<size_t>(m) * 4, false);
-      ALLOC(stmp, uint32_t*, static_cast<size_t>(hk_scan_tmp_words(m)) * 4, false);
-      ALLOC(total, uint64_t*, 8, false);
-      ALLOC(part, uint64_t*, static_cast<size_t>(P.nrows * sp.ew) * 8, false);
-      ALLOC(sp.flush, uint64_t*, static_cast<size_t>(groups * sp.fcap * W) * 8, false);
-      ALLOC(sp.foffs, uint32_t*, static_cast<size_t>(groups * (cfg.nparts + 1)) * 4, false);
-      {
-        ProfScope ps(ctx, "k_agg");
-        HIPCHK(agg_kernel_launch(ctx, X.st, v, P, T, cfg, ident, W, res->d_err, &sp), "aggregation kernel");
-      }
-      {
-        ProfScope ps(ctx, "k_scan");
-        HIPCHK(hk_scan(X.st, sp.hist, offs, m, stmp, total), "spill offsets");
-      }
-      {
-        ProfScope ps(ctx, "k_spill_scatter");
-        HIPCHK(hk_spill(X.st, 0, P, T, v->hash, sp, ident, W, offs, total, groups, part, res->d_err), "spill regrouping");
-      }
-      {
-        ProfScope ps(ctx, "k_spill_agg");
-        HIPCHK(hk_spill(X.st, 1, P, T, v->hash, sp, ident, W, offs, total, groups, part, res->d_err),
-               "spill aggregation");
-      }
-    } else {
-      ProfScope ps(ctx, "k_agg");
-      HIPCHK(agg_kernel_launch(ctx, X.st, v, P, T, cfg, ident, W, res->d_err, nullptr), "aggregation kernel");
-    }
-  } else {
-    ProfScope ps(ctx, "k_scalar_agg");
-    HIPCHK(hk_scalar_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, ident, W,
-                         res->d_err), "aggregation kernel");
+  }
+  // Spilling, the regions' owners write the groups as result rows and the
+  // table's regions are never read: only its side slot (the all-ones key)
+  // needs the identity and the final extraction.
+  const bool direct = grouped && cfg.spill;
+  HkAggTable Tside = T;
+  Tside.words = T.words + (nslots - 1) * W;
+  {
+    ProfScope ps(ctx, "k_init_aggtable");
+    HIPCHK(direct ? hk_init_aggtable(X.st, Tside.words, 1, ident, W) : hk_init_aggtable(X.st, T.words, nslots, ident, W),
+           "init table");
   }
   // result columns: groups, aggregates, count
   const int64_t cap = nslots;
@@ -1083,9 +1051,58 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
   int64_t* cnt;
   ALLOC(cnt, int64_t*, static_cast<size_t>(cap) * 8, true);
   res->cols.push_back({HAWK_RES_I64, cnt});
+  if (grouped) {
+    if (cfg.spill) {
+      HkSpill sp = cfg.sp;
+      const int64_t m = cfg.nparts * groups;
+      uint32_t *offs, *stmp;
+      uint64_t *total, *part, *scratch;
+      ALLOC(sp.buf, uint64_t*, static_cast<size_t>(P.nrows * sp.ew) * 8, false);
+      ALLOC(sp.hist, uint32_t*, static_cast<size_t>(m) * 4, false);
+      ALLOC(sp.cnt, uint32_t*, static_cast<size_t>(groups) * 4, false);
+      ALLOC(offs, uint32_t*, static_cast<size_t>(m) * 4, false);
+      ALLOC(stmp, uint32_t*, static_cast<size_t>(hk_scan_tmp_words(m)) * 4, false);
+      ALLOC(total, uint64_t*, 8, false);
+      ALLOC(part, uint64_t*, static_cast<size_t>(P.nrows * sp.ew) * 8, false);
+      ALLOC(sp.flush, uint64_t*, static_cast<size_t>(groups * sp.fcap * W) * 8, false);
+      ALLOC(sp.foffs, uint32_t*, static_cast<size_t>(groups * (cfg.nparts + 1)) * 4, false);
+      ALLOC(scratch, uint64_t*, static_cast<size_t>(cfg.nparts) * 32 * 8, false);
+      HkResOut O = {};
+      for (int g = 0; g < P.ngroup; ++g) O.gcol[g] = gcols[g];
+      for (int a = 0; a < P.naggs; ++a) O.acol[a] = acols[a];
+      O.count = cnt;
+      O.nrows = reinterpret_cast<unsigned long long*>(res->d_count);
+      {
+        ProfScope ps(ctx, "k_agg");
+        HIPCHK(agg_kernel_launch(ctx, X.st, v, P, T, cfg, ident, W, res->d_err, &sp), "aggregation kernel");
+      }
+      {
+        ProfScope ps(ctx, "k_scan");
+        HIPCHK(hk_scan(X.st, sp.hist, offs, m, stmp, total), "spill offsets");
+      }
+      {
+        ProfScope ps(ctx, "k_spill_scatter");
+        HIPCHK(hk_spill(X.st, 0, P, T, v->hash, sp, ident, W, offs, total, groups, part, res->d_err), "spill regrouping");
+      }
+      {
+        ProfScope ps(ctx, "k_spill_agg");
+        HIPCHK(hk_spill(X.st, 1, P, T, v->hash, sp, ident, W, offs, total, groups, part, res->d_err, &O, scratch),
+               "spill aggregation");
+      }
+    } else {
+      ProfScope ps(ctx, "k_agg");
+      HIPCHK(agg_kernel_launch(ctx, X.st, v, P, T, cfg, ident, W, res->d_err, nullptr), "aggregation kernel");
+    }
+  } else {
+    ProfScope ps(ctx, "k_scalar_agg");
+    HIPCHK(hk_scalar_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, ident, W,
+                         res->d_err), "aggregation kernel");
+  }
   {
     ProfScope ps(ctx, "k_finalize");
-    HIPCHK(hk_finalize(X.st, P, dev_main(X.q), T, nslots, gcols, acols, cnt, res->d_count, grouped ? 0 : 1), "finalize");
+    HIPCHK(direct ? hk_finalize(X.st, P, dev_main(X.q), Tside, 1, gcols, acols, cnt, res->d_count, 0)
+                  : hk_finalize(X.st, P, dev_main(X.q), T, nslots, gcols, acols, cnt, res->d_count, grouped ? 0 : 1),
+           "finalize");
   }
   return HAWK_OK;
 }

@@ -621,30 +621,36 @@ __device__ __forceinline__ double i128_to_f64(uint64_t lo, int64_t hi) {
 
 
 // writes the group row of slot words p (key, count, aggregates) at row pos of the result columns
-__device__ __forceinline__ void write_group_row(const HkPlan& P, const uint64_t* p, int64_t pos, const HkResOut& O) {
+// result row `pos` from a slot whose word j is at p[j * ws]
+__device__ __forceinline__ void write_group_row_s(const HkPlan& P, const uint64_t* p, int64_t ws, int64_t pos,
+                                                  const HkResOut& O) {
   const uint64_t key = p[0];  // the side slot keeps the all-ones key
   if (P.ngroup == 1) O.gcol[0][pos] = static_cast<int32_t>(static_cast<uint32_t>(key));
   if (P.ngroup == 2) {
     O.gcol[0][pos] = static_cast<int32_t>(static_cast<uint32_t>(key >> 32));
     O.gcol[1][pos] = static_cast<int32_t>(static_cast<uint32_t>(key));
   }
-  const uint64_t cnt = p[1];
+  const uint64_t cnt = p[ws];
   O.count[pos] = static_cast<int64_t>(cnt);
   for (int a = 0; a < P.naggs; ++a) {
     const HkAgg& A = P.aggs[a];
     if (A.fn == HK_COUNT) {
       static_cast<int64_t*>(O.acol[a])[pos] = static_cast<int64_t>(cnt);
     } else if (A.fn == HK_AVG) {
-      const double sum = A.wide ? i128_to_f64(p[A.word], static_cast<int64_t>(p[A.word + 1]))
-                                : static_cast<double>(static_cast<int64_t>(p[A.word]));
+      const double sum = A.wide ? i128_to_f64(p[A.word * ws], static_cast<int64_t>(p[(A.word + 1) * ws]))
+                                : static_cast<double>(static_cast<int64_t>(p[A.word * ws]));
       static_cast<double*>(O.acol[a])[pos] = sum / static_cast<double>(cnt);
     } else if (A.fn == HK_SUM && A.wide) {
-      static_cast<uint64_t*>(O.acol[a])[2 * pos] = p[A.word];
-      static_cast<uint64_t*>(O.acol[a])[2 * pos + 1] = p[A.word + 1];
+      static_cast<uint64_t*>(O.acol[a])[2 * pos] = p[A.word * ws];
+      static_cast<uint64_t*>(O.acol[a])[2 * pos + 1] = p[(A.word + 1) * ws];
     } else {
-      static_cast<int64_t*>(O.acol[a])[pos] = static_cast<int64_t>(p[A.word]);
+      static_cast<int64_t*>(O.acol[a])[pos] = static_cast<int64_t>(p[A.word * ws]);
     }
   }
+}
+
+__device__ __forceinline__ void write_group_row(const HkPlan& P, const uint64_t* p, int64_t pos, const HkResOut& O) {
+  write_group_row_s(P, p, 1, pos, O);
 }
 
 // ------------------------------------------------------------------ host-side launch helpers

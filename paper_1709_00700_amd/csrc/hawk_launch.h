@@ -57,9 +57,11 @@ inline size_t hk_agg_lds_bytes(int strat, uint32_t llog2, int32_t nw, int32_t re
   if (sp) lds += static_cast<size_t>(sp->nparts) * sizeof(uint32_t);
   return lds;
 }
+// step 1 with `out`: the groups become result rows (rows reserved by atomics
+// on out->nrows; scratch: 32 words per region) instead of returning to the table
 hipError_t hk_spill(hipStream_t st, int step, const HkPlan& P, const HkAggTable& T, int hash, const HkSpill& sp,
                     const uint64_t* ident, int32_t nw, const uint32_t* offs, const uint64_t* total, int64_t nwg,
-                    uint64_t* part, int* err);
+                    uint64_t* part, int* err, const HkResOut* out = nullptr, uint64_t* scratch = nullptr);
 hipError_t hk_scalar_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
                          int strat, int64_t groups, int32_t wg, const uint64_t* ident, int32_t nw, int* err);
 hipError_t hk_finalize(hipStream_t st, const HkPlan& P, const HkPlan* dP, const HkAggTable& T, int64_t nslots, int64_t* const* gcols,

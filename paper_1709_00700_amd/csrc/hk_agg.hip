@@ -140,11 +140,13 @@ __global__ void __launch_bounds__(1024) k_spill_scatter_lds(HkSpill sp, const ui
 // other kernel writes the region's slots in spill mode, so it starts from the
 // identity in LDS, merges the workgroups' merge entries of region p, then
 // aggregates partition p's spilled entries (LDS atomics, probing confined to
-// the region as in the table) and writes the region back.
+// the region as in the table). With O.nrows set its groups become result
+// rows directly, else the region is written back to the table.
 template <int HASH, class S>
 __global__ void __launch_bounds__(1024) k_spill_agg(HkPlan P, HkAggTable T, HkSpill sp, HkIdent id,
                                                    const uint32_t* __restrict__ offs, const uint64_t* total,
-                                                   int64_t nwg, const uint64_t* __restrict__ in, int* err) {
+                                                   int64_t nwg, const uint64_t* __restrict__ in, int* err,
+                                                   HkResOut O, uint64_t* scratch) {
   const int64_t p = blockIdx.x;
   const int64_t b = offs[p * nwg];
   const int64_t e = p + 1 < sp.nparts ? static_cast<int64_t>(offs[(p + 1) * nwg]) : static_cast<int64_t>(*total);
@@ -229,8 +231,39 @@ __global__ void __launch_bounds__(1024) k_spill_agg(HkPlan P, HkAggTable T, HkSp
     }
   }
   __syncthreads();
-  const uint32_t W32 = static_cast<uint32_t>(W);
-  for (uint32_t i = threadIdx.x; i < RW; i += blockDim.x) g[i] = lt[(i % W32) * R + i / W32];
+  if (!O.nrows) {
+    // the region goes back to the table (whose reader extracts the groups)
+    const uint32_t W32 = static_cast<uint32_t>(W);
+    for (uint32_t i = threadIdx.x; i < RW; i += blockDim.x) g[i] = lt[(i % W32) * R + i / W32];
+    return;
+  }
+  // The region's groups go straight to the result columns: each wave counts
+  // the live slots it will write, one device atomic per workgroup reserves
+  // the rows. The region takes all of the LDS, so the per-wave counts and
+  // the base pass through this region's words of `scratch` (global memory,
+  // ordered within the workgroup by the barriers).
+  const int wave = threadIdx.x / WAVE, nwv = (blockDim.x + WAVE - 1) / WAVE;
+  uint64_t* sc = scratch + p * 32;
+  uint32_t live = 0;
+  for (int64_t s = threadIdx.x; s < R; s += blockDim.x) live += lt[R + s] != 0 ? 1u : 0u;
+  for (int off = WAVE / 2; off > 0; off >>= 1) live += __shfl_xor(live, off, WAVE);
+  if (__lane_id() == 0) sc[wave] = live;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tot = 0;
+    for (int w = 0; w < nwv; ++w) tot += sc[w];
+    sc[16] = tot ? atomicAdd(O.nrows, tot) : 0ull;
+  }
+  __syncthreads();
+  uint64_t pos = sc[16];
+  for (int w = 0; w < wave; ++w) pos += sc[w];
+  for (int64_t s0 = 0; s0 < R; s0 += blockDim.x) {
+    const int64_t s = s0 + threadIdx.x;
+    const bool on = s < R && lt[R + s] != 0;
+    const uint64_t m = __ballot(on);
+    if (on) write_group_row_s(P, lt + s, R, static_cast<int64_t>(pos) + __popcll(m & lanemask_lt()), O);
+    pos += __popcll(m);
+  }
 }
 
 // cuckoo aggregation, phase 1: insert every group key that reaches the sink
@@ -305,7 +338,7 @@ hipError_t hk_agg_shape(hipStream_t st, const HkPlan& P, const HkAggTable& T, in
 template <class S>
 hipError_t hk_spill_shape(hipStream_t st, int step, const HkPlan& P, const HkAggTable& T, int hash, const HkSpill& sp,
                           const HkIdent& id, const uint32_t* offs, const uint64_t* total, int64_t nwg, uint64_t* part,
-                          int* err) {
+                          int* err, const HkResOut& O, uint64_t* scratch) {
   if (step == 0) {
     // two-word entries with 1024 threads: tiles sorted in LDS (8192 entries,
     // else 4096, whichever fits with the partition arrays)
@@ -347,7 +380,7 @@ hipError_t hk_spill_shape(hipStream_t st, int step, const HkPlan& P, const HkAgg
       le = lds_fits(k_spill_agg<HS, S>, lds);
       if (le == hipSuccess)
         hipLaunchKernelGGL((k_spill_agg<HS, S>), dim3(static_cast<uint32_t>(sp.nparts)), dim3(threads), lds, st, P, T,
-                           sp, id, offs, total, nwg, part, err);
+                           sp, id, offs, total, nwg, part, err, O, scratch);
     });
     if (le != hipSuccess) return le;
   }
@@ -359,4 +392,4 @@ template hipError_t hk_agg_shape<HK_SHAPE_CLASS>(hipStream_t, const HkPlan&, con
                                                  int32_t);
 template hipError_t hk_spill_shape<HK_SHAPE_CLASS>(hipStream_t, int, const HkPlan&, const HkAggTable&, int, const HkSpill&,
                                                    const HkIdent&, const uint32_t*, const uint64_t*, int64_t, uint64_t*,
-                                                   int*);
+                                                   int*, const HkResOut&, uint64_t*);

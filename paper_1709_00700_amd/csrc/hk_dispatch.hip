@@ -4,6 +4,8 @@
 // per class).
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "hawk_device.h"
 #include "hawk_launch.h"
 
@@ -14,7 +16,7 @@ hipError_t hk_agg_shape(hipStream_t st, const HkPlan& P, const HkAggTable& T, in
 template <class S>
 hipError_t hk_spill_shape(hipStream_t st, int step, const HkPlan& P, const HkAggTable& T, int hash, const HkSpill& sp,
                           const HkIdent& id, const uint32_t* offs, const uint64_t* total, int64_t nwg, uint64_t* part,
-                          int* err);
+                          int* err, const HkResOut& O, uint64_t* scratch);
 template <class S>
 hipError_t hk_scalar_shape(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
                            int strat, int64_t groups, int32_t wg, const HkIdent& id);
@@ -54,9 +56,15 @@ hipError_t hk_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem,
 
 hipError_t hk_spill(hipStream_t st, int step, const HkPlan& P, const HkAggTable& T, int hash, const HkSpill& sp,
                     const uint64_t* ident, int32_t nw, const uint32_t* offs, const uint64_t* total, int64_t nwg,
-                    uint64_t* part, int* err) {
+                    uint64_t* part, int* err, const HkResOut* out, uint64_t* scratch) {
   const HkIdent id = make_ident(ident, nw);
-  BY_SHAPE(P, hk_spill_shape<S>(st, step, P, T, hash, sp, id, offs, total, nwg, part, err));
+  HkResOut O;
+  std::memset(&O, 0, sizeof(O));
+  if (out) {
+    if (!scratch || !out->nrows) return hipErrorInvalidValue;
+    O = *out;
+  }
+  BY_SHAPE(P, hk_spill_shape<S>(st, step, P, T, hash, sp, id, offs, total, nwg, part, err, O, scratch));
 }
 
 hipError_t hk_scalar_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, int mem, int pred, int ht, int hash,
