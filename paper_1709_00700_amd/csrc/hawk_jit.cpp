@@ -113,6 +113,15 @@ hipError_t get_kernel(JitCache& cache, std::string& err_msg, const std::string& 
       err_msg = "specialised kernel not found in its module";
       return e;
     }
+    // the kernel's LDS must fit one workgroup's maximum (a launch beyond it would abort the queue)
+    int shared = 0, dev = 0, maxl = 0;
+    if (hipFuncGetAttribute(&shared, HIP_FUNC_ATTRIBUTE_SHARED_SIZE_BYTES, k.fn) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&maxl, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || shared > maxl) {
+      (void)hipModuleUnload(k.module);
+      err_msg = "the specialised kernel's LDS exceeds a workgroup's maximum";
+      return hipErrorInvalidValue;
+    }
     cache.compile_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     ++cache.compiled;
     it = cache.kernels.emplace(src, k).first;
@@ -138,14 +147,6 @@ hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st,
   const hipError_t ge =
       get_kernel(cache, err_msg, jit_agg_source(P, mem, pred, HK_LIN, hash, strat, sp != nullptr, lds), fn);
   if (ge != hipSuccess) return ge;
-  // the kernel's LDS must fit one workgroup's maximum (a launch beyond it would abort the queue)
-  int shared = 0, dev = 0, maxl = 0;
-  if (hipFuncGetAttribute(&shared, HIP_FUNC_ATTRIBUTE_SHARED_SIZE_BYTES, fn) != hipSuccess ||
-      hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&maxl, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || shared > maxl) {
-    err_msg = "the specialised kernel's LDS exceeds a workgroup's maximum";
-    return hipErrorInvalidValue;
-  }
   HkSpill none;
   std::memset(&none, 0, sizeof(none));
   HkPlan Pa = P;

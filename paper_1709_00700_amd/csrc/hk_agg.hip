@@ -6,6 +6,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
+#include <utility>
+#include <vector>
 
 #include "hawk_device.h"
 #include "hawk_launch.h"
@@ -283,17 +286,46 @@ __global__ void __launch_bounds__(256) k_agg_keys(HkPlan P, HkAggTable T, int* e
   }
 }
 
+// the LDS a workgroup may hold on `dev` (queried once per device)
+static int device_max_lds(int dev) {
+  static std::mutex mu;
+  static std::vector<std::pair<int, int>> known;
+  std::lock_guard<std::mutex> g(mu);
+  for (const auto& k : known)
+    if (k.first == dev) return k.second;
+  int maxl = 0;
+  if (hipDeviceGetAttribute(&maxl, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+  known.emplace_back(dev, maxl);
+  return maxl;
+}
+
 // a launch whose static plus dynamic LDS exceeds one workgroup's maximum
-// would abort the queue: such a launch is refused here instead
+// would abort the queue: such a launch is refused here instead (the
+// kernel's static LDS is queried once per kernel)
+static hipError_t lds_fits_fn(const void* kernel, size_t dyn) {
+  static std::mutex mu;
+  static std::vector<std::pair<const void*, size_t>> known;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const size_t maxl = static_cast<size_t>(device_max_lds(dev));
+  {
+    std::lock_guard<std::mutex> g(mu);
+    for (const auto& k : known)
+      if (k.first == kernel) return k.second + dyn <= maxl ? hipSuccess : hipErrorInvalidValue;
+  }
+  hipFuncAttributes a;
+  if ((e = hipFuncGetAttributes(&a, kernel)) != hipSuccess) return e;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    known.emplace_back(kernel, a.sharedSizeBytes);
+  }
+  return a.sharedSizeBytes + dyn <= maxl ? hipSuccess : hipErrorInvalidValue;
+}
+
 template <class K>
 static hipError_t lds_fits(K kernel, size_t dyn) {
-  hipFuncAttributes a;
-  hipError_t e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kernel));
-  if (e != hipSuccess) return e;
-  int dev = 0, maxl = 0;
-  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-  if ((e = hipDeviceGetAttribute(&maxl, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
-  return a.sharedSizeBytes + dyn <= static_cast<size_t>(maxl) ? hipSuccess : hipErrorInvalidValue;
+  return lds_fits_fn(reinterpret_cast<const void*>(kernel), dyn);
 }
 
 template <class S>
@@ -342,10 +374,10 @@ hipError_t hk_spill_shape(hipStream_t st, int step, const HkPlan& P, const HkAgg
   if (step == 0) {
     // two-word entries with 1024 threads: tiles sorted in LDS (8192 entries,
     // else 4096, whichever fits with the partition arrays)
-    int dev = 0, maxl = 0;
-    hipError_t ae = hipGetDevice(&dev);
-    if (ae == hipSuccess) ae = hipDeviceGetAttribute(&maxl, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    int dev = 0;
+    const hipError_t ae = hipGetDevice(&dev);
     if (ae != hipSuccess) return ae;
+    const int maxl = device_max_lds(dev);
     const size_t side = (3 * static_cast<size_t>(sp.nparts) + 1) * sizeof(uint32_t) + (1024 / WAVE) * sizeof(uint32_t);
     const size_t l8 = 8192 * 16 + side, l4 = 4096 * 16 + side;
     if (sp.ew == 2 && l8 <= static_cast<size_t>(maxl)) {
