@@ -765,6 +765,10 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
     sp.bs = static_cast<int32_t>(v->wg_size);
     sp.coal = v->mem == HAWK_COALESCED ? 1 : 0;
     sp.fcap = static_cast<int32_t>(int64_t(1) << c.llog2);
+    // Merge entries pay where a grid of at most one workgroup per CU holds
+    // large LDS tables: few workgroups, many distinct slots each. A wider
+    // grid merges its (smaller, more alike) tables with device-scope atomics.
+    sp.merge = groups <= ctx->num_cus ? 1 : 0;
   }
   return HAWK_OK;
 }
@@ -1027,7 +1031,7 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
   // Spilling, the regions' owners write the groups as result rows and the
   // table's regions are never read: only its side slot (the all-ones key)
   // needs the identity and the final extraction.
-  const bool direct = grouped && cfg.spill;
+  const bool direct = grouped && cfg.spill && cfg.sp.merge;
   HkAggTable Tside = T;
   Tside.words = T.words + (nslots - 1) * W;
   {
@@ -1064,9 +1068,12 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
       ALLOC(stmp, uint32_t*, static_cast<size_t>(hk_scan_tmp_words(m)) * 4, false);
       ALLOC(total, uint64_t*, 8, false);
       ALLOC(part, uint64_t*, static_cast<size_t>(P.nrows * sp.ew) * 8, false);
-      ALLOC(sp.flush, uint64_t*, static_cast<size_t>(groups * sp.fcap * W) * 8, false);
-      ALLOC(sp.foffs, uint32_t*, static_cast<size_t>(groups * (cfg.nparts + 1)) * 4, false);
-      ALLOC(scratch, uint64_t*, static_cast<size_t>(cfg.nparts) * 32 * 8, false);
+      scratch = nullptr;
+      if (sp.merge) {
+        ALLOC(sp.flush, uint64_t*, static_cast<size_t>(groups * sp.fcap * W) * 8, false);
+        ALLOC(sp.foffs, uint32_t*, static_cast<size_t>(groups * (cfg.nparts + 1)) * 4, false);
+        ALLOC(scratch, uint64_t*, static_cast<size_t>(cfg.nparts) * 32 * 8, false);
+      }
       HkResOut O = {};
       for (int g = 0; g < P.ngroup; ++g) O.gcol[g] = gcols[g];
       for (int a = 0; a < P.naggs; ++a) O.acol[a] = acols[a];
@@ -1086,7 +1093,8 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
       }
       {
         ProfScope ps(ctx, "k_spill_agg");
-        HIPCHK(hk_spill(X.st, 1, P, T, v->hash, sp, ident, W, offs, total, groups, part, res->d_err, &O, scratch),
+        HIPCHK(hk_spill(X.st, 1, P, T, v->hash, sp, ident, W, offs, total, groups, part, res->d_err,
+                        direct ? &O : nullptr, scratch),
                "spill aggregation");
       }
     } else {

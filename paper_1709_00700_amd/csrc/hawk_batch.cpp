@@ -248,12 +248,14 @@ hawk_status setup_memory(hawk_batch* B) {
           d.stmp = static_cast<uint32_t*>(balloc(B, static_cast<size_t>(hk_scan_tmp_words(m)) * 4, B->allocs));
           d.total = static_cast<uint64_t*>(balloc(B, 8, B->allocs));
           d.part = static_cast<uint64_t*>(balloc(B, static_cast<size_t>(n * d.sp.ew) * 8, B->allocs));
-          d.sp.flush = static_cast<uint64_t*>(
-              balloc(B, static_cast<size_t>(d.cfg.groups * d.sp.fcap * W) * 8, B->allocs));
-          d.sp.foffs = static_cast<uint32_t*>(
-              balloc(B, static_cast<size_t>(d.cfg.groups * (d.cfg.nparts + 1)) * 4, B->allocs));
-          if (!d.sp.buf || !d.sp.hist || !d.sp.cnt || !d.offs || !d.stmp || !d.total || !d.part || !d.sp.flush ||
-              !d.sp.foffs)
+          if (d.sp.merge) {
+            d.sp.flush = static_cast<uint64_t*>(
+                balloc(B, static_cast<size_t>(d.cfg.groups * d.sp.fcap * W) * 8, B->allocs));
+            d.sp.foffs = static_cast<uint32_t*>(
+                balloc(B, static_cast<size_t>(d.cfg.groups * (d.cfg.nparts + 1)) * 4, B->allocs));
+          }
+          if (!d.sp.buf || !d.sp.hist || !d.sp.cnt || !d.offs || !d.stmp || !d.total || !d.part ||
+              (d.sp.merge && (!d.sp.flush || !d.sp.foffs)))
             return berr(B, HAWK_E_OOM, "batch spill buffers");
         }
         if (ctx->jit) {

@@ -140,10 +140,11 @@ struct HkAggTable { uint64_t* words; uint32_t log2cap; int32_t slot_words; uint3
 // in its workgroup's LDS table is appended to the workgroup's spill region as
 // an entry [key, input values...]; the entries are then regrouped by table
 // region (partition = hash slot >> rlog2) and each region is aggregated by
-// the one workgroup that owns it. The LDS tables themselves reach the owners
-// too: each workgroup writes its slots out as merge entries [key, count,
-// aggregate words...], sorted by region, so no slot touches the table with
-// device-scope atomics either.
+// the one workgroup that owns it. The LDS tables themselves either reach the
+// owners too, each workgroup writing its slots out as merge entries [key,
+// count, aggregate words...] sorted by region (merge = 1: no slot touches the
+// table with device-scope atomics), or merge into the table with device-scope
+// atomics before the owners start from it (merge = 0).
 struct HkSpill {
   uint64_t* buf;              // one region per workgroup, as many entries as rows it scans (nrows in all)
   int64_t nrows;              // rows of the scan
@@ -158,5 +159,5 @@ struct HkSpill {
   uint64_t* flush;            // merge entries: fcap slots of slot_words words per workgroup
   uint32_t* foffs;            // per workgroup nparts + 1 offsets of its merge entries by region
   int32_t fcap;               // merge entries per workgroup, at most (its LDS table's slots)
-  int32_t pad;
+  int32_t merge;              // 1: LDS tables leave as merge entries; 0: they merge into the table with device-scope atomics
 };

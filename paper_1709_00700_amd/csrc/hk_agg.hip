@@ -139,12 +139,13 @@ __global__ void __launch_bounds__(1024) k_spill_scatter_lds(HkSpill sp, const ui
   }
 }
 
-// spill, step 3: workgroup p owns table region p for the whole kernel. No
-// other kernel writes the region's slots in spill mode, so it starts from the
-// identity in LDS, merges the workgroups' merge entries of region p, then
-// aggregates partition p's spilled entries (LDS atomics, probing confined to
-// the region as in the table). With O.nrows set its groups become result
-// rows directly, else the region is written back to the table.
+// spill, step 3: workgroup p owns table region p for the whole kernel. With
+// merge entries no other kernel writes the region's slots, so it starts from
+// the identity in LDS and merges the workgroups' merge entries of region p;
+// else it starts from the region's contents in the table. Then it aggregates
+// partition p's spilled entries (LDS atomics, probing confined to the region
+// as in the table). With O.nrows set its groups become result rows directly,
+// else the region is written back to the table.
 template <int HASH, class S>
 __global__ void __launch_bounds__(1024) k_spill_agg(HkPlan P, HkAggTable T, HkSpill sp, HkIdent id,
                                                    const uint32_t* __restrict__ offs, const uint64_t* total,
@@ -158,21 +159,30 @@ __global__ void __launch_bounds__(1024) k_spill_agg(HkPlan P, HkAggTable T, HkSp
   // holds no static LDS: the flag below is the region's first word, read
   // before the region is initialised.
   extern __shared__ uint64_t lt[];  // word w of region slot i at lt[w * R + i]
-  uint32_t* flag = reinterpret_cast<uint32_t*>(lt);
-  if (threadIdx.x == 0) *flag = 0;
-  __syncthreads();
-  for (int64_t w = threadIdx.x; w < nwg; w += blockDim.x)
-    if (sp.foffs[w * fstride + p + 1] > sp.foffs[w * fstride + p]) atomicOr(flag, 1u);
-  __syncthreads();
-  const bool merges = *flag != 0;
-  __syncthreads();
-  // nothing spilled and no merge entries here: the region keeps its identity
+  bool merges = false;
+  if (sp.merge) {
+    uint32_t* flag = reinterpret_cast<uint32_t*>(lt);
+    if (threadIdx.x == 0) *flag = 0;
+    __syncthreads();
+    for (int64_t w = threadIdx.x; w < nwg; w += blockDim.x)
+      if (sp.foffs[w * fstride + p + 1] > sp.foffs[w * fstride + p]) atomicOr(flag, 1u);
+    __syncthreads();
+    merges = *flag != 0;
+    __syncthreads();
+  }
+  // nothing spilled and no merge entries here: the region keeps its contents
+  // (the identity with merge entries, else what the table holds)
   if (!merges && b >= e) return;
   const int64_t R = static_cast<int64_t>(1) << T.rlog2;
   const int W = T.slot_words;
   uint64_t* g = T.words + p * R * W;
   const uint32_t RW = static_cast<uint32_t>(R * W);  // at most the LDS words of a workgroup
-  for (uint32_t i = threadIdx.x; i < RW; i += blockDim.x) lt[i] = id.w[i >> T.rlog2];
+  if (sp.merge) {
+    for (uint32_t i = threadIdx.x; i < RW; i += blockDim.x) lt[i] = id.w[i >> T.rlog2];
+  } else {
+    const uint32_t W32 = static_cast<uint32_t>(W);
+    for (uint32_t i = threadIdx.x; i < RW; i += blockDim.x) lt[(i % W32) * R + i / W32] = g[i];
+  }
   __syncthreads();
   const uint32_t rmask = static_cast<uint32_t>(R - 1);
   // the region slot of a key (inserted if new); -1 when the region is full
@@ -190,7 +200,7 @@ __global__ void __launch_bounds__(1024) k_spill_agg(HkPlan P, HkAggTable T, HkSp
   // merge entries: K threads per source workgroup (one when the sources
   // outnumber the threads), each taking every K-th of its entries
   const int64_t K = nwg < blockDim.x ? blockDim.x / nwg : 1;
-  for (int64_t x = threadIdx.x; x < nwg * K; x += blockDim.x) {
+  for (int64_t x = threadIdx.x; merges && x < nwg * K; x += blockDim.x) {
     const int64_t w = x % nwg;
     const int64_t mb = sp.foffs[w * fstride + p], me = sp.foffs[w * fstride + p + 1];
     const uint64_t* src = sp.flush + w * sp.fcap * W;

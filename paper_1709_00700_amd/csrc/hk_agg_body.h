@@ -24,7 +24,8 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
   if (wg_without_rows<MEM>(P.nrows, wgid, nwg, blockDim.x)) {
     if (SPILL) {
       for (int p = threadIdx.x; p < sp.nparts; p += blockDim.x) sp.hist[static_cast<int64_t>(p) * nwg + wgid] = 0;
-      for (int p = threadIdx.x; p <= sp.nparts; p += blockDim.x) sp.foffs[wgid * (sp.nparts + 1) + p] = 0;
+      if (sp.merge)
+        for (int p = threadIdx.x; p <= sp.nparts; p += blockDim.x) sp.foffs[wgid * (sp.nparts + 1) + p] = 0;
       if (threadIdx.x == 0) sp.cnt[wgid] = 0;
     }
     return;
@@ -135,7 +136,7 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
       row_step(rk, f[k]);
     }
   }
-  if (STRAT == HK_LOCAL && !SPILL) {
+  if (STRAT == HK_LOCAL && (!SPILL || !sp.merge)) {
     __syncthreads();
     for (int64_t s = threadIdx.x; s < LC; s += blockDim.x) {
       const uint64_t key = lds[s];
@@ -148,11 +149,12 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
     }
   }
   if (STRAT == HK_LOCAL && SPILL) {
-    // the spill histogram goes out, then the same LDS words count this
-    // table's slots by region and, scanned, place them as merge entries
+    // the spill histogram goes out, then (merge entries) the same LDS words
+    // count this table's slots by region and, scanned, place them
     __syncthreads();
     for (int p = threadIdx.x; p < sp.nparts; p += blockDim.x) sp.hist[static_cast<int64_t>(p) * nwg + wgid] = hist[p];
     if (threadIdx.x == 0) sp.cnt[wgid] = *cursor < rcap ? *cursor : static_cast<uint32_t>(rcap);
+    if (!sp.merge) return;
     __syncthreads();
     for (int p = threadIdx.x; p < sp.nparts; p += blockDim.x) hist[p] = 0;
     __syncthreads();
