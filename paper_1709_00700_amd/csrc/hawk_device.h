@@ -567,7 +567,7 @@ __device__ __forceinline__ void agg_merge(uint64_t* g, const uint64_t* l, int64_
 }
 
 // LDS slot lookup/insert for the local strategy; -1 = no slot within bound
-template <int HT, int HASH>
+template <int HT, int HASH, bool WINDOW = true>
 __device__ __forceinline__ int32_t lslot(uint64_t* lkeys, uint32_t llog2, const HkHash& h, uint64_t key) {
   if (HT == HK_LIN) {
     const uint32_t mask = (1u << llog2) - 1u;
@@ -577,6 +577,19 @@ __device__ __forceinline__ int32_t lslot(uint64_t* lkeys, uint32_t llog2, const 
     if (cur == HK_EMPTY) {
       cur = at_cas<true>(&lkeys[s0], HK_EMPTY, key);
       if (cur == HK_EMPTY || cur == key) return static_cast<int32_t>(s0);
+    }
+    if (!WINDOW) {
+      // one slot per round trip (fewer live registers)
+      for (int i = 1; i < HK_LOCAL_PROBES; ++i) {
+        const uint32_t s = (s0 + i) & mask;
+        cur = lkeys[s];
+        if (cur == key) return static_cast<int32_t>(s);
+        if (cur == HK_EMPTY) {
+          cur = at_cas<true>(&lkeys[s], HK_EMPTY, key);
+          if (cur == HK_EMPTY || cur == key) return static_cast<int32_t>(s);
+        }
+      }
+      return -1;
     }
     // the rest of the probe window in one round trip instead of one per slot.
     // A slot only ever changes from empty to a key, so a key read here stays,

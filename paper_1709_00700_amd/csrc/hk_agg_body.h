@@ -72,7 +72,7 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
       key = group_key(P, r);
       bool done = false;
       if (STRAT == HK_LOCAL && key != HK_EMPTY) {
-        const int32_t s = lslot<HT, HASH>(lds, llog2, P.hash, key);
+        const int32_t s = lslot<HT, HASH, (S::probes == 0)>(lds, llog2, P.hash, key);
         if (s >= 0) {
           agg_apply_w1<PRED, true, S>(lw1 + q * RS + s, WS, P, r, pass);
           done = true;

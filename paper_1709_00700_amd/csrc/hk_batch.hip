@@ -93,7 +93,7 @@ __device__ void tile_aggregate(const HkPlan& P, const HkBatchQuery& Q, int64_t r
     if (!eval_row<HK_BR, HK_LIN, HK_MURMUR, true, S>(P, row, r)) continue;
     const uint64_t key = group_key(P, r);
     if (key != HK_EMPTY) {
-      const int32_t s = lslot<HK_LIN, HK_MURMUR>(lds, Q.llog2, P.hash, key);
+      const int32_t s = lslot<HK_LIN, HK_MURMUR, false>(lds, Q.llog2, P.hash, key);
       if (s >= 0) {
         agg_apply<HK_BR, true, S>(lds + s, LC, P, r, true);
         continue;
