@@ -102,8 +102,16 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
           const int64_t pos = static_cast<int64_t>(base) + __popcll(m & lanemask_lt());
           if (pos < rcap) {
             uint64_t* ent = region + pos * sp.ew;
-            ent[0] = key;
-            for (int j = 0; j < sp.ncols; ++j) ent[1 + j] = static_cast<uint64_t>(r[sp.reg[j]]);
+            if (sp.ew == 2) {
+              // consecutive spilling lanes write consecutive 16-byte entries: one store each
+              ulonglong2 e2;
+              e2.x = key;
+              e2.y = static_cast<uint64_t>(r[sp.reg[0]]);
+              *reinterpret_cast<ulonglong2*>(ent) = e2;
+            } else {
+              ent[0] = key;
+              for (int j = 0; j < sp.ncols; ++j) ent[1 + j] = static_cast<uint64_t>(r[sp.reg[j]]);
+            }
             atomicAdd(&hist[hslot<HASH>(key, P.hash.a[0], T.log2cap) >> T.rlog2], 1u);
           } else {
             set_err(err, HK_ERR_CAPACITY);  // never expected: a region holds every row its workgroup scans
