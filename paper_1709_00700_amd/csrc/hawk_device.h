@@ -566,15 +566,32 @@ __device__ __forceinline__ void agg_merge(uint64_t* g, const uint64_t* l, int64_
   agg_merge_w1<S>(g, l + stride, stride, P);
 }
 
+// Admission filter of the local table (`door`: 2^dl2 bits in LDS): a key
+// that would take an empty slot enters only if its bit was already set, so a
+// key seen once by the workgroup leaves the slots to keys seen again. Sets
+// the bit; true when the key may enter.
+template <int HASH>
+__device__ __forceinline__ bool door_admits(uint32_t* door, uint32_t dl2, const HkHash& h, uint64_t key) {
+  const uint32_t b = hslot<HASH>(key, h.a[1], dl2);
+  const uint32_t m = 1u << (b & 31u);
+  return (atomicOr(&door[b >> 5], m) & m) != 0u;
+}
+
 // LDS slot lookup/insert for the local strategy; -1 = no slot within bound
-template <int HT, int HASH, bool WINDOW = true>
-__device__ __forceinline__ int32_t lslot(uint64_t* lkeys, uint32_t llog2, const HkHash& h, uint64_t key) {
+// (or, with a filter, a key not admitted yet)
+template <int HT, int HASH, bool WINDOW = true, bool ADMIT = false>
+__device__ __forceinline__ int32_t lslot(uint64_t* lkeys, uint32_t llog2, const HkHash& h, uint64_t key,
+                                         uint32_t* door = nullptr, uint32_t dl2 = 0) {
   if (HT == HK_LIN) {
     const uint32_t mask = (1u << llog2) - 1u;
     const uint32_t s0 = hslot<HASH>(key, h.a[0], llog2);
+    // admission decided at the first empty slot met, then kept
+    int adm = (ADMIT && dl2 > 0) ? -1 : 1;
     uint64_t cur = lkeys[s0];
     if (cur == key) return static_cast<int32_t>(s0);
     if (cur == HK_EMPTY) {
+      if (adm < 0) adm = door_admits<HASH>(door, dl2, h, key) ? 1 : 0;
+      if (!adm) return -1;
       cur = at_cas<true>(&lkeys[s0], HK_EMPTY, key);
       if (cur == HK_EMPTY || cur == key) return static_cast<int32_t>(s0);
     }
@@ -585,6 +602,8 @@ __device__ __forceinline__ int32_t lslot(uint64_t* lkeys, uint32_t llog2, const 
         cur = lkeys[s];
         if (cur == key) return static_cast<int32_t>(s);
         if (cur == HK_EMPTY) {
+          if (adm < 0) adm = door_admits<HASH>(door, dl2, h, key) ? 1 : 0;
+          if (!adm) return -1;
           cur = at_cas<true>(&lkeys[s], HK_EMPTY, key);
           if (cur == HK_EMPTY || cur == key) return static_cast<int32_t>(s);
         }
@@ -604,6 +623,8 @@ __device__ __forceinline__ int32_t lslot(uint64_t* lkeys, uint32_t llog2, const 
       cur = win[i - 1];
       if (cur == key) return static_cast<int32_t>(s);
       if (cur == HK_EMPTY) {
+        if (adm < 0) adm = door_admits<HASH>(door, dl2, h, key) ? 1 : 0;
+        if (!adm) return -1;
         cur = at_cas<true>(&lkeys[s], HK_EMPTY, key);
         if (cur == HK_EMPTY || cur == key) return static_cast<int32_t>(s);
       }

@@ -37,8 +37,11 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
   const int64_t WS = reps * RS;  // from word j to word j + 1 of one copy
   uint64_t* lw1 = lds + LC;      // word 1 of copy 0 of slot 0
   const int64_t q = __lane_id() & (reps - 1);
-  // spill mode: the partition histogram follows the LDS table
+  // spill mode: the partition histogram follows the LDS table, then the
+  // admission filter's words
   uint32_t* hist = reinterpret_cast<uint32_t*>(lds + LC + (id.nw - 1) * WS);
+  uint32_t* door = hist + (SPILL ? sp.nparts : 0);
+  const uint32_t dl2 = SPILL && sp.door_log2 > 0 ? static_cast<uint32_t>(sp.door_log2) : 0u;
   uint32_t* cursor = &spill_cursor;
   if (STRAT == HK_LOCAL) {
     for (int64_t i = threadIdx.x; i < LC; i += blockDim.x) lds[i] = id.w[0];
@@ -46,6 +49,7 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
       for (int64_t i = threadIdx.x; i < WS; i += blockDim.x) lw1[(w - 1) * WS + i] = id.w[w];
     if (SPILL) {
       for (int i = threadIdx.x; i < sp.nparts; i += blockDim.x) hist[i] = 0;
+      for (int i = threadIdx.x; i < (dl2 ? (1 << dl2) / 32 : 0); i += blockDim.x) door[i] = 0;
       if (threadIdx.x == 0) *cursor = 0;
     }
     __syncthreads();
@@ -72,7 +76,7 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
       key = group_key(P, r);
       bool done = false;
       if (STRAT == HK_LOCAL && key != HK_EMPTY) {
-        const int32_t s = lslot<HT, HASH, (S::probes == 0)>(lds, llog2, P.hash, key);
+        const int32_t s = lslot<HT, HASH, (S::probes == 0), SPILL>(lds, llog2, P.hash, key, door, dl2);
         if (s >= 0) {
           agg_apply_w1<PRED, true, S>(lw1 + q * RS + s, WS, P, r, pass);
           done = true;
