@@ -769,8 +769,9 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
     // large LDS tables: few workgroups, many distinct slots each. A wider
     // grid merges its (smaller, more alike) tables with device-scope atomics.
     sp.merge = groups <= ctx->num_cus ? 1 : 0;
-    // a 64K-bit admission filter where the LDS has room for it
-    sp.door_log2 = table_bytes + nparts * 4 + 8192 <= wg_lds ? 16 : 0;
+    // a 64K-bit admission filter on grids of at most one workgroup per CU
+    // (elsewhere its LDS would cost resident workgroups)
+    sp.door_log2 = whole_cu && table_bytes + nparts * 4 + 8192 <= wg_lds ? 16 : 0;
   }
   return HAWK_OK;
 }
