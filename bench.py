@@ -90,8 +90,8 @@ def make_pipelines(workload, rows):
 # device copy (--copy-calibration). Valid only for the kernel sources it was
 # measured on, with the same variants: bench.py reports null otherwise.
 TRAFFIC = {
-    ("k_agg", "c2"): {"sources_sha": "586efbd8b2471bb4", "variants_sha": "c62b14057a3f9b21",
-                      "bytes_per_launch": 1005585914},
+    ("k_agg", "c2"): {"sources_sha": "28f9545bf8c32692", "variants_sha": "c62b14057a3f9b21",
+                      "bytes_per_launch": 981707435},
 }
 
 
