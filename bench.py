@@ -300,8 +300,8 @@ def main():
     ap.add_argument("--pq-limit-ms", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build does not run across several GPUs "
-              "(every pipeline would shard by row ranges of its scanned table)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs each pipeline on one GPU "
+              "(across several, a pipeline would shard by row ranges of its scanned table)", file=sys.stderr)
         sys.exit(2)
 
     import torch
