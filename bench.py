@@ -84,14 +84,18 @@ def make_pipelines(workload, rows):
     return out
 
 
-# HBM traffic of the dominant kernel, from two rocprofv3 --pmc runs (FETCH_SIZE,
-# then WRITE_SIZE, KiB per dispatch) of this script's default workload, each
+# HBM traffic of the dominant kernel per workload, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of that workload, each
 # scaled by the ratio of known bytes to the counter's reading for a plain
 # device copy (--copy-calibration). Valid only for the kernel sources it was
 # measured on, with the same variants: bench.py reports null otherwise.
 TRAFFIC = {
     ("k_agg", "c2"): {"sources_sha": "28f9545bf8c32692", "variants_sha": "c62b14057a3f9b21",
                       "bytes_per_launch": 981707435},
+    ("k_agg", "c3"): {"sources_sha": "28f9545bf8c32692", "variants_sha": "4da2aec3e3d4646d",
+                      "bytes_per_launch": 3330324547},
+    ("k_agg", "c4"): {"sources_sha": "28f9545bf8c32692", "variants_sha": "eb3f0a286c66bac6",
+                      "bytes_per_launch": 13333290310},
 }
 
 
