@@ -1,0 +1,61 @@
+"""Host logic of the pick-quality evaluation (no GPU): the ratios of each
+picker's and Algorithm 1's runtimes to every query's exhaustive best, on
+stubbed timings whose ratios are known by hand."""
+import math
+
+import pytest
+
+from paper_1709_00700_amd import optimizer
+
+
+class _Query:
+    def __init__(self, kind):
+        self.kind = kind
+
+
+class _Picker:
+    def __init__(self, picks):
+        self.picks = picks
+
+    def pick(self, queries):
+        return self.picks, None
+
+
+def test_pick_quality_ratios(monkeypatch):
+    qs = [_Query(1), _Query(2)]
+    # exhaustive timings per query: variant key -> ms
+    tables = [{"a": 1.0, "b": 2.0, "c": 8.0}, {"a": 4.0, "b": 1.0, "c": 2.0}]
+    monkeypatch.setattr(optimizer, "exhaustive", lambda ctx, q, reps, lim: dict(tables[qs.index(q)]))
+    monkeypatch.setattr(optimizer, "variant_key", lambda q, v: v)
+    alg1 = {1: ("c", None), 2: ("c", None)}
+    out = optimizer.pick_quality(None, qs, _Picker(["a", "a"]), reps=1, limit_ms=10.0, alg1=alg1,
+                                 extra={"other": _Picker(["b", "b"])})
+    assert out["queries"] == 2
+    # model picks a: ratios 1 and 4
+    assert out["model"]["geomean_ratio"] == pytest.approx(2.0)
+    assert out["model"]["total_ratio"] == pytest.approx((1.0 + 4.0) / (1.0 + 1.0))
+    assert out["model"]["max_ratio"] == pytest.approx(4.0)
+    # the extra picker takes b: ratios 2 and 1
+    assert out["other"]["geomean_ratio"] == pytest.approx(math.sqrt(2.0))
+    assert out["other"]["total_ratio"] == pytest.approx(3.0 / 2.0)
+    # Algorithm 1's one variant per kind is c: ratios 8 and 2
+    assert out["alg1"]["geomean_ratio"] == pytest.approx(4.0)
+    assert out["alg1"]["max_ratio"] == pytest.approx(8.0)
+    rows = out["per_query"]
+    assert [r["best"] for r in rows] == ["a", "b"]
+    assert [r["pick"] for r in rows] == ["a", "a"] and [r["other"] for r in rows] == ["b", "b"]
+    assert all(r["alg1"] == "c" for r in rows)
+
+
+def test_pick_quality_pruned_pick(monkeypatch):
+    # a pick outside the exhaustive table is timed on its own; a pruned one (inf) is counted, not averaged
+    qs = [_Query(1), _Query(1)]
+    tables = [{"a": 1.0, "b": 3.0}, {"a": 2.0, "b": 2.0}]
+    monkeypatch.setattr(optimizer, "exhaustive", lambda ctx, q, reps, lim: dict(tables[qs.index(q)]))
+    monkeypatch.setattr(optimizer, "variant_key", lambda q, v: v)
+    monkeypatch.setattr(optimizer, "timed", lambda ctx, q, v, reps, lim: math.inf)
+    out = optimizer.pick_quality(None, qs, _Picker(["z", "a"]), reps=1, limit_ms=10.0, alg1={1: ("b", None)})
+    assert out["model"]["pruned_picks"] == 1
+    assert out["model"]["geomean_ratio"] == pytest.approx(1.0)  # over the finite ratio (query 2: 2/2)
+    assert out["alg1"]["pruned_picks"] == 0
+    assert out["alg1"]["geomean_ratio"] == pytest.approx(math.sqrt(3.0 * 1.0))
