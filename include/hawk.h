@@ -110,7 +110,9 @@ enum { HAWK_COUNT = 1, HAWK_SUM = 2, HAWK_MIN = 3, HAWK_MAX = 4, HAWK_AVG = 5 };
 
 typedef struct {
   int32_t fn;          /* HAWK_COUNT..HAWK_AVG */
-  int32_t wide;        /* SUM/AVG: 1 = exact 128-bit sum, 0 = 64-bit two's complement */
+  int32_t wide;        /* SUM: 1 = exact 128-bit sum, 0 = its low 64 bits (two's complement);
+                          AVG always divides the exact sum (128-bit accumulator for 64-bit
+                          attributes and arithmetic results, 64-bit for 8/32-bit ones) */
   const char* attr;    /* aggregated attribute (NULL for COUNT) */
 } hawk_agg;
 
@@ -218,18 +220,29 @@ typedef struct {
   int32_t reps;          /* timed runs per (query, variant); median decides */
   int32_t max_iters;     /* q of Algorithm 1 */
   double limit_ms;       /* prune rule: a run above this is +inf */
-  const char* timing_db; /* append-only text log of every measurement (NULL: none) */
+  const char* timing_db; /* append-only text log of every measurement (NULL: none): a line
+                            "#workload <sig> <k> mode=<m>" per exploration, then one line per
+                            (query, variant): sig, query index, the 12 features, the variant's
+                            text form, median ms (-1 when pruned) and status, tab-separated */
+  int32_t resume;        /* 1: first read timing_db; variants whose k measurements of this
+                            workload (same sig: query kinds, sizes, plan structure and
+                            constants, compute units) are logged are not measured again
+                            (the log is trusted to come from the same tables and device) */
+  int32_t reserved;
 } hawk_explore_opts;
 typedef struct {
   int64_t evaluated;     /* (workload, variant) configurations measured */
   int64_t pruned;        /* of which pruned or infeasible */
   double best_ms;        /* workload time of the returned variant */
   double seconds;        /* wall time of the exploration */
+  int64_t reused;        /* configurations taken from the timing log (resume) */
 } hawk_explore_report;
 /* Learns one variant for the workload W of k queries (Section 8.1): the
    variant minimising the summed per-query median time, by exhaustive search
    ("backtracking" of Section 9.3.2) or by Algorithm 1. Every query must be of
-   the same kind (all projection or all aggregation). */
+   the same kind (all projection or all aggregation). A variant that is pruned
+   (HAWK_E_TIMEOUT) or infeasible for any query counts as +inf; any other
+   error stops the exploration and is returned. */
 hawk_status hawk_explore(hawk_ctx* ctx, hawk_query* const* W, int32_t k, int32_t mode,
                          const hawk_explore_opts* opts, hawk_variant* best, hawk_explore_report* rep);
 
@@ -281,7 +294,7 @@ hawk_status hawk_features(const hawk_query* q, const hawk_variant* v, float* out
 /* A 12 -> 64 -> 64 -> 1 ReLU network in FP32 predicting ln(milliseconds) of a
    (query, variant) pair from hawk_features; the paper picks one variant per
    processor (Section 8) and leaves a per-query optimizer to future work
-   (Section 9.5), which this model provides. Parameters (5,057 floats):
+   (Sections 9.3.4 and 9.4), which this model provides. Parameters (5,057 floats):
    W1 [64x12] | b1 [64] | W2 [64x64] | b2 [64] | W3 [64] | b3 [1], row-major;
    features are standardised as (x - mu) / sd before the first layer. */
 hawk_status hawk_model_create(hawk_ctx* ctx, uint64_t seed, hawk_model** out);
@@ -317,7 +330,7 @@ hawk_status hawk_model_pick_ensemble(hawk_model* const* ms, int32_t nm, float pe
 /* ------------------------------------------------------------ batched execution */
 /* Many queries as one captured HIP graph of persistent kernels. Section 8
    tunes one variant per workload and the paper leaves per-query work
-   distribution open (Section 9.5); a batch instead runs every query of a
+   distribution open (Sections 9.3.4 and 9.4); a batch instead runs every query of a
    mixed workload in one launch sequence: a fill kernel resets the batch's
    tables and counters, a persistent kernel runs the tiles of every build
    pipeline (HASH_PUT, Table 1), one persistent kernel per plan shape runs
@@ -351,7 +364,10 @@ void hawk_batch_free(hawk_batch* b);
 hawk_status hawk_batch_run(hawk_batch* b);
 /* One untimed and `reps` timed replays with HIP events on the context
    stream; *median_ms is the median. Returns HAWK_E_CAPACITY when a hash table
-   of the batch overflowed (group hint or join size too small). */
+   of the batch overflowed (group hint or join size too small), HAWK_E_DUPKEY
+   when a build inserted a key twice, and HAWK_E_TIMEOUT when a projection
+   tile's bounded wait for the counts of the tiles before it gave up (never
+   expected: those tiles were handed out earlier to running workgroups). */
 hawk_status hawk_batch_time(hawk_batch* b, int32_t reps, double* median_ms);
 /* Times every schedule of the grid tile_rows_log2 14..18 x wgs_per_cu
    {1, 2, 4, 8} x order {0, 1} (`reps` timed replays each), keeps the fastest
@@ -363,7 +379,7 @@ hawk_status hawk_batch_opts_get(const hawk_batch* b, hawk_batch_opts* out);
    the next hawk_batch_run overwrites what it shows, and hawk_batch_free
    orphans it; release it with hawk_result_free. Errors as the result calls;
    HAWK_E_CAPACITY or HAWK_E_DUPKEY when the run's hash tables failed (no
-   retry inside a batch). */
+   retry inside a batch), HAWK_E_TIMEOUT when a look-back wait gave up. */
 hawk_status hawk_batch_result(hawk_batch* b, int32_t i, hawk_result** out);
 
 #ifdef __cplusplus

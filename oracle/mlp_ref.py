@@ -2,7 +2,7 @@
 
 The cost model is not in the paper: the paper's Section 8 learns one variant
 per processor and names a run-time, per-query optimizer as future work
-(Section 9.5). The model here predicts ln(run time in ms) of a (query,
+(Sections 9.3.4 and 9.4). The model here predicts ln(run time in ms) of a (query,
 variant) pair from 12 features:
 
     z1 = W1 @ ((x - mu) / sd) + b1,  h1 = relu(z1)        (64 units)

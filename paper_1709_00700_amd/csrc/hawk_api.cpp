@@ -506,11 +506,16 @@ extern "C" hawk_status hawk_query_create(hawk_ctx* ctx, const hawk_pipeline* pip
           HkAgg A;
           std::memset(&A, 0, sizeof(A));
           A.fn = static_cast<int8_t>(ag.fn);
-          A.wide = static_cast<int8_t>((ag.fn == HAWK_SUM || ag.fn == HAWK_AVG) && ag.wide ? 1 : 0);
+          A.wide = static_cast<int8_t>(ag.fn == HAWK_SUM && ag.wide ? 1 : 0);
           if (ag.fn != HAWK_COUNT) {
             int r;
             if ((st = L.attr(ag.attr, 2, &r))) break;
             A.reg = static_cast<int8_t>(r);
+            // AVG divides the exact sum. A 64-bit accumulator is exact for
+            // 8- and 32-bit attributes (fewer than 2^32 rows of |x| <= 2^31
+            // sum to less than 2^63 in magnitude); 64-bit attributes, and
+            // arithmetic results, take the 128-bit one.
+            if (ag.fn == HAWK_AVG && (ag.wide || L.dtype_of[ag.attr] == HAWK_I64)) A.wide = 1;
             A.word = word;
             word += A.wide ? 2 : 1;
           }
@@ -667,6 +672,8 @@ static hawk_status result_check(hawk_result* r) {
   r->nrows = static_cast<int64_t>(n);
   if (err & HK_ERR_DUPKEY) r->status = set_error(ctx, HAWK_E_DUPKEY, "a build pipeline inserted a key twice");
   else if (err & (HK_ERR_CAPACITY | HK_ERR_CUCKOO)) r->status = set_error(ctx, HAWK_E_CAPACITY, "hash table overflow");
+  else if (err & HK_ERR_TIMEOUT)
+    r->status = set_error(ctx, HAWK_E_TIMEOUT, "a bounded wait for another workgroup's result gave up");
   else r->status = HAWK_OK;
   return r->status;
 }

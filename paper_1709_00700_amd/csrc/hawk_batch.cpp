@@ -515,7 +515,9 @@ extern "C" hawk_status hawk_batch_time(hawk_batch* B, int32_t reps, double* medi
   }
   int err = 0;
   if (hipMemcpy(&err, B->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return berr(B, HAWK_E_DEVICE, "flags");
-  if (err) return berr(B, HAWK_E_CAPACITY, "batch hash table overflow or look-back failure");
+  if (err & HK_ERR_DUPKEY) return berr(B, HAWK_E_DUPKEY, "a build pipeline of the batch inserted a key twice");
+  if (err & (HK_ERR_CAPACITY | HK_ERR_CUCKOO)) return berr(B, HAWK_E_CAPACITY, "batch hash table overflow");
+  if (err) return berr(B, HAWK_E_TIMEOUT, "a projection look-back wait of the batch gave up");
   std::sort(t.begin(), t.end());
   *median_ms = t[t.size() / 2];
   return HAWK_OK;

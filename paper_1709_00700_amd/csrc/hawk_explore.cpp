@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <map>
@@ -169,6 +170,60 @@ std::string vkey(const hawk_variant& v) {
   return buf;
 }
 
+// Identity of a workload in the timing log: the kind, sizes and structure of
+// its queries (no device addresses), so that a later exploration of the same
+// workload can take its measurements from the log (Section 8.3: learned
+// configurations are stored and reused).
+std::string workload_signature(hawk_query* const* W, int32_t k, int num_cus) {
+  uint64_t h = 0xcbf29ce484222325ull;  // FNV-1a over a canonical text
+  auto mix = [&](const std::string& t) {
+    for (unsigned char c : t) h = (h ^ c) * 0x100000001b3ull;
+  };
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "cus=%d;k=%d;", num_cus, k);
+  mix(buf);
+  for (int32_t i = 0; i < k; ++i) {
+    const hawk_query* q = W[i];
+    const HkPlan& P = q->main;
+    std::snprintf(buf, sizeof(buf), "q%d:kind=%d,n=%lld,g=%lld,f=%d,p=%d,a=%d,gr=%d,ag=%d,pj=%d,w=%d;", i, q->kind,
+                  static_cast<long long>(P.nrows), static_cast<long long>(q->groups_hint), P.nfilters, P.nprobes,
+                  P.narith, P.ngroup, P.naggs, P.nproj, P.slot_words);
+    mix(buf);
+    for (int f = 0; f < P.nfilters; ++f) {
+      std::snprintf(buf, sizeof(buf), "F%d:%lld:%lld;", P.filters[f].reg, static_cast<long long>(P.filters[f].lo),
+                    static_cast<long long>(P.filters[f].hi));
+      mix(buf);
+    }
+    for (int c = 0; c < P.ncolA + P.ncolB + P.ncolC; ++c) {
+      const HkCol& col = c < P.ncolA ? P.colA[c] : c < P.ncolA + P.ncolB ? P.colB[c - P.ncolA]
+                                                                        : P.colC[c - P.ncolA - P.ncolB];
+      std::snprintf(buf, sizeof(buf), "C%d:%d;", col.dtype, col.reg);
+      mix(buf);
+    }
+    for (int a = 0; a < P.narith; ++a) {
+      const HkArith& A = P.arith[a];
+      std::snprintf(buf, sizeof(buf), "A%d:%d:%d:%d:%d:%d:%lld:%lld;", A.op, A.dst, A.x, A.y, A.xc, A.yc,
+                    static_cast<long long>(A.cx), static_cast<long long>(A.cy));
+      mix(buf);
+    }
+    for (int a = 0; a < P.naggs; ++a) {
+      std::snprintf(buf, sizeof(buf), "G%d:%d:%d;", P.aggs[a].fn, P.aggs[a].wide, P.aggs[a].reg);
+      mix(buf);
+    }
+    for (const QueryBuild& B : q->builds) {
+      std::snprintf(buf, sizeof(buf), "B%lld:%d;", static_cast<long long>(B.nrows), B.plan.nfilters);
+      mix(buf);
+      for (int f = 0; f < B.plan.nfilters; ++f) {
+        std::snprintf(buf, sizeof(buf), "%lld:%lld;", static_cast<long long>(B.plan.filters[f].lo),
+                      static_cast<long long>(B.plan.filters[f].hi));
+        mix(buf);
+      }
+    }
+  }
+  std::snprintf(buf, sizeof(buf), "%016llx", static_cast<unsigned long long>(h));
+  return buf;
+}
+
 struct Explorer {
   hawk_ctx* ctx;
   hawk_query* const* W;
@@ -176,10 +231,13 @@ struct Explorer {
   const hawk_explore_opts* opts;
   Space space;
   std::map<std::string, double> memo;
-  int64_t evaluated = 0, pruned = 0;
+  int64_t evaluated = 0, pruned = 0, reused = 0;
   FILE* db = nullptr;
+  std::string sig;
+  hawk_status fatal = HAWK_OK;  // an error other than pruning or infeasibility stops the search
 
   double workload_time(const hawk_variant& v) {
+    if (fatal) return kInf;
     const std::string key = vkey(v);
     auto it = memo.find(key);
     if (it != memo.end()) return it->second;
@@ -188,12 +246,17 @@ struct Explorer {
     for (int32_t i = 0; i < k && !bad; ++i) {
       double ms = 0;
       hawk_status st = hawk_time_variant(ctx, W[i], &v, opts->reps > 0 ? opts->reps : 3, opts->limit_ms, &ms);
+      if (st != HAWK_OK && st != HAWK_E_TIMEOUT && st != HAWK_E_INFEASIBLE) {
+        fatal = st;  // the context keeps the message
+        return kInf;
+      }
       float f[12];
       query_features(W[i], &v, ctx->num_cus, f);
       if (db) {
-        std::fprintf(db, "%d", i);
+        std::fprintf(db, "%s\t%d", sig.c_str(), i);
         for (float x : f) std::fprintf(db, "\t%.6g", x);
         std::fprintf(db, "\t%s\t%.6f\t%d\n", key.c_str(), st == HAWK_OK ? ms : -1.0, st);
+        std::fflush(db);
       }
       if (st != HAWK_OK) bad = true;
       else total += ms;
@@ -206,6 +269,39 @@ struct Explorer {
     }
     memo[key] = total;
     return total;
+  }
+
+  // Reads the measurements of this workload from an earlier log: a variant
+  // whose k per-query lines are all there enters the memo (any pruned or
+  // infeasible query makes it +inf).
+  void resume(const char* path) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    std::map<std::string, std::map<int32_t, double>> seen;  // variant -> query -> ms (inf: pruned)
+    char line[1024];
+    while (std::fgets(line, sizeof(line), f)) {
+      if (line[0] == '#') continue;
+      std::vector<std::string> tok;
+      std::string cur;
+      for (const char* p = line; *p && *p != '\n'; ++p) {
+        if (*p == '\t') { tok.push_back(cur); cur.clear(); }
+        else cur += *p;
+      }
+      tok.push_back(cur);
+      if (tok.size() != 17 || tok[0] != sig) continue;  // sig, query, 12 features, variant, ms, status
+      const int32_t qi = std::atoi(tok[1].c_str());
+      const int st = std::atoi(tok[16].c_str());
+      if (qi < 0 || qi >= k) continue;
+      seen[tok[14]][qi] = st == HAWK_OK ? std::atof(tok[15].c_str()) : kInf;
+    }
+    std::fclose(f);
+    for (const auto& kv : seen) {
+      if (static_cast<int32_t>(kv.second.size()) != k || memo.count(kv.first)) continue;
+      double total = 0;
+      for (const auto& qt : kv.second) total += qt.second;
+      memo[kv.first] = total;
+      ++reused;
+    }
   }
 };
 
@@ -222,7 +318,7 @@ extern "C" hawk_status hawk_explore(hawk_ctx* ctx, hawk_query* const* W, int32_t
   if (!ctx) return HAWK_E_ARG;
   if (!W || k < 1 || !opts || !best) return set_error(ctx, HAWK_E_ARG, "null argument");
   const auto t0 = std::chrono::steady_clock::now();
-  Explorer E{ctx, W, k, opts, {}, {}, 0, 0, nullptr};
+  Explorer E{ctx, W, k, opts, {}, {}, 0, 0, 0, nullptr, {}, HAWK_OK};
   E.space.kind = W[0]->kind;
   E.space.table = false;
   for (int32_t i = 0; i < k; ++i) {
@@ -236,7 +332,14 @@ extern "C" hawk_status hawk_explore(hawk_ctx* ctx, hawk_query* const* W, int32_t
     E.space.sizes.push_back(2);
     E.space.sizes.push_back(2);
   }
-  if (opts->timing_db) E.db = std::fopen(opts->timing_db, "a");
+  E.sig = workload_signature(W, k, ctx->num_cus);
+  if (opts->timing_db && opts->resume) E.resume(opts->timing_db);
+  if (opts->timing_db) {
+    E.db = std::fopen(opts->timing_db, "a");
+    if (!E.db) return set_error(ctx, HAWK_E_ARG, std::string("cannot open the timing log ") + opts->timing_db);
+    std::fprintf(E.db, "#workload\t%s\t%d\tmode=%d\n", E.sig.c_str(), k, mode);
+    std::fflush(E.db);
+  }
   std::vector<int32_t> cfg(E.space.sizes.size(), 0);
   hawk_status st = HAWK_OK;
   if (mode == HAWK_EXPLORE_FEATURE_WISE) {
@@ -266,10 +369,12 @@ extern "C" hawk_status hawk_explore(hawk_ctx* ctx, hawk_query* const* W, int32_t
   }
   if (E.db) std::fclose(E.db);
   if (st) return st;
+  if (E.fatal) return E.fatal;
   *best = E.space.at(cfg);
   if (rep) {
     rep->evaluated = E.evaluated;
     rep->pruned = E.pruned;
+    rep->reused = E.reused;
     rep->best_ms = E.workload_time(*best);
     rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }

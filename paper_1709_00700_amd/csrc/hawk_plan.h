@@ -48,7 +48,8 @@ enum { HK_ADD = 1, HK_SUB = 2, HK_MUL = 3 };
 enum { HK_COUNT = 1, HK_SUM = 2, HK_MIN = 3, HK_MAX = 4, HK_AVG = 5 };
 
 // error flag bits written by kernels
-enum { HK_ERR_CAPACITY = 1, HK_ERR_DUPKEY = 2, HK_ERR_CUCKOO = 4 };
+// (HK_ERR_TIMEOUT: a bounded wait for another workgroup's result gave up)
+enum { HK_ERR_CAPACITY = 1, HK_ERR_DUPKEY = 2, HK_ERR_CUCKOO = 4, HK_ERR_TIMEOUT = 8 };
 
 struct HkCol { const void* ptr; int32_t dtype; int32_t reg; };
 struct HkFilter { int64_t lo, hi; int32_t reg; int32_t pad; };

@@ -172,7 +172,7 @@ __device__ void tile_project(const HkPlan& P, const HkBatchQuery& Q, int64_t t, 
           continue;
         }
         if (++spins > LB_SPIN_LIMIT) {  // never expected: report instead of hanging
-          set_err(Q.err, HK_ERR_CAPACITY);
+          set_err(Q.err, HK_ERR_TIMEOUT);
           break;
         }
         __builtin_amdgcn_s_sleep(1);

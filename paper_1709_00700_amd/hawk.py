@@ -93,7 +93,7 @@ class hawk_variant(ctypes.Structure):
 
 class hawk_explore_opts(ctypes.Structure):
     _fields_ = [("reps", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("limit_ms", ctypes.c_double),
-                ("timing_db", ctypes.c_char_p)]
+                ("timing_db", ctypes.c_char_p), ("resume", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class hawk_train_opts(ctypes.Structure):
@@ -112,7 +112,7 @@ class hawk_batch_opts(ctypes.Structure):
 
 class hawk_explore_report(ctypes.Structure):
     _fields_ = [("evaluated", ctypes.c_int64), ("pruned", ctypes.c_int64), ("best_ms", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("reused", ctypes.c_int64)]
 
 
 COST_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_void_p)
@@ -483,14 +483,16 @@ def learn_feature_wise(dim_sizes, cost, q=5, order=None):
     return tuple(best), calls.value
 
 
-def explore(ctx: Context, queries: list, mode: int, reps=3, max_iters=5, limit_ms=1000.0, timing_db=None):
+def explore(ctx: Context, queries: list, mode: int, reps=3, max_iters=5, limit_ms=1000.0, timing_db=None,
+            resume=False):
     W = (ctypes.c_void_p * len(queries))(*[q.handle.value for q in queries])
-    opts = hawk_explore_opts(reps, max_iters, limit_ms, timing_db.encode() if timing_db else None)
+    opts = hawk_explore_opts(reps, max_iters, limit_ms, timing_db.encode() if timing_db else None, int(resume), 0)
     best = hawk_variant()
     rep = hawk_explore_report()
     check(L().hawk_explore(ctx.handle, W, len(queries), mode, ctypes.byref(opts), ctypes.byref(best),
                            ctypes.byref(rep)), ctx.handle)
-    return best, {"evaluated": rep.evaluated, "pruned": rep.pruned, "best_ms": rep.best_ms, "seconds": rep.seconds}
+    return best, {"evaluated": rep.evaluated, "pruned": rep.pruned, "best_ms": rep.best_ms, "seconds": rep.seconds,
+                  "reused": rep.reused}
 
 
 # ---------------------------------------------------------------- learned cost model

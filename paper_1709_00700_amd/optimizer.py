@@ -1,5 +1,5 @@
 """Variant selection over a workload of many pipelines (Section 8, and the
-per-query optimizer the paper leaves to future work in Section 9.5).
+per-query optimizer the paper leaves to future work in Sections 9.3.4 and 9.4).
 
 Three ways to choose variants, all driven through the C ABI:
   * exhaustive search per query (the reference for pick quality);

@@ -30,7 +30,7 @@ def all_variants(ctx, tables, spec):
 
 
 # ------------------------------------------------------------------ projection
-@pytest.mark.parametrize("n", [100_003])
+@pytest.mark.parametrize("n", [1_000_000, 100_003])
 def test_c1_all_32_variants(ctx, n):
     tables, spec = dg.c1_projection(n=n)
     vs = all_variants(ctx, tables, spec)
@@ -237,3 +237,57 @@ def test_async_execution_matches(ctx):
     for r in rs:
         compare(r.to_numpy(spec), ref, spec, "async")
         r.free()
+
+
+# ------------------------------------------------------------------ AVG of sums beyond 64 bits
+def _avg_overflow_table(n, ngroups, seed):
+    # every value lies in [2^62 - 2^40, 2^62) or its negation: any two rows of
+    # one sign already sum past 2^63, so a 64-bit accumulator would wrap
+    rng = np.random.default_rng(seed)
+    mag = rng.integers((1 << 62) - (1 << 40), 1 << 62, size=n, dtype=np.int64)
+    sign = np.where(rng.integers(0, 8, size=n) == 0, -1, 1).astype(np.int64)
+    t = {"g": rng.integers(0, ngroups, size=n).astype(np.int32) * 7919 - 3,
+         "v": mag * sign,
+         "q": rng.integers(-50, 50, size=n).astype(np.int32)}
+    aggs = [("avg", "v", False), ("count", None, False), ("sum", "v", False), ("avg", "q", False)]
+    return t, aggs
+
+
+@pytest.mark.parametrize("ngroups", [16, 40_000, 0])
+def test_narrow_avg_of_overflowing_sum(ctx, ngroups):
+    """AVG(v) with wide=0 divides the exact sum (the oracle's reading), on the
+    local/global, linear/cuckoo, spilling and non-grouped paths."""
+    t, aggs = _avg_overflow_table(90_001, max(ngroups, 1), 21 + ngroups % 97)
+    spec = {"builds": [], "main": {"table": "t", "filters": [("q", -45, 45)], "probes": [], "arith": [],
+                                   "group_by": ["g"] if ngroups else [], "aggs": aggs,
+                                   "groups_hint": max(ngroups, 1)}}
+    ref = oracle.run({"t": t}, spec)
+    # the exact per-group sums really leave the int64 range
+    assert any(abs(a * c) > (1 << 63) for a, c in zip(ref["aggs"][0], ref["count"]) if c)
+    vs = all_variants(ctx, {"t": t}, spec)
+    picked = sample(vs, 48, seed=ngroups + 1)
+    if ngroups >= 10_000:
+        picked += sample(local_linear(vs), 24, seed=5)   # spilling variants
+    say("narrow AVG of overflowing sums, groups", ngroups, "variants", len(picked))
+    run_variants(ctx, {"t": t}, spec, picked, ref=ref, label=f"avg{ngroups}")
+
+
+def test_narrow_avg_run_time_kernel_and_batch(ctx):
+    t, aggs = _avg_overflow_table(120_003, 30_000, 77)
+    spec = {"builds": [], "main": {"table": "t", "filters": [], "probes": [], "arith": [],
+                                   "group_by": ["g"], "aggs": aggs, "groups_hint": 30_000}}
+    ref = oracle.run({"t": t}, spec)
+    ctx.set_jit(True)
+    vs = [hawk.variant(agg_strategy=s, ht=0, hash=h, mem=1, pred=p, thread_mult=tm, wg_size=wg)
+          for s, h, p, tm, wg in [(0, 1, 0, 1, 1024), (0, 0, 1, 8, 256), (1, 1, 0, 1, 512), (0, 1, 1, 64, 128)]]
+    say("narrow AVG: run-time compiled kernels")
+    q, _ = run_variants(ctx, {"t": t}, spec, vs, ref=ref, label="avg-jit")
+    assert ctx.jit_stats()[0] >= 1
+    say("narrow AVG: batch")
+    for sep in (0, 1):
+        b = hawk.Batch(ctx, [q], separate=sep)
+        b.run()
+        r = b.result(0)
+        compare(r.to_numpy(spec), ref, spec, f"avg-batch separate={sep}")
+        r.free()
+        b.free()

@@ -50,8 +50,10 @@ def test_learned_picks_beat_algorithm1_per_workload(ctx):
             f"best {r['best']} {r['best_ms']:.4f} ms, pick {r['pick']} {r['pick_ms']:.4f} ms")
     assert pq["model"]["pruned_picks"] == 0
     # per-query picks from the model are closer to each pipeline's best than
-    # one learned variant per kind (geometric mean of t(pick) / t(best), the
-    # pick-quality figure); the total-time ratios are reported above
+    # one learned variant per kind, both per pipeline (geometric mean of
+    # t(pick) / t(best)) and over the whole workload (total time), and within
+    # 1.15x of the exhaustive best on the geometric mean
     assert pq["model"]["geomean_ratio"] < pq["alg1"]["geomean_ratio"]
-    assert pq["model"]["geomean_ratio"] < 1.3
+    assert pq["model"]["total_ratio"] < pq["alg1"]["total_ratio"]
+    assert pq["model"]["geomean_ratio"] <= 1.15
     ens.free()

@@ -228,3 +228,36 @@ def test_handles_outliving_their_context_are_orphaned():
     assert hawk.L().hawk_features(q.handle, ctypes.byref(hawk.variant()), f) == hawk.HAWK_E_ARG
     hawk.L().hawk_query_free(q.handle)   # only host memory is released; no crash
     q.handle = None
+
+
+@pytest.mark.parametrize("mode", [hawk.HAWK_EXPLORE_EXHAUSTIVE, hawk.HAWK_EXPLORE_FEATURE_WISE])
+def test_explore_resumes_from_timing_log(plan_ctx, tmp_path, mode):
+    """A planning context cannot time anything: the first exploration logs its
+    workload line and stops with HAWK_E_DEVICE. Once the log holds a timing for
+    every variant of that workload, a resumed exploration measures nothing and
+    returns the argmin of the logged times (ties: the first in search order)."""
+    tables, spec = dg.c2_aggregation(n=10, dist="uniform")
+    plan_ctx.register_shapes(_shapes(tables))
+    q = hawk.build_query(plan_ctx, spec)
+    db = str(tmp_path / "timings.tsv")
+    with pytest.raises(hawk.HawkError) as e:
+        hawk.explore(plan_ctx, [q], mode, timing_db=db)
+    assert e.value.code == hawk.HAWK_E_DEVICE
+    head = [ln for ln in open(db) if ln.startswith("#workload")]
+    assert len(head) == 1
+    sig = head[0].split("\t")[1]
+    space = hawk.variant_space(q)
+    rng = np.random.default_rng(3)
+    times = {hawk.format_variant(v): float(rng.uniform(1.0, 9.0)) for v in space}
+    pruned = [hawk.format_variant(v) for v in space[::7]]
+    with open(db, "a") as f:
+        f.write("other\t0" + "\t0" * 12 + f"\t{hawk.format_variant(space[0])}\t0.001\t0\n")  # another workload
+        for key, ms in times.items():
+            st = hawk.HAWK_E_TIMEOUT if key in pruned else 0
+            f.write(f"{sig}\t0" + "\t0" * 12 + f"\t{key}\t{-1.0 if st else ms:.6f}\t{st}\n")
+    best, rep = hawk.explore(plan_ctx, [q], mode, timing_db=db, resume=True)
+    assert rep["evaluated"] == 0 and rep["reused"] == len(space)
+    feasible = {k: t for k, t in times.items() if k not in pruned}
+    if mode == hawk.HAWK_EXPLORE_EXHAUSTIVE:
+        assert hawk.format_variant(best) == min(feasible, key=feasible.get)
+    assert rep["best_ms"] == pytest.approx(feasible[hawk.format_variant(best)], abs=1e-6)
