@@ -1,26 +1,33 @@
 #!/usr/bin/env python3
 """Benchmark of the pipeline hot path on one MI355X.
 
-A step is one pass of the whole hot path over the configured workload: every
-pipeline of the workload runs once (build pipelines, scan, selection, probes,
-arithmetic, aggregation or projection, result extraction) in the variant the
-variant optimizer picked for it. Inputs are resident in HBM before the timed
-region; K steps are timed between stream synchronisations.
+Default run (N=1): every workload configuration, with inputs resident in HBM
+before any timed region.
 
-Default workload (N=1): grouped aggregation over 64M rows with an int32 key
-and an int64 value, COUNT/SUM/MIN/MAX per group, once with 16 uniform groups
-and once with zipf(1.1) keys over 1M ranks (the two grouped-aggregation
-cases). `value` is input rows per second of the whole step.
-
-Also reported: the dominant kernel's roofline (algorithmic bytes per launch /
-its average launch duration, timed live with HIP events on the library's
-stream), per-pipeline rows/s and GB/s, and the CPU oracle timed on a bounded
-sample of the same workload on the host.
+* The timed step (`value`, `ms_per_step`) is one pass of the wide
+  scan-aggregate over 600M rows (the largest configuration): LOOP, six column
+  loads, four ARITHMETIC steps, HASH_AGGREGATE of 8 aggregates into 6 groups
+  with an exact 128-bit sum, result extraction, in the variant the exhaustive
+  search picked. `value` is input rows per second.
+* `roofline`: that step's dominant kernel, algorithmic bytes per launch over
+  its average launch duration (HIP events the library records on its own
+  stream during the timed steps).
+* `per_pipeline`: every configuration's pipeline (selection+projection at 1M
+  and 256M rows, grouped aggregation over 64M rows with 16 uniform and 1M zipf
+  groups, the 120M-row star join, the wide aggregation) with rows/s,
+  algorithmic GB/s, roofline fraction of the whole pipeline and of its
+  dominant kernel, per-kernel times and measured HBM traffic.
+* `c5`: 256 mixed pipelines as one batched graph launch, and the learned
+  per-query variant picks against each query's exhaustive best and against
+  Algorithm 1's per-workload variant, on queries of 4M-64M rows.
+* `cpu_baseline`: the CPU oracle on all host cores and on one core, on a
+  bounded sample of the timed workload.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -41,13 +48,16 @@ DEFAULT_VARIANTS = {
     "c3": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=1, agg_strategy=0, thread_mult=8, wg_size=512),
     "c4": dict(proj_strategy=1, mem=1, pred=1, ht=0, hash=1, agg_strategy=0, thread_mult=8, wg_size=512),
 }
+DEFAULT_VARIANTS["c1_256m"] = DEFAULT_VARIANTS["c1"]
 
-# algorithmic bytes read per input row of each pipeline (columns the
-# pipeline must read once), plus the kernel family that dominates it
-ALGO_BYTES_PER_ROW = {"c1": None, "c2u": 12, "c2z": 12, "c3": 24, "c4": 22}
+# algorithmic bytes per input row: the columns a pipeline must read once, plus
+# (projection) the qualifying rows' other columns and outputs at the
+# recipe's selectivity: 8 B (a, b) + 0.05 x (8 B c, d + 8 B out) = 8.8 B
+ALGO_BYTES_PER_ROW = {"c1": 8.8, "c1_256m": 8.8, "c2u": 12, "c2z": 12, "c3": 24, "c4": 22}
 KERNEL_FAMILIES = ["k_agg", "k_scalar_agg", "k_mp_filter", "k_mp_project", "k_sp", "k_build", "k_finalize",
                    "k_init_aggtable", "k_scan", "k_sp_concat", "k_spill_scatter", "k_spill_agg"]
 WORKLOADS = {
+    "all": ["c4", "c1", "c1_256m", "c2u", "c2z", "c3"],
     "c1": ["c1"],
     "c2": ["c2u", "c2z"],
     "c3": ["c3"],
@@ -56,73 +66,70 @@ WORKLOADS = {
 }
 DESCRIPTION = {
     "c1": "selection+projection: 1M rows, 4 int32 cols uniform [0,1000), a<100 AND 200<=b<700, out int64 c*d+a in row order",
-    "c2": "grouped aggregation: 64M rows int32 key + int64 value uniform [0,1e6); 16 uniform groups and zipf(1.1) over 1M ranks; COUNT/SUM/MIN/MAX",
+    "c1_256m": "selection+projection scaled to 256M rows (same recipe)",
+    "c2u": "grouped aggregation: 64M rows, int32 key over 16 uniform groups, int64 value [0,1e6); COUNT/SUM/MIN/MAX",
+    "c2z": "grouped aggregation: 64M rows, int32 key zipf(1.1) over 1M ranks, int64 value [0,1e6); COUNT/SUM/MIN/MAX",
     "c3": "star join: 120M-row fact, 4 int32 FKs into dims 2.5k/200k/30k/80k filtered 20/5/20/1 %, SUM(int64 rev) by (d0.g, d2.g)",
-    "c4": "wide scan-aggregate: 600M rows, 6 skewed groups, 8 aggregates incl. exact 128-bit SUM(price*(100-disc)*(100+tax))",
+    "c4": "wide scan-aggregate: 600M rows, 6 skewed groups (flag1 x flag2), 8 aggregates incl. exact 128-bit SUM(price*(100-disc)*(100+tax))",
     "c5": "mixed workload: 256 projection / aggregation / star-join pipelines over windows of 200M-row pools, "
           "lognormal rows in [1M, 200M], one batched graph launch",
 }
+# the timed step of each workload choice
+HEADLINE = {"all": "c4", "c1": "c1", "c3": "c3", "c4": "c4"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_pipelines(workload, rows):
+def make_pipeline(name, rows=None):
     from paper_1709_00700_amd import datagen as dg
-    out = []
-    for name in WORKLOADS[workload]:
+    if name == "c1_256m":
+        tables, spec = dg.workload("c1", n=rows or (256 << 20))
+    else:
         kw = {} if rows is None else {"n": rows}
         tables, spec = dg.workload(name, **kw)
-        # one table namespace per pipeline
-        ren = {t: f"{name}_{t}" for t in tables}
-        tables = {ren[t]: c for t, c in tables.items()}
-        spec["main"]["table"] = ren[spec["main"]["table"]]
-        for b in spec["builds"]:
-            b["table"] = ren[b["table"]]
-        out.append((name, tables, spec))
-    return out
+    # one table namespace per pipeline
+    ren = {t: f"{name}_{t}" for t in tables}
+    tables = {ren[t]: c for t, c in tables.items()}
+    spec["main"]["table"] = ren[spec["main"]["table"]]
+    for b in spec["builds"]:
+        b["table"] = ren[b["table"]]
+    return tables, spec
 
 
-# HBM traffic of the dominant kernel per workload, from two rocprofv3 --pmc
-# runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of that workload, each
-# scaled by the ratio of known bytes to the counter's reading for a plain
-# device copy (--copy-calibration). Valid only for the kernel sources it was
-# measured on, with the same variants: bench.py reports null otherwise.
-TRAFFIC = {
-    ("k_agg", "c2"): {"sources_sha": "28f9545bf8c32692", "variants_sha": "c62b14057a3f9b21",
-                      "bytes_per_launch": 981707435},
-    ("k_agg", "c3"): {"sources_sha": "28f9545bf8c32692", "variants_sha": "4da2aec3e3d4646d",
-                      "bytes_per_launch": 3330324547},
-    ("k_agg", "c4"): {"sources_sha": "28f9545bf8c32692", "variants_sha": "eb3f0a286c66bac6",
-                      "bytes_per_launch": 13333290310},
-}
+# HBM traffic of each pipeline, from two rocprofv3 --pmc runs (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch) of `bench.py --workload W`, summed over the
+# pipeline's kernels and scaled by the ratio of known bytes to the counters'
+# reading for a plain device copy (--copy-calibration: FETCH x 2.000, WRITE x
+# 1.000). Valid only for the kernel sources it was measured on, with the same
+# variant: reported as null otherwise.
+TRAFFIC = {}
+TRAFFIC_SOURCES = ["hk_agg.hip", "hk_agg_body.h", "hawk_jit.cpp", "hawk_device.h", "hawk_plan.h", "hk_proj.hip",
+                   "hk_common.hip", "hk_scalar.hip"]
 
 
-def kernel_sources_sha(kernel):
+def kernel_sources_sha():
     import hashlib
-    files = {"k_agg": ["hk_agg.hip", "hk_agg_body.h", "hawk_jit.cpp", "hawk_device.h", "hawk_plan.h"]}.get(kernel, [])
-    if not files:
-        return None
     h = hashlib.sha256()
-    for f in files:
+    for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, "paper_1709_00700_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def variants_sha(workload):
+def variant_sha(name):
     import hashlib
-    return hashlib.sha256(json.dumps([DEFAULT_VARIANTS[p] for p in WORKLOADS[workload]],
-                                     sort_keys=True).encode()).hexdigest()[:16]
+    return hashlib.sha256(json.dumps(DEFAULT_VARIANTS[name], sort_keys=True).encode()).hexdigest()[:16]
 
 
-def traffic_for(kernel, workload):
-    """Measured HBM bytes per launch, while the kernel sources and the workload's variants are unchanged."""
-    t = TRAFFIC.get((kernel, workload))
-    if not t or t["sources_sha"] != kernel_sources_sha(kernel) or t.get("variants_sha") != variants_sha(workload):
+def traffic_for(name):
+    """Measured HBM bytes of one pass of the pipeline, per kernel, while its
+    kernel sources and variant are unchanged; None otherwise."""
+    t = TRAFFIC.get(name)
+    if not t or t["sources_sha"] != kernel_sources_sha() or t["variant_sha"] != variant_sha(name):
         return None
-    return t["bytes_per_launch"]
+    return t
 
 
 def copy_calibration(nbytes):
@@ -144,164 +151,244 @@ def explore(ctx, pipes, mode, timing_db, args_limit_ms):
     m = hawk.HAWK_EXPLORE_EXHAUSTIVE if mode == "exhaustive" else hawk.HAWK_EXPLORE_FEATURE_WISE
     for name, q, v, nrows in pipes:
         log(f"[bench] exploring {name} ({mode})")
-        best, rep = hawk.explore(ctx, [q], m, reps=2, max_iters=5, limit_ms=args_limit_ms, timing_db=timing_db)
+        best, rep = hawk.explore(ctx, [q], m, reps=2, max_iters=5, limit_ms=args_limit_ms, timing_db=timing_db,
+                                 resume=bool(timing_db))
         print(json.dumps({"explore": name, "mode": mode, "rows": nrows, "best": hawk.format_variant(best),
                           "best_variant": best.as_dict(), **rep}), flush=True)
 
 
-def run_c5(args):
-    """Mixed workload: every pipeline in one batched graph launch (rows/s of the
-    whole batch); with --pick-quality also the learned per-query picks against
-    exhaustive search and Algorithm 1, on a smaller seeded instance."""
+# ------------------------------------------------------------------ per-pipeline measurement
+def pipeline_entry(ctx, name, q, v, nrows, reps):
+    """Median pipeline time (HIP events around the whole execution) and the
+    per-kernel launch durations the library records, over `reps` runs."""
+    from paper_1709_00700_amd import hawk
+    ms = hawk.time_variant(ctx, q, v, reps=reps)
+    hawk.profile_enable(ctx, True)
+    for _ in range(reps):
+        hawk.execute(ctx, q, v, sync=False).free()
+    stats = {f: hawk.profile_read(ctx, f) for f in KERNEL_FAMILIES}
+    hawk.profile_enable(ctx, False)
+    stats = {f: (t / n, n / reps) for f, (t, n) in stats.items() if n}
+    dom = max(stats, key=lambda f: stats[f][0] * stats[f][1])
+    algo = nrows * ALGO_BYTES_PER_ROW[name]
+    entry = {"pipeline": name, "rows": nrows, "ms": ms, "rows_per_s": nrows / (ms / 1e3),
+             "variant": hawk.format_variant(v), "algo_bytes": algo,
+             "algo_gb_per_s": algo / (ms / 1e3) / 1e9, "frac": algo / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+             "dominant_kernel": dom, "kernel_ms": stats[dom][0],
+             "kernel_frac": algo / (stats[dom][0] / 1e3) / 1e9 / HBM_PEAK_GBS,
+             "kernels_ms": {f: round(s[0], 4) for f, s in stats.items()},
+             "launches_per_run": {f: s[1] for f, s in stats.items()}}
+    t = traffic_for(name)
+    entry["traffic"] = None if t is None else {"bytes": t["total"], "per_kernel": t["per_kernel"],
+                                               "vs_algo": t["total"] / algo}
+    return entry
+
+
+# ------------------------------------------------------------------ C5: batch and pick quality
+def c5_algo_bytes(q):
+    """Bytes a C5 pipeline must read (and write) at its target selectivity s:
+    projection a (4 B) for every row, b, c, d (12 B) and the output (8 B) per
+    qualifying row; aggregation the filter column (4 B) for every row, key and
+    value (12 B) per qualifying row; star join the first key (4 B) for every
+    row, each further key for the rows the probes before it keep (per-dimension
+    selectivity s^(1/4)), and the revenue (8 B) per joined row."""
+    n, s = q["rows"], q["selectivity"]
+    if q["kind"] == 1:
+        return n * (4 + s * 20)
+    if q["kind"] == 2:
+        return n * (4 + s * 12)
+    d = s ** 0.25
+    return n * (4 * (1 + d + d * d + d * d * d) + 8 * s)
+
+
+def c5_batch(ctx, dev, pools_np, nq, pool_rows, schedule, autotune, steps, warmup):
+    """The 256-pipeline mixed workload as one graph replay; also by pipeline kind."""
     import torch
     from paper_1709_00700_amd import datagen as dg
     from paper_1709_00700_amd import hawk, optimizer
-
-    pool_rows = args.rows or 200_000_000
-    nq = args.c5_queries
-    ctx = hawk.Context(0)
-    if not args.no_jit:
-        ctx.set_jit(True)
-    ncu, _ = ctx.device_info()
-    log(f"[bench] c5: generating pools of {pool_rows} rows, {nq} pipelines")
-    pools = dg.c5_pools(pool_rows)
     qs = dg.c5_queries(nq, pool_rows, min_rows=min(1_000_000, pool_rows), max_rows=pool_rows)
-    hs = optimizer.register_c5(ctx, pools, qs)
-    del pools
+    hs = optimizer.register_c5(ctx, pools_np, qs, prefix="c5_", dev=dev)
     total_rows = sum(q["rows"] for q in qs)
-    log("[bench] c5: capturing the batch")
-    b = hawk.Batch(ctx, hs)
-    if args.autotune:
+    b = hawk.Batch(ctx, hs, **schedule)
+    if autotune:
         best, ms = b.autotune(reps=2)
         log(f"[bench] c5: autotuned schedule {best} ({ms:.3f} ms)")
     b.run()
     r = b.result(0)
     r.info()  # raises if any hash table of the batch overflowed
     r.free()
-    for _ in range(args.warmup):
-        b.run()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(ctx.stream)
-    for _ in range(args.steps):
-        b.run()
-    e1.record(ctx.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1) / args.steps
-    out = {"metric": METRIC, "value": total_rows / (ms / 1e3), "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-           "config": {"workload": DESCRIPTION["c5"], "pipelines": nq, "rows_per_step": total_rows,
-                      "pool_rows": pool_rows, "schedule": b.opts(), "compute_units": ncu,
-                      "codegen": dict(zip(("run_time_kernels", "compile_ms"), ctx.jit_stats()),
-                                      run_time=not args.no_jit),
-                      "kinds": {k: sum(1 for q in qs if q["kind"] == k) for k in (1, 2, 3)}},
-           "wall_s_timed": wall}
+    ms = b.time(reps=max(steps, 3))
+    out = {"pipelines": nq, "rows": total_rows, "ms": ms, "rows_per_s": total_rows / (ms / 1e3),
+           "schedule": b.opts(), "kinds": {}}
     b.free()
-    if args.pick_quality:
-        out["pick_quality"] = c5_pick_quality(ctx, args)
-    print(json.dumps(out), flush=True)
-    ctx.close()
+    out["algo_bytes"] = sum(c5_algo_bytes(q) for q in qs)
+    out["algo_gb_per_s"] = out["algo_bytes"] / (ms / 1e3) / 1e9
+    for kind in (1, 2, 3):
+        sub = [h for h, q in zip(hs, qs) if q["kind"] == kind]
+        rows = sum(q["rows"] for q in qs if q["kind"] == kind)
+        algo = sum(c5_algo_bytes(q) for q in qs if q["kind"] == kind)
+        bk = hawk.Batch(ctx, sub, **out["schedule"])
+        kms = bk.time(reps=3)
+        bk.free()
+        out["kinds"][str(kind)] = {"pipelines": len(sub), "rows": rows, "ms": kms, "rows_per_s": rows / (kms / 1e3),
+                                   "algo_bytes": algo, "algo_gb_per_s": algo / (kms / 1e3) / 1e9}
+    torch.cuda.synchronize()
+    return out
 
 
-def c5_pick_quality(ctx, args):
-    """Train the cost model on sampled-variant timings of one seeded C5 instance,
-    then compare its per-query picks and Algorithm 1's per-kind variant with the
-    exhaustive best of each query of another instance."""
+def c5_pick_quality(ctx, dev, pools_np, pool_rows, args):
+    """The learned per-query picks on C5 queries of 4M-64M rows (their best
+    variants are HBM-bound), against each query's exhaustive best (pruned at
+    10x the running best) and Algorithm 1's per-kind variant; training timings
+    come from other seeded C5 queries over the same pools."""
     from paper_1709_00700_amd import datagen as dg
     from paper_1709_00700_amd import hawk, optimizer
-
-    pool = args.pq_pool_rows
-    lim = args.pq_limit_ms
-    # the optimizer measures the kernels compiled ahead of time (compiling
-    # every variant of every plan at run time would dominate the search)
-    ctx.set_jit(False)
+    t_start = time.perf_counter()
+    ctx.set_jit(False)  # the optimizer times the kernels compiled ahead of time
     seed_train, seed_test = dg.MASTER_SEED + 1005, dg.MASTER_SEED + 5
-    log(f"[bench] pick quality: pools of {pool} rows, {args.pq_train} training / {args.pq_test} test pipelines")
-    tr_pools = dg.c5_pools(pool, seed_train)
-    tr = dg.c5_queries(args.pq_train, pool, seed_train, min_rows=min(10_000, pool), max_rows=pool)
-    tr_h = optimizer.register_c5(ctx, tr_pools, tr, prefix="train_")
-    del tr_pools
-    te_pools = dg.c5_pools(pool, seed_test)
-    te = dg.c5_queries(args.pq_test, pool, seed_test, min_rows=min(10_000, pool), max_rows=pool)
-    te_h = optimizer.register_c5(ctx, te_pools, te, prefix="test_")
-    del te_pools
+    hi = min(args.pq_max_rows, pool_rows)
+    tr = dg.c5_queries(args.pq_train, pool_rows, seed_train, min_rows=min(args.pq_min_rows // 4, hi), max_rows=hi)
+    te = dg.c5_queries(args.pq_test, pool_rows, seed_test + 77, min_rows=min(args.pq_min_rows, hi), max_rows=hi)
+    tr_h = optimizer.register_c5(ctx, pools_np, tr, prefix="pqtr_", dev=dev)
+    te_h = optimizer.register_c5(ctx, pools_np, te, prefix="pqte_", dev=dev)
     t0 = time.perf_counter()
-    X, y = optimizer.training_set(ctx, tr_h, args.pq_per_query, reps=2, limit_ms=lim, seed=7,
-                                  progress=lambda m: log("[bench] " + m))
+    X, y = optimizer.training_set(ctx, tr_h, args.pq_per_query, reps=2, limit_ms=args.pq_limit_ms, seed=7,
+                                  progress=lambda m: log("[bench] " + m), factor=10.0)
     t_collect = time.perf_counter() - t0
-    log(f"[bench] pick quality: {len(y)} training samples in {t_collect:.1f} s")
-    # the picks come from an ensemble of five models (mean + one standard
-    # deviation of their predictions); a single model is scored beside it
     ens = optimizer.Ensemble(ctx, size=5, penalty=1.0, seed=1)
     t0 = time.perf_counter()
     loss = ens.train(X, y, epochs=300, batch=512, lr=3e-3, seed=2)
+    X, y = optimizer.refine(ctx, tr_h, ens, X, y, top=4, rounds=2, reps=2, limit_ms=args.pq_limit_ms, factor=10.0,
+                            progress=lambda m: log("[bench] " + m), epochs=300, batch=512, lr=3e-3, seed=2)
     t_train = time.perf_counter() - t0
-    single = ens.models[0]
     t0 = time.perf_counter()
-    alg1 = optimizer.alg1_per_kind(ctx, te_h, reps=2, limit_ms=lim)
+    alg1 = optimizer.alg1_per_kind(ctx, te_h, reps=2, limit_ms=args.pq_limit_ms)
     t_alg1 = time.perf_counter() - t0
-    log("[bench] pick quality: exhaustive search of the test pipelines")
     t0 = time.perf_counter()
-    pq = optimizer.pick_quality(ctx, te_h, ens, reps=2, limit_ms=lim, alg1=alg1,
-                                progress=lambda m: log("[bench] " + m), extra={"single_model": single})
+    deadline = t_start + args.pq_budget_s
+    pq = optimizer.pick_quality(ctx, te_h, ens, reps=2, limit_ms=args.pq_limit_ms, alg1=alg1,
+                                progress=lambda m: log("[bench] " + m), extra={"single_model": ens.models[0]},
+                                factor=10.0, deadline=deadline)
     t_ex = time.perf_counter() - t0
-    pq.update({"training_samples": int(len(y)), "train_mse": loss, "collect_s": t_collect, "train_s": t_train,
-               "alg1_s": t_alg1, "exhaustive_s": t_ex, "pool_rows": pool,
+    done = pq["queries"]
+    rows = pq.pop("per_query")
+    for q, r in zip(te[:done], rows):
+        r.update({"kind": q["kind"], "rows": q["rows"]})
+    # the same queries back to back in their exhaustive-best variants (each a
+    # separate execution: host launches included), against one batch replay
+    best_vs = []
+    for h, r in zip(te_h[:done], rows):
+        best_vs.append(next(v for v in hawk.variant_space(h) if optimizer.variant_key(h, v) == r["best"]))
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for h, v in zip(te_h[:done], best_vs):
+        hawk.execute(ctx, h, v).free()
+    seq = []
+    for _ in range(3):
+        e0.record(ctx.stream)
+        res = [hawk.execute(ctx, h, v, sync=False) for h, v in zip(te_h[:done], best_vs)]
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        for r_ in res:
+            r_.free()
+        seq.append(e0.elapsed_time(e1))
+    b = hawk.Batch(ctx, te_h[:done], tile_rows_log2=17, wgs_per_cu=8, order=0)
+    batch_ms = b.time(reps=3)
+    b.free()
+    ctx.set_jit(not args.no_jit)
+    pq.update({"training_samples": int(len(y)), "train_mse": loss, "active_sampling": "2 rounds x top 4 per training query", "collect_s": t_collect, "train_s": t_train,
+               "alg1_s": t_alg1, "exhaustive_s": t_ex, "pool_rows": pool_rows,
+               "rows_range": [min(q["rows"] for q in te), max(q["rows"] for q in te)],
+               "best_ms_median": float(sorted(r["best_ms"] for r in rows)[len(rows) // 2]) if rows else None,
+               "prune": "a variant slower than 10x the fastest measured so far for the query is +inf",
                "alg1_variants": {str(k): hawk.format_variant(v) for k, (v, _) in alg1.items()},
-               "alg1_evaluated": {str(k): r["evaluated"] for k, (_, r) in alg1.items()},
-               "picker": "ensemble of 5 cost models, mean + 1 sd of predicted ln(ms)"})
+               "picker": "ensemble of 5 cost models, mean + 1 sd of predicted ln(ms)",
+               "kernels": "compiled ahead of time (run-time compilation off for the whole evaluation)",
+               "sum_best_ms": sum(r["best_ms"] for r in rows),
+               "sum_best_sequential_ms": sorted(seq)[1],
+               "batch_ms": batch_ms, "per_query": rows})
     ens.free()
     return pq
 
 
-def cpu_baseline(workload, budget_s=20.0):
-    """The oracle as it stands, single-threaded, on a bounded sample of the workload."""
+# ------------------------------------------------------------------ CPU baseline
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(name, budget_s=15.0):
+    """The oracle as it stands on a bounded sample of the timed workload (its
+    first n rows, n doubling from 2^20 while the budget lasts): on all host
+    cores of this GPU's share (row-partitioned: contiguous ranges, one thread
+    each, partial results merged), and on one core."""
     import oracle
     from paper_1709_00700_amd import datagen as dg
-    rows_done, secs, samples = 0, 0.0, []
-    names = WORKLOADS[workload]
-    n = 1 << 20
-    while secs < budget_s and n <= (1 << 26):
-        for name in names:
-            tables, spec = dg.workload(name, n=n) if name != "c3" else dg.workload(name, n=n)
+    try:
+        share = len(os.sched_getaffinity(0))
+    except AttributeError:
+        share = os.cpu_count() or 1
+    threads = max(1, min(share, 16))
+    out = {}
+    for leg, th in (("all", threads), ("one", 1)):
+        rows_done, secs, samples, last = 0, 0.0, [], 0.0
+        n = 1 << 20
+        # the next sample (twice the rows) is taken while it should end within the budget
+        while (not samples or secs + 2.2 * last <= budget_s) and n <= (1 << 28):
+            tables, spec = make_pipeline(name, rows=n)
             t0 = time.perf_counter()
-            oracle.run(tables, spec)
-            dt = time.perf_counter() - t0
+            oracle.run(tables, spec, threads=th)
+            last = time.perf_counter() - t0
+            secs += last
             rows_done += n
-            secs += dt
-            samples.append(f"{name}:{n}")
-        n *= 2
-    return {"value": rows_done / secs, "unit": "rows/s", "cores": 1, "kind": "oracle",
-            "sample": f"first rows of the same seeded workload: {', '.join(samples)} ({secs:.1f} s total)"}
+            samples.append(n)
+            del tables
+            n *= 2
+        out[leg] = {"value": rows_done / secs, "cores": th, "seconds": secs,
+                    "sample": f"first rows of the same seeded {name} workload, n = {samples[0]}..{samples[-1]} "
+                              f"doubling ({rows_done} rows in all)"}
+    res = {"value": out["all"]["value"], "unit": "rows/s", "cores": out["all"]["cores"], "kind": "oracle",
+           "sample": out["all"]["sample"] + ", row-partitioned over threads",
+           "single_core": {"value": out["one"]["value"], "cores": 1, "sample": out["one"]["sample"]},
+           "host": {"cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity": share}}
+    return res
 
 
+# ------------------------------------------------------------------ main
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="all", choices=sorted(WORKLOADS))
     ap.add_argument("--rows", type=int, default=None, help="override the input rows per pipeline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds per CPU baseline leg")
+    ap.add_argument("--no-c5", action="store_true", help="all: skip the mixed workload")
+    ap.add_argument("--no-pick-quality", action="store_true", help="skip the learned-pick evaluation")
     ap.add_argument("--explore", choices=["exhaustive", "feature_wise"], default=None,
                     help="run the variant optimizer on each pipeline instead of the timed steps")
-    ap.add_argument("--timing-db", default=None, help="append every exploration measurement to this file")
+    ap.add_argument("--timing-db", default=None, help="append every exploration measurement to this file (and resume)")
     ap.add_argument("--explore-limit-ms", type=float, default=200.0, help="pruning limit of the exploration")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration)")
     ap.add_argument("--no-jit", action="store_true", help="use only the kernels compiled ahead of time")
     ap.add_argument("--c5-queries", type=int, default=256)
+    ap.add_argument("--c5-pool-rows", type=int, default=200_000_000)
     ap.add_argument("--autotune", action="store_true", help="c5: autotune the batch schedule first")
-    ap.add_argument("--pick-quality", action="store_true", help="c5: also evaluate the learned per-query picks")
-    ap.add_argument("--pq-pool-rows", type=int, default=2_000_000)
-    ap.add_argument("--pq-train", type=int, default=48)
-    ap.add_argument("--pq-test", type=int, default=24)
-    ap.add_argument("--pq-per-query", type=int, default=64)
-    ap.add_argument("--pq-limit-ms", type=float, default=10.0)
+    ap.add_argument("--pq-train", type=int, default=32)
+    ap.add_argument("--pq-test", type=int, default=16)
+    ap.add_argument("--pq-per-query", type=int, default=40)
+    ap.add_argument("--pq-min-rows", type=int, default=4_000_000)
+    ap.add_argument("--pq-max-rows", type=int, default=64_000_000)
+    ap.add_argument("--pq-limit-ms", type=float, default=100.0)
+    ap.add_argument("--pq-budget-s", type=float, default=200.0, help="wall budget of the pick-quality leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library runs each pipeline on one GPU "
@@ -315,107 +402,117 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
-    if args.workload == "c5":
-        run_c5(args)
-        return
+    t_run = time.perf_counter()
     ctx = hawk.Context(0)
     if not args.no_jit and not args.explore:
         ctx.set_jit(True)  # aggregation kernels compiled for each plan structure during the warm-up
     ncu, lds_bytes = ctx.device_info()
     log(f"[bench] device: {ncu} compute units, {lds_bytes} LDS bytes per workgroup")
+    out = {}
     pipes = []
-    total_rows = 0
-    for name, tables, spec in make_pipelines(args.workload, args.rows):
+    for name in WORKLOADS[args.workload]:
         log(f"[bench] generating + uploading {name}")
+        tables, spec = make_pipeline(name, args.rows)
         ctx.register_numpy(tables)
         q = hawk.build_query(ctx, spec)
         v = hawk.variant(**DEFAULT_VARIANTS[name])
         nrows = len(next(iter(tables[spec["main"]["table"]].values())))
-        total_rows += nrows
         pipes.append((name, q, v, nrows))
         del tables
-    stream = ctx.stream
     if args.explore:
         explore(ctx, pipes, args.explore, args.timing_db, args.explore_limit_ms)
         ctx.close()
         return
-
-    def step():
-        for _, q, v, _ in pipes:
-            hawk.execute(ctx, q, v, sync=False).free()
-
-    # warm-up, checked end to end once
+    # every pipeline once, checked end to end (and its run-time kernel compiled)
     for name, q, v, _ in pipes:
         r = hawk.execute(ctx, q, v)
         r.info()
         r.free()
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"[bench] timing {args.steps} steps")
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    # the library brackets each of its launches with HIP events on its own
-    # stream while the timed steps run: the roofline's kernel durations
-    hawk.profile_enable(ctx, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = e0.elapsed_time(e1) / args.steps
-    value = total_rows / (ms_per_step / 1e3)
-    timed = {f: hawk.profile_read(ctx, f) for f in KERNEL_FAMILIES}
-    hawk.profile_enable(ctx, False)
 
-    # per-pipeline times and the dominant kernel, timed with events on the library stream
-    per = []
-    kern_stats = {}
-    for name, q, v, nrows in pipes:
-        ms = hawk.time_variant(ctx, q, v, reps=max(5, args.steps // 2))
+    head = HEADLINE.get(args.workload)
+    if head is None:
+        head_pipes = pipes
+        workload_desc = DESCRIPTION["c2u"] + "; and " + DESCRIPTION["c2z"] if args.workload == "c2" else None
+    else:
+        head_pipes = [p for p in pipes if p[0] == head]
+        workload_desc = DESCRIPTION[head]
+    stream = ctx.stream
+    per, value, ms_per_step, roofline, wall = [], None, None, None, None
+    if head_pipes:
+        def step():
+            for _, q, v, _ in head_pipes:
+                hawk.execute(ctx, q, v, sync=False).free()
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        log(f"[bench] timing {args.steps} steps of {[p[0] for p in head_pipes]}")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        # the library brackets each of its launches with HIP events on its own
+        # stream while the timed steps run: the roofline's kernel durations
         hawk.profile_enable(ctx, True)
-        for _ in range(max(5, args.steps // 2)):
-            hawk.execute(ctx, q, v, sync=False).free()
-        stats = {f: hawk.profile_read(ctx, f) for f in KERNEL_FAMILIES}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms_per_step = e0.elapsed_time(e1) / args.steps
+        step_rows = sum(p[3] for p in head_pipes)
+        value = step_rows / (ms_per_step / 1e3)
+        timed = {f: hawk.profile_read(ctx, f) for f in KERNEL_FAMILIES}
         hawk.profile_enable(ctx, False)
-        stats = {f: (t / n, n) for f, (t, n) in stats.items() if n}
-        dom = max(stats, key=lambda f: stats[f][0])
-        bpr = ALGO_BYTES_PER_ROW[name]
-        entry = {"pipeline": name, "rows": nrows, "ms": ms, "rows_per_s": nrows / (ms / 1e3),
-                 "variant": hawk.format_variant(v), "dominant_kernel": dom, "kernel_ms": stats[dom][0],
-                 "kernels_ms": {f: round(s[0], 4) for f, s in stats.items()}}
-        if bpr:
-            entry["algo_gb_per_s"] = nrows * bpr / (ms / 1e3) / 1e9
-            entry["kernel_algo_gb_per_s"] = nrows * bpr / (stats[dom][0] / 1e3) / 1e9
-        per.append(entry)
-        kern_stats.setdefault(dom, []).append((stats[dom][0], nrows * (bpr or 0)))
-    # roofline of the dominant kernel of the timed steps: algorithmic bytes
-    # per launch (the pipelines' launches are equally many) / the average
-    # launch duration recorded during the timed region
-    dom = max(timed, key=lambda f: timed[f][0])
-    tot_ms, nl = timed[dom]
-    avg_ms = tot_ms / nl
-    launches = [b for _, b in kern_stats.get(dom, [])]
-    avg_bytes = sum(launches) / len(launches) if launches else 0.0
-    achieved = avg_bytes / (avg_ms / 1e3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom, args.workload),
-                "algo_bytes_per_launch": avg_bytes, "avg_launch_ms": round(avg_ms, 4), "launches_timed": nl}
-
-    out = {"metric": METRIC, "value": value, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
+        # dominant kernel of the timed steps: algorithmic bytes per launch
+        # (one launch per pipeline per step) over its average launch duration
+        dom = max(timed, key=lambda f: timed[f][0])
+        tot_ms, nl = timed[dom]
+        avg_ms = tot_ms / nl
+        algo = sum(p[3] * ALGO_BYTES_PER_ROW[p[0]] for p in head_pipes) / len(head_pipes)
+        achieved = algo / (avg_ms / 1e3) / 1e9
+        tr = [traffic_for(p[0]) for p in head_pipes]
+        traffic = None
+        if all(t is not None for t in tr):
+            traffic = sum(t["per_kernel"].get(dom, 0) for t in tr) / len(tr)
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "algo_bytes_per_launch": algo, "avg_launch_ms": round(avg_ms, 4), "launches_timed": nl}
+    for name, q, v, nrows in pipes:
+        log(f"[bench] pipeline {name}")
+        per.append(pipeline_entry(ctx, name, q, v, nrows, reps=max(5, args.steps // 2)))
+    if args.workload in ("all", "c5") and not args.no_c5:
+        from paper_1709_00700_amd import datagen as dg
+        from paper_1709_00700_amd import optimizer
+        pool_rows = args.rows or args.c5_pool_rows
+        log(f"[bench] c5: generating + uploading pools of {pool_rows} rows")
+        pools_np = dg.c5_pools(pool_rows)
+        dev = optimizer.upload_pools(ctx, pools_np)
+        log("[bench] c5: batch")
+        sched = dict(tile_rows_log2=17, wgs_per_cu=8, order=0)
+        c5 = c5_batch(ctx, dev, pools_np, args.c5_queries, pool_rows, sched, args.autotune, args.steps,
+                      args.warmup)
+        c5["codegen"] = dict(zip(("run_time_kernels", "compile_ms"), ctx.jit_stats()))
+        if not args.no_pick_quality:
+            log("[bench] c5: pick quality")
+            c5["pick_quality"] = c5_pick_quality(ctx, dev, pools_np, pool_rows, args)
+        out["c5"] = c5
+        del pools_np
+        if not head_pipes:
+            value, ms_per_step, workload_desc = c5["rows_per_s"], c5["ms"], DESCRIPTION["c5"]
+    res = {"metric": METRIC, "value": value, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-           "config": {"workload": DESCRIPTION[args.workload], "pipelines": [p[0] for p in pipes],
-                      "rows_per_step": total_rows, "compute_units": ncu,
+           "config": {"workload": workload_desc, "timed_pipelines": [p[0] for p in head_pipes],
+                      "rows_per_step": sum(p[3] for p in head_pipes), "compute_units": ncu,
                       "codegen": dict(zip(("run_time_kernels", "compile_ms"), ctx.jit_stats()),
                                       run_time=not args.no_jit)},
-           "roofline": roofline, "per_pipeline": per, "wall_s_timed": wall}
-    if not args.no_cpu_baseline:
+           "roofline": roofline, "per_pipeline": per, **out, "wall_s_timed": wall}
+    if not args.no_cpu_baseline and head_pipes:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget)
-    print(json.dumps(out), flush=True)
+        res["cpu_baseline"] = cpu_baseline(head_pipes[0][0], args.cpu_budget)
+    res["run_s"] = time.perf_counter() - t_run
+    print(json.dumps(res), flush=True)
     ctx.close()
 
 

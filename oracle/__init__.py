@@ -83,7 +83,7 @@ class _Main(ctypes.Structure):
 def build(force: bool = True) -> str:
     """Compile the oracle with g++ (plain host code)."""
     if force or not os.path.exists(_SO):
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", _SO + ".tmp",
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-o", _SO + ".tmp",
                                os.path.join(_HERE, "hawk_oracle.cpp")])
         os.replace(_SO + ".tmp", _SO)
     return _SO
@@ -98,6 +98,9 @@ def _load():
         L.orc_run.argtypes = [ctypes.POINTER(_Build), ctypes.c_int32, ctypes.POINTER(_Main),
                               ctypes.POINTER(ctypes.c_void_p)]
         L.orc_run.restype = ctypes.c_int32
+        L.orc_run_parallel.argtypes = [ctypes.POINTER(_Build), ctypes.c_int32, ctypes.POINTER(_Main), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+        L.orc_run_parallel.restype = ctypes.c_int32
         L.orc_free.argtypes = [ctypes.c_void_p]
         L.orc_rows.argtypes = [ctypes.c_void_p]
         L.orc_rows.restype = ctypes.c_int64
@@ -128,8 +131,10 @@ def _filters(flist, names):
     return fs
 
 
-def run(tables: dict, spec: dict) -> dict:
-    """Interpret the query described by ``spec`` over ``tables`` (numpy columns)."""
+def run(tables: dict, spec: dict, threads: int = 1) -> dict:
+    """Interpret the query described by ``spec`` over ``tables`` (numpy columns).
+    threads > 1: the main pipeline's rows in that many contiguous ranges on as
+    many threads (same answer)."""
     L = _load()
     keep = []
     builds = []
@@ -169,7 +174,10 @@ def run(tables: dict, spec: dict) -> dict:
     main = _Main(nrows, cols, len(names), len(fl), fs, len(probes), parr, len(ariths), aarr,
                  1 if is_proj else 2, len(proj), projarr, len(group), grparr, len(aggs), aggarr)
     h = ctypes.c_void_p()
-    st = L.orc_run(barr, len(builds), ctypes.byref(main), ctypes.byref(h))
+    if threads > 1:
+        st = L.orc_run_parallel(barr, len(builds), ctypes.byref(main), int(threads), ctypes.byref(h))
+    else:
+        st = L.orc_run(barr, len(builds), ctypes.byref(main), ctypes.byref(h))
     if st != 0:
         raise OracleError(st)
     try:

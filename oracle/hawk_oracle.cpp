@@ -23,6 +23,7 @@
 #include <climits>
 #include <cstring>
 #include <map>
+#include <thread>
 #include <vector>
 
 namespace {
@@ -47,10 +48,11 @@ int64_t load(const orc_col& c, int64_t i) {
   }
 }
 
-// FILTER: refine a selection vector, one conjunct at a time.
-std::vector<int64_t> select(int64_t n, const orc_col* cols, int32_t nf, const orc_filter* f) {
-  std::vector<int64_t> sv(static_cast<size_t>(n));
-  for (int64_t i = 0; i < n; ++i) sv[i] = i;
+// LOOP over rows [r0, r1), then FILTER: refine the selection vector, one
+// conjunct at a time.
+std::vector<int64_t> select(int64_t r0, int64_t r1, const orc_col* cols, int32_t nf, const orc_filter* f) {
+  std::vector<int64_t> sv(static_cast<size_t>(r1 - r0));
+  for (int64_t i = r0; i < r1; ++i) sv[i - r0] = i;
   for (int32_t k = 0; k < nf; ++k) {
     std::vector<int64_t> next;
     next.reserve(sv.size());
@@ -66,26 +68,43 @@ std::vector<int64_t> select(int64_t n, const orc_col* cols, int32_t nf, const or
 
 int64_t wrap(uint64_t v) { int64_t r; std::memcpy(&r, &v, 8); return r; }
 
-}  // namespace
+typedef std::vector<std::map<int64_t, int64_t>> BuildTables;
 
-struct orc_result : Result {};
-
-extern "C" int32_t orc_run(const orc_build* builds, int32_t nbuilds, const orc_main* m,
-                           orc_result** out) {
-  if (!m || !out || m->nrows < 0) return ORC_E_ARG;
-  // build pipelines: LOOP, FILTER, HASH_PUT
-  std::vector<std::map<int64_t, int64_t>> tables(static_cast<size_t>(nbuilds));
+// build pipelines: LOOP, FILTER, HASH_PUT
+int32_t run_builds(const orc_build* builds, int32_t nbuilds, BuildTables& tables) {
+  tables.assign(static_cast<size_t>(nbuilds), std::map<int64_t, int64_t>());
   for (int32_t b = 0; b < nbuilds; ++b) {
     const orc_build& B = builds[b];
-    std::vector<int64_t> sv = select(B.nrows, B.cols, B.nfilters, B.filters);
+    std::vector<int64_t> sv = select(0, B.nrows, B.cols, B.nfilters, B.filters);
     for (int64_t i : sv) {
       int64_t key = load(B.cols[B.key_col], i);
       int64_t pay = load(B.cols[B.payload_col], i);
       if (!tables[b].emplace(key, pay).second) return ORC_E_DUPKEY;
     }
   }
-  // main pipeline
-  std::vector<int64_t> sv = select(m->nrows, m->cols, m->nfilters, m->filters);
+  return ORC_OK;
+}
+
+// running aggregates of one group: the row count and, per aggregate, the
+// exact value (sum, minimum or maximum)
+struct Acc { int64_t count = 0; std::vector<i128> v; };
+typedef std::map<std::vector<int64_t>, Acc> Groups;
+
+// the main pipeline over rows [r0, r1): projected rows in row order, or the groups
+struct Part {
+  std::vector<std::vector<int64_t>> proj;
+  Groups groups;
+};
+
+std::vector<i128> agg_init(const orc_main* m) {
+  std::vector<i128> init(static_cast<size_t>(m->naggs));
+  for (int32_t a = 0; a < m->naggs; ++a)
+    init[a] = m->aggs[a].fn == ORC_MIN ? i128(INT64_MAX) : m->aggs[a].fn == ORC_MAX ? i128(INT64_MIN) : 0;
+  return init;
+}
+
+int32_t run_main(const BuildTables& tables, int32_t nbuilds, const orc_main* m, int64_t r0, int64_t r1, Part& out) {
+  std::vector<int64_t> sv = select(r0, r1, m->cols, m->nfilters, m->filters);
   const int32_t nattr = m->ncols + m->nprobes + m->narith;
   // computed attributes, materialised over the selection vector
   std::vector<std::vector<int64_t>> comp(static_cast<size_t>(m->nprobes + m->narith));
@@ -124,22 +143,16 @@ extern "C" int32_t orc_run(const orc_build* builds, int32_t nbuilds, const orc_m
       dst[j] = wrap(r);
     }
   }
-  Result res;
-  res.kind = m->kind;
   if (m->kind == ORC_PROJECT) {
-    res.rows = static_cast<int64_t>(sv.size());
-    res.proj.resize(static_cast<size_t>(m->nproj));
+    out.proj.resize(static_cast<size_t>(m->nproj));
     for (int32_t c = 0; c < m->nproj; ++c) {
       if (m->proj[c] < 0 || m->proj[c] >= nattr) return ORC_E_ARG;
-      res.proj[c].resize(sv.size());
-      for (size_t j = 0; j < sv.size(); ++j) res.proj[c][j] = attr(m->proj[c], j);
+      out.proj[c].resize(sv.size());
+      for (size_t j = 0; j < sv.size(); ++j) out.proj[c][j] = attr(m->proj[c], j);
     }
   } else {
-    struct Acc { int64_t count = 0; std::vector<i128> v; };
-    std::map<std::vector<int64_t>, Acc> groups;
-    std::vector<i128> init(static_cast<size_t>(m->naggs));
-    for (int32_t a = 0; a < m->naggs; ++a)
-      init[a] = m->aggs[a].fn == ORC_MIN ? i128(INT64_MAX) : m->aggs[a].fn == ORC_MAX ? i128(INT64_MIN) : 0;
+    Groups& groups = out.groups;
+    const std::vector<i128> init = agg_init(m);
     if (m->ngroup == 0) groups[std::vector<int64_t>()].v = init;  // AGGREGATE: one row even when empty
     std::vector<int64_t> key(static_cast<size_t>(m->ngroup));
     for (size_t j = 0; j < sv.size(); ++j) {
@@ -157,6 +170,19 @@ extern "C" int32_t orc_run(const orc_build* builds, int32_t nbuilds, const orc_m
         else if (A.fn == ORC_MAX) { if (x > acc.v[a]) acc.v[a] = x; }
       }
     }
+  }
+  return ORC_OK;
+}
+
+// the result of the main pipeline from its (merged) part
+Result finish(const orc_main* m, Part& part) {
+  Result res;
+  res.kind = m->kind;
+  if (m->kind == ORC_PROJECT) {
+    res.rows = m->nproj > 0 ? static_cast<int64_t>(part.proj[0].size()) : 0;
+    res.proj.swap(part.proj);
+  } else {
+    const Groups& groups = part.groups;
     res.rows = static_cast<int64_t>(groups.size());
     res.keys.assign(static_cast<size_t>(m->ngroup), std::vector<int64_t>());
     res.vals.assign(static_cast<size_t>(m->naggs), std::vector<i128>());
@@ -173,8 +199,84 @@ extern "C" int32_t orc_run(const orc_build* builds, int32_t nbuilds, const orc_m
       }
     }
   }
+  return res;
+}
+
+// folds the groups of `from` into `into` (row counts and sums add, minima and
+// maxima combine): the groups of rows [a, b) and of rows [b, c) give those of
+// rows [a, c)
+void merge_groups(const orc_main* m, Groups& into, const Groups& from) {
+  for (const auto& kv : from) {
+    auto it = into.find(kv.first);
+    if (it == into.end()) {
+      into.emplace(kv.first, kv.second);
+      continue;
+    }
+    Acc& acc = it->second;
+    acc.count += kv.second.count;
+    for (int32_t a = 0; a < m->naggs; ++a) {
+      const int fn = m->aggs[a].fn;
+      const i128 x = kv.second.v[a];
+      if (fn == ORC_SUM || fn == ORC_AVG) acc.v[a] += x;
+      else if (fn == ORC_MIN) { if (x < acc.v[a]) acc.v[a] = x; }
+      else if (fn == ORC_MAX) { if (x > acc.v[a]) acc.v[a] = x; }
+    }
+  }
+}
+
+}  // namespace
+
+struct orc_result : Result {};
+
+extern "C" int32_t orc_run(const orc_build* builds, int32_t nbuilds, const orc_main* m,
+                           orc_result** out) {
+  if (!m || !out || m->nrows < 0) return ORC_E_ARG;
+  BuildTables tables;
+  int32_t st = run_builds(builds, nbuilds, tables);
+  if (st != ORC_OK) return st;
+  Part part;
+  st = run_main(tables, nbuilds, m, 0, m->nrows, part);
+  if (st != ORC_OK) return st;
   orc_result* r = new orc_result();
-  static_cast<Result&>(*r) = std::move(res);
+  static_cast<Result&>(*r) = finish(m, part);
+  *out = r;
+  return ORC_OK;
+}
+
+// The same query with the main pipeline's rows split into nthreads
+// contiguous ranges, each interpreted as above on its own thread; the
+// ranges' projected rows are concatenated in range order and their groups
+// merged. Used to time the oracle on all host cores.
+extern "C" int32_t orc_run_parallel(const orc_build* builds, int32_t nbuilds, const orc_main* m, int32_t nthreads,
+                                    orc_result** out) {
+  if (!m || !out || m->nrows < 0 || nthreads < 1) return ORC_E_ARG;
+  BuildTables tables;
+  int32_t st = run_builds(builds, nbuilds, tables);
+  if (st != ORC_OK) return st;
+  const int64_t n = m->nrows;
+  std::vector<Part> parts(static_cast<size_t>(nthreads));
+  std::vector<int32_t> sts(static_cast<size_t>(nthreads), ORC_OK);
+  std::vector<std::thread> th;
+  for (int32_t t = 0; t < nthreads; ++t) {
+    const int64_t r0 = n * t / nthreads, r1 = n * (t + 1) / nthreads;
+    th.emplace_back([&, t, r0, r1] { sts[t] = run_main(tables, nbuilds, m, r0, r1, parts[t]); });
+  }
+  for (auto& x : th) x.join();
+  for (int32_t t = 0; t < nthreads; ++t)
+    if (sts[t] != ORC_OK) return sts[t];
+  Part& all = parts[0];
+  for (int32_t t = 1; t < nthreads; ++t) {
+    if (m->kind == ORC_PROJECT) {
+      for (int32_t c = 0; c < m->nproj; ++c)
+        all.proj[c].insert(all.proj[c].end(), parts[t].proj[c].begin(), parts[t].proj[c].end());
+    } else {
+      merge_groups(m, all.groups, parts[t].groups);
+    }
+    Part().proj.swap(parts[t].proj);
+    Groups().swap(parts[t].groups);
+  }
+  orc_result* r = new orc_result();
+  static_cast<Result&>(*r) = finish(m, all);
   *out = r;
   return ORC_OK;
 }

@@ -53,6 +53,11 @@ typedef struct orc_result orc_result;
 
 /* Runs the query. On success *out receives a result the caller frees. */
 int32_t orc_run(const orc_build* builds, int32_t nbuilds, const orc_main* m, orc_result** out);
+/* The same result, with the main pipeline's rows split into nthreads
+   contiguous ranges interpreted on as many threads (the ranges' rows
+   concatenated in order, their groups merged): the oracle on all host cores. */
+int32_t orc_run_parallel(const orc_build* builds, int32_t nbuilds, const orc_main* m, int32_t nthreads,
+                         orc_result** out);
 void orc_free(orc_result* r);
 int64_t orc_rows(const orc_result* r);
 /* projection: column c (int64, row order) */

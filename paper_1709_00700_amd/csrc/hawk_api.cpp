@@ -952,7 +952,7 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
     }
     {
       ProfScope ps(ctx, "k_scan");
-      HIPCHK(hk_scan(X.st, counts, offsets, m, tmp, res->d_count), "prefix sum");
+      HIPCHK(hk_scan(X.st, counts, offsets, m, tmp, res->d_count, res->d_err), "prefix sum");
     }
     {
       ProfScope ps(ctx, "k_mp_project");
@@ -983,7 +983,7 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
     }
     {
       ProfScope ps(ctx, "k_scan");
-      HIPCHK(hk_scan(X.st, counts, offsets, nregions, stmp, res->d_count), "prefix sum");
+      HIPCHK(hk_scan(X.st, counts, offsets, nregions, stmp, res->d_count, res->d_err), "prefix sum");
     }
     {
       ProfScope ps(ctx, "k_sp_concat");
@@ -1095,7 +1095,7 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
       }
       {
         ProfScope ps(ctx, "k_scan");
-        HIPCHK(hk_scan(X.st, sp.hist, offs, m, stmp, total), "spill offsets");
+        HIPCHK(hk_scan(X.st, sp.hist, offs, m, stmp, total, res->d_err), "spill offsets");
       }
       {
         ProfScope ps(ctx, "k_spill_scatter");

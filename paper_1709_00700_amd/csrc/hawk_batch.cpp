@@ -395,7 +395,7 @@ hawk_status setup_schedule(hawk_batch* B, const hawk_batch_opts& o) {
     le = agg_kernel_launch(ctx, B->cap, &d.v, Q.plan, Q.table, d.cfg, Q.ident.w, Q.ident.nw, B->d_err,
                            d.cfg.spill ? &d.sp : nullptr);
     if (le == hipSuccess && d.cfg.spill) {
-      le = hk_scan(B->cap, d.sp.hist, d.offs, d.cfg.nparts * d.cfg.groups, d.stmp, d.total);
+      le = hk_scan(B->cap, d.sp.hist, d.offs, d.cfg.nparts * d.cfg.groups, d.stmp, d.total, B->d_err);
       if (le == hipSuccess)
         le = hk_spill(B->cap, 0, Q.plan, Q.table, d.v.hash, d.sp, Q.ident.w, Q.ident.nw, d.offs, d.total, d.cfg.groups,
                       d.part, B->d_err);

@@ -31,9 +31,12 @@ hipError_t hk_sp(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int
 hipError_t hk_sp_concat(hipStream_t st, int64_t* const* tmp, int32_t nproj, int64_t region, int64_t nregions,
                         const uint32_t* counts, const uint32_t* offsets, int64_t* const* out);
 
-// exclusive scan of m u32 counts; tmp needs hk_scan_tmp_words(m) u32 words; *total = sum
+// exclusive scan of m u32 counts; tmp needs hk_scan_tmp_words(m) u32 words,
+// 8-byte aligned; *total = sum; err (may be null) gets HK_ERR_TIMEOUT if a
+// tile's bounded wait for the tiles before it gives up
 int64_t hk_scan_tmp_words(int64_t m);
-hipError_t hk_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t m, uint32_t* tmp, uint64_t* total);
+hipError_t hk_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t m, uint32_t* tmp, uint64_t* total,
+                   int* err = nullptr);
 
 // grouped aggregation (cuckoo: key phase first; reps: copies of the aggregate
 // words of the LDS table, a power of two), non-grouped aggregation, result extraction

@@ -92,69 +92,116 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, ui
   return res;
 }
 
-#define SCAN_ITEMS 8
+// Single-pass exclusive scan (decoupled look-back). A tile is 1024 threads x
+// 16 consecutive counts per thread (vector loads and stores). Tiles take
+// their index from an atomic counter, so every tile that one waits for was
+// handed out earlier to a running workgroup; a tile publishes its total,
+// then its inclusive prefix once the tiles before it have theirs. A scan of
+// one tile (up to 16384 counts) needs neither the counter nor the status
+// words. The waits are bounded: past the bound the tile reports
+// HK_ERR_TIMEOUT instead of hanging.
+#define SCAN_ITEMS 16
 #define SCAN_TILE (1024 * SCAN_ITEMS)
+#define SCAN_PART 1ull   // status word: the tile's own total
+#define SCAN_INCL 2ull   // status word: the inclusive prefix through the tile
+#define SCAN_SPIN_LIMIT (1 << 24)
 
-// one block scans `m` entries tile by tile
-__global__ void __launch_bounds__(1024) k_scan_single(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
-                                                      int64_t m, const uint32_t* __restrict__ base, uint64_t* total) {
+__global__ void __launch_bounds__(1024) k_scan_lb(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                  int64_t m, uint64_t* status, unsigned int* counter,
+                                                  uint64_t* total, int* err) {
   __shared__ uint32_t sh[WAVE + 1];
-  uint32_t carry = base ? *base : 0u;
-  for (int64_t t0 = 0; t0 < m; t0 += SCAN_TILE) {
-    uint32_t v[SCAN_ITEMS];
-    uint32_t s = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-      const int64_t j = t0 + threadIdx.x * SCAN_ITEMS + i;
-      v[i] = j < m ? in[j] : 0u;
-      s += v[i];
-    }
-    uint32_t tot;
-    uint32_t pre = block_excl_scan(s, sh, &tot) + carry;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-      const int64_t j = t0 + threadIdx.x * SCAN_ITEMS + i;
-      if (j < m) out[j] = pre;
-      pre += v[i];
-    }
-    carry += tot;
+  __shared__ uint32_t tile_sh;
+  __shared__ uint64_t excl_sh;
+  const int64_t ntiles = (m + SCAN_TILE - 1) / SCAN_TILE;
+  if (m <= 0) {
+    if (total && threadIdx.x == 0) *total = 0;
+    return;
   }
-  if (total && threadIdx.x == 0) *total = carry;
-}
-
-__global__ void __launch_bounds__(1024) k_scan_reduce(const uint32_t* __restrict__ in, int64_t m, uint32_t* __restrict__ sums) {
-  __shared__ uint32_t sh[WAVE + 1];
-  const int64_t t0 = blockIdx.x * (int64_t)SCAN_TILE;
-  uint32_t s = 0;
-#pragma unroll
-  for (int i = 0; i < SCAN_ITEMS; ++i) {
-    const int64_t j = t0 + threadIdx.x * SCAN_ITEMS + i;
-    s += j < m ? in[j] : 0u;
+  uint32_t tile = 0;
+  if (ntiles > 1) {
+    if (threadIdx.x == 0) tile_sh = atomicAdd(counter, 1u);
+    __syncthreads();
+    tile = tile_sh;
   }
-  uint32_t tot;
-  block_excl_scan(s, sh, &tot);
-  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
-}
-
-__global__ void __launch_bounds__(1024) k_scan_apply(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t m,
-                                                     const uint32_t* __restrict__ tile_off) {
-  __shared__ uint32_t sh[WAVE + 1];
-  const int64_t t0 = blockIdx.x * (int64_t)SCAN_TILE;
+  const int64_t j0 = static_cast<int64_t>(tile) * SCAN_TILE + static_cast<int64_t>(threadIdx.x) * SCAN_ITEMS;
+  const bool vec = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u) == 0;
   uint32_t v[SCAN_ITEMS];
+  if (vec && j0 + SCAN_ITEMS <= m) {
+    const uint4* src = reinterpret_cast<const uint4*>(in + j0);
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS / 4; ++i) {
+      const uint4 x = src[i];
+      v[4 * i] = x.x;
+      v[4 * i + 1] = x.y;
+      v[4 * i + 2] = x.z;
+      v[4 * i + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) v[i] = j0 + i < m ? in[j0 + i] : 0u;
+  }
   uint32_t s = 0;
 #pragma unroll
-  for (int i = 0; i < SCAN_ITEMS; ++i) {
-    const int64_t j = t0 + threadIdx.x * SCAN_ITEMS + i;
-    v[i] = j < m ? in[j] : 0u;
-    s += v[i];
-  }
+  for (int i = 0; i < SCAN_ITEMS; ++i) s += v[i];
   uint32_t tot;
-  uint32_t pre = block_excl_scan(s, sh, &tot) + tile_off[blockIdx.x];
+  const uint32_t pre = block_excl_scan(s, sh, &tot);
+  if (threadIdx.x == 0) {
+    uint64_t excl = 0;
+    if (ntiles > 1) {
+      if (tile == 0) {
+        __hip_atomic_store(&status[0], (SCAN_INCL << 62) | tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        __hip_atomic_store(&status[tile], (SCAN_PART << 62) | tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int64_t p = static_cast<int64_t>(tile) - 1;
+        int spins = 0;
+        while (p >= 0) {
+          const uint64_t w = __hip_atomic_load(&status[p], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          const uint64_t st = w >> 62, val = w & ((1ull << 62) - 1);
+          if (st == SCAN_INCL) {
+            excl += val;
+            break;
+          }
+          if (st == SCAN_PART) {
+            excl += val;
+            --p;
+            continue;
+          }
+          if (++spins > SCAN_SPIN_LIMIT) {  // never expected: report instead of hanging
+            if (err) set_err(err, HK_ERR_TIMEOUT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        __hip_atomic_store(&status[tile], (SCAN_INCL << 62) | (excl + tot), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    excl_sh = excl;
+    if (total && tile == ntiles - 1) *total = excl + tot;
+  }
+  __syncthreads();
+  uint32_t run = static_cast<uint32_t>(excl_sh) + pre;
+  if (vec && j0 + SCAN_ITEMS <= m) {
+    uint4* dst = reinterpret_cast<uint4*>(out + j0);
 #pragma unroll
-  for (int i = 0; i < SCAN_ITEMS; ++i) {
-    const int64_t j = t0 + threadIdx.x * SCAN_ITEMS + i;
-    if (j < m) out[j] = pre;
-    pre += v[i];
+    for (int i = 0; i < SCAN_ITEMS / 4; ++i) {
+      uint4 x;
+      x.x = run;
+      run += v[4 * i];
+      x.y = run;
+      run += v[4 * i + 1];
+      x.z = run;
+      run += v[4 * i + 2];
+      x.w = run;
+      run += v[4 * i + 3];
+      dst[i] = x;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+      if (j0 + i < m) out[j0 + i] = run;
+      run += v[i];
+    }
   }
 }
 
@@ -248,19 +295,22 @@ hipError_t hk_sp_concat(hipStream_t st, int64_t* const* tmp, int32_t nproj, int6
   HK_CHECK_LAUNCH();
 }
 
-int64_t hk_scan_tmp_words(int64_t m) { return (m + SCAN_TILE - 1) / SCAN_TILE * 2 + 2; }
+// the status words (one per tile) and the tile counter, in u32 words
+int64_t hk_scan_tmp_words(int64_t m) { return ((m + SCAN_TILE - 1) / SCAN_TILE + 1) * 2 + 2; }
 
-hipError_t hk_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t m, uint32_t* tmp, uint64_t* total) {
-  if (m <= 8 * SCAN_TILE) {
-    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, in, out, m, nullptr, total);
-    HK_CHECK_LAUNCH();
+hipError_t hk_scan(hipStream_t st, const uint32_t* in, uint32_t* out, int64_t m, uint32_t* tmp, uint64_t* total,
+                   int* err) {
+  const int64_t ntiles = m > 0 ? (m + SCAN_TILE - 1) / SCAN_TILE : 1;
+  uint64_t* status = reinterpret_cast<uint64_t*>(tmp);
+  unsigned int* counter = reinterpret_cast<unsigned int*>(status + ntiles);
+  if (ntiles > 1) {
+    // status words and counter start at zero (a kernel, not a memset node: the
+    // scan may run inside a captured graph)
+    const hipError_t e = hk_fill_u64(st, status, ntiles + 1, 0);
+    if (e != hipSuccess) return e;
   }
-  const int64_t tiles = (m + SCAN_TILE - 1) / SCAN_TILE;
-  uint32_t* sums = tmp;
-  uint32_t* offs = tmp + tiles + 1;
-  hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(1024), 0, st, in, m, sums);
-  hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, sums, offs, tiles, nullptr, total);
-  hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(1024), 0, st, in, out, m, offs);
+  hipLaunchKernelGGL(k_scan_lb, dim3(static_cast<uint32_t>(ntiles)), dim3(1024), 0, st, in, out, m, status, counter,
+                     total, err);
   HK_CHECK_LAUNCH();
 }
 

@@ -21,13 +21,21 @@ import numpy as np
 from . import hawk
 
 
-def register_c5(ctx, pools: dict, queries: list, prefix: str = "") -> list:
-    """Registers the pools' dimension tables and each query's window; returns query handles
-    (with the query's selectivity as its catalog statistic)."""
+def upload_pools(ctx, pools: dict) -> dict:
+    """The pools as device tensors (kept alive by the context)."""
     import torch
     dev = {p: {c: torch.from_numpy(np.ascontiguousarray(a)).to("cuda") for c, a in cols.items()}
            for p, cols in pools.items()}
     ctx._keep.append(dev)
+    return dev
+
+
+def register_c5(ctx, pools: dict, queries: list, prefix: str = "", dev: dict | None = None) -> list:
+    """Registers the pools' dimension tables and each query's window; returns query handles
+    (with the query's selectivity as its catalog statistic). `dev`: the pools
+    already on the device (upload_pools), else they are uploaded here."""
+    if dev is None:
+        dev = upload_pools(ctx, pools)
     for j in range(4):
         name = f"d{j}"
         if name not in ctx.tables:
@@ -55,10 +63,10 @@ def timed(ctx, q, v, reps: int, limit_ms: float) -> float:
         raise
 
 
-def variant_key(q, v) -> str:
+def variant_key(q, v, tabled: bool | None = None) -> str:
     """Variant identity within q's space (hash-table dimensions vanish without a table)."""
-    space = hawk.variant_space(q)
-    tabled = any(x.ht or x.hash for x in space)
+    if tabled is None:
+        tabled = any(x.ht or x.hash for x in hawk.variant_space(q))
     if not tabled:
         v = hawk.hawk_variant(v.proj_strategy, v.mem, v.pred, 0, 0, v.agg_strategy, v.reserved0, v.reserved1,
                               v.thread_mult, v.wg_size)
@@ -87,26 +95,94 @@ class Ensemble:
             m.free()
 
 
-def training_set(ctx, queries: list, per_query: int, reps: int, limit_ms: float, seed: int, progress=None):
+# a variant that is fast for most pipelines of a kind: the reference of the
+# relative pruning limit of the training timings
+REFERENCE = {1: dict(proj_strategy=1, mem=1, pred=0, thread_mult=1024, wg_size=256),
+             2: dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=1, agg_strategy=0, thread_mult=8, wg_size=256)}
+
+
+def training_set(ctx, queries: list, per_query: int, reps: int, limit_ms: float, seed: int, progress=None,
+                 factor: float | None = None):
     """Features and ln(ms) of up to `per_query` sampled variants of each query.
-    A pruned variant enters with the limit as its time."""
+    A pruned variant enters with its limit as its time. With `factor` the
+    limit of a query is min(limit_ms, factor x its reference variant's time)."""
     rng = np.random.default_rng(seed)
     X, y = [], []
     for n, q in enumerate(queries):
         if progress:
             progress(f"training timings: query {n + 1}/{len(queries)}")
         space = hawk.variant_space(q)
+        lim = limit_ms
+        if factor is not None:
+            ref = timed(ctx, q, hawk.variant(**REFERENCE[q.kind]), reps, limit_ms)
+            if math.isfinite(ref):
+                lim = min(limit_ms, factor * ref)
         idx = rng.choice(len(space), size=min(per_query, len(space)), replace=False)
         for i in sorted(idx):
-            ms = timed(ctx, q, space[i], reps, limit_ms)
+            ms = timed(ctx, q, space[i], reps, lim)
             X.append(q.features(space[i]))
-            y.append(math.log(min(ms, limit_ms)))
+            y.append(math.log(min(ms, lim)))
     return np.asarray(X, np.float32), np.asarray(y, np.float32)
 
 
-def exhaustive(ctx, q, reps: int, limit_ms: float) -> dict:
-    """Time of every variant of q's space, keyed by variant_key."""
-    return {variant_key(q, v): timed(ctx, q, v, reps, limit_ms) for v in hawk.variant_space(q)}
+def ranked(ens, q, k: int) -> list:
+    """The k variants of q's space with the lowest ensemble score (mean +
+    penalty x standard deviation of the members' predicted ln(ms)), best first."""
+    space = hawk.variant_space(q)
+    X = np.stack([q.features(v) for v in space])
+    P = np.stack([m.predict(X) for m in ens.models]).astype(np.float64)
+    score = P.mean(axis=0) + ens.penalty * P.std(axis=0)
+    return [space[i] for i in np.argsort(score, kind="stable")[:k]]
+
+
+def refine(ctx, queries: list, ens, X, y, top: int, rounds: int, reps: int, limit_ms: float,
+           factor: float | None = None, progress=None, **train_kw):
+    """Active sampling: times each training query's `top` best-ranked
+    variants under the current ensemble, adds them to the training set and
+    retrains, `rounds` times. A model that ranks a slow variant first learns
+    its real time here, where one-off sampling rarely reaches. Returns the
+    grown training set."""
+    for r in range(rounds):
+        nx, ny = [], []
+        for n, q in enumerate(queries):
+            if progress and n % 16 == 0:
+                progress(f"active sampling round {r + 1}: query {n + 1}/{len(queries)}")
+            lim = limit_ms
+            if factor is not None:
+                ref = timed(ctx, q, hawk.variant(**REFERENCE[q.kind]), reps, limit_ms)
+                if math.isfinite(ref):
+                    lim = min(limit_ms, factor * ref)
+            for v in ranked(ens, q, top):
+                ms = timed(ctx, q, v, reps, lim)
+                nx.append(q.features(v))
+                ny.append(math.log(min(ms, lim)))
+        X = np.concatenate([X, np.asarray(nx, np.float32)])
+        y = np.concatenate([y, np.asarray(ny, np.float32)])
+        ens.train(X, y, **train_kw)
+    return X, y
+
+
+def exhaustive(ctx, q, reps: int, limit_ms: float, factor: float | None = None, first=()) -> dict:
+    """Time of every variant of q's space, keyed by variant_key. With `factor`,
+    the pruning limit follows the search: a variant slower than `factor` times
+    the fastest one measured so far (and than limit_ms) counts as +inf (the
+    pruning rule of Section 9.1, relative to the running best). The variants in
+    `first` are measured first, under limit_ms only."""
+    out = {}
+    best = math.inf
+    space = hawk.variant_space(q)
+    tabled = any(x.ht or x.hash for x in space)
+    first_keys = {variant_key(q, f, tabled) for f in first}
+    for v in list(first) + list(space):
+        key = variant_key(q, v, tabled)
+        if key in out:
+            continue
+        lim = limit_ms if factor is None or not math.isfinite(best) or key in first_keys \
+            else min(limit_ms, factor * best)
+        t = timed(ctx, q, v, reps, lim)
+        out[key] = t
+        best = min(best, t)
+    return out
 
 
 def alg1_per_kind(ctx, queries: list, reps: int, limit_ms: float, max_iters: int = 5) -> dict:
@@ -121,19 +197,26 @@ def alg1_per_kind(ctx, queries: list, reps: int, limit_ms: float, max_iters: int
 
 
 def pick_quality(ctx, queries: list, model, reps: int, limit_ms: float, alg1: dict | None = None,
-                 progress=None, extra: dict | None = None) -> dict:
+                 progress=None, extra: dict | None = None, factor: float | None = None,
+                 deadline: float | None = None) -> dict:
     """Runtime of the model's per-query picks and of Algorithm 1's per-workload variant,
     relative to each query's exhaustive best: r_q = t(pick_q) / t(best_q). `extra`
-    names further pickers (objects with .pick(queries)) scored on the same search."""
+    names further pickers (objects with .pick(queries)) scored on the same search.
+    `factor`: prune relative to the running best (the picks are measured first);
+    `deadline` (time.perf_counter() value): stop after the query that passes it."""
+    import time
     if alg1 is None:
         alg1 = alg1_per_kind(ctx, queries, reps, limit_ms)
     pickers = {"model": model, **(extra or {})}
     picks = {name: p.pick(queries)[0] for name, p in pickers.items()}
     rows = []
     for n, q in enumerate(queries):
+        if deadline is not None and time.perf_counter() > deadline:
+            break
         if progress:
             progress(f"exhaustive search: query {n + 1}/{len(queries)}")
-        table = exhaustive(ctx, q, reps, limit_ms)
+        first = [pv[n] for pv in picks.values()] + [alg1[q.kind][0]]
+        table = exhaustive(ctx, q, reps, limit_ms, factor=factor, first=first)
         best_key = min(table, key=table.get)
         row = {"best_ms": table[best_key], "best": best_key}
         chosen = {name: pv[n] for name, pv in picks.items()}
@@ -150,7 +233,7 @@ def pick_quality(ctx, queries: list, model, reps: int, limit_ms: float, alg1: di
     def ratios(k):
         return np.array([r[k] / r["best_ms"] for r in rows])
 
-    out = {"queries": len(rows)}
+    out = {"queries": len(rows), "queries_planned": len(queries)}
     for name in list(pickers) + ["alg1"]:
         k = ("pick" if name == "model" else name) + "_ms"
         r = ratios(k)

@@ -1,6 +1,6 @@
 """Host logic of bench.py (no GPU): the measured-traffic table is reported
-only while the kernel sources and the workload's variants are the ones it
-was measured on."""
+only while the kernel sources and the pipeline's variant are the ones it was
+measured on, and the algorithmic byte counts of the mixed workload."""
 import importlib.util
 import os
 
@@ -18,29 +18,42 @@ def bench():
 
 
 def test_traffic_entries_well_formed(bench):
-    assert bench.TRAFFIC, "no measured traffic"
-    for (kernel, workload), t in bench.TRAFFIC.items():
-        assert workload in bench.WORKLOADS and kernel == "k_agg"
-        assert set(t) == {"sources_sha", "variants_sha", "bytes_per_launch"}
-        assert t["bytes_per_launch"] > 0 and len(t["sources_sha"]) == 16 and len(t["variants_sha"]) == 16
+    for name, t in bench.TRAFFIC.items():
+        assert name in bench.DEFAULT_VARIANTS
+        assert set(t) == {"sources_sha", "variant_sha", "per_kernel", "total"}
+        assert len(t["sources_sha"]) == 16 and len(t["variant_sha"]) == 16
+        assert t["total"] == pytest.approx(sum(t["per_kernel"].values()))
+        assert all(k in bench.KERNEL_FAMILIES for k in t["per_kernel"])
 
 
-def test_traffic_only_for_the_measured_sources_and_variants(bench, monkeypatch):
-    (kernel, workload), t = next(iter(bench.TRAFFIC.items()))
-    monkeypatch.setattr(bench, "kernel_sources_sha", lambda k: t["sources_sha"])
-    monkeypatch.setattr(bench, "variants_sha", lambda w: t["variants_sha"])
-    assert bench.traffic_for(kernel, workload) == t["bytes_per_launch"]
-    monkeypatch.setattr(bench, "kernel_sources_sha", lambda k: "0" * 16)
-    assert bench.traffic_for(kernel, workload) is None
-    monkeypatch.setattr(bench, "kernel_sources_sha", lambda k: t["sources_sha"])
-    monkeypatch.setattr(bench, "variants_sha", lambda w: "f" * 16)
-    assert bench.traffic_for(kernel, workload) is None
-    assert bench.traffic_for("k_other", workload) is None
-
-
-def test_variants_sha_follows_the_default_variants(bench, monkeypatch):
-    before = bench.variants_sha("c2")
+def test_traffic_only_for_the_measured_sources_and_variant(bench, monkeypatch):
+    entry = {"sources_sha": bench.kernel_sources_sha(), "variant_sha": bench.variant_sha("c2z"),
+             "per_kernel": {"k_agg": 9.0e8, "k_spill_agg": 3.0e8}, "total": 1.2e9}
+    monkeypatch.setattr(bench, "TRAFFIC", {"c2z": entry})
+    assert bench.traffic_for("c2z") == entry
+    assert bench.traffic_for("c2u") is None
+    monkeypatch.setattr(bench, "kernel_sources_sha", lambda: "0" * 16)
+    assert bench.traffic_for("c2z") is None
+    monkeypatch.setattr(bench, "kernel_sources_sha", lambda: entry["sources_sha"])
     changed = {k: dict(v) for k, v in bench.DEFAULT_VARIANTS.items()}
     changed["c2z"]["wg_size"] = 512
     monkeypatch.setattr(bench, "DEFAULT_VARIANTS", changed)
-    assert bench.variants_sha("c2") != before
+    assert bench.traffic_for("c2z") is None
+
+
+def test_c5_algorithmic_bytes(bench):
+    # projection: 4 B per row + 20 B per qualifying row
+    assert bench.c5_algo_bytes({"kind": 1, "rows": 1000, "selectivity": 0.5}) == pytest.approx(1000 * (4 + 10))
+    # aggregation: 4 B per row + 12 B per qualifying row
+    assert bench.c5_algo_bytes({"kind": 2, "rows": 1000, "selectivity": 0.25}) == pytest.approx(1000 * (4 + 3))
+    # star join, all rows joining: four keys and the revenue for every row = 24 B
+    assert bench.c5_algo_bytes({"kind": 3, "rows": 1000, "selectivity": 1.0}) == pytest.approx(24_000)
+    # per-dimension selectivity 1/2: keys 4 (1 + 1/2 + 1/4 + 1/8) + revenue 8/16
+    assert bench.c5_algo_bytes({"kind": 3, "rows": 16, "selectivity": 1 / 16}) == pytest.approx(16 * (7.5 + 0.5))
+
+
+def test_every_timed_pipeline_has_bytes_and_a_variant(bench):
+    for w, names in bench.WORKLOADS.items():
+        for n in names:
+            assert n in bench.DEFAULT_VARIANTS and n in bench.ALGO_BYTES_PER_ROW
+    assert bench.HEADLINE["all"] == "c4"

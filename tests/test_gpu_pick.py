@@ -40,6 +40,11 @@ def test_learned_picks_beat_algorithm1_per_workload(ctx):
     ens = optimizer.Ensemble(ctx, size=5, penalty=1.0, seed=1)
     loss = ens.train(X, y, epochs=300, batch=512, lr=3e-3, seed=2)
     say("training mse", loss)
+    # two rounds of active sampling: each training pipeline's four best-ranked
+    # variants are timed and added before retraining
+    X, y = optimizer.refine(ctx, tr_h, ens, X, y, top=4, rounds=2, reps=2, limit_ms=lim, progress=say,
+                            epochs=300, batch=512, lr=3e-3, seed=2)
+    say("training samples after active sampling", len(y))
     alg1 = optimizer.alg1_per_kind(ctx, te_h, reps=2, limit_ms=lim)
     pq = optimizer.pick_quality(ctx, te_h, ens, reps=2, limit_ms=lim, alg1=alg1, progress=say,
                                 extra={"single_model": ens.models[0]})

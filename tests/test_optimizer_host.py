@@ -25,8 +25,8 @@ def test_pick_quality_ratios(monkeypatch):
     qs = [_Query(1), _Query(2)]
     # exhaustive timings per query: variant key -> ms
     tables = [{"a": 1.0, "b": 2.0, "c": 8.0}, {"a": 4.0, "b": 1.0, "c": 2.0}]
-    monkeypatch.setattr(optimizer, "exhaustive", lambda ctx, q, reps, lim: dict(tables[qs.index(q)]))
-    monkeypatch.setattr(optimizer, "variant_key", lambda q, v: v)
+    monkeypatch.setattr(optimizer, "exhaustive", lambda ctx, q, reps, lim, **kw: dict(tables[qs.index(q)]))
+    monkeypatch.setattr(optimizer, "variant_key", lambda q, v, tabled=None: v)
     alg1 = {1: ("c", None), 2: ("c", None)}
     out = optimizer.pick_quality(None, qs, _Picker(["a", "a"]), reps=1, limit_ms=10.0, alg1=alg1,
                                  extra={"other": _Picker(["b", "b"])})
@@ -51,11 +51,33 @@ def test_pick_quality_pruned_pick(monkeypatch):
     # a pick outside the exhaustive table is timed on its own; a pruned one (inf) is counted, not averaged
     qs = [_Query(1), _Query(1)]
     tables = [{"a": 1.0, "b": 3.0}, {"a": 2.0, "b": 2.0}]
-    monkeypatch.setattr(optimizer, "exhaustive", lambda ctx, q, reps, lim: dict(tables[qs.index(q)]))
-    monkeypatch.setattr(optimizer, "variant_key", lambda q, v: v)
+    monkeypatch.setattr(optimizer, "exhaustive", lambda ctx, q, reps, lim, **kw: dict(tables[qs.index(q)]))
+    monkeypatch.setattr(optimizer, "variant_key", lambda q, v, tabled=None: v)
     monkeypatch.setattr(optimizer, "timed", lambda ctx, q, v, reps, lim: math.inf)
     out = optimizer.pick_quality(None, qs, _Picker(["z", "a"]), reps=1, limit_ms=10.0, alg1={1: ("b", None)})
     assert out["model"]["pruned_picks"] == 1
     assert out["model"]["geomean_ratio"] == pytest.approx(1.0)  # over the finite ratio (query 2: 2/2)
     assert out["alg1"]["pruned_picks"] == 0
     assert out["alg1"]["geomean_ratio"] == pytest.approx(math.sqrt(3.0 * 1.0))
+
+
+def test_exhaustive_prunes_relative_to_the_running_best(monkeypatch):
+    """With factor f, each variant after the first ones is timed under the limit
+    min(limit_ms, f * fastest so far); the `first` variants get limit_ms."""
+    class V:
+        def __init__(self, k, ms):
+            self.k, self.ms, self.ht, self.hash = k, ms, 0, 0
+    space = [V("a", 5.0), V("b", 2.0), V("c", 30.0), V("d", 1.0), V("e", 9.0)]
+    seen = []
+
+    def timed(ctx, q, v, reps, lim):
+        seen.append((v.k, lim))
+        return v.ms if v.ms <= lim else math.inf
+
+    monkeypatch.setattr(optimizer.hawk, "variant_space", lambda q: space)
+    monkeypatch.setattr(optimizer, "variant_key", lambda q, v, tabled=None: v.k)
+    monkeypatch.setattr(optimizer, "timed", timed)
+    out = optimizer.exhaustive(None, None, reps=1, limit_ms=100.0, factor=4.0, first=[space[4]])
+    # e first (limit 100), then a (4*9), b (4*5), c (4*2 -> pruned), d (4*2), and e is not timed again
+    assert seen == [("e", 100.0), ("a", 36.0), ("b", 20.0), ("c", 8.0), ("d", 8.0)]
+    assert out == {"e": 9.0, "a": 5.0, "b": 2.0, "c": math.inf, "d": 1.0}
