@@ -249,6 +249,9 @@ def c5_pick_quality(ctx, dev, pools_np, pool_rows, args):
     hi = min(args.pq_max_rows, pool_rows)
     tr = dg.c5_queries(args.pq_train, pool_rows, seed_train, min_rows=min(args.pq_min_rows // 4, hi), max_rows=hi)
     te = dg.c5_queries(args.pq_test, pool_rows, seed_test + 77, min_rows=min(args.pq_min_rows, hi), max_rows=hi)
+    # kinds in turn, so that a search cut short by the time budget still covers each kind
+    by_kind = [[q for q in te if q["kind"] == k] for k in (1, 2, 3)]
+    te = [q for grp in zip(*[g + [None] * (len(te) - len(g)) for g in by_kind]) for q in grp if q is not None]
     tr_h = optimizer.register_c5(ctx, pools_np, tr, prefix="pqtr_", dev=dev)
     te_h = optimizer.register_c5(ctx, pools_np, te, prefix="pqte_", dev=dev)
     t0 = time.perf_counter()
@@ -266,9 +269,15 @@ def c5_pick_quality(ctx, dev, pools_np, pool_rows, args):
     t_alg1 = time.perf_counter() - t0
     t0 = time.perf_counter()
     deadline = t_start + args.pq_budget_s
-    pq = optimizer.pick_quality(ctx, te_h, ens, reps=2, limit_ms=args.pq_limit_ms, alg1=alg1,
-                                progress=lambda m: log("[bench] " + m), extra={"single_model": ens.models[0]},
-                                factor=10.0, deadline=deadline)
+    # the per-query optimizer: the ensemble's pick where its members agree it
+    # beats Algorithm 1's variant for the query's kind, else that variant
+    picker = optimizer.WithFallback(ens, {k: v for k, (v, _) in alg1.items()})
+    # one timed run per variant in the search; the search's best and the picks
+    # are then timed again with 5 runs each and compared on those times
+    pq = optimizer.pick_quality(ctx, te_h, picker, reps=1, limit_ms=args.pq_limit_ms, alg1=alg1,
+                                progress=lambda m: log("[bench] " + m),
+                                extra={"ensemble": ens, "single_model": ens.models[0]},
+                                factor=10.0, deadline=deadline, confirm_reps=5)
     t_ex = time.perf_counter() - t0
     done = pq["queries"]
     rows = pq.pop("per_query")
@@ -301,8 +310,10 @@ def c5_pick_quality(ctx, dev, pools_np, pool_rows, args):
                "rows_range": [min(q["rows"] for q in te), max(q["rows"] for q in te)],
                "best_ms_median": float(sorted(r["best_ms"] for r in rows)[len(rows) // 2]) if rows else None,
                "prune": "a variant slower than 10x the fastest measured so far for the query is +inf",
+               "confirm": "the search's best and every pick timed again (5 runs each) and compared on those times",
                "alg1_variants": {str(k): hawk.format_variant(v) for k, (v, _) in alg1.items()},
-               "picker": "ensemble of 5 cost models, mean + 1 sd of predicted ln(ms)",
+               "picker": "ensemble of 5 cost models (mean + 1 sd of predicted ln(ms)); Algorithm 1's variant for the "
+                         "query's kind unless the ensemble's pick is predicted faster at mean + 1 sd than it at its mean",
                "kernels": "compiled ahead of time (run-time compilation off for the whole evaluation)",
                "sum_best_ms": sum(r["best_ms"] for r in rows),
                "sum_best_sequential_ms": sorted(seq)[1],
@@ -388,7 +399,7 @@ def main():
     ap.add_argument("--pq-min-rows", type=int, default=4_000_000)
     ap.add_argument("--pq-max-rows", type=int, default=64_000_000)
     ap.add_argument("--pq-limit-ms", type=float, default=100.0)
-    ap.add_argument("--pq-budget-s", type=float, default=200.0, help="wall budget of the pick-quality leg")
+    ap.add_argument("--pq-budget-s", type=float, default=330.0, help="wall budget of the pick-quality leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library runs each pipeline on one GPU "

@@ -90,9 +90,40 @@ class Ensemble:
     def pick(self, queries: list):
         return hawk.model_pick_ensemble(self.models, self.penalty, queries)
 
+    def scores(self, q, variants: list):
+        """Members' mean and standard deviation of predicted ln(ms) per variant."""
+        X = np.stack([q.features(v) for v in variants])
+        P = np.stack([m.predict(X) for m in self.models]).astype(np.float64)
+        return P.mean(axis=0), P.std(axis=0)
+
     def free(self):
         for m in self.models:
             m.free()
+
+
+class WithFallback:
+    """Per-query picks of an ensemble over a per-workload variant: a query
+    keeps `fallback[kind]` (e.g. Algorithm 1's variant for its kind) unless the
+    ensemble's own pick is predicted faster even at its pessimistic score
+    (mean + penalty x sd of the members' ln(ms)) than the fallback at its
+    mean. Greedy search stays the fallback; the model departs from it only
+    where its members agree on a gain."""
+
+    def __init__(self, ens: Ensemble, fallback: dict):
+        self.ens = ens
+        self.fallback = fallback
+
+    def pick(self, queries: list):
+        picks, _ = self.ens.pick(queries)
+        out = []
+        for q, v in zip(queries, picks):
+            fb = self.fallback.get(q.kind)
+            if fb is None:
+                out.append(v)
+                continue
+            mean, sd = self.ens.scores(q, [v, fb])
+            out.append(v if mean[0] + self.ens.penalty * sd[0] < mean[1] else fb)
+        return out, None
 
 
 # a variant that is fast for most pipelines of a kind: the reference of the
@@ -198,12 +229,17 @@ def alg1_per_kind(ctx, queries: list, reps: int, limit_ms: float, max_iters: int
 
 def pick_quality(ctx, queries: list, model, reps: int, limit_ms: float, alg1: dict | None = None,
                  progress=None, extra: dict | None = None, factor: float | None = None,
-                 deadline: float | None = None) -> dict:
+                 deadline: float | None = None, confirm_reps: int = 0) -> dict:
     """Runtime of the model's per-query picks and of Algorithm 1's per-workload variant,
     relative to each query's exhaustive best: r_q = t(pick_q) / t(best_q). `extra`
     names further pickers (objects with .pick(queries)) scored on the same search.
     `factor`: prune relative to the running best (the picks are measured first);
-    `deadline` (time.perf_counter() value): stop after the query that passes it."""
+    `deadline` (time.perf_counter() value): stop after the query that passes it.
+    `confirm_reps` > 0: the search's best variant and every picked variant are
+    timed again with that many runs each, and those times are compared (the
+    best is the fastest of them). The minimum over hundreds of short, noisy
+    medians is biased low; timing the finalists alike removes that bias from
+    the ratios."""
     import time
     if alg1 is None:
         alg1 = alg1_per_kind(ctx, queries, reps, limit_ms)
@@ -218,9 +254,18 @@ def pick_quality(ctx, queries: list, model, reps: int, limit_ms: float, alg1: di
         first = [pv[n] for pv in picks.values()] + [alg1[q.kind][0]]
         table = exhaustive(ctx, q, reps, limit_ms, factor=factor, first=first)
         best_key = min(table, key=table.get)
-        row = {"best_ms": table[best_key], "best": best_key}
         chosen = {name: pv[n] for name, pv in picks.items()}
         chosen["alg1"] = alg1[q.kind][0]
+        if confirm_reps > 0:
+            space = hawk.variant_space(q)
+            tabled = any(x.ht or x.hash for x in space)
+            finalists = {variant_key(q, v, tabled): v for v in chosen.values()}
+            finalists.setdefault(best_key, next(v for v in space if variant_key(q, v, tabled) == best_key))
+            for key, v in finalists.items():
+                if math.isfinite(table.get(key, math.inf)):
+                    table[key] = timed(ctx, q, v, confirm_reps, limit_ms)
+            best_key = min(finalists, key=lambda k_: table.get(k_, math.inf))
+        row = {"best_ms": table[best_key], "best": best_key}
         for name, v in chosen.items():
             t = table.get(variant_key(q, v))
             if t is None:

@@ -5,6 +5,8 @@ rows (16 uniform groups; zipf over 1M ranks), the 120M-row star join, the
 wide aggregation at 600M rows and a 64M-row stress instance whose 128-bit
 sums pass 2^63, and spilling at sizes where every workgroup regroups its
 spilled rows in many 8192-entry tiles."""
+import os
+
 import numpy as np
 import pytest
 
@@ -28,9 +30,17 @@ def ctx():
     c.close()
 
 
+def oracle_threads():
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return max(1, min(16, os.cpu_count() or 1))
+
+
 def run_one(ctx, tables, spec, v, label):
     say(label, "oracle")
-    ref = oracle.run(tables, spec)
+    # row ranges on the host cores, merged exactly (pinned to the one-thread answer)
+    ref = oracle.run(tables, spec, threads=oracle_threads())
     say(label, "device run", hawk.format_variant(v))
     dev = ctx.register_numpy(tables)
     q = hawk.build_query(ctx, spec)

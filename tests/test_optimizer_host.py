@@ -81,3 +81,34 @@ def test_exhaustive_prunes_relative_to_the_running_best(monkeypatch):
     # e first (limit 100), then a (4*9), b (4*5), c (4*2 -> pruned), d (4*2), and e is not timed again
     assert seen == [("e", 100.0), ("a", 36.0), ("b", 20.0), ("c", 8.0), ("d", 8.0)]
     assert out == {"e": 9.0, "a": 5.0, "b": 2.0, "c": math.inf, "d": 1.0}
+
+
+def test_pick_quality_confirms_the_finalists(monkeypatch):
+    """With confirm_reps, the search's best and the picks are timed again and
+    compared on those times: a best that was only lucky in the search loses
+    its place to a pick that is as fast when both are timed alike."""
+    class V:
+        def __init__(self, k):
+            self.k, self.ht, self.hash = k, 0, 0
+    space = [V("a"), V("b"), V("c")]
+    qs = [_Query(2)]
+    noisy = {"a": 1.0, "b": 1.2, "c": 3.0}        # the search's medians
+    confirmed = {"a": 1.3, "b": 1.2, "c": 3.1}    # the finalists timed again
+    retimed = []
+
+    def timed(ctx, q, v, reps, lim):
+        retimed.append((v.k, reps))
+        return confirmed[v.k]
+
+    monkeypatch.setattr(optimizer, "exhaustive", lambda ctx, q, reps, lim, **kw: dict(noisy))
+    monkeypatch.setattr(optimizer.hawk, "variant_space", lambda q: space)
+    monkeypatch.setattr(optimizer, "variant_key", lambda q, v, tabled=None: v.k)
+    monkeypatch.setattr(optimizer, "timed", timed)
+    out = optimizer.pick_quality(None, qs, _Picker([space[1]]), reps=2, limit_ms=10.0,
+                                 alg1={2: (space[2], None)}, confirm_reps=5)
+    # finalists: the pick b, Algorithm 1's c and the search's best a, each timed with 5 runs
+    assert sorted(retimed) == [("a", 5), ("b", 5), ("c", 5)]
+    row = out["per_query"][0]
+    assert row["best"] == "b" and row["best_ms"] == pytest.approx(1.2)
+    assert out["model"]["geomean_ratio"] == pytest.approx(1.0)
+    assert out["alg1"]["geomean_ratio"] == pytest.approx(3.1 / 1.2)
