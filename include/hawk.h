@@ -180,6 +180,39 @@ hawk_status hawk_execute(hawk_ctx* ctx, const hawk_query* q, const hawk_variant*
    duplicate-key errors are reported by hawk_result_info. */
 hawk_status hawk_execute_async(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v, hawk_result** out);
 
+/* Execution that allocates nothing, for callers that cannot allocate device
+   memory: code under HIP graph capture, tight serving loops, harnesses that
+   forbid hipMalloc. It runs q in variant v once, as hawk_execute does but
+   without its retries, and synchronises the context stream before it
+   returns. Every device buffer except the result columns (flags, plans, join
+   and aggregation tables, scan and projection buffers) lies in a scratch array
+   of HAWK_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs
+   on until the process ends; only kernels compiled ahead of time run
+   (hawk_ctx_set_jit does not apply).
+   cols: ncols caller-owned device pointers in the column order of
+   hawk_result_info (projection: one per projected attribute; aggregation:
+   the group attributes, the aggregates, the row count), each with room for
+   cap_rows elements (16 bytes in a HAWK_RES_I128 column, 8 otherwise). With
+   cols == NULL nothing runs and *nrows receives the cap_rows the execution
+   needs (projection: input rows + 1; grouped aggregation: the table's slots
+   + 1, from the group hint); this sizing call also works on a planning
+   context. On success *nrows = result rows, laid out as
+   hawk_execute's (projection rows in input order, group rows in hash-table
+   order).
+   Errors: HAWK_E_ARG (null pointer, wrong column count, cap_rows below the
+   need), HAWK_E_CAPACITY (the execution needs more scratch than the array
+   holds - e.g. a spilling aggregation or a projection of several hundred
+   million rows - or a hash table overflowed: no retry here, raise the
+   query's group hint), HAWK_E_DUPKEY, HAWK_E_INFEASIBLE, HAWK_E_TIMEOUT,
+   HAWK_E_DEVICE.
+   The scratch array is shared by every call on one device and keeps the last
+   call's contents (each call initialises what it reads): calls that overlap
+   on one device, from two host threads or two contexts, race and give
+   undefined results. */
+#define HAWK_NOALLOC_SCRATCH_BYTES (64ull << 20)
+hawk_status hawk_execute_noalloc(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v, void* const* cols,
+                                 int32_t ncols, int64_t cap_rows, int64_t* nrows);
+
 /* Result rows and columns. Projection: one HAWK_RES_I64 column per projected
    attribute, rows in input order. Aggregation: the group attributes
    (HAWK_RES_I64), then one column per aggregate (COUNT/MIN/MAX/narrow SUM:

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -118,7 +119,7 @@ static hipEvent_t prof_event(hawk_ctx* ctx) {
 }
 
 ProfScope::ProfScope(hawk_ctx* c, const char* name) : ctx(c), idx(static_cast<size_t>(-1)) {
-  if (!ctx->prof_on) return;
+  if (!ctx || !ctx->prof_on) return;  // null: a launch that is not profiled
   ProfRec r{name, prof_event(ctx), prof_event(ctx)};
   if (!r.a || !r.b) return;
   (void)hipEventRecord(r.a, ctx->stream);
@@ -166,6 +167,34 @@ extern "C" hawk_status hawk_profile_read(hawk_ctx* ctx, const char* kernel, doub
   return HAWK_OK;
 }
 
+// ------------------------------------------------------------------ scratch of the non-allocating execution
+// hawk_execute_noalloc places every device buffer of an execution except the
+// caller's result columns in this array, one per device, held until the
+// process ends. In host code its name denotes a host-side stand-in, not device
+// memory: kernels and copies get the address that hipGetSymbolAddress returns
+// with the device current, looked up once per device by hawk_ctx_create.
+static __device__ __align__(256) unsigned char scratch[HAWK_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;  // device -> its scratch array
+
+// with `device` current
+static hipError_t scratch_lookup(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr.count(device)) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+static void* scratch_of(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
+
 // ------------------------------------------------------------------ context
 extern "C" hawk_status hawk_ctx_create(int32_t device, void* hip_stream, hawk_ctx** out) {
   if (!out) return HAWK_E_ARG;
@@ -191,9 +220,17 @@ extern "C" hawk_status hawk_ctx_create(int32_t device, void* hip_stream, hawk_ct
   c->num_cus = prop.multiProcessorCount;
   c->lds_bytes = static_cast<int64_t>(prop.sharedMemPerBlock);
   c->seed = 0x48415748ull;  // fixed: results never depend on it, timings stay reproducible
+  // staging for plan uploads of up to 8 build pipelines, and the flags read
+  // back by the non-allocating execution; the device's scratch address
+  c->stage_bytes = sizeof(HkPlan) + 8 * sizeof(HkBuild);
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
-      hipMalloc(&c->dummy, 256) != hipSuccess || hipMemset(c->dummy, 0, 256) != hipSuccess) {
+      hipMalloc(&c->dummy, 256) != hipSuccess || hipMemset(c->dummy, 0, 256) != hipSuccess ||
+      hipHostMalloc(&c->h_stage, c->stage_bytes, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->h_flags), 16, hipHostMallocDefault) != hipSuccess ||
+      scratch_lookup(device) != hipSuccess) {
     if (c->dummy) (void)hipFree(c->dummy);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    if (c->h_flags) (void)hipHostFree(c->h_flags);
     delete c;
     return HAWK_E_DEVICE;
   }
@@ -228,6 +265,8 @@ extern "C" void hawk_ctx_destroy(hawk_ctx* ctx) {
   (void)hipEventDestroy(ctx->ev0);
   (void)hipEventDestroy(ctx->ev1);
   (void)hipFree(ctx->dummy);
+  (void)hipHostFree(ctx->h_stage);
+  (void)hipHostFree(ctx->h_flags);
   delete ctx;
 }
 
@@ -785,9 +824,9 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
 
 hipError_t agg_kernel_launch(hawk_ctx* ctx, hipStream_t st, const hawk_variant* v, const HkPlan& P,
                              const HkAggTable& T, const AggConfig& c, const uint64_t* ident, int32_t W, int* err,
-                             const HkSpill* sp) {
+                             const HkSpill* sp, bool allow_jit) {
   const int32_t wg = static_cast<int32_t>(v->wg_size);
-  if (ctx->jit && v->ht == HAWK_LINEAR_PROBING) {
+  if (allow_jit && ctx->jit && v->ht == HAWK_LINEAR_PROBING) {
     HkIdent id = {};
     for (int i = 0; i < W; ++i) id.w[i] = ident[i];
     id.nw = W;
@@ -803,6 +842,15 @@ hipError_t agg_kernel_launch(hawk_ctx* ctx, hipStream_t st, const hawk_variant* 
 
 namespace {
 
+// Where the device buffers of one execution come from.
+//  POOL: the context's pool; result columns are owned by the result.
+//  ARENA: consecutive 256-byte aligned pieces of one region [base, base+cap),
+//   handed out in call order. A pass with base == nullptr enqueues nothing and
+//   only measures the bytes (and result rows) that a pass over a real region
+//   then uses at the same offsets. Result columns are the caller's (`outs`,
+//   `out_rows` elements each) or, without `outs`, pieces of the region too.
+enum ExecMem { EXEC_POOL = 0, EXEC_ARENA = 1 };
+
 struct Exec {
   hawk_ctx* ctx;
   const hawk_query* q;
@@ -811,12 +859,34 @@ struct Exec {
   std::vector<void*> scratch;
   int attempt;
   hipStream_t st;
+  int mem = EXEC_POOL;
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  bool launch = true;          // enqueue kernels and fills (false: addresses and sizes only)
+  bool upload = true;          // copy the plans to the device in this pass
+  bool allow_jit = true;       // kernels compiled at run time may be used (and compiled)
+  void* const* outs = nullptr; // caller's result columns (ARENA)
+  int32_t nouts = 0;
+  int64_t out_rows = 0;
+  int32_t next_out = 0;
+  int64_t need_rows = 0;       // largest result column requested so far
+  const void* d_plans = nullptr;  // device copy of [main plan][builds] read by build and finalize kernels
 
+  bool sizing() const { return mem == EXEC_ARENA && !base; }
   void* get(size_t bytes, bool owned) {
+    if (mem == EXEC_ARENA) {
+      bytes = bytes < 256 ? 256 : (bytes + 255) & ~static_cast<size_t>(255);
+      const size_t at = used;
+      used += bytes;
+      if (!base) return reinterpret_cast<void*>(static_cast<uintptr_t>(256));  // sizing: never dereferenced
+      return used <= cap ? base + at : nullptr;
+    }
     void* p = ctx->pool.get(bytes);
     if (p) (owned ? res->owned : scratch).push_back(p);
     return p;
   }
+  // profiled launches: pool executions on the context stream only
+  hawk_ctx* prof() const { return mem == EXEC_POOL && launch ? ctx : nullptr; }
   ~Exec() {
     for (void* p : scratch) ctx->pool.put(p);
   }
@@ -832,6 +902,34 @@ struct Exec {
     ptr = static_cast<type>(X.get((bytes), (owned)));                         \
     if (!ptr) return set_error(X.ctx, HAWK_E_OOM, "device allocation failed"); \
   } while (0)
+// a kernel launch or device fill of the execution (skipped by address-only passes)
+#define LAUNCH(call, where)                                      \
+  do {                                                           \
+    if (X.launch) {                                              \
+      hipError_t e_ = (call);                                    \
+      if (e_ != hipSuccess) return hip_error(X.ctx, e_, where);  \
+    }                                                            \
+  } while (0)
+
+// One result column of `rows` elements of `kind`: a pool block the result
+// owns, a piece of the arena, or the caller's next column (which must hold
+// `rows` elements).
+hawk_status result_col(Exec& X, int32_t kind, int64_t rows, void** ptr) {
+  const size_t esize = kind == HAWK_RES_I128 ? 16 : 8;
+  X.need_rows = std::max(X.need_rows, rows);
+  if (X.mem == EXEC_ARENA && X.outs) {
+    if (X.next_out >= X.nouts) return set_error(X.ctx, HAWK_E_ARG, "fewer result columns than the query produces");
+    if (rows > X.out_rows)
+      return set_error(X.ctx, HAWK_E_ARG, "result columns hold " + std::to_string(X.out_rows) + " rows, the query needs " +
+                                              std::to_string(rows));
+    *ptr = X.outs[X.next_out++];
+    if (!*ptr) return set_error(X.ctx, HAWK_E_ARG, "null result column");
+    return HAWK_OK;
+  }
+  *ptr = X.get(static_cast<size_t>(rows) * esize, true);
+  if (!*ptr) return set_error(X.ctx, HAWK_E_OOM, "device allocation failed");
+  return HAWK_OK;
+}
 
 HkHash make_hash(hawk_ctx* ctx, const hawk_variant* v, int attempt) {
   uint64_t s = ctx->seed + 0x1000193ull * static_cast<uint64_t>(attempt);
@@ -849,6 +947,21 @@ HkHash make_hash(hawk_ctx* ctx, const hawk_variant* v, int attempt) {
 hawk_status upload_plans(Exec& X, const HkPlan& main, const std::vector<HkBuild>& builds) {
   hawk_query* q = const_cast<hawk_query*>(X.q);
   const size_t bytes = sizeof(HkPlan) + builds.size() * sizeof(HkBuild);
+  if (X.mem == EXEC_ARENA) {
+    // the plans take a piece of the arena and are copied from the context's
+    // pinned staging buffer (the caller synchronises before it is reused)
+    void* d;
+    ALLOC(d, void*, bytes, false);
+    X.d_plans = d;
+    if (X.sizing() || !X.upload) return HAWK_OK;
+    if (bytes > X.ctx->stage_bytes) return set_error(X.ctx, HAWK_E_PLAN, "too many build pipelines for the staging buffer");
+    std::memcpy(X.ctx->h_stage, &main, sizeof(HkPlan));
+    if (!builds.empty())
+      std::memcpy(static_cast<char*>(X.ctx->h_stage) + sizeof(HkPlan), builds.data(), builds.size() * sizeof(HkBuild));
+    HIPCHK(hipMemcpyAsync(d, X.ctx->h_stage, bytes, hipMemcpyHostToDevice, X.st), "plan upload");
+    return HAWK_OK;
+  }
+  X.d_plans = q->d_plans;
   std::vector<char> now(bytes);
   std::memcpy(now.data(), &main, sizeof(HkPlan));
   if (!builds.empty()) std::memcpy(now.data() + sizeof(HkPlan), builds.data(), builds.size() * sizeof(HkBuild));
@@ -858,6 +971,7 @@ hawk_status upload_plans(Exec& X, const HkPlan& main, const std::vector<HkBuild>
       return set_error(X.ctx, HAWK_E_OOM, "plan staging buffer");
     if (hipEventCreateWithFlags(&q->up_ev, hipEventDisableTiming) != hipSuccess)
       return set_error(X.ctx, HAWK_E_DEVICE, "plan upload event");
+    X.d_plans = q->d_plans;
   }
   if (now == q->uploaded) return HAWK_OK;
   if (q->up_pending) HIPCHK(hipEventSynchronize(q->up_ev), "plan upload wait");
@@ -869,9 +983,9 @@ hawk_status upload_plans(Exec& X, const HkPlan& main, const std::vector<HkBuild>
   return HAWK_OK;
 }
 
-const HkPlan* dev_main(const hawk_query* q) { return static_cast<const HkPlan*>(q->d_plans); }
-const HkBuild* dev_build(const hawk_query* q, size_t i) {
-  return reinterpret_cast<const HkBuild*>(static_cast<const char*>(q->d_plans) + sizeof(HkPlan)) + i;
+const HkPlan* dev_main(const Exec& X) { return static_cast<const HkPlan*>(X.d_plans); }
+const HkBuild* dev_build(const Exec& X, size_t i) {
+  return reinterpret_cast<const HkBuild*>(static_cast<const char*>(X.d_plans) + sizeof(HkPlan)) + i;
 }
 
 hawk_status run_builds(Exec& X, HkPlan& main, const HkHash& h, int grow) {
@@ -883,7 +997,11 @@ hawk_status run_builds(Exec& X, HkPlan& main, const HkHash& h, int grow) {
     JoinTableMem& m = q->jt[i];
     const uint32_t l2 = std::max<uint32_t>(4, ceil_log2(static_cast<uint64_t>(std::max<int64_t>(1, B.nrows)) * 2)) + grow;
     if (l2 > 31) return set_error(X.ctx, HAWK_E_CAPACITY, "join table beyond 2^31 slots");
-    if (!m.slots || m.log2cap != l2) {
+    uint64_t *slots = m.slots, *side = m.side;
+    if (X.mem == EXEC_ARENA) {
+      ALLOC(slots, uint64_t*, (static_cast<size_t>(1) << l2) * 8, false);
+      ALLOC(side, uint64_t*, 8, false);
+    } else if (!m.slots || m.log2cap != l2) {
       if (m.slots) {
         HIPCHK(hipStreamSynchronize(X.st), "synchronize");
         (void)hipFree(m.slots);
@@ -893,6 +1011,8 @@ hawk_status run_builds(Exec& X, HkPlan& main, const HkHash& h, int grow) {
       if (hipMalloc(&m.slots, (static_cast<size_t>(1) << l2) * 8) != hipSuccess || hipMalloc(&m.side, 8) != hipSuccess)
         return set_error(X.ctx, HAWK_E_OOM, "join table allocation failed");
       m.log2cap = l2;
+      slots = m.slots;
+      side = m.side;
     }
     HkBuild b;
     std::memset(&b, 0, sizeof(b));
@@ -900,8 +1020,8 @@ hawk_status run_builds(Exec& X, HkPlan& main, const HkHash& h, int grow) {
     b.p.hash = h;
     b.key = B.key;
     b.payload = B.payload;
-    b.t.slots = m.slots;
-    b.t.side = m.side;
+    b.t.slots = slots;
+    b.t.side = side;
     b.t.log2cap = l2;
     bs.push_back(b);
   }
@@ -909,10 +1029,10 @@ hawk_status run_builds(Exec& X, HkPlan& main, const HkHash& h, int grow) {
   hawk_status st = upload_plans(X, main, bs);
   if (st) return st;
   for (size_t i = 0; i < bs.size(); ++i) {
-    HIPCHK(hk_fill_u64(X.st, bs[i].t.slots, int64_t(1) << bs[i].t.log2cap, HK_EMPTY), "fill join table");
-    HIPCHK(hk_fill_u64(X.st, bs[i].t.side, 1, 0), "fill side slot");
-    ProfScope ps(X.ctx, "k_build");
-    HIPCHK(hk_build(X.st, bs[i], dev_build(q, i), X.v->ht, X.v->hash, X.res->d_err), "build");
+    LAUNCH(hk_fill_u64(X.st, bs[i].t.slots, int64_t(1) << bs[i].t.log2cap, HK_EMPTY), "fill join table");
+    LAUNCH(hk_fill_u64(X.st, bs[i].t.side, 1, 0), "fill side slot");
+    ProfScope ps(X.prof(), "k_build");
+    LAUNCH(hk_build(X.st, bs[i], dev_build(X, i), X.v->ht, X.v->hash, X.res->d_err), "build");
   }
   return HAWK_OK;
 }
@@ -924,7 +1044,10 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
   hawk_result* res = X.res;
   int64_t* out[HK_MAX_PROJ] = {};
   for (int c = 0; c < P.nproj; ++c) {
-    ALLOC(out[c], int64_t*, static_cast<size_t>(n + 1) * 8, true);
+    void* p;
+    hawk_status rst = result_col(X, HAWK_RES_I64, n + 1, &p);  // + the dump slot of predicated writes
+    if (rst) return rst;
+    out[c] = static_cast<int64_t*>(p);
     res->cols.push_back({HAWK_RES_I64, out[c]});
   }
   if (v->proj_strategy == HAWK_MULTI_PASS) {
@@ -947,16 +1070,16 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
     ALLOC(offsets, uint32_t*, static_cast<size_t>(m) * 4, false);
     ALLOC(tmp, uint32_t*, static_cast<size_t>(hk_scan_tmp_words(m)) * 4, false);
     {
-      ProfScope ps(ctx, "k_mp_filter");
-      HIPCHK(hk_mp_filter(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, counts), "filter kernel");
+      ProfScope ps(X.prof(), "k_mp_filter");
+      LAUNCH(hk_mp_filter(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, counts), "filter kernel");
     }
     {
-      ProfScope ps(ctx, "k_scan");
-      HIPCHK(hk_scan(X.st, counts, offsets, m, tmp, res->d_count, res->d_err), "prefix sum");
+      ProfScope ps(X.prof(), "k_scan");
+      LAUNCH(hk_scan(X.st, counts, offsets, m, tmp, res->d_count, res->d_err), "prefix sum");
     }
     {
-      ProfScope ps(ctx, "k_mp_project");
-      HIPCHK(hk_mp_project(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, offsets, res->d_count, nact,
+      ProfScope ps(X.prof(), "k_mp_project");
+      LAUNCH(hk_mp_project(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, offsets, res->d_count, nact,
                            out, n), "projection kernel");
     }
   } else {
@@ -978,16 +1101,16 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
     ALLOC(offsets, uint32_t*, static_cast<size_t>(nregions) * 4, false);
     ALLOC(stmp, uint32_t*, static_cast<size_t>(hk_scan_tmp_words(nregions)) * 4, false);
     {
-      ProfScope ps(ctx, "k_sp");
-      HIPCHK(hk_sp(X.st, P, v->mem, v->pred, v->ht, v->hash, inst, tmp, region, counts), "single-pass kernel");
+      ProfScope ps(X.prof(), "k_sp");
+      LAUNCH(hk_sp(X.st, P, v->mem, v->pred, v->ht, v->hash, inst, tmp, region, counts), "single-pass kernel");
     }
     {
-      ProfScope ps(ctx, "k_scan");
-      HIPCHK(hk_scan(X.st, counts, offsets, nregions, stmp, res->d_count, res->d_err), "prefix sum");
+      ProfScope ps(X.prof(), "k_scan");
+      LAUNCH(hk_scan(X.st, counts, offsets, nregions, stmp, res->d_count, res->d_err), "prefix sum");
     }
     {
-      ProfScope ps(ctx, "k_sp_concat");
-      HIPCHK(hk_sp_concat(X.st, tmp, P.nproj, region, nregions, counts, offsets, out), "concatenation");
+      ProfScope ps(X.prof(), "k_sp_concat");
+      LAUNCH(hk_sp_concat(X.st, tmp, P.nproj, region, nregions, counts, offsets, out), "concatenation");
     }
   }
   return HAWK_OK;
@@ -1045,25 +1168,32 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
   HkAggTable Tside = T;
   Tside.words = T.words + (nslots - 1) * W;
   {
-    ProfScope ps(ctx, "k_init_aggtable");
-    HIPCHK(direct ? hk_init_aggtable(X.st, Tside.words, 1, ident, W) : hk_init_aggtable(X.st, T.words, nslots, ident, W),
+    ProfScope ps(X.prof(), "k_init_aggtable");
+    LAUNCH(direct ? hk_init_aggtable(X.st, Tside.words, 1, ident, W) : hk_init_aggtable(X.st, T.words, nslots, ident, W),
            "init table");
   }
   // result columns: groups, aggregates, count
   const int64_t cap = nslots;
   int64_t* gcols[2] = {};
+  hawk_status rst;
   for (int g = 0; g < P.ngroup; ++g) {
-    ALLOC(gcols[g], int64_t*, static_cast<size_t>(cap) * 8, true);
+    void* p;
+    if ((rst = result_col(X, HAWK_RES_I64, cap, &p))) return rst;
+    gcols[g] = static_cast<int64_t*>(p);
     res->cols.push_back({HAWK_RES_I64, gcols[g]});
   }
   void* acols[HK_MAX_AGGS] = {};
   for (int a = 0; a < P.naggs; ++a) {
     const int kind = X.q->res_kinds[a];
-    ALLOC(acols[a], void*, static_cast<size_t>(cap) * (kind == HAWK_RES_I128 ? 16 : 8), true);
+    if ((rst = result_col(X, kind, cap, &acols[a]))) return rst;
     res->cols.push_back({kind, acols[a]});
   }
   int64_t* cnt;
-  ALLOC(cnt, int64_t*, static_cast<size_t>(cap) * 8, true);
+  {
+    void* p;
+    if ((rst = result_col(X, HAWK_RES_I64, cap, &p))) return rst;
+    cnt = static_cast<int64_t*>(p);
+  }
   res->cols.push_back({HAWK_RES_I64, cnt});
   if (grouped) {
     if (cfg.spill) {
@@ -1090,39 +1220,58 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
       O.count = cnt;
       O.nrows = reinterpret_cast<unsigned long long*>(res->d_count);
       {
-        ProfScope ps(ctx, "k_agg");
-        HIPCHK(agg_kernel_launch(ctx, X.st, v, P, T, cfg, ident, W, res->d_err, &sp), "aggregation kernel");
+        ProfScope ps(X.prof(), "k_agg");
+        LAUNCH(agg_kernel_launch(ctx, X.st, v, P, T, cfg, ident, W, res->d_err, &sp, X.allow_jit), "aggregation kernel");
       }
       {
-        ProfScope ps(ctx, "k_scan");
-        HIPCHK(hk_scan(X.st, sp.hist, offs, m, stmp, total, res->d_err), "spill offsets");
+        ProfScope ps(X.prof(), "k_scan");
+        LAUNCH(hk_scan(X.st, sp.hist, offs, m, stmp, total, res->d_err), "spill offsets");
       }
       {
-        ProfScope ps(ctx, "k_spill_scatter");
-        HIPCHK(hk_spill(X.st, 0, P, T, v->hash, sp, ident, W, offs, total, groups, part, res->d_err), "spill regrouping");
+        ProfScope ps(X.prof(), "k_spill_scatter");
+        LAUNCH(hk_spill(X.st, 0, P, T, v->hash, sp, ident, W, offs, total, groups, part, res->d_err), "spill regrouping");
       }
       {
-        ProfScope ps(ctx, "k_spill_agg");
-        HIPCHK(hk_spill(X.st, 1, P, T, v->hash, sp, ident, W, offs, total, groups, part, res->d_err,
+        ProfScope ps(X.prof(), "k_spill_agg");
+        LAUNCH(hk_spill(X.st, 1, P, T, v->hash, sp, ident, W, offs, total, groups, part, res->d_err,
                         direct ? &O : nullptr, scratch),
                "spill aggregation");
       }
     } else {
-      ProfScope ps(ctx, "k_agg");
-      HIPCHK(agg_kernel_launch(ctx, X.st, v, P, T, cfg, ident, W, res->d_err, nullptr), "aggregation kernel");
+      ProfScope ps(X.prof(), "k_agg");
+      LAUNCH(agg_kernel_launch(ctx, X.st, v, P, T, cfg, ident, W, res->d_err, nullptr, X.allow_jit), "aggregation kernel");
     }
   } else {
-    ProfScope ps(ctx, "k_scalar_agg");
-    HIPCHK(hk_scalar_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, ident, W,
+    ProfScope ps(X.prof(), "k_scalar_agg");
+    LAUNCH(hk_scalar_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, ident, W,
                          res->d_err), "aggregation kernel");
   }
   {
-    ProfScope ps(ctx, "k_finalize");
-    HIPCHK(direct ? hk_finalize(X.st, P, dev_main(X.q), Tside, 1, gcols, acols, cnt, res->d_count, 0)
-                  : hk_finalize(X.st, P, dev_main(X.q), T, nslots, gcols, acols, cnt, res->d_count, grouped ? 0 : 1),
+    ProfScope ps(X.prof(), "k_finalize");
+    LAUNCH(direct ? hk_finalize(X.st, P, dev_main(X), Tside, 1, gcols, acols, cnt, res->d_count, 0)
+                  : hk_finalize(X.st, P, dev_main(X), T, nslots, gcols, acols, cnt, res->d_count, grouped ? 0 : 1),
            "finalize");
   }
   return HAWK_OK;
+}
+
+// One execution of (X.q, X.v) as set up in X: the flags cleared, the build
+// pipelines, then the main pipeline's kernels.
+hawk_status run_query(Exec& X, int grow) {
+  const hawk_variant* v = X.v;
+  if (v->mem > 1 || v->pred > 1 || v->ht > 1 || v->hash > 1 || v->agg_strategy > 1 || v->proj_strategy > 1 ||
+      v->thread_mult < 1)
+    return set_error(X.ctx, HAWK_E_ARG, "variant value out of range");
+  void* flags;
+  ALLOC(flags, void*, 16, true);
+  X.res->d_count = static_cast<uint64_t*>(flags);
+  X.res->d_err = reinterpret_cast<int*>(X.res->d_count + 1);
+  LAUNCH(hk_fill_u64(X.st, X.res->d_count, 2, 0), "clear flags");
+  HkPlan P = X.q->main;
+  P.hash = make_hash(X.ctx, v, X.attempt);
+  hawk_status st = run_builds(X, P, P.hash, grow);
+  if (!st) st = X.q->kind == 1 ? run_projection(X, P) : run_aggregation(X, P, grow);
+  return st;
 }
 
 hawk_status execute_once(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v, int attempt, int grow,
@@ -1134,23 +1283,11 @@ hawk_status execute_once(hawk_ctx* ctx, const hawk_query* q, const hawk_variant*
   res->kind = q->kind;
   ctx->results.insert(res);
   Exec X{ctx, q, v, res, {}, attempt, ctx->stream};
-  auto fail = [&](hawk_status st) {
+  hawk_status st = run_query(X, grow);
+  if (st) {
     hawk_result_free(res);
     return st;
-  };
-  if (v->mem > 1 || v->pred > 1 || v->ht > 1 || v->hash > 1 || v->agg_strategy > 1 || v->proj_strategy > 1 ||
-      v->thread_mult < 1)
-    return fail(set_error(ctx, HAWK_E_ARG, "variant value out of range"));
-  res->d_count = static_cast<uint64_t*>(X.get(16, true));
-  res->d_err = reinterpret_cast<int*>(res->d_count + 1);
-  if (!res->d_count) return fail(set_error(ctx, HAWK_E_OOM, "device allocation failed"));
-  hipError_t e = hk_fill_u64(ctx->stream, res->d_count, 2, 0);
-  if (e != hipSuccess) return fail(hip_error(ctx, e, "clear flags"));
-  HkPlan P = q->main;
-  P.hash = make_hash(ctx, v, attempt);
-  hawk_status st = run_builds(X, P, P.hash, grow);
-  if (!st) st = q->kind == 1 ? run_projection(X, P) : run_aggregation(X, P, grow);
-  if (st) return fail(st);
+  }
   *out = res;
   return HAWK_OK;
 }
@@ -1187,6 +1324,65 @@ extern "C" hawk_status hawk_execute(hawk_ctx* ctx, const hawk_query* q, const ha
     else if (attempt >= 1) grow += 1;
   }
   return set_error(ctx, HAWK_E_CAPACITY, "hash table overflow after retries");
+}
+
+extern "C" hawk_status hawk_execute_noalloc(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v,
+                                            void* const* cols, int32_t ncols, int64_t cap_rows, int64_t* nrows) {
+  if (!ctx) return HAWK_E_ARG;
+  if (!q || !v || !nrows || (cols && (ncols < 1 || cap_rows < 0))) return set_error(ctx, HAWK_E_ARG, "bad argument");
+  if (q->ctx != ctx) return set_error(ctx, HAWK_E_ARG, "query of another context");
+  if (cols && ctx->device < 0) return set_error(ctx, HAWK_E_DEVICE, "planning context cannot execute");
+  // The result holds the flags and the column list only; it owns nothing.
+  hawk_result res;
+  res.ctx = ctx;
+  res.kind = q->kind;
+  // pass 1: scratch bytes and result rows the execution needs (nothing enqueued)
+  Exec S{ctx, q, v, &res, {}, 0, ctx->stream};
+  S.mem = EXEC_ARENA;
+  S.launch = false;
+  S.allow_jit = false;
+  S.outs = cols;
+  S.nouts = ncols;
+  S.out_rows = cap_rows;
+  hawk_status st = run_query(S, 0);
+  if (st) return st;
+  if (!cols) {
+    *nrows = S.need_rows;
+    return HAWK_OK;
+  }
+  if (S.next_out != ncols)
+    return set_error(ctx, HAWK_E_ARG, "the query produces " + std::to_string(S.next_out) + " result columns");
+  if (S.used > HAWK_NOALLOC_SCRATCH_BYTES)
+    return set_error(ctx, HAWK_E_CAPACITY, "the execution needs " + std::to_string(S.used) +
+                                               " bytes of scratch, more than the " +
+                                               std::to_string(HAWK_NOALLOC_SCRATCH_BYTES) + " the library holds");
+  // pass 2: the same buffers at the same offsets of this device's scratch
+  void* base = scratch_of(ctx->device);
+  if (!base) return set_error(ctx, HAWK_E_DEVICE, "no scratch address for this device");
+  res.cols.clear();
+  Exec X{ctx, q, v, &res, {}, 0, ctx->stream};
+  X.mem = EXEC_ARENA;
+  X.base = static_cast<char*>(base);
+  X.cap = HAWK_NOALLOC_SCRATCH_BYTES;
+  X.allow_jit = false;
+  X.outs = cols;
+  X.nouts = ncols;
+  X.out_rows = cap_rows;
+  st = run_query(X, 0);
+  if (st) {
+    (void)hipStreamSynchronize(ctx->stream);
+    return st;
+  }
+  hipError_t e = hipMemcpyAsync(ctx->h_flags, res.d_count, 16, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_error(ctx, e, "read flags");
+  const int err = static_cast<int>(ctx->h_flags[1] & 0xffffffffu);
+  if (err & HK_ERR_DUPKEY) return set_error(ctx, HAWK_E_DUPKEY, "a build pipeline inserted a key twice");
+  if (err & (HK_ERR_CAPACITY | HK_ERR_CUCKOO))
+    return set_error(ctx, HAWK_E_CAPACITY, "hash table overflow (no retry without allocation; raise the group hint)");
+  if (err & HK_ERR_TIMEOUT) return set_error(ctx, HAWK_E_TIMEOUT, "a bounded wait for another workgroup's result gave up");
+  *nrows = static_cast<int64_t>(ctx->h_flags[0]);
+  return HAWK_OK;
 }
 
 // ------------------------------------------------------------------ timing

@@ -38,6 +38,9 @@ struct hawk_ctx {
   DevicePool pool;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   void* dummy = nullptr;  // 256 zero bytes in device memory: the column of a plan's unused column slots
+  void* h_stage = nullptr;      // pinned staging of plan uploads into an arena
+  size_t stage_bytes = 0;
+  uint64_t* h_flags = nullptr;  // pinned: row count and error flags read back by the non-allocating execution
   bool jit = false;       // grouped aggregation runs kernels specialised at run time for the plan
   JitCache jit_cache;
   // live handles; destroying the context releases their device state and
@@ -125,7 +128,7 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
 // the context does so (linear probing), else the precompiled one
 hipError_t agg_kernel_launch(hawk_ctx* ctx, hipStream_t st, const hawk_variant* v, const HkPlan& P,
                              const HkAggTable& T, const AggConfig& c, const uint64_t* ident, int32_t W, int* err,
-                             const HkSpill* sp);
+                             const HkSpill* sp, bool allow_jit = true);
 void query_release_device(hawk_query* q);
 void model_release_device(struct hawk_model* m);
 void batch_release_device(struct hawk_batch* b);

@@ -36,7 +36,7 @@ EXPORTS = [
     "hawk_table_register", "hawk_table_unregister",
     "hawk_query_create", "hawk_query_free", "hawk_query_kind",
     "hawk_variant_space", "hawk_variant_format",
-    "hawk_execute", "hawk_execute_async",
+    "hawk_execute", "hawk_execute_async", "hawk_execute_noalloc",
     "hawk_result_info", "hawk_result_column", "hawk_result_copy_column", "hawk_result_free",
     "hawk_time_variant", "hawk_learn_feature_wise", "hawk_explore",
     "hawk_query_set_stats", "hawk_features",
@@ -142,6 +142,7 @@ def L():
             "hawk_variant_format": ([P(hawk_variant), ctypes.c_char_p, i32], i32),
             "hawk_execute": ([vp, vp, P(hawk_variant), P(vp)], i32),
             "hawk_execute_async": ([vp, vp, P(hawk_variant), P(vp)], i32),
+            "hawk_execute_noalloc": ([vp, vp, P(hawk_variant), P(vp), i32, i64, P(i64)], i32),
             "hawk_result_info": ([vp, P(i64), P(i32)], i32),
             "hawk_result_column": ([vp, i32, P(i32), P(vp)], i32),
             "hawk_result_copy_column": ([vp, i32, vp, i64], i32),
@@ -459,6 +460,21 @@ def execute(ctx: Context, query: Query, v: hawk_variant, sync: bool = True) -> R
     fn = L().hawk_execute if sync else L().hawk_execute_async
     check(fn(ctx.handle, query.handle, ctypes.byref(v), ctypes.byref(h)), ctx.handle)
     return Result(ctx, h)
+
+
+def execute_noalloc(ctx: Context, query: Query, v: hawk_variant, cols=None, cap_rows: int = 0) -> int:
+    """hawk_execute_noalloc: `cols` are device addresses (ints) of the result
+    columns, each of cap_rows elements; None asks for the cap_rows the
+    execution needs. Returns the result rows (or that capacity)."""
+    n = ctypes.c_int64()
+    if cols is None:
+        check(L().hawk_execute_noalloc(ctx.handle, query.handle, ctypes.byref(v), None, 0, 0, ctypes.byref(n)),
+              ctx.handle)
+        return n.value
+    arr = (ctypes.c_void_p * len(cols))(*cols)
+    check(L().hawk_execute_noalloc(ctx.handle, query.handle, ctypes.byref(v), arr, len(cols), cap_rows,
+                                   ctypes.byref(n)), ctx.handle)
+    return n.value
 
 
 def time_variant(ctx: Context, query: Query, v: hawk_variant, reps=5, limit_ms=0.0) -> float:

@@ -261,3 +261,32 @@ def test_explore_resumes_from_timing_log(plan_ctx, tmp_path, mode):
     if mode == hawk.HAWK_EXPLORE_EXHAUSTIVE:
         assert hawk.format_variant(best) == min(feasible, key=feasible.get)
     assert rep["best_ms"] == pytest.approx(feasible[hawk.format_variant(best)], abs=1e-6)
+
+
+def test_noalloc_sizing_on_a_planning_context(plan_ctx):
+    """hawk_execute_noalloc's sizing call (no result columns) needs no device:
+    a projection needs its input rows plus the dump slot, a grouped
+    aggregation the slots of its table (a power of two >= 2 x the group hint,
+    at least 64) plus the side slot, a non-grouped one a single row; asking
+    to run on a planning context is a device error."""
+    tables, spec = dg.c1_projection(n=1000)
+    plan_ctx.register_shapes({"p_" + t: c for t, c in tables.items()})
+    spec["main"]["table"] = "p_t"
+    q = hawk.build_query(plan_ctx, spec)
+    assert hawk.execute_noalloc(plan_ctx, q, hawk.variant(proj_strategy=1, thread_mult=64)) == 1001
+    assert hawk.execute_noalloc(plan_ctx, q, hawk.variant(proj_strategy=0)) == 1001
+    tables, spec = dg.c3_star_join(n=500, dims=(40, 40, 40, 40))
+    plan_ctx.register_shapes({"s_" + t: c for t, c in tables.items()})
+    spec["main"]["table"] = "s_f"
+    for b in spec["builds"]:
+        b["table"] = "s_" + b["table"]
+    q = hawk.build_query(plan_ctx, spec)
+    hint = spec["main"]["groups_hint"]
+    slots = max(64, 1 << (2 * hint - 1).bit_length())
+    assert hawk.execute_noalloc(plan_ctx, q, hawk.variant(agg_strategy=0, thread_mult=8, wg_size=256)) == slots + 1
+    spec["main"]["group_by"] = []
+    q = hawk.build_query(plan_ctx, spec)
+    assert hawk.execute_noalloc(plan_ctx, q, hawk.variant(agg_strategy=1, wg_size=256)) == 1
+    with pytest.raises(hawk.HawkError) as e:
+        hawk.execute_noalloc(plan_ctx, q, hawk.variant(), [0x1000] * 3, 1)
+    assert e.value.code == hawk.HAWK_E_DEVICE
