@@ -48,7 +48,9 @@ DEFAULT_VARIANTS = {
     "c3": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=1, agg_strategy=0, thread_mult=8, wg_size=512),
     "c4": dict(proj_strategy=1, mem=1, pred=1, ht=0, hash=1, agg_strategy=0, thread_mult=8, wg_size=512),
 }
-DEFAULT_VARIANTS["c1_256m"] = DEFAULT_VARIANTS["c1"]
+# the 256M-row point: the exhaustive search's best over the 32 projection variants
+DEFAULT_VARIANTS["c1_256m"] = dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=65536,
+                                   wg_size=256)
 
 # algorithmic bytes per input row: the columns a pipeline must read once, plus
 # (projection) the qualifying rows' other columns and outputs at the
@@ -201,8 +203,10 @@ def c5_algo_bytes(q):
     return n * (4 * (1 + d + d * d + d * d * d) + 8 * s)
 
 
-def c5_batch(ctx, dev, pools_np, nq, pool_rows, schedule, autotune, steps, warmup):
-    """The 256-pipeline mixed workload as one graph replay; also by pipeline kind."""
+def c5_batch(ctx, dev, pools_np, nq, pool_rows, schedule, autotune, steps, warmup, picker=None):
+    """The 256-pipeline mixed workload as one graph replay in the tile kernels,
+    also by pipeline kind; and (with a picker) with each query in its learned
+    variant inside the same kind of graph."""
     import torch
     from paper_1709_00700_amd import datagen as dg
     from paper_1709_00700_amd import hawk, optimizer
@@ -232,28 +236,42 @@ def c5_batch(ctx, dev, pools_np, nq, pool_rows, schedule, autotune, steps, warmu
         bk.free()
         out["kinds"][str(kind)] = {"pipelines": len(sub), "rows": rows, "ms": kms, "rows_per_s": rows / (kms / 1e3),
                                    "algo_bytes": algo, "algo_gb_per_s": algo / (kms / 1e3) / 1e9}
+    if picker is not None:
+        # every query in the variant the learned optimizer picks for it, each
+        # with its own kernels as nodes of one graph (the kernels compiled
+        # ahead of time, which the cost model was trained on)
+        jit = getattr(ctx, "jit", False)
+        ctx.set_jit(False)
+        picks, _ = picker.pick(hs)
+        bp = hawk.Batch(ctx, hs, variants=picks, **out["schedule"])
+        pms = bp.time(reps=3)
+        bp.free()
+        kinds = {}
+        for kind in (1, 2, 3):
+            sub = [(h, v) for h, v, q in zip(hs, picks, qs) if q["kind"] == kind]
+            rows = sum(q["rows"] for q in qs if q["kind"] == kind)
+            bk = hawk.Batch(ctx, [h for h, _ in sub], variants=[v for _, v in sub], **out["schedule"])
+            kms = bk.time(reps=3)
+            bk.free()
+            kinds[str(kind)] = {"ms": kms, "rows_per_s": rows / (kms / 1e3)}
+        ctx.set_jit(jit)
+        out["learned_variants"] = {"ms": pms, "rows_per_s": total_rows / (pms / 1e3),
+                                   "algo_gb_per_s": out["algo_bytes"] / (pms / 1e3) / 1e9, "kinds": kinds,
+                                   "distinct_variants": len({hawk.format_variant(v) for v in picks})}
     torch.cuda.synchronize()
     return out
 
 
-def c5_pick_quality(ctx, dev, pools_np, pool_rows, args):
-    """The learned per-query picks on C5 queries of 4M-64M rows (their best
-    variants are HBM-bound), against each query's exhaustive best (pruned at
-    10x the running best) and Algorithm 1's per-kind variant; training timings
-    come from other seeded C5 queries over the same pools."""
+def c5_train(ctx, dev, pools_np, pool_rows, args):
+    """The cost model's training timings (sampled variants of other seeded C5
+    queries of 1M-64M rows over the same pools, then two rounds of active
+    sampling) and the five-member ensemble trained on them."""
     from paper_1709_00700_amd import datagen as dg
-    from paper_1709_00700_amd import hawk, optimizer
-    t_start = time.perf_counter()
-    ctx.set_jit(False)  # the optimizer times the kernels compiled ahead of time
-    seed_train, seed_test = dg.MASTER_SEED + 1005, dg.MASTER_SEED + 5
+    from paper_1709_00700_amd import optimizer
     hi = min(args.pq_max_rows, pool_rows)
-    tr = dg.c5_queries(args.pq_train, pool_rows, seed_train, min_rows=min(args.pq_min_rows // 4, hi), max_rows=hi)
-    te = dg.c5_queries(args.pq_test, pool_rows, seed_test + 77, min_rows=min(args.pq_min_rows, hi), max_rows=hi)
-    # kinds in turn, so that a search cut short by the time budget still covers each kind
-    by_kind = [[q for q in te if q["kind"] == k] for k in (1, 2, 3)]
-    te = [q for grp in zip(*[g + [None] * (len(te) - len(g)) for g in by_kind]) for q in grp if q is not None]
+    tr = dg.c5_queries(args.pq_train, pool_rows, dg.MASTER_SEED + 1005, min_rows=min(args.pq_min_rows // 4, hi),
+                       max_rows=hi)
     tr_h = optimizer.register_c5(ctx, pools_np, tr, prefix="pqtr_", dev=dev)
-    te_h = optimizer.register_c5(ctx, pools_np, te, prefix="pqte_", dev=dev)
     t0 = time.perf_counter()
     X, y = optimizer.training_set(ctx, tr_h, args.pq_per_query, reps=2, limit_ms=args.pq_limit_ms, seed=7,
                                   progress=lambda m: log("[bench] " + m), factor=10.0)
@@ -263,15 +281,34 @@ def c5_pick_quality(ctx, dev, pools_np, pool_rows, args):
     loss = ens.train(X, y, epochs=300, batch=512, lr=3e-3, seed=2)
     X, y = optimizer.refine(ctx, tr_h, ens, X, y, top=4, rounds=2, reps=2, limit_ms=args.pq_limit_ms, factor=10.0,
                             progress=lambda m: log("[bench] " + m), epochs=300, batch=512, lr=3e-3, seed=2)
-    t_train = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    alg1 = optimizer.alg1_per_kind(ctx, te_h, reps=2, limit_ms=args.pq_limit_ms)
-    t_alg1 = time.perf_counter() - t0
+    stats = {"training_samples": int(len(y)), "train_mse": loss,
+             "active_sampling": "2 rounds x top 4 per training query", "collect_s": t_collect,
+             "train_s": time.perf_counter() - t0}
+    return ens, stats
+
+
+def c5_test_queries(ctx, dev, pools_np, pool_rows, args):
+    """The pick-quality queries (4M-64M rows), kinds in turn, so that a search
+    cut short by the time budget still covers each kind."""
+    from paper_1709_00700_amd import datagen as dg
+    from paper_1709_00700_amd import optimizer
+    hi = min(args.pq_max_rows, pool_rows)
+    te = dg.c5_queries(args.pq_test, pool_rows, dg.MASTER_SEED + 5 + 77, min_rows=min(args.pq_min_rows, hi),
+                       max_rows=hi)
+    by_kind = [[q for q in te if q["kind"] == k] for k in (1, 2, 3)]
+    te = [q for grp in zip(*[g + [None] * (len(te) - len(g)) for g in by_kind]) for q in grp if q is not None]
+    return te, optimizer.register_c5(ctx, pools_np, te, prefix="pqte_", dev=dev)
+
+
+def c5_pick_quality(ctx, te, te_h, ens, alg1, picker, train_stats, t_alg1, args, t_start):
+    """The learned per-query picks on C5 queries of 4M-64M rows (their best
+    variants are HBM-bound), against each query's exhaustive best (pruned at
+    10x the running best) and Algorithm 1's per-kind variant; then the same
+    queries back to back in their best variants against one batch replay in
+    the tile kernels, in the picked variants and in the best variants."""
+    from paper_1709_00700_amd import hawk, optimizer
     t0 = time.perf_counter()
     deadline = t_start + args.pq_budget_s
-    # the per-query optimizer: the ensemble's pick where its members agree it
-    # beats Algorithm 1's variant for the query's kind, else that variant
-    picker = optimizer.WithFallback(ens, {k: v for k, (v, _) in alg1.items()})
     # one timed run per variant in the search; the search's best and the picks
     # are then timed again with 5 runs each and compared on those times
     pq = optimizer.pick_quality(ctx, te_h, picker, reps=1, limit_ms=args.pq_limit_ms, alg1=alg1,
@@ -284,7 +321,7 @@ def c5_pick_quality(ctx, dev, pools_np, pool_rows, args):
     for q, r in zip(te[:done], rows):
         r.update({"kind": q["kind"], "rows": q["rows"]})
     # the same queries back to back in their exhaustive-best variants (each a
-    # separate execution: host launches included), against one batch replay
+    # separate execution: host launches included), against batch replays
     best_vs = []
     for h, r in zip(te_h[:done], rows):
         best_vs.append(next(v for v in hawk.variant_space(h) if optimizer.variant_key(h, v) == r["best"]))
@@ -301,12 +338,14 @@ def c5_pick_quality(ctx, dev, pools_np, pool_rows, args):
         for r_ in res:
             r_.free()
         seq.append(e0.elapsed_time(e1))
-    b = hawk.Batch(ctx, te_h[:done], tile_rows_log2=17, wgs_per_cu=8, order=0)
-    batch_ms = b.time(reps=3)
-    b.free()
-    ctx.set_jit(not args.no_jit)
-    pq.update({"training_samples": int(len(y)), "train_mse": loss, "active_sampling": "2 rounds x top 4 per training query", "collect_s": t_collect, "train_s": t_train,
-               "alg1_s": t_alg1, "exhaustive_s": t_ex, "pool_rows": pool_rows,
+    sched = dict(tile_rows_log2=17, wgs_per_cu=8, order=0)
+    batch = {}
+    for name, vs in (("tile", None), ("picked", picker.pick(te_h[:done])[0]), ("best", best_vs)):
+        b = hawk.Batch(ctx, te_h[:done], variants=vs, **sched)
+        batch[name] = b.time(reps=3)
+        b.free()
+    pq.update(train_stats)
+    pq.update({"alg1_s": t_alg1, "exhaustive_s": t_ex, "pool_rows": args.rows or args.c5_pool_rows,
                "rows_range": [min(q["rows"] for q in te), max(q["rows"] for q in te)],
                "best_ms_median": float(sorted(r["best_ms"] for r in rows)[len(rows) // 2]) if rows else None,
                "prune": "a variant slower than 10x the fastest measured so far for the query is +inf",
@@ -317,8 +356,8 @@ def c5_pick_quality(ctx, dev, pools_np, pool_rows, args):
                "kernels": "compiled ahead of time (run-time compilation off for the whole evaluation)",
                "sum_best_ms": sum(r["best_ms"] for r in rows),
                "sum_best_sequential_ms": sorted(seq)[1],
-               "batch_ms": batch_ms, "per_query": rows})
-    ens.free()
+               "batch_ms": batch["tile"], "batch_picked_ms": batch["picked"], "batch_best_ms": batch["best"],
+               "per_query": rows})
     return pq
 
 
@@ -499,14 +538,32 @@ def main():
         log(f"[bench] c5: generating + uploading pools of {pool_rows} rows")
         pools_np = dg.c5_pools(pool_rows)
         dev = optimizer.upload_pools(ctx, pools_np)
+        picker, ens = None, None
+        if not args.no_pick_quality:
+            t_start = time.perf_counter()
+            ctx.set_jit(False)  # the optimizer times the kernels compiled ahead of time
+            log("[bench] c5: cost model training")
+            ens, train_stats = c5_train(ctx, dev, pools_np, pool_rows, args)
+            te, te_h = c5_test_queries(ctx, dev, pools_np, pool_rows, args)
+            t0 = time.perf_counter()
+            alg1 = optimizer.alg1_per_kind(ctx, te_h, reps=2, limit_ms=args.pq_limit_ms)
+            t_alg1 = time.perf_counter() - t0
+            # the per-query optimizer: the ensemble's pick where its members
+            # agree it beats Algorithm 1's variant for the query's kind
+            picker = optimizer.WithFallback(ens, {k: v for k, (v, _) in alg1.items()})
+            ctx.set_jit(not args.no_jit)
         log("[bench] c5: batch")
         sched = dict(tile_rows_log2=17, wgs_per_cu=8, order=0)
         c5 = c5_batch(ctx, dev, pools_np, args.c5_queries, pool_rows, sched, args.autotune, args.steps,
-                      args.warmup)
+                      args.warmup, picker=picker)
         c5["codegen"] = dict(zip(("run_time_kernels", "compile_ms"), ctx.jit_stats()))
-        if not args.no_pick_quality:
+        if picker is not None:
             log("[bench] c5: pick quality")
-            c5["pick_quality"] = c5_pick_quality(ctx, dev, pools_np, pool_rows, args)
+            ctx.set_jit(False)
+            c5["pick_quality"] = c5_pick_quality(ctx, te, te_h, ens, alg1, picker, train_stats, t_alg1, args,
+                                                 t_start)
+            ctx.set_jit(not args.no_jit)
+            ens.free()
         out["c5"] = c5
         del pools_np
         if not head_pipes:

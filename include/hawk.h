@@ -361,35 +361,44 @@ hawk_status hawk_model_pick_ensemble(hawk_model* const* ms, int32_t nm, float pe
                                      int32_t n, hawk_variant* out, float* predicted_ms);
 
 /* ------------------------------------------------------------ batched execution */
-/* Many queries as one captured HIP graph of persistent kernels. Section 8
-   tunes one variant per workload and the paper leaves per-query work
-   distribution open (Sections 9.3.4 and 9.4); a batch instead runs every query of a
-   mixed workload in one launch sequence: a fill kernel resets the batch's
-   tables and counters, a persistent kernel runs the tiles of every build
-   pipeline (HASH_PUT, Table 1), one persistent kernel per plan shape runs
-   the main pipelines' tiles (LOOP, FILTER, HASH_PROBE, ARITHMETIC, then
-   HASH_AGGREGATE/AGGREGATE or order-preserving PROJECT), and a persistent
-   kernel writes every aggregation's result rows. Workgroups take
-   (query, tile) items from an atomic counter. Inside a batch every query uses
-   one fixed variant: coalesced access, branched evaluation, linear probing
-   with Murmur hashing, local (LDS) pre-aggregation; projections keep input
-   order with a single-pass look-back over tile counts.
+/* Many queries as one captured HIP graph. Section 8 tunes one variant per
+   workload and the paper leaves per-query work distribution open (Sections
+   9.3.4 and 9.4); a batch instead runs every query of a mixed workload in one
+   launch sequence, each query in its own variant or in the batch's tile
+   kernels:
+   - Tile kernels: a fill kernel resets the batch's tables and counters, a
+     persistent kernel runs the tiles of every build pipeline (HASH_PUT,
+     Table 1), one persistent kernel per plan shape runs the main pipelines'
+     tiles (LOOP, FILTER, HASH_PROBE, ARITHMETIC, then HASH_AGGREGATE /
+     AGGREGATE or order-preserving PROJECT), and a persistent kernel writes
+     every aggregation's result rows. Workgroups take (query, tile) items from
+     an atomic counter. These tiles run one fixed variant: coalesced access,
+     branched evaluation, linear probing with Murmur hashing, local (LDS)
+     pre-aggregation; projections keep input order with a single-pass
+     look-back over tile counts.
+   - Own variant: the query's builds and main pipeline run the kernels of its
+     variant (as hawk_execute would, without retries) as nodes of the same
+     graph, over device memory the batch reserves for it at creation.
    Schedule options: tile_rows_log2 in [14, 18] (rows per work item),
    wgs_per_cu in [1, 32] (persistent workgroups per compute unit), order 0
    (submission order) or 1 (largest query first); separate 1 gives grouped
-   aggregations of at least 2^20 rows with more groups than a tile's LDS
-   table holds their own launches in the graph (the spilling local strategy,
-   compiled at run time when the context does so), 0 keeps every pipeline
-   in the persistent kernels. NULL opts = {16, 2, 1, 1}. */
+   aggregations without a variant of their own, of at least 2^20 rows and
+   with more groups than a tile's LDS table holds, their own variant (the
+   spilling local strategy with linear probing, compiled at run time when the
+   context does so); 0 keeps them in the tile kernels. NULL opts =
+   {16, 2, 1, 1}. */
 typedef struct { int32_t tile_rows_log2; int32_t wgs_per_cu; int32_t order; int32_t separate; } hawk_batch_opts;
 /* Creates a batch of n queries of ctx (borrowed: they must outlive the batch;
-   their tables must stay registered and unmodified). Allocates the batch's
-   device memory (tables sized from the queries' row counts and group hints,
-   outputs sized for every input row) and captures the graph. Errors:
-   HAWK_E_ARG, HAWK_E_DEVICE (planning context, HIP error), HAWK_E_OOM,
-   HAWK_E_INFEASIBLE (tile does not fit in LDS). */
-hawk_status hawk_batch_create(hawk_ctx* ctx, hawk_query* const* qs, int32_t n, const hawk_batch_opts* opts,
-                              hawk_batch** out);
+   their tables must stay registered and unmodified). variants: NULL, or one
+   per query: a variant of the query's variant space runs the query with its
+   own kernels; a variant with thread_mult 0 puts the query in the tile
+   kernels. Allocates the batch's device memory (tables sized from the
+   queries' row counts and group hints, outputs sized for every input row)
+   and captures the graph. Errors: HAWK_E_ARG (bad variant values),
+   HAWK_E_DEVICE (planning context, HIP error), HAWK_E_OOM, HAWK_E_INFEASIBLE
+   (a tile or a query's variant does not fit in LDS). */
+hawk_status hawk_batch_create(hawk_ctx* ctx, hawk_query* const* qs, int32_t n, const hawk_variant* variants,
+                              const hawk_batch_opts* opts, hawk_batch** out);
 /* Releases the batch's device memory (synchronises the context stream);
    its result views are orphaned (every call on them returns HAWK_E_ARG). */
 void hawk_batch_free(hawk_batch* b);

@@ -356,6 +356,9 @@ struct Lowering {
     auto it = reg_of.find(nm);
     if (it != reg_of.end()) {
       *reg = it->second;
+      // a filter column read again after the filters
+      for (int c = 0; c < P.ncolA && phase > 0; ++c)
+        if (P.colA[c].reg == it->second) P.liveA |= 1u << c;
       return HAWK_OK;
     }
     int c = find_col(nm);
@@ -364,7 +367,7 @@ struct Lowering {
     HkCol col = {table->cols[c].ptr, table->cols[c].dtype, nreg};
     if (phase == 0) {
       if (P.ncolA >= HK_MAX_COLS_A) return set_error(ctx, HAWK_E_PLAN, "too many filter columns");
-      P.colA[P.ncolA++] = col;
+      P.colA[P.ncolA++] = col;  // read by its filter; live once read again (above)
     } else if (phase == 1) {
       if (P.ncolB >= HK_MAX_COLS_B) return set_error(ctx, HAWK_E_PLAN, "too many join-key columns");
       P.colB[P.ncolB++] = col;
@@ -1293,6 +1296,31 @@ hawk_status execute_once(hawk_ctx* ctx, const hawk_query* q, const hawk_variant*
 }
 
 }  // namespace
+
+static hawk_status prepare_run_time_kernel(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v);
+
+hawk_status exec_arena(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v, hipStream_t st, char* base,
+                       size_t cap, bool launch, bool upload, hawk_result* holder, size_t* used) {
+  if (ctx->device < 0) return set_error(ctx, HAWK_E_DEVICE, "planning context cannot execute");
+  if (q->ctx != ctx) return set_error(ctx, HAWK_E_ARG, "query of another context");
+  if (upload && base) {
+    // a run-time kernel is compiled before any launch of it is recorded
+    hawk_status pst = prepare_run_time_kernel(ctx, q, v);
+    if (pst) return pst;
+  }
+  holder->ctx = ctx;
+  holder->kind = q->kind;
+  holder->cols.clear();
+  Exec X{ctx, q, v, holder, {}, 0, st};
+  X.mem = EXEC_ARENA;
+  X.base = base;
+  X.cap = cap;
+  X.launch = launch;
+  X.upload = upload;
+  hawk_status rst = run_query(X, 0);
+  if (used) *used = X.used;
+  return rst;
+}
 
 extern "C" hawk_status hawk_execute_async(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v, hawk_result** out) {
   if (!ctx) return HAWK_E_ARG;

@@ -44,6 +44,7 @@ uint64_t sm64(uint64_t& s) {
 struct hawk_batch {
   hawk_ctx* ctx = nullptr;
   std::vector<hawk_query*> qs;
+  std::vector<hawk_variant> variants;   // per query (empty: none given)
   hawk_batch_opts opts{};
   std::vector<void*> allocs;            // device memory owned by the batch
   std::vector<HkBatchQuery> hq;         // per query descriptors (host copy)
@@ -76,21 +77,20 @@ struct hawk_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::set<hawk_result*> views;         // live result views of this batch
-  // grouped aggregations run with their own launches inside the graph (large
-  // or high-cardinality ones): the aggregation kernel of a fixed variant and,
-  // when its LDS table cannot hold the groups, the spill kernels
-  struct Direct {
+  // queries that run their own variant's kernels inside the graph: those
+  // given a variant, and (by default) large grouped aggregations with more
+  // groups than a tile's LDS table holds (spilling instead of device-scope
+  // atomics). Each owns one region of device memory laid out by the
+  // execution itself (exec_arena); `holder` describes its flags and results.
+  struct Own {
     int32_t q;
     hawk_variant v;
-    AggConfig cfg;
-    HkSpill sp;
-    uint32_t* offs;
-    uint32_t* stmp;
-    uint64_t* total;
-    uint64_t* part;
+    char* region;
+    size_t bytes;
+    hawk_result holder;
   };
-  std::vector<Direct> direct;
-  std::vector<char> is_direct;
+  std::vector<Own> own;
+  std::vector<char> is_own;
 };
 
 namespace {
@@ -123,6 +123,45 @@ void add_zero(hawk_batch* B, uint64_t* ptr, int64_t n) {
   add_fill(B, ptr, n, &z, 1);
 }
 
+// Whether query i runs its own kernels, and in which variant: the one given
+// for it (thread_mult 0 = the tile kernels), or, without one and with
+// `separate`, a grouped aggregation of at least kDirectRows rows whose groups
+// do not fit a tile's LDS table runs the local strategy with linear probing
+// (spilling scans without probes: one workgroup of 1024 per CU; with probes,
+// which are latency-bound: about 64K rows per workgroup of 512, up to 8 per CU).
+bool own_variant(const hawk_batch* B, size_t i, hawk_variant& v) {
+  if (!B->variants.empty() && B->variants[i].thread_mult != 0) {
+    v = B->variants[i];
+    return true;
+  }
+  const hawk_query* q = B->qs[i];
+  const int64_t n = q->main.nrows;
+  if (!B->opts.separate || q->kind != 2 || q->main.ngroup == 0 || n < kDirectRows) return false;
+  const int W = q->main.slot_words;
+  const uint64_t groups = static_cast<uint64_t>(std::max<int64_t>(1, std::min<int64_t>(q->groups_hint, n)));
+  uint32_t fit = 0;
+  while ((int64_t(2) << fit) * W * 8 <= kLdsBudget) ++fit;
+  const uint32_t llog2 = std::min(std::max<uint32_t>(4, clog2(groups * 2)), fit);
+  if ((uint64_t(1) << llog2) >= 2 * groups) return false;
+  v = hawk_variant{};
+  v.proj_strategy = HAWK_MULTI_PASS;
+  v.mem = HAWK_COALESCED;
+  v.pred = HAWK_BRANCHED;
+  v.ht = HAWK_LINEAR_PROBING;
+  v.hash = HAWK_MURMUR;
+  v.agg_strategy = HAWK_LOCAL;
+  if (q->main.nprobes == 0) {
+    v.thread_mult = 1;
+    v.wg_size = 1024;
+  } else {
+    uint32_t tm = 1;
+    while (tm < 8 && n / (static_cast<int64_t>(B->ctx->num_cus) * 2 * tm) >= 65536) tm *= 2;
+    v.thread_mult = tm;
+    v.wg_size = 512;
+  }
+  return true;
+}
+
 // device memory of every query: tables, outputs, counters (independent of the schedule)
 hawk_status setup_memory(hawk_batch* B) {
   hawk_ctx* ctx = B->ctx;
@@ -135,12 +174,26 @@ hawk_status setup_memory(hawk_batch* B) {
   add_zero(B, reinterpret_cast<uint64_t*>(B->d_heads), HEAD_COUNT);
   add_zero(B, reinterpret_cast<uint64_t*>(B->d_err), 1);
   const int64_t min_tile = 1 << 14;
+  B->is_own.assign(B->qs.size(), 0);
   for (size_t i = 0; i < B->qs.size(); ++i) {
     const hawk_query* q = B->qs[i];
     HkBatchQuery Q;
     std::memset(&Q, 0, sizeof(Q));
     Q.plan = q->main;
     Q.plan.hash = h;
+    hawk_variant ov{};
+    if (own_variant(B, i, ov)) {
+      // its own kernels, tables and results: nothing of the tile kernels' state
+      Q.kind = q->kind == 1 ? HK_BQ_PROJECT : (Q.plan.ngroup > 0 ? HK_BQ_GROUPED : HK_BQ_SCALAR);
+      Q.shape = hk_shape_of(Q.plan);
+      B->hq.push_back(Q);
+      B->is_own[i] = 1;
+      hawk_batch::Own o{};
+      o.q = static_cast<int32_t>(i);
+      o.v = ov;
+      B->own.push_back(o);
+      continue;
+    }
     // build pipelines of this query
     std::vector<HkJoinTable> tabs;
     for (const QueryBuild& qb : q->builds) {
@@ -212,60 +265,6 @@ hawk_status setup_memory(hawk_batch* B) {
       }
       Q.table.words = static_cast<uint64_t*>(balloc(B, static_cast<size_t>(Q.nslots * W) * 8, B->allocs));
       if (!Q.table.words) return berr(B, HAWK_E_OOM, "batch aggregation table");
-      const int64_t ghint = std::max<int64_t>(1, std::min<int64_t>(q->groups_hint, n));
-      if (grouped && B->opts.separate && n >= kDirectRows && (int64_t(1) << Q.llog2) < 2 * ghint) {
-        // own launches: local strategy, coalesced, linear probing with the
-        // batch's Murmur seeds (the join tables of its probes use them too)
-        hawk_batch::Direct d{};
-        d.q = static_cast<int32_t>(i);
-        d.v.proj_strategy = HAWK_MULTI_PASS;
-        d.v.mem = HAWK_COALESCED;
-        d.v.ht = HAWK_LINEAR_PROBING;
-        d.v.hash = HAWK_MURMUR;
-        d.v.agg_strategy = HAWK_LOCAL;
-        // about 64K rows or more per workgroup, up to 8 workgroups per CU
-        uint32_t tm = 1;
-        while (tm < 8 && n / (static_cast<int64_t>(ctx->num_cus) * 2 * tm) >= 65536) tm *= 2;
-        d.v.thread_mult = tm;
-        d.v.wg_size = 512;
-        hawk_status cst = agg_config(ctx, Q.plan, Q.table, ghint, &d.v, static_cast<int64_t>(tm) * ctx->num_cus, d.cfg);
-        if (!cst && d.cfg.spill && Q.plan.nprobes == 0) {
-          // a spilling scan without probes does best with one large workgroup
-          // per CU; probes are latency-bound and keep the wider grid
-          d.v.thread_mult = 1;
-          d.v.wg_size = 1024;
-          cst = agg_config(ctx, Q.plan, Q.table, ghint, &d.v, ctx->num_cus, d.cfg);
-        }
-        if (cst) return cst;
-        Q.table.rlog2 = d.cfg.rlog2;
-        if (d.cfg.spill) {
-          d.sp = d.cfg.sp;
-          const int64_t m = d.cfg.nparts * d.cfg.groups;
-          d.sp.buf = static_cast<uint64_t*>(balloc(B, static_cast<size_t>(n * d.sp.ew) * 8, B->allocs));
-          d.sp.hist = static_cast<uint32_t*>(balloc(B, static_cast<size_t>(m) * 4, B->allocs));
-          d.sp.cnt = static_cast<uint32_t*>(balloc(B, static_cast<size_t>(d.cfg.groups) * 4, B->allocs));
-          d.offs = static_cast<uint32_t*>(balloc(B, static_cast<size_t>(m) * 4, B->allocs));
-          d.stmp = static_cast<uint32_t*>(balloc(B, static_cast<size_t>(hk_scan_tmp_words(m)) * 4, B->allocs));
-          d.total = static_cast<uint64_t*>(balloc(B, 8, B->allocs));
-          d.part = static_cast<uint64_t*>(balloc(B, static_cast<size_t>(n * d.sp.ew) * 8, B->allocs));
-          if (d.sp.merge) {
-            d.sp.flush = static_cast<uint64_t*>(
-                balloc(B, static_cast<size_t>(d.cfg.groups * d.sp.fcap * W) * 8, B->allocs));
-            d.sp.foffs = static_cast<uint32_t*>(
-                balloc(B, static_cast<size_t>(d.cfg.groups * (d.cfg.nparts + 1)) * 4, B->allocs));
-          }
-          if (!d.sp.buf || !d.sp.hist || !d.sp.cnt || !d.offs || !d.stmp || !d.total || !d.part ||
-              (d.sp.merge && (!d.sp.flush || !d.sp.foffs)))
-            return berr(B, HAWK_E_OOM, "batch spill buffers");
-        }
-        if (ctx->jit) {
-          std::string msg;
-          if (jit_agg_prepare(ctx->jit_cache, msg, Q.plan, d.v.mem, d.v.pred, d.v.hash, d.v.agg_strategy,
-                              d.cfg.llog2, Q.ident.nw, d.cfg.reps, d.cfg.spill ? &d.sp : nullptr) != hipSuccess)
-            return berr(B, HAWK_E_DEVICE, "run-time compilation: " + msg);
-        }
-        B->direct.push_back(d);
-      }
       add_fill(B, Q.table.words, Q.nslots * W, Q.ident.w, W);
       const int64_t cap = Q.nslots;
       for (int g = 0; g < Q.plan.ngroup; ++g) {
@@ -284,8 +283,19 @@ hawk_status setup_memory(hawk_batch* B) {
     }
     B->hq.push_back(Q);
   }
-  B->is_direct.assign(B->hq.size(), 0);
-  for (const auto& d : B->direct) B->is_direct[d.q] = 1;
+  // regions of the queries with their own kernels: sizes from a pass that
+  // enqueues nothing, then a pass that uploads their plans (and compiles
+  // their run-time kernels) with the final addresses
+  for (auto& o : B->own) {
+    const hawk_query* q = B->qs[o.q];
+    hawk_status st = exec_arena(ctx, q, &o.v, ctx->stream, nullptr, 0, false, false, &o.holder, &o.bytes);
+    if (st) return st;
+    o.region = static_cast<char*>(balloc(B, o.bytes, B->allocs));
+    if (!o.region) return berr(B, HAWK_E_OOM, "batch region of a query with its own variant");
+    st = exec_arena(ctx, q, &o.v, ctx->stream, o.region, o.bytes, false, true, &o.holder, nullptr);
+    if (st) return st;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return berr(B, HAWK_E_DEVICE, "plan upload");
+  }
   return HAWK_OK;
 }
 
@@ -333,7 +343,7 @@ hawk_status setup_schedule(hawk_batch* B, const hawk_batch_opts& o) {
     size_t lds = 64;
     for (int32_t i : order) {
       const HkBatchQuery& Q = hq[i];
-      if (Q.shape != s || Q.ntiles == 0 || B->is_direct[i]) continue;
+      if (Q.shape != s || Q.ntiles == 0 || B->is_own[i]) continue;
       qi.push_back(i);
       nt.push_back(Q.ntiles);
       size_t need;
@@ -356,7 +366,7 @@ hawk_status setup_schedule(hawk_batch* B, const hawk_batch_opts& o) {
   std::vector<int32_t> fq;
   std::vector<int64_t> fn;
   for (size_t i = 0; i < hq.size(); ++i)
-    if (hq[i].kind != HK_BQ_PROJECT) {
+    if (hq[i].kind != HK_BQ_PROJECT && !B->is_own[i]) {
       fq.push_back(static_cast<int32_t>(i));
       fn.push_back((hq[i].nslots + kFinalTile - 1) / kFinalTile);
     }
@@ -389,19 +399,15 @@ hawk_status setup_schedule(hawk_batch* B, const hawk_batch_opts& o) {
     le = hk_batch_build(B->cap, std::min<int64_t>(grid, std::max<int64_t>(1, B->build_items)), B->d_builds,
                         B->d_build_bases, static_cast<int32_t>(B->hb.size()), B->build_items, kBuildTile,
                         B->d_heads + HEAD_BUILD, B->d_err);
-  for (const auto& d : B->direct) {
+  // the queries with their own variant: their kernels over their regions
+  for (auto& o : B->own) {
     if (le != hipSuccess) break;
-    const HkBatchQuery& Q = hq[d.q];
-    le = agg_kernel_launch(ctx, B->cap, &d.v, Q.plan, Q.table, d.cfg, Q.ident.w, Q.ident.nw, B->d_err,
-                           d.cfg.spill ? &d.sp : nullptr);
-    if (le == hipSuccess && d.cfg.spill) {
-      le = hk_scan(B->cap, d.sp.hist, d.offs, d.cfg.nparts * d.cfg.groups, d.stmp, d.total, B->d_err);
-      if (le == hipSuccess)
-        le = hk_spill(B->cap, 0, Q.plan, Q.table, d.v.hash, d.sp, Q.ident.w, Q.ident.nw, d.offs, d.total, d.cfg.groups,
-                      d.part, B->d_err);
-      if (le == hipSuccess)
-        le = hk_spill(B->cap, 1, Q.plan, Q.table, d.v.hash, d.sp, Q.ident.w, Q.ident.nw, d.offs, d.total, d.cfg.groups,
-                      d.part, B->d_err);
+    const hawk_status st = exec_arena(ctx, B->qs[o.q], &o.v, B->cap, o.region, o.bytes, true, false, &o.holder, nullptr);
+    if (st) {
+      (void)hipStreamEndCapture(B->cap, &B->graph);
+      if (B->graph) (void)hipGraphDestroy(B->graph);
+      B->graph = nullptr;
+      return st;
     }
   }
   for (int s = 0; s < 5 && le == hipSuccess; ++s)
@@ -446,7 +452,8 @@ void batch_release_device(hawk_batch* B) {
   B->ctx = nullptr;
 }
 
-extern "C" hawk_status hawk_batch_create(hawk_ctx* ctx, hawk_query* const* qs, int32_t n, const hawk_batch_opts* opts,
+extern "C" hawk_status hawk_batch_create(hawk_ctx* ctx, hawk_query* const* qs, int32_t n,
+                                         const hawk_variant* variants, const hawk_batch_opts* opts,
                                          hawk_batch** out) {
   if (!ctx) return HAWK_E_ARG;
   if (!qs || n < 1 || !out) return set_error(ctx, HAWK_E_ARG, "null argument");
@@ -462,6 +469,15 @@ extern "C" hawk_status hawk_batch_create(hawk_ctx* ctx, hawk_query* const* qs, i
       return set_error(ctx, HAWK_E_ARG, "query of another context");
     }
     B->qs.push_back(qs[i]);
+    if (variants) {
+      const hawk_variant& v = variants[i];
+      if (v.thread_mult != 0 && (v.mem > 1 || v.pred > 1 || v.ht > 1 || v.hash > 1 || v.agg_strategy > 1 ||
+                                 v.proj_strategy > 1 || v.wg_size < 1 || v.wg_size > 1024)) {
+        delete B;
+        return set_error(ctx, HAWK_E_ARG, "variant value out of range");
+      }
+      B->variants.push_back(v);
+    }
   }
   if (hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess) {
     delete B;
@@ -515,6 +531,12 @@ extern "C" hawk_status hawk_batch_time(hawk_batch* B, int32_t reps, double* medi
   }
   int err = 0;
   if (hipMemcpy(&err, B->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return berr(B, HAWK_E_DEVICE, "flags");
+  for (const auto& o : B->own) {
+    int e1 = 0;
+    if (hipMemcpy(&e1, o.holder.d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+      return berr(B, HAWK_E_DEVICE, "flags");
+    err |= e1;
+  }
   if (err & HK_ERR_DUPKEY) return berr(B, HAWK_E_DUPKEY, "a build pipeline of the batch inserted a key twice");
   if (err & (HK_ERR_CAPACITY | HK_ERR_CUCKOO)) return berr(B, HAWK_E_CAPACITY, "batch hash table overflow");
   if (err) return berr(B, HAWK_E_TIMEOUT, "a projection look-back wait of the batch gave up");
@@ -559,7 +581,14 @@ extern "C" hawk_status hawk_batch_result(hawk_batch* B, int32_t i, hawk_result**
   r->kind = B->qs[i]->kind;
   r->d_count = Q.count;
   r->d_err = B->d_err;
-  if (Q.kind == HK_BQ_PROJECT) {
+  const hawk_batch::Own* own = nullptr;
+  for (const auto& o : B->own)
+    if (o.q == i) own = &o;
+  if (own) {
+    r->d_count = own->holder.d_count;
+    r->d_err = own->holder.d_err;
+    r->cols = own->holder.cols;
+  } else if (Q.kind == HK_BQ_PROJECT) {
     for (int c = 0; c < Q.plan.nproj; ++c) r->cols.push_back({HAWK_RES_I64, Q.out.col[c]});
   } else {
     for (int g = 0; g < Q.plan.ngroup; ++g) r->cols.push_back({HAWK_RES_I64, Q.res.gcol[g]});

@@ -309,6 +309,56 @@ __device__ __forceinline__ bool eval_row_f(const HkPlan& P, int64_t row, const H
   return pass;
 }
 
+// Every column load of a row (all three phases), for rows already known to
+// pass: a projection kernel gathers them one block ahead of their use.
+template <class S>
+struct HkAll {
+  HkRaw a[S::colA > 0 ? S::colA : 1], b[S::colB > 0 ? S::colB : 1], c[S::colC > 0 ? S::colC : 1];
+};
+
+template <class S>
+__device__ __forceinline__ void fetch_all(const HkPlan& P, int64_t row, HkAll<S>& f) {
+  // a filter-only column reads row 0 (one line for the whole wave) instead
+#pragma unroll
+  for (int c = 0; c < S::colA; ++c) load_raw(P.colA[c], c < P.ncolA && ((P.liveA >> c) & 1u) ? row : 0, f.a[c]);
+#pragma unroll
+  for (int c = 0; c < S::colB; ++c) load_raw(P.colB[c], c < P.ncolB ? row : 0, f.b[c]);
+#pragma unroll
+  for (int c = 0; c < S::colC; ++c) load_raw(P.colC[c], c < P.ncolC ? row : 0, f.c[c]);
+}
+
+// A row known to pass (its filters held and its probes found their keys):
+// the registers from the gathered columns, the probes' payloads and the
+// arithmetic, without the filters and early exits of eval_row_f.
+template <int HT, int HASH, class S>
+__device__ __forceinline__ void eval_passing_row(const HkPlan& P, int64_t row, const HkAll<S>& f, v16i64& r) {
+#pragma unroll
+  for (int c = 0; c < S::colA; ++c)
+    if (c < P.ncolA && ((P.liveA >> c) & 1u)) r[P.colA[c].reg] = raw_value(P.colA[c], row, f.a[c]);
+#pragma unroll
+  for (int c = 0; c < S::colB; ++c)
+    if (c < P.ncolB) r[P.colB[c].reg] = raw_value(P.colB[c], row, f.b[c]);
+#pragma unroll
+  for (int p = 0; p < S::probes; ++p) {
+    if (p >= P.nprobes) break;
+    int32_t pay = 0;
+    join_lookup<HT, HASH>(P.probes[p].t, P.hash, static_cast<int32_t>(r[P.probes[p].fk_reg]), pay);
+    r[P.probes[p].pay_reg] = pay;
+  }
+#pragma unroll
+  for (int c = 0; c < S::colC; ++c)
+    if (c < P.ncolC) r[P.colC[c].reg] = raw_value(P.colC[c], row, f.c[c]);
+#pragma unroll
+  for (int k = 0; k < S::arith; ++k) {
+    if (k >= P.narith) break;
+    const HkArith& A = P.arith[k];
+    const uint64_t x = A.xc ? static_cast<uint64_t>(A.cx) : static_cast<uint64_t>(r[A.x]);
+    const uint64_t y = A.yc ? static_cast<uint64_t>(A.cy) : static_cast<uint64_t>(r[A.y]);
+    const uint64_t v = A.op == HK_ADD ? x + y : (A.op == HK_SUB ? x - y : x * y);
+    r[A.dst] = static_cast<long long>(v);
+  }
+}
+
 template <int PRED, int HT, int HASH, bool VALUES, class S>
 __device__ __forceinline__ bool eval_row(const HkPlan& P, int64_t row, v16i64& r) {
   const HkFirst<S> none{};

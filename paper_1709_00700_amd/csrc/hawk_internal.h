@@ -129,6 +129,17 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
 hipError_t agg_kernel_launch(hawk_ctx* ctx, hipStream_t st, const hawk_variant* v, const HkPlan& P,
                              const HkAggTable& T, const AggConfig& c, const uint64_t* ident, int32_t W, int* err,
                              const HkSpill* sp, bool allow_jit = true);
+// One execution of (q, v) over an arena [base, base + cap): every device
+// buffer, result columns included, is the next 256-byte aligned piece, in an
+// order that depends only on (q, v). base == nullptr: nothing is enqueued and
+// *used receives the bytes needed. launch: the kernels and fills are enqueued
+// on `st` (stream capture allowed: nothing else is called on the device);
+// upload (with a base): the plans are copied on `st` from the context's
+// staging buffer (the caller synchronises before the next upload) and a
+// run-time kernel is compiled first. `holder` receives the flags and result
+// columns (pieces of the arena; it owns nothing). No retry on overflow.
+hawk_status exec_arena(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v, hipStream_t st, char* base,
+                       size_t cap, bool launch, bool upload, hawk_result* holder, size_t* used);
 void query_release_device(hawk_query* q);
 void model_release_device(struct hawk_model* m);
 void batch_release_device(struct hawk_batch* b);

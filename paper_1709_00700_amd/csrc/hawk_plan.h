@@ -81,6 +81,9 @@ struct HkPlan {
   // aggregation table: AoS slots of slot_words 64-bit words:
   // [key, count, aggregate words...]; wide sums take two words (lo, hi)
   int32_t slot_words;
+  // bit c: colA[c] is read after the filters (a column that only a filter
+  // reads is not loaded again for rows already known to pass)
+  uint32_t liveA;
 };
 
 // a build pipeline (LOOP, FILTER, HASH_PUT): filter part, key and payload columns, target table

@@ -23,15 +23,33 @@ __global__ void __launch_bounds__(256) k_mp_filter(HkPlan P, uint64_t* __restric
   const int64_t T = (int64_t)gridDim.x * blockDim.x;
   const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (MEM == HK_COAL) {
-    // lanes of one wave cover one 64-row block per iteration: id = thread, id += threads
-    for (int64_t base = gt - __lane_id(); base < n; base += T) {
-      const int64_t row = base + __lane_id();
-      bool pass = false;
-      if (row < n) pass = eval_row<PRED, HT, HASH, false, S>(P, row, r);
-      const uint64_t m = __ballot(pass);
-      if (__lane_id() == 0) {
-        masks[base >> 6] = m;
-        counts[base >> 6] = static_cast<uint32_t>(__popcll(m));
+    // lanes of one wave cover one 64-row block per iteration: id = thread,
+    // id += threads. Software pipeline: the first load phase of the next AH
+    // blocks is in flight while a block is evaluated; the loop is unrolled by
+    // the ring size so every buffer index is a constant.
+    constexpr int AH = 3, NB = AH + 1;
+    HkFirst<S> f[NB] = {};
+    const int64_t b0 = gt - __lane_id();
+    // rows past the end fetch the last row again (the fetch count stays fixed)
+    auto at = [&](int64_t row) { return row < n ? row : n - 1; };
+    if (b0 < n) {
+#pragma unroll
+      for (int k = 0; k < AH; ++k) fetch_first<S>(P, at(b0 + k * T + __lane_id()), f[k]);
+    }
+    for (int64_t base = b0; base < n; base += NB * T) {
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const int64_t bk = base + k * T;
+        if (bk >= n) break;  // uniform over the wave
+        fetch_first<S>(P, at(bk + AH * T + __lane_id()), f[(k + AH) % NB]);
+        const int64_t row = bk + __lane_id();
+        bool pass = false;
+        if (row < n) pass = eval_row_f<PRED, HT, HASH, false, S, true>(P, row, f[k], r);
+        const uint64_t m = __ballot(pass);
+        if (__lane_id() == 0) {
+          masks[bk >> 6] = m;
+          counts[bk >> 6] = static_cast<uint32_t>(__popcll(m));
+        }
       }
     }
   } else {
@@ -64,21 +82,112 @@ __global__ void __launch_bounds__(256) k_mp_project(HkPlan P, const uint64_t* __
   const int64_t n = P.nrows;
   const int64_t T = (int64_t)gridDim.x * blockDim.x;
   const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (MEM == HK_COAL) {
-    for (int64_t base = gt - __lane_id(); base < n; base += T) {
-      const uint64_t m = masks[base >> 6];
-      if (PRED == HK_BR && m == 0) continue;
-      const int64_t row = base + __lane_id();
-      const bool pass = (m >> __lane_id()) & 1ull;
-      const int64_t pos = offsets[base >> 6] + __popcll(m & lanemask_lt());
-      if (PRED == HK_BR) {
-        if (pass) {
-          eval_row<HK_BR, HT, HASH, true, S>(P, row, r);
-          write_proj<S>(P, O, pos, r);
+  if (MEM == HK_COAL && PRED == HK_BR) {
+    // The wave's blocks j = 0, 1, ... start at b0 + j * threads. Their
+    // passing rows are handed to the lanes densely: for 64 blocks at a time,
+    // lane l holds block j0 + l's flag word, offset and (scanned over the
+    // lanes) the rank of its first passing row among those blocks; then the
+    // i-th passing row goes to lane i % 64 of round i / 64, which finds its
+    // block by a search over the ranks and its row as the matching set bit.
+    // All lanes of a round evaluate rows, not a few lanes per block.
+    const int64_t b0 = gt - __lane_id();
+    if (b0 >= n) return;  // uniform over the wave
+    const int64_t nbw = (n - b0 + T - 1) / T;  // blocks of this wave
+    uint64_t mnext = 0;
+    uint32_t onext = 0;
+    auto load_batch = [&](int64_t j0, uint64_t& ml, uint32_t& ol) {
+      const int64_t j = j0 + __lane_id();
+      ml = 0;
+      ol = 0;
+      if (j < nbw) {
+        const int64_t bi = (b0 + j * T) >> 6;
+        ml = masks[bi];
+        ol = offsets[bi];
+      }
+    };
+    load_batch(0, mnext, onext);
+    for (int64_t j0 = 0; j0 < nbw; j0 += WAVE) {
+      const uint64_t ml = mnext;
+      const uint32_t ol = onext;
+      load_batch(j0 + WAVE, mnext, onext);  // the next 64 blocks' words in flight
+      const uint32_t cl = static_cast<uint32_t>(__popcll(ml));
+      // inclusive scan of the counts over the lanes
+      uint32_t incl = cl;
+#pragma unroll
+      for (int d = 1; d < WAVE; d <<= 1) {
+        const uint32_t t = __shfl_up(incl, d, WAVE);
+        if (__lane_id() >= d) incl += t;
+      }
+      const uint32_t excl = incl - cl;
+      const uint32_t total = __builtin_amdgcn_readlane(incl, WAVE - 1);
+      for (uint32_t c0 = 0; c0 < total; c0 += WAVE) {
+        const uint32_t i = c0 + __lane_id();
+        // the last lane whose first rank is <= i holds row i (it has a
+        // passing row: the next lane's first rank exceeds i)
+        int src = 0;
+#pragma unroll
+        for (int step = WAVE / 2; step >= 1; step >>= 1) {
+          const uint32_t e = __shfl(excl, src + step, WAVE);
+          if (e <= i) src += step;
         }
-      } else if (row < n) {
-        eval_row<HK_PRED, HT, HASH, true, S>(P, row, r);
-        write_proj<S>(P, O, pass ? pos : O.dump, r);
+        const uint64_t m = (static_cast<uint64_t>(static_cast<uint32_t>(__shfl(static_cast<int>(ml >> 32), src, WAVE))) << 32) |
+                           static_cast<uint32_t>(__shfl(static_cast<int>(ml), src, WAVE));
+        const uint32_t o = static_cast<uint32_t>(__shfl(static_cast<int>(ol), src, WAVE));
+        uint32_t k = i - static_cast<uint32_t>(__shfl(static_cast<int>(excl), src, WAVE));
+        const uint32_t rank = k;
+        // position of the k-th set bit of m
+        uint64_t x = m;
+        int bit = 0;
+#pragma unroll
+        for (int w = 32; w >= 1; w >>= 1) {
+          const uint32_t c = static_cast<uint32_t>(__popcll(x & ((1ull << w) - 1)));
+          if (k >= c) {
+            k -= c;
+            x >>= w;
+            bit += w;
+          }
+        }
+        if (i < total) {
+          const int64_t row = b0 + (j0 + src) * T + bit;
+          HkAll<S> f;
+          fetch_all<S>(P, row, f);
+          eval_passing_row<HT, HASH, S>(P, row, f, r);
+          write_proj<S>(P, O, static_cast<int64_t>(o) + rank, r);
+        }
+      }
+    }
+  } else if (MEM == HK_COAL) {
+    // predicated: every row is evaluated and written (a dropped row to the
+    // dump slot); the flag word and offset of the next AH blocks are in
+    // flight while a block is projected
+    constexpr int AH = 3, NB = AH + 1;
+    uint64_t mk[NB] = {};
+    uint32_t ok[NB] = {};
+    const int64_t b0 = gt - __lane_id();
+    const int64_t lastb = n > 0 ? (n - 1) >> 6 : 0;
+    auto blk = [&](int64_t base) { return base < n ? base >> 6 : lastb; };
+    if (b0 < n) {
+#pragma unroll
+      for (int k = 0; k < AH; ++k) {
+        mk[k] = masks[blk(b0 + k * T)];
+        ok[k] = offsets[blk(b0 + k * T)];
+      }
+    }
+    for (int64_t base0 = b0; base0 < n; base0 += NB * T) {
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const int64_t base = base0 + k * T;
+        if (base >= n) break;  // uniform over the wave
+        mk[(k + AH) % NB] = masks[blk(base + AH * T)];
+        ok[(k + AH) % NB] = offsets[blk(base + AH * T)];
+        const uint64_t m = mk[k];
+        const int64_t row = base + __lane_id();
+        const bool pass = (m >> __lane_id()) & 1ull;
+        const int64_t pos = ok[k] + __popcll(m & lanemask_lt());
+        if (row < n) {
+          eval_row<HK_PRED, HT, HASH, true, S>(P, row, r);
+          write_proj<S>(P, O, pass ? pos : O.dump, r);
+        }
       }
     }
   } else {

@@ -167,7 +167,7 @@ def L():
                                           P(ctypes.c_float)], i32),
             "hawk_profile_enable": ([vp, i32], i32),
             "hawk_profile_read": ([vp, ctypes.c_char_p, P(ctypes.c_double), P(i64)], i32),
-            "hawk_batch_create": ([vp, P(vp), i32, P(hawk_batch_opts), P(vp)], i32),
+            "hawk_batch_create": ([vp, P(vp), i32, P(hawk_variant), P(hawk_batch_opts), P(vp)], i32),
             "hawk_batch_free": ([vp], None),
             "hawk_batch_run": ([vp], i32),
             "hawk_batch_time": ([vp, i32, P(ctypes.c_double)], i32),
@@ -243,6 +243,7 @@ class Context:
     def set_jit(self, on: bool = True):
         """Run-time compiled aggregation kernels for each plan structure (see hawk.h)."""
         check(L().hawk_ctx_set_jit(self.handle, int(on)), self.handle)
+        self.jit = bool(on)
 
     def jit_stats(self):
         """(kernels compiled, total compile milliseconds)."""
@@ -584,16 +585,22 @@ def model_pick_ensemble(models: list, penalty: float, queries: list):
 
 
 # ---------------------------------------------------------------- batched execution
-class Batch:
-    """Many queries replayed as one captured graph of persistent kernels (see hawk.h, batched execution)."""
+TILE = hawk_variant(0, 0, 0, 0, 0, 0, 0, 0, 0, 0)  # in a batch: the query runs in the tile kernels
 
-    def __init__(self, ctx: Context, queries: list, tile_rows_log2=16, wgs_per_cu=2, order=1, separate=1):
+
+class Batch:
+    """Many queries replayed as one captured graph (see hawk.h, batched execution).
+    variants: None, or one hawk_variant per query (TILE: the tile kernels)."""
+
+    def __init__(self, ctx: Context, queries: list, tile_rows_log2=16, wgs_per_cu=2, order=1, separate=1,
+                 variants=None):
         self.ctx = ctx
         self.queries = list(queries)  # the batch borrows them
         W = (ctypes.c_void_p * len(queries))(*[q.handle.value for q in queries])
+        V = None if variants is None else (hawk_variant * len(queries))(*variants)
         o = hawk_batch_opts(tile_rows_log2, wgs_per_cu, order, separate)
         h = ctypes.c_void_p()
-        check(L().hawk_batch_create(ctx.handle, W, len(queries), ctypes.byref(o), ctypes.byref(h)), ctx.handle)
+        check(L().hawk_batch_create(ctx.handle, W, len(queries), V, ctypes.byref(o), ctypes.byref(h)), ctx.handle)
         self.handle = h
 
     def free(self):

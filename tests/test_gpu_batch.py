@@ -127,3 +127,58 @@ def test_batch_view_orphaned_by_free(ctx):
     with pytest.raises(hawk.HawkError):
         r.info()
     r.free()
+
+
+def feasible_variants(ctx, h, rng, k):
+    """k variants drawn from the query's space that execute on their own
+    (a local table that cannot fit in LDS is infeasible for large group counts)."""
+    space = hawk.variant_space(h)
+    out = []
+    for i in rng.permutation(len(space)):
+        v = space[i]
+        try:
+            hawk.execute(ctx, h, v).free()
+        except hawk.HawkError as e:
+            if e.code == hawk.HAWK_E_INFEASIBLE:
+                continue
+            raise
+        out.append(v)
+        if len(out) == k:
+            break
+    return out
+
+
+def test_batch_per_query_variants(ctx):
+    """Every query in a variant of its own space (or in the tile kernels),
+    all in one graph: each result against the oracle over replays, after a
+    re-capture for another schedule, and with the same variants given again."""
+    say("batch: per-query variants")
+    qs, hs, refs = c5_setup(ctx, 18, 1_000_000, 1000, 1_000_000, seed=dg.MASTER_SEED + 60)
+    rng = np.random.default_rng(3)
+    variants = []
+    for n, h in enumerate(hs):
+        variants.append(hawk.TILE if n % 4 == 3 else feasible_variants(ctx, h, rng, 1)[0])
+    for q, v in zip(qs, variants):
+        say("kind", q["kind"], "rows", q["rows"], "tile" if v.thread_mult == 0 else hawk.format_variant(v))
+    b = hawk.Batch(ctx, hs, variants=variants, tile_rows_log2=15, wgs_per_cu=4, order=0)
+    for rep in range(2):
+        b.run()
+        check_batch(b, qs, refs, f"per-query variants, replay {rep}")
+    assert b.time(reps=2) > 0
+    best, _ = b.autotune(reps=1)
+    b.run()
+    check_batch(b, qs, refs, f"per-query variants, schedule {best}")
+    b.free()
+    # variants that the tile kernels do not have: cuckoo tables, global
+    # aggregation, sequential access, single-pass projection
+    special = []
+    for q, h in zip(qs, hs):
+        if q["kind"] == 1:
+            special.append(hawk.variant(proj_strategy=0, mem=0, pred=1))
+        else:
+            special.append(hawk.variant(agg_strategy=1, ht=1, hash=1, mem=0, pred=1, wg_size=512))
+    b = hawk.Batch(ctx, hs, variants=special)
+    b.run()
+    b.run()
+    check_batch(b, qs, refs, "cuckoo/global/sequential/single-pass")
+    b.free()
