@@ -352,7 +352,8 @@ def c5_pick_quality(ctx, te, te_h, ens, alg1, picker, train_stats, t_alg1, args,
                "confirm": "the search's best and every pick timed again (5 runs each) and compared on those times",
                "alg1_variants": {str(k): hawk.format_variant(v) for k, (v, _) in alg1.items()},
                "picker": "ensemble of 5 cost models (mean + 1 sd of predicted ln(ms)); Algorithm 1's variant for the "
-                         "query's kind unless the ensemble's pick is predicted faster at mean + 1 sd than it at its mean",
+                         "query's kind unless the ensemble's pick is predicted faster at mean + 1 sd than it at "
+                         "mean - 1 sd",
                "kernels": "compiled ahead of time (run-time compilation off for the whole evaluation)",
                "sum_best_ms": sum(r["best_ms"] for r in rows),
                "sum_best_sequential_ms": sorted(seq)[1],

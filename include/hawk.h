@@ -94,7 +94,7 @@ hawk_status hawk_table_register(hawk_ctx* ctx, const char* name, int64_t nrows,
 hawk_status hawk_table_unregister(hawk_ctx* ctx, int32_t table_id);
 
 /* ------------------------------------------------------------ pipeline programs */
-/* Pipeline operations of Section 3.1, Table 1 (CROSS_JOIN is not supported). */
+/* Pipeline operations of Section 3.1, Table 1. */
 enum {
   HAWK_LOOP = 1,           /* LOOP(T): iterate the rows of table `table` */
   HAWK_FILTER = 2,         /* FILTER(lo <= a <= hi) on a column of the looped table */
@@ -103,7 +103,11 @@ enum {
   HAWK_ARITHMETIC = 5,     /* ARITHMETIC: attribute `a` := x (arith_op) y, x = attr `b` or const `lo`, y = attr `c` or const `hi` */
   HAWK_AGGREGATE = 6,      /* AGGREGATE(F): non-grouped aggregation */
   HAWK_HASH_AGGREGATE = 7, /* HASH_AGGREGATE(G, F): group by attrs[0..nattrs) (1 or 2, at most 32-bit each) */
-  HAWK_PROJECT = 8         /* PROJECT(attrs): materialise attributes in input row order */
+  HAWK_PROJECT = 8,        /* PROJECT(attrs): materialise attributes in input row order */
+  HAWK_CROSS_JOIN = 9      /* CROSS_JOIN(T): table id `table`; every tuple is paired with every row of T
+                              (row-major: T's rows vary fastest); later operations see the columns of
+                              both tables (names must differ); one per main pipeline, after LOOP and
+                              FILTERs on the looped table, before probes; fewer than 2^32 pairs */
 };
 enum { HAWK_ADD = 1, HAWK_SUB = 2, HAWK_MUL = 3 };
 enum { HAWK_COUNT = 1, HAWK_SUM = 2, HAWK_MIN = 3, HAWK_MAX = 4, HAWK_AVG = 5 };
@@ -136,8 +140,8 @@ typedef struct { const hawk_op* ops; int32_t nops; } hawk_pipeline;
 
 /* A query is an ordered list of pipelines (Table 2): zero or more build
    pipelines (LOOP, FILTER*, HASH_PUT) followed by one main pipeline
-   (LOOP, FILTER*, HASH_PROBE*, ARITHMETIC*, then PROJECT | AGGREGATE |
-   HASH_AGGREGATE). The plan is validated here: names and types, build/probe
+   (LOOP, FILTER*, [CROSS_JOIN, FILTER*], HASH_PROBE*, ARITHMETIC*, then
+   PROJECT | AGGREGATE | HASH_AGGREGATE). The plan is validated here: names and types, build/probe
    pairing by `ht` (Section 5.1: a build and its probes share one table), and
    the kernel limits (12 columns, 6 filters, 4 probes, 8 arithmetic steps,
    8 aggregates, 4 projected attributes, 16 live attributes). The query keeps

@@ -11,7 +11,8 @@ the paper is silent are listed in the module docstring of ``hawk_oracle.cpp``
 and in the design notes):
 
 * projection: ``{"kind": "project", "rows": n, "cols": [int64 arrays]}``,
-  rows in ascending input order;
+  rows in ascending input order (with a CROSS_JOIN, ``spec["main"]["cross"]``:
+  ascending (row, second-table row) pairs);
 * aggregation: ``{"kind": "aggregate", "rows": g, "keys": [int64 arrays],
   "count": int64 array, "aggs": [array per aggregate]}`` sorted by group key;
   SUM/COUNT/MIN/MAX are int64 arrays (wide SUMs: Python ``int`` object
@@ -72,6 +73,8 @@ class _Agg(ctypes.Structure):
 class _Main(ctypes.Structure):
     _fields_ = [("nrows", ctypes.c_int64), ("cols", ctypes.POINTER(_Col)), ("ncols", ctypes.c_int32),
                 ("nfilters", ctypes.c_int32), ("filters", ctypes.POINTER(_Filter)),
+                ("inner_nrows", ctypes.c_int64), ("inner_cols", ctypes.POINTER(_Col)), ("ninner", ctypes.c_int32),
+                ("nfilters2", ctypes.c_int32), ("filters2", ctypes.POINTER(_Filter)),
                 ("nprobes", ctypes.c_int32), ("probes", ctypes.POINTER(_Probe)),
                 ("narith", ctypes.c_int32), ("arith", ctypes.POINTER(_Arith)),
                 ("kind", ctypes.c_int32),
@@ -149,9 +152,18 @@ def run(tables: dict, spec: dict, threads: int = 1) -> dict:
     m = spec["main"]
     names, cols, nrows = _cols(tables[m["table"]], keep)
     attrs = list(names)
+    # CROSS_JOIN: the second table's columns follow the looped table's
+    inner_names, inner_cols, inner_n = [], (_Col * 1)(), 0
+    if m.get("cross"):
+        inner_names, inner_cols, inner_n = _cols(tables[m["cross"]], keep)
+        attrs += inner_names
+    keep.append(inner_cols)
+    f2 = m.get("cross_filters", [])
+    fs2 = (_Filter * max(1, len(f2)))(*[_Filter(attrs.index(c), 0, int(lo), int(hi)) for c, lo, hi in f2])
+    keep.append(fs2)
     probes = []
     for fk, bi, pname in m.get("probes", []):
-        probes.append(_Probe(names.index(fk), bi))
+        probes.append(_Probe(attrs.index(fk), bi))
         attrs.append(pname)
     ariths = []
     for out, op, x, y in m.get("arith", []):
@@ -171,7 +183,8 @@ def run(tables: dict, spec: dict, threads: int = 1) -> dict:
     projarr = (ctypes.c_int32 * max(1, len(proj)))(*proj)
     grparr = (ctypes.c_int32 * max(1, len(group)))(*group)
     aggarr = (_Agg * max(1, len(aggs)))(*[_Agg(f, a, w, 0) for f, a, w in aggs])
-    main = _Main(nrows, cols, len(names), len(fl), fs, len(probes), parr, len(ariths), aarr,
+    main = _Main(nrows, cols, len(names), len(fl), fs, inner_n, inner_cols, len(inner_names), len(f2), fs2,
+                 len(probes), parr, len(ariths), aarr,
                  1 if is_proj else 2, len(proj), projarr, len(group), grparr, len(aggs), aggarr)
     h = ctypes.c_void_p()
     if threads > 1:

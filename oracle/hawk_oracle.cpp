@@ -5,6 +5,9 @@
 //   LOOP           -> selection vector of all row ids, ascending
 //   FILTER         -> keep ids whose attribute lies in [lo, hi] (conjunction,
 //                     one predicate after the other)
+//   CROSS_JOIN     -> every surviving id paired with every row of the second
+//                     table (row-major: the second table's rows vary fastest);
+//                     later operations see pairs (FILTER again on either side)
 //   HASH_PUT       -> build pipeline: filter the dimension, then an ordered
 //                     map key -> payload (a repeated key is an error)
 //   HASH_PROBE     -> inner equi-join: keep ids whose key is in the map and
@@ -105,38 +108,72 @@ std::vector<i128> agg_init(const orc_main* m) {
 
 int32_t run_main(const BuildTables& tables, int32_t nbuilds, const orc_main* m, int64_t r0, int64_t r1, Part& out) {
   std::vector<int64_t> sv = select(r0, r1, m->cols, m->nfilters, m->filters);
-  const int32_t nattr = m->ncols + m->nprobes + m->narith;
-  // computed attributes, materialised over the selection vector
+  // row of the looped table and (CROSS_JOIN) of the second table, per tuple
+  std::vector<int64_t> po, pi;
+  if (m->ninner > 0) {
+    for (int64_t i : sv)
+      for (int64_t j = 0; j < m->inner_nrows; ++j) {
+        po.push_back(i);
+        pi.push_back(j);
+      }
+    // FILTERs after the CROSS_JOIN, one conjunct at a time over the pairs
+    for (int32_t k = 0; k < m->nfilters2; ++k) {
+      const orc_filter& F = m->filters2[k];
+      std::vector<int64_t> no, ni;
+      for (size_t t = 0; t < po.size(); ++t) {
+        const int64_t x = F.col < m->ncols ? load(m->cols[F.col], po[t]) : load(m->inner_cols[F.col - m->ncols], pi[t]);
+        if (x >= F.lo && x <= F.hi) {
+          no.push_back(po[t]);
+          ni.push_back(pi[t]);
+        }
+      }
+      po.swap(no);
+      pi.swap(ni);
+    }
+  } else {
+    po.swap(sv);
+  }
+  const int32_t ntab = m->ncols + m->ninner;  // table attributes
+  const int32_t nattr = ntab + m->nprobes + m->narith;
+  auto tab = [&](int32_t a, size_t j) -> int64_t {
+    return a < m->ncols ? load(m->cols[a], po[j]) : load(m->inner_cols[a - m->ncols], pi[j]);
+  };
+  // computed attributes, materialised over the tuples
   std::vector<std::vector<int64_t>> comp(static_cast<size_t>(m->nprobes + m->narith));
   for (int32_t p = 0; p < m->nprobes; ++p) {
     const orc_probe& P = m->probes[p];
-    if (P.build < 0 || P.build >= nbuilds) return ORC_E_ARG;
+    if (P.build < 0 || P.build >= nbuilds || P.fk_col < 0 || P.fk_col >= ntab) return ORC_E_ARG;
     const auto& T = tables[P.build];
-    std::vector<int64_t> keep;
     std::vector<size_t> pos;
     std::vector<int64_t> pay;
-    for (size_t j = 0; j < sv.size(); ++j) {
-      auto it = T.find(load(m->cols[P.fk_col], sv[j]));
-      if (it != T.end()) { keep.push_back(sv[j]); pos.push_back(j); pay.push_back(it->second); }
+    for (size_t j = 0; j < po.size(); ++j) {
+      auto it = T.find(tab(P.fk_col, j));
+      if (it != T.end()) { pos.push_back(j); pay.push_back(it->second); }
     }
-    // earlier payloads follow the shrinking selection vector
+    // the tuples and earlier payloads follow the shrinking selection
+    std::vector<int64_t> no(pos.size()), ni(m->ninner > 0 ? pos.size() : 0);
+    for (size_t j = 0; j < pos.size(); ++j) {
+      no[j] = po[pos[j]];
+      if (m->ninner > 0) ni[j] = pi[pos[j]];
+    }
+    po.swap(no);
+    pi.swap(ni);
     for (int32_t q = 0; q < p; ++q) {
       std::vector<int64_t> v(pos.size());
       for (size_t j = 0; j < pos.size(); ++j) v[j] = comp[q][pos[j]];
       comp[q].swap(v);
     }
     comp[p].swap(pay);
-    sv.swap(keep);
   }
   auto attr = [&](int32_t a, size_t j) -> int64_t {
-    if (a < m->ncols) return load(m->cols[a], sv[j]);
-    return comp[a - m->ncols][j];
+    if (a < ntab) return tab(a, j);
+    return comp[a - ntab][j];
   };
   for (int32_t k = 0; k < m->narith; ++k) {
     const orc_arith& A = m->arith[k];
     std::vector<int64_t>& dst = comp[m->nprobes + k];
-    dst.resize(sv.size());
-    for (size_t j = 0; j < sv.size(); ++j) {
+    dst.resize(po.size());
+    for (size_t j = 0; j < po.size(); ++j) {
       uint64_t x = static_cast<uint64_t>(A.x_const ? A.xc : attr(A.x, j));
       uint64_t y = static_cast<uint64_t>(A.y_const ? A.yc : attr(A.y, j));
       uint64_t r = A.op == ORC_ADD ? x + y : A.op == ORC_SUB ? x - y : x * y;
@@ -147,15 +184,15 @@ int32_t run_main(const BuildTables& tables, int32_t nbuilds, const orc_main* m, 
     out.proj.resize(static_cast<size_t>(m->nproj));
     for (int32_t c = 0; c < m->nproj; ++c) {
       if (m->proj[c] < 0 || m->proj[c] >= nattr) return ORC_E_ARG;
-      out.proj[c].resize(sv.size());
-      for (size_t j = 0; j < sv.size(); ++j) out.proj[c][j] = attr(m->proj[c], j);
+      out.proj[c].resize(po.size());
+      for (size_t j = 0; j < po.size(); ++j) out.proj[c][j] = attr(m->proj[c], j);
     }
   } else {
     Groups& groups = out.groups;
     const std::vector<i128> init = agg_init(m);
     if (m->ngroup == 0) groups[std::vector<int64_t>()].v = init;  // AGGREGATE: one row even when empty
     std::vector<int64_t> key(static_cast<size_t>(m->ngroup));
-    for (size_t j = 0; j < sv.size(); ++j) {
+    for (size_t j = 0; j < po.size(); ++j) {
       for (int32_t g = 0; g < m->ngroup; ++g) key[g] = attr(m->group[g], j);
       auto it = groups.find(key);
       if (it == groups.end()) { it = groups.emplace(key, Acc()).first; it->second.v = init; }

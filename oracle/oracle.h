@@ -32,15 +32,20 @@ typedef struct {
   int32_t key_col; int32_t payload_col;
 } orc_build;
 
-/* Attribute ids of the main pipeline: [0, ncols) table columns, then one per
-   probe (its payload), then one per arithmetic step (its output). */
+/* Attribute ids of the main pipeline: [0, ncols) table columns, then
+   [ncols, ncols + ninner) the columns of the CROSS_JOIN table (if any), then
+   one per probe (its payload), then one per arithmetic step (its output). */
 typedef struct { int32_t fk_col; int32_t build; } orc_probe;
 typedef struct { int32_t op; int32_t x_const, y_const; int32_t x, y; int32_t pad; int64_t xc, yc; } orc_arith;
 typedef struct { int32_t fn; int32_t attr; int32_t wide; int32_t pad; } orc_agg;
 
 typedef struct {
   int64_t nrows; const orc_col* cols; int32_t ncols;
-  int32_t nfilters; const orc_filter* filters;
+  int32_t nfilters; const orc_filter* filters;       /* FILTERs before the CROSS_JOIN (table columns) */
+  /* CROSS_JOIN (Table 1): every surviving row is paired with every row of a
+     second table, in row-major order; ninner = 0: no CROSS_JOIN */
+  int64_t inner_nrows; const orc_col* inner_cols; int32_t ninner;
+  int32_t nfilters2; const orc_filter* filters2;     /* FILTERs after it (either table's columns) */
   int32_t nprobes; const orc_probe* probes;
   int32_t narith; const orc_arith* arith;
   int32_t kind;

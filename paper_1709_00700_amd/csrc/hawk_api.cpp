@@ -337,6 +337,7 @@ namespace {
 struct Lowering {
   hawk_ctx* ctx;
   const TableReg* table = nullptr;
+  const TableReg* inner = nullptr;  // the CROSS_JOIN table (its columns load with side 2)
   HkPlan P;
   int nreg = 0;
   // attribute name -> register; columns are loaded on first use
@@ -348,6 +349,12 @@ struct Lowering {
   int find_col(const std::string& nm) const {
     for (size_t i = 0; i < table->cols.size(); ++i)
       if (table->cols[i].name == nm) return static_cast<int>(i);
+    return -1;
+  }
+  int find_inner(const std::string& nm) const {
+    if (!inner) return -1;
+    for (size_t i = 0; i < inner->cols.size(); ++i)
+      if (inner->cols[i].name == nm) return static_cast<int>(i);
     return -1;
   }
   // register holding `nm`, loading the column in `phase` (0 = A, 1 = B, 2 = C) if needed
@@ -362,9 +369,13 @@ struct Lowering {
       return HAWK_OK;
     }
     int c = find_col(nm);
-    if (c < 0) return set_error(ctx, HAWK_E_NOTFOUND, std::string("unknown attribute ") + nm);
+    const int ci = find_inner(nm);
+    if (c >= 0 && ci >= 0)
+      return set_error(ctx, HAWK_E_PLAN, std::string("attribute in both tables of the CROSS_JOIN: ") + nm);
+    if (c < 0 && ci < 0) return set_error(ctx, HAWK_E_NOTFOUND, std::string("unknown attribute ") + nm);
     if (nreg >= HK_NREG) return set_error(ctx, HAWK_E_PLAN, "more than 16 live attributes");
-    HkCol col = {table->cols[c].ptr, table->cols[c].dtype, nreg};
+    const ColReg& cr = c >= 0 ? table->cols[c] : inner->cols[ci];
+    HkCol col = {cr.ptr, static_cast<int16_t>(cr.dtype), static_cast<int16_t>(!inner ? 0 : (c >= 0 ? 1 : 2)), nreg};
     if (phase == 0) {
       if (P.ncolA >= HK_MAX_COLS_A) return set_error(ctx, HAWK_E_PLAN, "too many filter columns");
       P.colA[P.ncolA++] = col;  // read by its filter; live once read again (above)
@@ -376,13 +387,13 @@ struct Lowering {
       P.colC[P.ncolC++] = col;
     }
     reg_of[nm] = nreg;
-    dtype_of[nm] = table->cols[c].dtype;
+    dtype_of[nm] = cr.dtype;
     *reg = nreg++;
     return HAWK_OK;
   }
   hawk_status new_attr(const char* nm, int dtype, int* reg) {
     if (!nm) return set_error(ctx, HAWK_E_ARG, "missing attribute name");
-    if (reg_of.count(nm) || find_col(nm) >= 0)
+    if (reg_of.count(nm) || find_col(nm) >= 0 || find_inner(nm) >= 0)
       return set_error(ctx, HAWK_E_PLAN, std::string("attribute defined twice: ") + nm);
     if (nreg >= HK_NREG) return set_error(ctx, HAWK_E_PLAN, "more than 16 live attributes");
     reg_of[nm] = nreg;
@@ -405,7 +416,8 @@ hawk_status lower_loop(hawk_ctx* ctx, const hawk_pipeline& p, Lowering& L) {
 
 hawk_status lower_filter(hawk_ctx* ctx, const hawk_op& op, Lowering& L) {
   if (L.P.nfilters >= HK_MAX_FILTERS) return set_error(ctx, HAWK_E_PLAN, "too many filters");
-  if (L.find_col(op.a ? op.a : "") < 0)
+  // a column of the looped table, or (after a CROSS_JOIN) of the second table
+  if (L.find_col(op.a ? op.a : "") < 0 && L.find_inner(op.a ? op.a : "") < 0)
     return set_error(ctx, HAWK_E_NOTFOUND, std::string("FILTER on unknown column ") + (op.a ? op.a : "(null)"));
   int reg;
   hawk_status st = L.attr(op.a, 0, &reg);
@@ -445,8 +457,8 @@ extern "C" hawk_status hawk_query_create(hawk_ctx* ctx, const hawk_pipeline* pip
           st = set_error(ctx, HAWK_E_TYPE, "HASH_PUT key and payload must be at most 32-bit");
         else if (build_of_ht.count(op.ht)) st = set_error(ctx, HAWK_E_PLAN, "hash table built twice");
         else {
-          B.key = {L.table->cols[kc].ptr, L.table->cols[kc].dtype, 0};
-          B.payload = {L.table->cols[pc].ptr, L.table->cols[pc].dtype, 0};
+          B.key = {L.table->cols[kc].ptr, static_cast<int16_t>(L.table->cols[kc].dtype), 0, 0};
+          B.payload = {L.table->cols[pc].ptr, static_cast<int16_t>(L.table->cols[pc].dtype), 0, 0};
           B.payload_dtype = L.table->cols[pc].dtype;
           B.ht_id = op.ht;
           put = true;
@@ -478,15 +490,40 @@ extern "C" hawk_status hawk_query_create(hawk_ctx* ctx, const hawk_pipeline* pip
         if (stage > 0) st = set_error(ctx, HAWK_E_PLAN, "FILTER after HASH_PROBE/ARITHMETIC is not supported");
         else st = lower_filter(ctx, op, L);
         break;
+      case HAWK_CROSS_JOIN: {
+        // the pipeline now loops over the product of its table and this one
+        if (stage > 0 || L.inner) { st = set_error(ctx, HAWK_E_PLAN, "one CROSS_JOIN, before probes and arithmetic"); break; }
+        if (op.table < 0 || op.table >= static_cast<int32_t>(ctx->tables.size()) || !ctx->tables[op.table].live) {
+          st = set_error(ctx, HAWK_E_NOTFOUND, "CROSS_JOIN of an unknown table");
+          break;
+        }
+        const TableReg* u = &ctx->tables[op.table];
+        for (const auto& c : u->cols)
+          if (L.find_col(c.name) >= 0) { st = set_error(ctx, HAWK_E_PLAN, "column name in both tables of the CROSS_JOIN: " + c.name); break; }
+        if (st) break;
+        const uint64_t prod = static_cast<uint64_t>(L.P.nrows) * static_cast<uint64_t>(u->nrows);
+        if (prod >= (uint64_t(1) << 32)) { st = set_error(ctx, HAWK_E_PLAN, "CROSS_JOIN of 2^32 or more pairs"); break; }
+        L.inner = u;
+        // columns loaded so far (filters on the looped table) address its rows
+        for (int c = 0; c < L.P.ncolA; ++c) L.P.colA[c].side = 1;
+        L.P.xinner = static_cast<uint32_t>(u->nrows);
+        L.P.xmagic = u->nrows > 1 ? ~0ull / static_cast<uint64_t>(u->nrows) + 1 : 0;
+        L.P.nrows = static_cast<int64_t>(prod);
+        break;
+      }
       case HAWK_HASH_PROBE: {
         if (stage > 1) { st = set_error(ctx, HAWK_E_PLAN, "HASH_PROBE after ARITHMETIC"); break; }
         stage = 1;
         auto it = build_of_ht.find(op.ht);
         if (it == build_of_ht.end()) { st = set_error(ctx, HAWK_E_PLAN, "HASH_PROBE of a table no pipeline builds"); break; }
         if (L.P.nprobes >= HK_MAX_PROBES) { st = set_error(ctx, HAWK_E_PLAN, "too many probes"); break; }
-        int c = L.find_col(op.a ? op.a : "");
-        if (c < 0) { st = set_error(ctx, HAWK_E_NOTFOUND, "HASH_PROBE on unknown column"); break; }
-        if (L.table->cols[c].dtype == HAWK_I64) { st = set_error(ctx, HAWK_E_TYPE, "join keys are at most 32-bit"); break; }
+        // the key is a column of the looped table or (after a CROSS_JOIN) of the second one
+        const int c = L.find_col(op.a ? op.a : ""), ci = L.find_inner(op.a ? op.a : "");
+        if (c < 0 && ci < 0) { st = set_error(ctx, HAWK_E_NOTFOUND, "HASH_PROBE on unknown column"); break; }
+        if ((c >= 0 ? L.table->cols[c] : L.inner->cols[ci]).dtype == HAWK_I64) {
+          st = set_error(ctx, HAWK_E_TYPE, "join keys are at most 32-bit");
+          break;
+        }
         int fk, pay;
         if ((st = L.attr(op.a, 1, &fk))) break;
         if ((st = L.new_attr(op.b, q->builds[it->second].payload_dtype, &pay))) break;
@@ -576,9 +613,9 @@ extern "C" hawk_status hawk_query_create(hawk_ctx* ctx, const hawk_pipeline* pip
   if (st) { delete q; return st; }
   // unused column slots read the context's zero block, so kernels may load
   // every slot of their shape class without a per-slot condition
-  for (int c = L.P.ncolA; c < HK_MAX_COLS_A; ++c) L.P.colA[c] = HkCol{ctx->dummy, HK_T_I64, 0};
-  for (int c = L.P.ncolB; c < HK_MAX_COLS_B; ++c) L.P.colB[c] = HkCol{ctx->dummy, HK_T_I64, 0};
-  for (int c = L.P.ncolC; c < HK_MAX_COLS_C; ++c) L.P.colC[c] = HkCol{ctx->dummy, HK_T_I64, 0};
+  for (int c = L.P.ncolA; c < HK_MAX_COLS_A; ++c) L.P.colA[c] = HkCol{ctx->dummy, HK_T_I64, 0, 0};
+  for (int c = L.P.ncolB; c < HK_MAX_COLS_B; ++c) L.P.colB[c] = HkCol{ctx->dummy, HK_T_I64, 0, 0};
+  for (int c = L.P.ncolC; c < HK_MAX_COLS_C; ++c) L.P.colC[c] = HkCol{ctx->dummy, HK_T_I64, 0, 0};
   q->main = L.P;
   q->has_table = L.P.nprobes > 0 || L.P.ngroup > 0;
   ctx->queries.insert(q);
@@ -829,7 +866,7 @@ hipError_t agg_kernel_launch(hawk_ctx* ctx, hipStream_t st, const hawk_variant* 
                              const HkAggTable& T, const AggConfig& c, const uint64_t* ident, int32_t W, int* err,
                              const HkSpill* sp, bool allow_jit) {
   const int32_t wg = static_cast<int32_t>(v->wg_size);
-  if (allow_jit && ctx->jit && v->ht == HAWK_LINEAR_PROBING) {
+  if (allow_jit && ctx->jit && v->ht == HAWK_LINEAR_PROBING && P.xinner == 0) {
     HkIdent id = {};
     for (int i = 0; i < W; ++i) id.w[i] = ident[i];
     id.nw = W;
@@ -1417,7 +1454,8 @@ extern "C" hawk_status hawk_execute_noalloc(hawk_ctx* ctx, const hawk_query* q, 
 // Compiles the run-time kernel that executing (q, v) will launch, so that a
 // timed run measures the kernels and not the compiler.
 static hawk_status prepare_run_time_kernel(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v) {
-  if (!ctx->jit || q->kind == 1 || q->main.ngroup == 0 || v->ht != HAWK_LINEAR_PROBING) return HAWK_OK;
+  if (!ctx->jit || q->kind == 1 || q->main.ngroup == 0 || v->ht != HAWK_LINEAR_PROBING || q->main.xinner > 0)
+    return HAWK_OK;  // (plans with a CROSS_JOIN run the kernels compiled ahead of time)
   if (v->wg_size < 1 || v->wg_size > 1024 || v->thread_mult < 1) return HAWK_OK;  // execution reports it
   HkAggTable T{};
   T.slot_words = q->main.slot_words;

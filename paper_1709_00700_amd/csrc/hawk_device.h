@@ -43,6 +43,18 @@ __device__ __forceinline__ int64_t raw_value(const HkCol& c, int64_t row, const 
   return static_cast<int64_t>((v.w >> sh) << top) >> top;
 }
 
+// The row of a column's own table behind pipeline row v. With a CROSS_JOIN
+// (kernels of a class that handles one), v runs over the product in
+// row-major order: v / xinner on the looped table, v % xinner on the second
+// (quotient by multiplication with the rounded-up reciprocal, exact for
+// 32-bit v: Lemire, Kaser and Kurz, "Faster remainder by direct computation").
+template <class S>
+__device__ __forceinline__ int64_t xrow(const HkPlan& P, const HkCol& c, int64_t v) {
+  if (!S::cross || P.xinner == 0 || c.side == 0) return v;
+  const uint64_t q = P.xinner == 1 ? static_cast<uint64_t>(v) : __umul64hi(P.xmagic, static_cast<uint64_t>(v));
+  return c.side == 1 ? static_cast<int64_t>(q) : v - static_cast<int64_t>(q) * P.xinner;
+}
+
 // Murmur3 64-bit finaliser (Appleby, public domain).
 __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
   k ^= k >> 33;
@@ -228,11 +240,11 @@ struct HkFirst {
 template <class S>
 __device__ __forceinline__ void fetch_first(const HkPlan& P, int64_t row, HkFirst<S>& f) {
 #pragma unroll
-  for (int c = 0; c < HkFirst<S>::A; ++c) load_raw(P.colA[c], c < P.ncolA ? row : 0, f.a[c]);
+  for (int c = 0; c < HkFirst<S>::A; ++c) load_raw(P.colA[c], xrow<S>(P, P.colA[c], c < P.ncolA ? row : 0), f.a[c]);
 #pragma unroll
-  for (int c = 0; c < HkFirst<S>::B; ++c) load_raw(P.colB[c], c < P.ncolB ? row : 0, f.b[c]);
+  for (int c = 0; c < HkFirst<S>::B; ++c) load_raw(P.colB[c], xrow<S>(P, P.colB[c], c < P.ncolB ? row : 0), f.b[c]);
 #pragma unroll
-  for (int c = 0; c < HkFirst<S>::C; ++c) load_raw(P.colC[c], c < P.ncolC ? row : 0, f.c[c]);
+  for (int c = 0; c < HkFirst<S>::C; ++c) load_raw(P.colC[c], xrow<S>(P, P.colC[c], c < P.ncolC ? row : 0), f.c[c]);
 }
 
 // Pushes one row through LOOP's loads, FILTER, HASH_PROBE and (if VALUES)
@@ -249,11 +261,11 @@ __device__ __forceinline__ bool eval_row_f(const HkPlan& P, int64_t row, const H
     for (int c = 0; c < S::colA; ++c)
       if (c < P.ncolA) {
         if (PRE) la[c] = f.a[c];
-        else load_raw(P.colA[c], row, la[c]);
+        else load_raw(P.colA[c], xrow<S>(P, P.colA[c], row), la[c]);
       }
 #pragma unroll
     for (int c = 0; c < S::colA; ++c)
-      if (c < P.ncolA) r[P.colA[c].reg] = raw_value(P.colA[c], row, la[c]);
+      if (c < P.ncolA) r[P.colA[c].reg] = raw_value(P.colA[c], xrow<S>(P, P.colA[c], row), la[c]);
   }
   bool pass = true;
 #pragma unroll
@@ -269,11 +281,11 @@ __device__ __forceinline__ bool eval_row_f(const HkPlan& P, int64_t row, const H
     for (int c = 0; c < S::colB; ++c)
       if (c < P.ncolB) {
         if (PRE && c < HkFirst<S>::B) lb[c] = f.b[c < HkFirst<S>::B ? c : 0];
-        else load_raw(P.colB[c], row, lb[c]);
+        else load_raw(P.colB[c], xrow<S>(P, P.colB[c], row), lb[c]);
       }
 #pragma unroll
     for (int c = 0; c < S::colB; ++c)
-      if (c < P.ncolB) r[P.colB[c].reg] = raw_value(P.colB[c], row, lb[c]);
+      if (c < P.ncolB) r[P.colB[c].reg] = raw_value(P.colB[c], xrow<S>(P, P.colB[c], row), lb[c]);
   }
 #pragma unroll
   for (int p = 0; p < S::probes; ++p) {
@@ -291,11 +303,11 @@ __device__ __forceinline__ bool eval_row_f(const HkPlan& P, int64_t row, const H
     for (int c = 0; c < S::colC; ++c)
       if (c < P.ncolC) {
         if (PRE && c < HkFirst<S>::C) lc[c] = f.c[c < HkFirst<S>::C ? c : 0];
-        else load_raw(P.colC[c], row, lc[c]);
+        else load_raw(P.colC[c], xrow<S>(P, P.colC[c], row), lc[c]);
       }
 #pragma unroll
     for (int c = 0; c < S::colC; ++c)
-      if (c < P.ncolC) r[P.colC[c].reg] = raw_value(P.colC[c], row, lc[c]);
+      if (c < P.ncolC) r[P.colC[c].reg] = raw_value(P.colC[c], xrow<S>(P, P.colC[c], row), lc[c]);
   }
 #pragma unroll
   for (int k = 0; k < S::arith; ++k) {
@@ -320,11 +332,11 @@ template <class S>
 __device__ __forceinline__ void fetch_all(const HkPlan& P, int64_t row, HkAll<S>& f) {
   // a filter-only column reads row 0 (one line for the whole wave) instead
 #pragma unroll
-  for (int c = 0; c < S::colA; ++c) load_raw(P.colA[c], c < P.ncolA && ((P.liveA >> c) & 1u) ? row : 0, f.a[c]);
+  for (int c = 0; c < S::colA; ++c) load_raw(P.colA[c], xrow<S>(P, P.colA[c], c < P.ncolA && ((P.liveA >> c) & 1u) ? row : 0), f.a[c]);
 #pragma unroll
-  for (int c = 0; c < S::colB; ++c) load_raw(P.colB[c], c < P.ncolB ? row : 0, f.b[c]);
+  for (int c = 0; c < S::colB; ++c) load_raw(P.colB[c], xrow<S>(P, P.colB[c], c < P.ncolB ? row : 0), f.b[c]);
 #pragma unroll
-  for (int c = 0; c < S::colC; ++c) load_raw(P.colC[c], c < P.ncolC ? row : 0, f.c[c]);
+  for (int c = 0; c < S::colC; ++c) load_raw(P.colC[c], xrow<S>(P, P.colC[c], c < P.ncolC ? row : 0), f.c[c]);
 }
 
 // A row known to pass (its filters held and its probes found their keys):
@@ -334,10 +346,10 @@ template <int HT, int HASH, class S>
 __device__ __forceinline__ void eval_passing_row(const HkPlan& P, int64_t row, const HkAll<S>& f, v16i64& r) {
 #pragma unroll
   for (int c = 0; c < S::colA; ++c)
-    if (c < P.ncolA && ((P.liveA >> c) & 1u)) r[P.colA[c].reg] = raw_value(P.colA[c], row, f.a[c]);
+    if (c < P.ncolA && ((P.liveA >> c) & 1u)) r[P.colA[c].reg] = raw_value(P.colA[c], xrow<S>(P, P.colA[c], row), f.a[c]);
 #pragma unroll
   for (int c = 0; c < S::colB; ++c)
-    if (c < P.ncolB) r[P.colB[c].reg] = raw_value(P.colB[c], row, f.b[c]);
+    if (c < P.ncolB) r[P.colB[c].reg] = raw_value(P.colB[c], xrow<S>(P, P.colB[c], row), f.b[c]);
 #pragma unroll
   for (int p = 0; p < S::probes; ++p) {
     if (p >= P.nprobes) break;
@@ -347,7 +359,7 @@ __device__ __forceinline__ void eval_passing_row(const HkPlan& P, int64_t row, c
   }
 #pragma unroll
   for (int c = 0; c < S::colC; ++c)
-    if (c < P.ncolC) r[P.colC[c].reg] = raw_value(P.colC[c], row, f.c[c]);
+    if (c < P.ncolC) r[P.colC[c].reg] = raw_value(P.colC[c], xrow<S>(P, P.colC[c], row), f.c[c]);
 #pragma unroll
   for (int k = 0; k < S::arith; ++k) {
     if (k >= P.narith) break;

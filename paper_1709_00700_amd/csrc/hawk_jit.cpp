@@ -17,7 +17,8 @@ namespace {
 
 void emit_col(std::ostringstream& o, const char* arr, int c, const HkCol& col) {
   o << "  P." << arr << "[" << c << "].ptr = Prt." << arr << "[" << c << "].ptr; P." << arr << "[" << c
-    << "].dtype = " << col.dtype << "; P." << arr << "[" << c << "].reg = " << col.reg << ";\n";
+    << "].dtype = " << col.dtype << "; P." << arr << "[" << c << "].side = " << col.side << "; P." << arr << "["
+    << c << "].reg = " << col.reg << ";\n";
 }
 
 }  // namespace

@@ -12,6 +12,7 @@
 // compiled at run time (hipRTC): fixed-width types come from the runtime's own header
 typedef __hip_internal::int8_t int8_t;
 typedef __hip_internal::uint8_t uint8_t;
+typedef __hip_internal::int16_t int16_t;
 typedef __hip_internal::int32_t int32_t;
 typedef __hip_internal::uint32_t uint32_t;
 typedef __hip_internal::int64_t int64_t;
@@ -51,7 +52,9 @@ enum { HK_COUNT = 1, HK_SUM = 2, HK_MIN = 3, HK_MAX = 4, HK_AVG = 5 };
 // (HK_ERR_TIMEOUT: a bounded wait for another workgroup's result gave up)
 enum { HK_ERR_CAPACITY = 1, HK_ERR_DUPKEY = 2, HK_ERR_CUCKOO = 4, HK_ERR_TIMEOUT = 8 };
 
-struct HkCol { const void* ptr; int32_t dtype; int32_t reg; };
+// a column load into register `reg`; side: 0 = the looped table's row,
+// with a CROSS_JOIN 1 = its row of the looped table, 2 = its row of the second table
+struct HkCol { const void* ptr; int16_t dtype; int16_t side; int32_t reg; };
 struct HkFilter { int64_t lo, hi; int32_t reg; int32_t pad; };
 // hash functions of one query: murmur xor keys or multiply-shift odd multipliers
 struct HkHash { uint64_t a[HK_CUCKOO_D]; };
@@ -84,6 +87,12 @@ struct HkPlan {
   // bit c: colA[c] is read after the filters (a column that only a filter
   // reads is not loaded again for rows already known to pass)
   uint32_t liveA;
+  // CROSS_JOIN (Table 1): xinner > 0 rows of a second table; nrows is then the
+  // product and row v stands for row v / xinner of the looped table and row
+  // v % xinner of the second (xmagic = 2^64 / xinner rounded up: the quotient
+  // of a 32-bit v is the high word of xmagic * v)
+  uint32_t xinner;
+  uint64_t xmagic;
 };
 
 // a build pipeline (LOOP, FILTER, HASH_PUT): filter part, key and payload columns, target table
@@ -97,16 +106,17 @@ struct HkBuild {
 // instantiated for a class touches only the plan fields that class can use,
 // so those fields stay in scalar registers for the whole row loop. The
 // dispatcher picks the smallest class that holds the plan (hk_shape_of).
-template <int A, int F, int B, int PR, int C, int AR, int AG, int PJ>
+template <int A, int F, int B, int PR, int C, int AR, int AG, int PJ, int X = 0>
 struct HkShape {
   static constexpr int colA = A, filters = F, colB = B, probes = PR, colC = C, arith = AR, aggs = AG, proj = PJ;
+  static constexpr int cross = X;  // 1: handles plans with a CROSS_JOIN
 };
 using HkShapeA = HkShape<0, 0, 0, 0, 2, 0, 4, 0>;   // group-aggregate of value columns (no filters, joins, arithmetic)
 using HkShapeF = HkShape<2, 2, 0, 0, 3, 2, 4, 2>;   // filters, a little arithmetic, projection or aggregation
 using HkShapeJ = HkShape<0, 0, 4, 4, 1, 0, 2, 2>;   // joins: up to 4 probes
 using HkShapeW = HkShape<0, 0, 0, 0, 6, 4, 8, 2>;   // wide: many value columns, arithmetic steps, aggregates
 using HkShapeG = HkShape<HK_MAX_COLS_A, HK_MAX_FILTERS, HK_MAX_COLS_B, HK_MAX_PROBES, HK_MAX_COLS_C, HK_MAX_ARITH,
-                         HK_MAX_AGGS, HK_MAX_PROJ>;   // anything the plan format allows
+                         HK_MAX_AGGS, HK_MAX_PROJ, 1>;   // anything the plan format allows, CROSS_JOIN included
 enum { HK_SHAPE_A = 0, HK_SHAPE_F = 1, HK_SHAPE_J = 2, HK_SHAPE_W = 3, HK_SHAPE_G = 4 };
 
 template <class S>
@@ -115,6 +125,7 @@ inline bool hk_fits(const HkPlan& P) {
          P.ncolC <= S::colC && P.narith <= S::arith && P.naggs <= S::aggs && P.nproj <= S::proj;
 }
 inline int hk_shape_of(const HkPlan& P) {
+  if (P.xinner > 0) return HK_SHAPE_G;
   if (hk_fits<HkShapeA>(P)) return HK_SHAPE_A;
   if (hk_fits<HkShapeF>(P)) return HK_SHAPE_F;
   if (hk_fits<HkShapeJ>(P)) return HK_SHAPE_J;

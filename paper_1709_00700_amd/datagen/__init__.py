@@ -11,6 +11,7 @@ Query description ("spec"), consumed by ``oracle`` and by the library binding:
                  "key": col, "payload": col}, ...],          # HASH_PUT pipelines
      "main": {"table": str,
               "filters": [(col, lo, hi), ...],                # lo <= col <= hi, conjunctive
+              "cross": str, "cross_filters": [(col, lo, hi), ...],  # optional CROSS_JOIN, then FILTERs
               "probes": [(fk_col, build_index, payload_name), ...],
               "arith": [(out_name, "add"|"sub"|"mul", x, y), ...],  # x, y: attr name or int
               "project": [attr, ...],                         # projection pipeline, or
@@ -222,6 +223,33 @@ def c4_wide(n=FULL_ROWS["c4"], seed=MASTER_SEED, price_hi=100_001):
                               ("max", "disc", False), ("avg", "qty", False)],
                      "groups_hint": 6}}
     return {"t": t}, spec
+
+
+def cross_join(n=20_000, m=64, nd=40, seed=MASTER_SEED, sink="project"):
+    """A pipeline with a CROSS_JOIN (Table 1): rows of `t` that pass a filter,
+    paired with every row of the small table `u`, a band filter on the pair
+    (u.b within range, t.a again), a probe keyed by u.fk into dimension `d`,
+    arithmetic over both sides; sink "project" (ab, vw, p) or "group" (COUNT,
+    wide SUM, MIN, MAX, AVG by (p, b))."""
+    keys = sparse_keys(seed, _stream(6, 0), nd)
+    tables = {
+        "d": {"key": keys, "g": uniform(seed, _stream(6, 1), nd, -3, 4, np.int32)},
+        "t": {"a": uniform(seed, _stream(6, 2), n, -1000, 1000, np.int32),
+              "v": uniform(seed, _stream(6, 3), n, -(1 << 40), 1 << 40, np.int64)},
+        "u": {"b": uniform(seed, _stream(6, 4), m, -1000, 1000, np.int32),
+              "fk": foreign_keys(seed, _stream(6, 5), _stream(6, 0), m, nd),
+              "w": uniform(seed, _stream(6, 6), m, -5, 6, np.int8)},
+    }
+    main = {"table": "t", "filters": [("a", -800, 900)], "cross": "u",
+            "cross_filters": [("b", -600, 700), ("a", -700, 900)],
+            "probes": [("fk", 0, "p")], "arith": [("vw", "mul", "v", "w"), ("ab", "sub", "a", "b")]}
+    if sink == "project":
+        main["project"] = ["ab", "vw", "p"]
+    else:
+        main.update(group_by=["p", "b"], groups_hint=7 * m,
+                    aggs=[("count", None, False), ("sum", "vw", True), ("min", "ab", False),
+                          ("max", "v", False), ("avg", "vw", False)])
+    return tables, {"builds": [{"table": "d", "filters": [], "key": "key", "payload": "g"}], "main": main}
 
 
 def workload(name: str, **kw):

@@ -25,7 +25,7 @@ HAWK_E_INFEASIBLE, HAWK_E_CAPACITY, HAWK_E_DUPKEY, HAWK_E_DEVICE, HAWK_E_OOM, HA
 HAWK_I8, HAWK_I32, HAWK_I64 = 1, 2, 3
 HAWK_RES_I64, HAWK_RES_I128, HAWK_RES_F64 = 3, 4, 5
 (HAWK_LOOP, HAWK_FILTER, HAWK_HASH_PUT, HAWK_HASH_PROBE, HAWK_ARITHMETIC, HAWK_AGGREGATE,
- HAWK_HASH_AGGREGATE, HAWK_PROJECT) = range(1, 9)
+ HAWK_HASH_AGGREGATE, HAWK_PROJECT, HAWK_CROSS_JOIN) = range(1, 10)
 ARITH = {"add": 1, "sub": 2, "mul": 3}
 AGG_FN = {"count": 1, "sum": 2, "min": 3, "max": 4, "avg": 5}
 HAWK_EXPLORE_EXHAUSTIVE, HAWK_EXPLORE_FEATURE_WISE = 0, 1
@@ -364,6 +364,10 @@ def build_query(ctx: Context, spec: dict) -> Query:
     ops = [_op(kind=HAWK_LOOP, table=ctx.tables[m["table"]])]
     for c, lo, hi in m.get("filters", []):
         ops.append(_op(kind=HAWK_FILTER, a=cs(c), lo=int(lo), hi=int(hi)))
+    if m.get("cross"):
+        ops.append(_op(kind=HAWK_CROSS_JOIN, table=ctx.tables[m["cross"]]))
+        for c, lo, hi in m.get("cross_filters", []):
+            ops.append(_op(kind=HAWK_FILTER, a=cs(c), lo=int(lo), hi=int(hi)))
     for fk, bi, pname in m.get("probes", []):
         ops.append(_op(kind=HAWK_HASH_PROBE, a=cs(fk), b=cs(pname), ht=int(bi)))
     for out, opn, x, y in m.get("arith", []):

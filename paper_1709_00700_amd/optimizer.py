@@ -104,10 +104,11 @@ class Ensemble:
 class WithFallback:
     """Per-query picks of an ensemble over a per-workload variant: a query
     keeps `fallback[kind]` (e.g. Algorithm 1's variant for its kind) unless the
-    ensemble's own pick is predicted faster even at its pessimistic score
-    (mean + penalty x sd of the members' ln(ms)) than the fallback at its
-    mean. Greedy search stays the fallback; the model departs from it only
-    where its members agree on a gain."""
+    ensemble's own pick is predicted faster at its pessimistic score (mean +
+    penalty x sd of the members' ln(ms)) than the fallback at its optimistic
+    one (mean - penalty x sd). Greedy search stays the fallback; the model
+    departs from it only where its members agree on a gain larger than their
+    spread on both variants."""
 
     def __init__(self, ens: Ensemble, fallback: dict):
         self.ens = ens
@@ -122,7 +123,7 @@ class WithFallback:
                 out.append(v)
                 continue
             mean, sd = self.ens.scores(q, [v, fb])
-            out.append(v if mean[0] + self.ens.penalty * sd[0] < mean[1] else fb)
+            out.append(v if mean[0] + self.ens.penalty * sd[0] < mean[1] - self.ens.penalty * sd[1] else fb)
         return out, None
 
 

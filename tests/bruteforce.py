@@ -35,13 +35,20 @@ def _build_rows(tables, b):
             if _passes(t, i, b.get("filters", []))]
 
 
-def _row_attrs(tables, spec, i, dims):
-    """Push fact row i through FILTER, HASH_PROBE, ARITHMETIC; None if dropped."""
+def _row_attrs(tables, spec, i, dims, j=None):
+    """Push fact row i (paired with row j of the CROSS_JOIN table, if any)
+    through FILTER, CROSS_JOIN, FILTER, HASH_PROBE, ARITHMETIC; None if dropped."""
     m = spec["main"]
     t = tables[m["table"]]
     if not _passes(t, i, m.get("filters", [])):
         return None
     env = {c: int(t[c][i]) for c in t}
+    if j is not None:
+        u = tables[m["cross"]]
+        env.update({c: int(u[c][j]) for c in u})
+        for col, lo, hi in m.get("cross_filters", []):
+            if not (lo <= env[col] <= hi):
+                return None
     for fk, bi, pname in m.get("probes", []):
         matches = [pay for key, pay in dims[bi] if key == env[fk]]   # nested loop
         if not matches:
@@ -64,7 +71,13 @@ def run(tables, spec):
             return {"error": "dupkey"}
     t = tables[m["table"]]
     n = len(next(iter(t.values())))
-    envs = [e for e in (_row_attrs(tables, spec, i, dims) for i in range(n)) if e is not None]
+    if m.get("cross"):
+        # nested loops: the second table's rows vary fastest
+        ni = len(next(iter(tables[m["cross"]].values())))
+        cand = (_row_attrs(tables, spec, i, dims, j) for i in range(n) for j in range(ni))
+    else:
+        cand = (_row_attrs(tables, spec, i, dims) for i in range(n))
+    envs = [e for e in cand if e is not None]
     if "project" in m:
         return {"kind": "project", "rows": len(envs),
                 "cols": [[e[a] for e in envs] for a in m["project"]]}

@@ -182,3 +182,28 @@ def test_batch_per_query_variants(ctx):
     b.run()
     check_batch(b, qs, refs, "cuckoo/global/sequential/single-pass")
     b.free()
+
+
+def test_batch_cross_join_queries(ctx):
+    """Pipelines with a CROSS_JOIN in a batch, in the tile kernels and in
+    variants of their own, next to ordinary ones."""
+    say("batch: cross joins")
+    qs, hs, refs = c5_setup(ctx, 4, 200_000, 1000, 200_000, seed=dg.MASTER_SEED + 61)
+    specs = [q["spec"] for q in qs]
+    for sink in ("project", "group"):
+        tables, spec = dg.cross_join(n=9_000, m=40, sink=sink)
+        tables = {f"bx{sink}_{t}": c for t, c in tables.items()}
+        spec["main"]["table"], spec["main"]["cross"] = f"bx{sink}_t", f"bx{sink}_u"
+        spec["builds"][0]["table"] = f"bx{sink}_d"
+        refs.append(oracle.run(tables, spec))
+        ctx.register_numpy(tables)
+        hs.append(hawk.build_query(ctx, spec))
+        specs.append(spec)
+    fake = [{"spec": s, "kind": 0, "rows": 0} for s in specs]
+    for variants in (None, [hawk.TILE] * 4 + [hawk.variant(proj_strategy=0, mem=1),
+                                              hawk.variant(agg_strategy=1, ht=1, hash=1, wg_size=256)]):
+        b = hawk.Batch(ctx, hs, variants=variants, tile_rows_log2=14, wgs_per_cu=2)
+        b.run()
+        b.run()
+        check_batch(b, fake, refs, "cross joins" if variants is None else "cross joins, own variants")
+        b.free()

@@ -291,3 +291,32 @@ def test_narrow_avg_run_time_kernel_and_batch(ctx):
         compare(r.to_numpy(spec), ref, spec, f"avg-batch separate={sep}")
         r.free()
         b.free()
+
+
+@pytest.mark.parametrize("sink", ["project", "group"])
+def test_cross_join_variants(ctx, sink):
+    """CROSS_JOIN (Table 1): 20k x 64 pairs (a filter on each side, a band
+    filter on the pair, a probe keyed by the second table, arithmetic over
+    both), projection in (row, second-table row) order or grouping, in every
+    projection variant or a sample of the aggregation variants."""
+    tables, spec = dg.cross_join(n=20_000, m=64, sink=sink)
+    tables = {f"x{sink}_{t}": c for t, c in tables.items()}
+    spec["main"]["table"] = f"x{sink}_t"
+    spec["main"]["cross"] = f"x{sink}_u"
+    spec["builds"][0]["table"] = f"x{sink}_d"
+    plan = hawk.PlanningContext()
+    plan.register_shapes(tables)
+    vs = hawk.variant_space(hawk.build_query(plan, spec))
+    plan.close()
+    say("cross join", sink, "variants", len(vs))
+    run_variants(ctx, tables, spec, vs if sink == "project" else sample(vs, 48, seed=5), label=f"cross {sink}")
+
+
+def test_cross_join_ragged_and_empty(ctx):
+    for i, (n, m) in enumerate([(1, 1), (63, 1), (65, 3), (0, 5), (7, 0), (4097, 17)]):
+        tables, spec = dg.cross_join(n=n, m=m, nd=5, sink="project" if i % 2 else "group")
+        tables = {f"xr{i}_{t}": c for t, c in tables.items()}
+        spec["main"]["table"], spec["main"]["cross"] = f"xr{i}_t", f"xr{i}_u"
+        spec["builds"][0]["table"] = f"xr{i}_d"
+        run_variants(ctx, tables, spec, [hawk.variant(proj_strategy=1, thread_mult=8),
+                                          hawk.variant(agg_strategy=1, ht=1, wg_size=64)], label=f"cross {n}x{m}")

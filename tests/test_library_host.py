@@ -290,3 +290,36 @@ def test_noalloc_sizing_on_a_planning_context(plan_ctx):
     with pytest.raises(hawk.HawkError) as e:
         hawk.execute_noalloc(plan_ctx, q, hawk.variant(), [0x1000] * 3, 1)
     assert e.value.code == hawk.HAWK_E_DEVICE
+
+
+def test_cross_join_plan_validation(plan_ctx):
+    """CROSS_JOIN (Table 1): the pipeline loops over the product of its table
+    and a second one; names must differ between the two, the product must
+    stay below 2^32 pairs, and its variant space is that of its sink."""
+    tables, spec = dg.cross_join(n=100, m=7, sink="project")
+    plan_ctx.register_shapes({"cj_" + t: c for t, c in tables.items()})
+    spec["main"]["table"], spec["main"]["cross"] = "cj_t", "cj_u"
+    spec["builds"][0]["table"] = "cj_d"
+    q = hawk.build_query(plan_ctx, spec)
+    assert len(hawk.variant_space(q)) == 32 * 4   # projection with a probe: hash-table dimensions too
+    assert hawk.execute_noalloc(plan_ctx, q, hawk.variant(proj_strategy=1, thread_mult=8)) == 100 * 7 + 1
+    bad = {**spec, "main": {**spec["main"], "cross": "cj_t"}}
+    _expect(plan_ctx, bad, hawk.HAWK_E_PLAN)                       # every name in both tables
+    plan_ctx.register_shapes({"cj_big": {"a": ("int32", 1 << 20), "v": ("int64", 1 << 20)},
+                              "cj_wide": {"b": ("int32", 1 << 12), "fk": ("int32", 1 << 12), "w": ("int8", 1 << 12)}})
+    big = {**spec, "main": {**spec["main"], "table": "cj_big", "cross": "cj_wide"}}
+    _expect(plan_ctx, big, hawk.HAWK_E_PLAN)                       # 2^32 pairs
+
+
+def test_cross_join_quotient_by_reciprocal():
+    """The device divides a pipeline row v < 2^32 by the second table's row
+    count d as the high word of (2^64 / d rounded up) * v: exact for every
+    32-bit v and d > 1 (the identity the kernels rely on)."""
+    rng = np.random.default_rng(11)
+    ds = [2, 3, 7, 64, 1000, 65537, (1 << 31) - 1, (1 << 32) - 1] + [int(x) for x in rng.integers(2, 1 << 32, 40)]
+    vs = [0, 1, (1 << 32) - 1, (1 << 31)] + [int(x) for x in rng.integers(0, 1 << 32, 200)]
+    for d in ds:
+        m = (2 ** 64 - 1) // d + 1
+        for v in vs + [d - 1, d, d + 1, 2 * d - 1]:
+            if v < 1 << 32:
+                assert (m * v) >> 64 == v // d, (d, v)

@@ -143,6 +143,60 @@ def test_bruteforce_join_group(seed):
     assert_matches_bruteforce(oracle.run(tables, spec), bruteforce.run(tables, spec), spec)
 
 
+def cross_case(rng, n, ni, nd):
+    """A pipeline with a CROSS_JOIN (Table 1) over random tiny tables: a
+    filter on the looped table, the cross product with table `u`, a filter
+    on either side, a probe keyed by a column of `u`, arithmetic over both."""
+    keys = rng.choice(np.arange(-20, 20), size=nd, replace=False).astype(np.int32)
+    tables = {"d": {"key": keys, "g": rng.integers(-3, 4, size=nd).astype(np.int32)},
+              "t": {"a": rng.integers(-10, 10, size=n).astype(np.int32),
+                    "v": rng.integers(-(1 << 40), 1 << 40, size=n).astype(np.int64)},
+              "u": {"b": rng.integers(-10, 10, size=ni).astype(np.int32),
+                    "fk": rng.integers(-20, 20, size=ni).astype(np.int32),
+                    "w": rng.integers(-5, 6, size=ni).astype(np.int8)}}
+    main = {"table": "t", "filters": [("a", -6, 9)], "cross": "u", "cross_filters": [("b", -4, 8), ("a", -5, 9)],
+            "probes": [("fk", 0, "p")], "arith": [("vw", "mul", "v", "w"), ("ab", "sub", "a", "b")]}
+    return tables, {"builds": [{"table": "d", "filters": [], "key": "key", "payload": "g"}], "main": main}
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_bruteforce_cross_join(seed):
+    """CROSS_JOIN against nested loops: projection in (row, second-table
+    row) order, and grouping over attributes of both sides and a payload."""
+    rng = np.random.default_rng(300 + seed)
+    tables, spec = cross_case(rng, int(rng.integers(0, 40)), int(rng.integers(0, 25)), int(rng.integers(1, 20)))
+    proj = {**spec, "main": {**spec["main"], "project": ["ab", "vw", "p", "fk"]}}
+    assert_matches_bruteforce(oracle.run(tables, proj), bruteforce.run(tables, proj), proj)
+    grp = {**spec, "main": {**spec["main"], "group_by": ["p", "b"],
+                            "aggs": [("count", None, False), ("sum", "vw", True), ("min", "ab", False),
+                                     ("max", "v", False), ("avg", "vw", False)], "groups_hint": 64}}
+    assert_matches_bruteforce(oracle.run(tables, grp), bruteforce.run(tables, grp), grp)
+
+
+def test_cross_join_closed_forms():
+    """Without filters a CROSS_JOIN of n and m rows has n*m tuples in
+    row-major order, and SUM over an attribute of one side is its column sum
+    times the other side's row count."""
+    n, m = 37, 11
+    t = {"x": np.arange(n, dtype=np.int64) * 3 - 50}
+    u = {"y": np.arange(m, dtype=np.int32) - 4}
+    spec = {"builds": [], "main": {"table": "t", "filters": [], "cross": "u", "probes": [], "arith": [],
+                                   "project": ["x", "y"]}}
+    r = oracle.run({"t": t, "u": u}, spec)
+    assert r["rows"] == n * m
+    assert np.array_equal(r["cols"][0], np.repeat(t["x"], m))
+    assert np.array_equal(r["cols"][1], np.tile(u["y"].astype(np.int64), n))
+    agg = {"builds": [], "main": {"table": "t", "filters": [], "cross": "u", "probes": [], "arith": [],
+                                  "aggs": [("count", None, False), ("sum", "x", False), ("sum", "y", False)]}}
+    r = oracle.run({"t": t, "u": u}, agg)
+    assert int(r["count"][0]) == n * m
+    assert int(r["aggs"][1][0]) == int(t["x"].sum()) * m
+    assert int(r["aggs"][2][0]) == int(u["y"].sum()) * n
+    # an empty side empties the product
+    r = oracle.run({"t": t, "u": {"y": u["y"][:0]}}, spec)
+    assert r["rows"] == 0
+
+
 def test_duplicate_build_key_is_error():
     tables = {"d": {"key": np.array([1, 2, 1], np.int32), "g": np.array([0, 1, 2], np.int32)},
               "f": {"fk": np.array([1, 2], np.int32)}}

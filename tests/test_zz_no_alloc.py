@@ -73,6 +73,8 @@ def check_pair(ctx, make, sizes, v, label):
         ren = {t: f"{label}{i}_{t}" for t in tables}
         tables = {ren[t]: c for t, c in tables.items()}
         spec["main"]["table"] = ren[spec["main"]["table"]]
+        if spec["main"].get("cross"):
+            spec["main"]["cross"] = ren[spec["main"]["cross"]]
         for b in spec["builds"]:
             b["table"] = ren[b["table"]]
         ctx.register_numpy(tables)
@@ -140,3 +142,12 @@ def test_limits_are_reported(ctx):
     # the entry point still works after the errors
     n = hawk.execute_noalloc(ctx, q, v, [b.data_ptr() for b in bufs[:6]], cap)
     assert n == 16
+
+
+def test_cross_join(ctx):
+    # global table (a local one too small for the groups would spill, which
+    # needs scratch for every pair)
+    check_pair(ctx, lambda n: dg.cross_join(n=n, m=48, sink="group"), [30_000, 2_001],
+               hawk.variant(agg_strategy=1, ht=0, hash=1, wg_size=256), "xj")
+    check_pair(ctx, lambda n: dg.cross_join(n=n, m=48, sink="project"), [30_000, 2_001],
+               hawk.variant(proj_strategy=1, mem=1, thread_mult=64), "xp")
