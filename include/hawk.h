@@ -151,6 +151,57 @@ void hawk_query_free(hawk_query* q);
 /* 1 = projection pipeline, 2 = aggregation pipeline */
 hawk_status hawk_query_kind(const hawk_query* q, int32_t* kind);
 
+/* ------------------------------------------------------------ relational plans */
+/* A relational operator tree, partitioned into pipelines by the
+   produce/consume model (Section 2.1): a hash join's build side becomes a
+   build pipeline (LOOP, FILTER*, HASH_PUT), every other operator adds its
+   operation to the pipeline of the tuples that reach it, and the root ends
+   the probe pipeline (Table 2). Nodes refer to their children by index. */
+enum {
+  HAWK_REL_SCAN = 1,       /* the rows of table `table` */
+  HAWK_REL_SELECT = 2,     /* input's tuples with lo <= a <= hi */
+  HAWK_REL_MAP = 3,        /* input's tuples plus a := x (arith_op) y; x = attr b or const lo, y = attr c or const hi */
+  HAWK_REL_HASH_JOIN = 4,  /* inner equi-join of input (probe side) with right (build side, unique keys) on
+                              input.a = right.b; the result is input's tuple plus right's attribute c */
+  HAWK_REL_CROSS_JOIN = 5, /* every tuple of input with every tuple of right (row-major) */
+  HAWK_REL_GROUP_BY = 6,   /* root only: group input by attrs[0..nattrs) (none: one row) computing aggs */
+  HAWK_REL_PROJECT = 7     /* root only: attrs of input's tuples, in input order */
+};
+typedef struct {
+  int32_t kind;                 /* HAWK_REL_* */
+  int32_t input;                /* child node index (-1 for SCAN) */
+  int32_t right;                /* HASH_JOIN: build side; CROSS_JOIN: second input */
+  int32_t table;                /* SCAN: table id */
+  const char* a;
+  const char* b;
+  const char* c;
+  int32_t arith_op;             /* MAP: HAWK_ADD | HAWK_SUB | HAWK_MUL */
+  int32_t nattrs;
+  int64_t lo, hi;
+  const char* const* attrs;     /* GROUP_BY keys / PROJECT attributes */
+  const hawk_agg* aggs;         /* GROUP_BY */
+  int32_t naggs;
+  int32_t reserved;
+  int64_t groups_hint;          /* GROUP_BY with keys: expected distinct groups */
+} hawk_rel;
+/* Compiles the plan of n nodes rooted at `root` into a query: build
+   pipelines in the order the produce pass meets the joins, then the probe
+   pipeline with its operations ordered LOOP, FILTERs on the scanned table,
+   CROSS_JOIN and its FILTERs, HASH_PROBEs, ARITHMETIC, sink (selections
+   commute with inner joins and arithmetic). A hash join's build side and a
+   cross join's second input must be scans under selections; selections read
+   scanned columns (not join payloads or computed attributes). The query is
+   validated as by hawk_query_create. Errors: HAWK_E_ARG (indices, unknown
+   operator), HAWK_E_PLAN (unsupported shape, a node reaching itself),
+   anything hawk_query_create returns. */
+hawk_status hawk_query_from_plan(hawk_ctx* ctx, const hawk_rel* nodes, int32_t n, int32_t root, hawk_query** out);
+/* The query's pipeline programs as text, one pipeline per line (build
+   pipelines first), in the notation of Table 2, e.g.
+   "LOOP(T1) FILTER(x in [5, 5]) HASH_PUT(a -> x; ht 0)". Two-call sizing:
+   *len receives the length (without the terminating zero); buf (cap bytes)
+   may be NULL. */
+hawk_status hawk_query_program(const hawk_query* q, char* buf, int64_t cap, int64_t* len);
+
 /* ------------------------------------------------------------ variants */
 /* One point of the variant space of Section 9.2. Value order of each
    dimension follows the paper's listing (first value first). */

@@ -431,6 +431,58 @@ hawk_status lower_filter(hawk_ctx* ctx, const hawk_op& op, Lowering& L) {
 
 }  // namespace
 
+// The pipeline programs in the notation of Table 2, one pipeline per line.
+static std::string program_text(const hawk_ctx* ctx, const hawk_pipeline* pipes, int32_t npipes) {
+  auto nm = [](const char* s) { return std::string(s ? s : "?"); };
+  auto bound = [](int64_t v) {
+    return v == INT64_MIN ? std::string("min") : v == INT64_MAX ? std::string("max") : std::to_string(v);
+  };
+  auto table = [&](int32_t t) {
+    return t >= 0 && t < static_cast<int32_t>(ctx->tables.size()) ? ctx->tables[t].name : std::to_string(t);
+  };
+  static const char* fns[] = {"?", "COUNT", "SUM", "MIN", "MAX", "AVG"};
+  static const char* ops[] = {"?", "+", "-", "*"};
+  std::string out;
+  for (int32_t pi = 0; pi < npipes; ++pi) {
+    std::string line;
+    for (int32_t k = 0; k < pipes[pi].nops; ++k) {
+      const hawk_op& o = pipes[pi].ops[k];
+      std::string t;
+      switch (o.kind) {
+        case HAWK_LOOP: t = "LOOP(" + table(o.table) + ")"; break;
+        case HAWK_FILTER: t = "FILTER(" + nm(o.a) + " in [" + bound(o.lo) + ", " + bound(o.hi) + "])"; break;
+        case HAWK_HASH_PUT: t = "HASH_PUT(" + nm(o.a) + " -> " + nm(o.b) + "; ht " + std::to_string(o.ht) + ")"; break;
+        case HAWK_HASH_PROBE: t = "HASH_PROBE(" + nm(o.a) + " -> " + nm(o.b) + "; ht " + std::to_string(o.ht) + ")"; break;
+        case HAWK_CROSS_JOIN: t = "CROSS_JOIN(" + table(o.table) + ")"; break;
+        case HAWK_ARITHMETIC:
+          t = "ARITHMETIC(" + nm(o.a) + " = " + (o.b ? nm(o.b) : std::to_string(o.lo)) + " " +
+              ops[o.arith_op >= 1 && o.arith_op <= 3 ? o.arith_op : 0] + " " + (o.c ? nm(o.c) : std::to_string(o.hi)) + ")";
+          break;
+        case HAWK_PROJECT:
+        case HAWK_AGGREGATE:
+        case HAWK_HASH_AGGREGATE: {
+          t = o.kind == HAWK_PROJECT ? "PROJECT(" : o.kind == HAWK_AGGREGATE ? "AGGREGATE(" : "HASH_AGGREGATE(";
+          for (int32_t j = 0; j < o.nattrs && o.attrs; ++j) t += (j ? ", " : "") + nm(o.attrs[j]);
+          if (o.kind != HAWK_PROJECT) {
+            if (o.nattrs > 0) t += "; ";
+            for (int32_t j = 0; j < o.naggs && o.aggs; ++j) {
+              const hawk_agg& a = o.aggs[j];
+              t += std::string(j ? ", " : "") + fns[a.fn >= 1 && a.fn <= 5 ? a.fn : 0];
+              if (a.fn != HAWK_COUNT) t += "(" + nm(a.attr) + ")";
+            }
+          }
+          t += ")";
+          break;
+        }
+        default: t = "?";
+      }
+      line += (k ? " " : "") + t;
+    }
+    out += line + "\n";
+  }
+  return out;
+}
+
 extern "C" hawk_status hawk_query_create(hawk_ctx* ctx, const hawk_pipeline* pipes, int32_t npipes, hawk_query** out) {
   if (!ctx) return HAWK_E_ARG;
   if (!pipes || npipes < 1 || !out) return set_error(ctx, HAWK_E_ARG, "null argument");
@@ -618,6 +670,7 @@ extern "C" hawk_status hawk_query_create(hawk_ctx* ctx, const hawk_pipeline* pip
   for (int c = L.P.ncolC; c < HK_MAX_COLS_C; ++c) L.P.colC[c] = HkCol{ctx->dummy, HK_T_I64, 0, 0};
   q->main = L.P;
   q->has_table = L.P.nprobes > 0 || L.P.ngroup > 0;
+  q->program = program_text(ctx, pipes, npipes);
   ctx->queries.insert(q);
   *out = q;
   return HAWK_OK;
@@ -645,6 +698,15 @@ extern "C" void hawk_query_free(hawk_query* q) {
     q->ctx->queries.erase(q);
   }
   delete q;
+}
+
+extern "C" hawk_status hawk_query_program(const hawk_query* q, char* buf, int64_t cap, int64_t* len) {
+  if (!q || !len) return HAWK_E_ARG;
+  *len = static_cast<int64_t>(q->program.size());
+  if (!buf) return HAWK_OK;
+  if (cap < *len + 1) return set_error(q->ctx, HAWK_E_ARG, "buffer too small");
+  std::memcpy(buf, q->program.c_str(), q->program.size() + 1);
+  return HAWK_OK;
 }
 
 extern "C" hawk_status hawk_query_kind(const hawk_query* q, int32_t* kind) {

@@ -91,6 +91,7 @@ struct hawk_query {
   int64_t groups_hint = 1;
   double stat_selectivity = 1.0;     // catalog statistic: fraction of rows reaching the sink
   bool has_table = false;            // probes or grouping: hash-table dimensions apply
+  std::string program;               // the pipeline programs as text (hawk_query_program)
 };
 
 struct ResCol { int32_t kind; void* ptr; };

@@ -34,7 +34,7 @@ HAWK_EXPLORE_EXHAUSTIVE, HAWK_EXPLORE_FEATURE_WISE = 0, 1
 EXPORTS = [
     "hawk_ctx_create", "hawk_ctx_destroy", "hawk_last_error", "hawk_device_info",
     "hawk_table_register", "hawk_table_unregister",
-    "hawk_query_create", "hawk_query_free", "hawk_query_kind",
+    "hawk_query_create", "hawk_query_free", "hawk_query_kind", "hawk_query_from_plan", "hawk_query_program",
     "hawk_variant_space", "hawk_variant_format",
     "hawk_execute", "hawk_execute_async", "hawk_execute_noalloc",
     "hawk_result_info", "hawk_result_column", "hawk_result_copy_column", "hawk_result_free",
@@ -76,6 +76,15 @@ class hawk_op(ctypes.Structure):
 
 class hawk_pipeline(ctypes.Structure):
     _fields_ = [("ops", ctypes.POINTER(hawk_op)), ("nops", ctypes.c_int32)]
+
+
+class hawk_rel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("input", ctypes.c_int32), ("right", ctypes.c_int32),
+                ("table", ctypes.c_int32), ("a", ctypes.c_char_p), ("b", ctypes.c_char_p), ("c", ctypes.c_char_p),
+                ("arith_op", ctypes.c_int32), ("nattrs", ctypes.c_int32), ("lo", ctypes.c_int64),
+                ("hi", ctypes.c_int64), ("attrs", ctypes.POINTER(ctypes.c_char_p)),
+                ("aggs", ctypes.POINTER(hawk_agg)), ("naggs", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("groups_hint", ctypes.c_int64)]
 
 
 class hawk_variant(ctypes.Structure):
@@ -138,6 +147,8 @@ def L():
             "hawk_query_create": ([vp, P(hawk_pipeline), i32, P(vp)], i32),
             "hawk_query_free": ([vp], None),
             "hawk_query_kind": ([vp, P(i32)], i32),
+            "hawk_query_from_plan": ([vp, P(hawk_rel), i32, i32, P(vp)], i32),
+            "hawk_query_program": ([vp, ctypes.c_char_p, i64, P(i64)], i32),
             "hawk_variant_space": ([vp, P(hawk_variant), i64, P(i64)], i32),
             "hawk_variant_format": ([P(hawk_variant), ctypes.c_char_p, i32], i32),
             "hawk_execute": ([vp, vp, P(hawk_variant), P(vp)], i32),
@@ -327,6 +338,14 @@ class Query:
         check(L().hawk_query_kind(self.handle, ctypes.byref(k)))
         return k.value
 
+    def program(self) -> str:
+        """The pipeline programs as text (hawk_query_program)."""
+        n = ctypes.c_int64()
+        check(L().hawk_query_program(self.handle, None, 0, ctypes.byref(n)), self.ctx.handle)
+        buf = ctypes.create_string_buffer(n.value + 1)
+        check(L().hawk_query_program(self.handle, buf, n.value + 1, ctypes.byref(n)), self.ctx.handle)
+        return buf.value.decode()
+
     def set_stats(self, selectivity: float):
         check(L().hawk_query_set_stats(self.handle, float(selectivity)))
 
@@ -395,6 +414,53 @@ def build_query(ctx: Context, spec: dict) -> Query:
     parr = (hawk_pipeline * len(pipes))(*pipes)
     h = ctypes.c_void_p()
     check(L().hawk_query_create(ctx.handle, parr, len(pipes), ctypes.byref(h)), ctx.handle)
+    return Query(ctx, h)
+
+
+REL = {"scan": 1, "select": 2, "map": 3, "hash_join": 4, "cross_join": 5, "group_by": 6, "project": 7}
+
+
+def query_from_plan(ctx: Context, plan: dict) -> Query:
+    """Marshals a relational plan ({"root": k, "nodes": [...]}, the format
+    oracle.relalg documents) into hawk_rel nodes and compiles it
+    (hawk_query_from_plan)."""
+    keep = []
+
+    def cs(s):
+        return s.encode() if isinstance(s, str) else None
+
+    nodes = []
+    for nd in plan["nodes"]:
+        r = hawk_rel()
+        r.kind = REL[nd["op"]]
+        r.input = nd.get("input", -1)
+        r.right = nd.get("build", nd.get("right", -1))
+        op = nd["op"]
+        if op == "scan":
+            r.table = ctx.tables[nd["table"]]
+        elif op == "select":
+            r.a, r.lo, r.hi = cs(nd["attr"]), int(nd["lo"]), int(nd["hi"])
+        elif op == "map":
+            x, y = nd["x"], nd["y"]
+            r.a, r.arith_op = cs(nd["out"]), ARITH[nd["fn"]]
+            r.b, r.lo = (cs(x), 0) if isinstance(x, str) else (None, int(x))
+            r.c, r.hi = (cs(y), 0) if isinstance(y, str) else (None, int(y))
+        elif op == "hash_join":
+            r.a, r.b, r.c = cs(nd["probe_key"]), cs(nd["build_key"]), cs(nd["payload"])
+        elif op in ("group_by", "project"):
+            names = nd["keys"] if op == "group_by" else nd["attrs"]
+            arr = (ctypes.c_char_p * max(1, len(names)))(*[cs(a) for a in names])
+            keep.append(arr)
+            r.attrs, r.nattrs = arr, len(names)
+            if op == "group_by":
+                aggs = (hawk_agg * len(nd["aggs"]))(*[hawk_agg(AGG_FN[f], int(bool(w)), cs(a))
+                                                      for f, a, w in nd["aggs"]])
+                keep.append(aggs)
+                r.aggs, r.naggs, r.groups_hint = aggs, len(nd["aggs"]), int(nd.get("groups_hint", 1))
+        nodes.append(r)
+    arr = (hawk_rel * len(nodes))(*nodes)
+    h = ctypes.c_void_p()
+    check(L().hawk_query_from_plan(ctx.handle, arr, len(nodes), int(plan["root"]), ctypes.byref(h)), ctx.handle)
     return Query(ctx, h)
 
 
