@@ -208,11 +208,18 @@ hawk_status hawk_query_program(const hawk_query* q, char* buf, int64_t cap, int6
 enum { HAWK_SINGLE_PASS = 0, HAWK_MULTI_PASS = 1 };    /* projection strategy (Section 4.1) */
 enum { HAWK_SEQUENTIAL = 0, HAWK_COALESCED = 1 };      /* memory access pattern (Section 6.1) */
 enum { HAWK_BRANCHED = 0, HAWK_PREDICATED = 1 };       /* predication mode (Section 6.1) */
-enum { HAWK_LINEAR_PROBING = 0, HAWK_CUCKOO = 1 };     /* hash table (Section 5.1) */
+enum { HAWK_LINEAR_PROBING = 0, HAWK_CUCKOO = 1,       /* hash table (Section 5.1) */
+       HAWK_ROBIN_HOOD = 2 };  /* join tables only (extension of Section 7.5.1): robin-hood linear probing;
+                                  grouping tables of such a variant use linear probing */
+enum { HAWK_FILTER_SCALAR = 0, HAWK_FILTER_SIMD = 1 }; /* FILTER mode (extension of Section 7.5.2) */
 enum { HAWK_MURMUR = 0, HAWK_MULTIPLY_SHIFT = 1 };     /* hash function (Section 9.2) */
 enum { HAWK_LOCAL = 0, HAWK_GLOBAL = 1 };              /* aggregation strategy (Section 4.2) */
 typedef struct {
-  uint8_t proj_strategy, mem, pred, ht, hash, agg_strategy, reserved0, reserved1;
+  uint8_t proj_strategy, mem, pred, ht, hash, agg_strategy;
+  uint8_t unroll;        /* loop unrolling (Section 6.1): rows per loop iteration of the multi-pass filter
+                            kernel, taken with element access offsets 0..unroll-1 (1, 2 or 4; 0 = the
+                            default 4) */
+  uint8_t filter_mode;   /* HAWK_FILTER_SCALAR | HAWK_FILTER_SIMD (multi-pass coalesced projections) */
   uint32_t thread_mult;  /* multi-pass projection threads / local hash tables, as a multiple of the CUs */
   uint32_t wg_size;      /* aggregation: threads per hash table (16..1024) */
 } hawk_variant;
@@ -220,9 +227,22 @@ typedef struct {
 /* Writes the variant space of q (two-call sizing: out may be NULL, *n is the
    size). Projection: 4 single-pass + 28 multi-pass; aggregation: 784 local +
    112 global (Section 9.2). Hash-table dimensions are multiplied in only when
-   the query has a hash table (probes or groups). */
+   the query has a hash table (probes or groups). With extra dimensions set on
+   the query's context (hawk_ctx_set_variant_dims) the space grows where they
+   apply. */
 hawk_status hawk_variant_space(const hawk_query* q, hawk_variant* out, int64_t cap, int64_t* n);
-/* Text form "strat=mp,mem=coal,pred=br,ht=lin,hash=murmur,agg=local,tm=64,wg=256". */
+/* Extra variant dimensions beyond Section 9.2, the extensions the paper
+   sketches (Sections 6.1, 7.5.1, 7.5.2): HAWK_DIM_ROBIN_HOOD adds ht =
+   HAWK_ROBIN_HOOD for pipelines with probes; HAWK_DIM_UNROLL adds unroll 2
+   and 1 to multi-pass coalesced projections (the default is 4);
+   HAWK_DIM_SIMD_FILTER adds filter_mode = HAWK_FILTER_SIMD to multi-pass
+   coalesced projections with filters, no probes and 16-byte aligned filter
+   columns (executing it otherwise is HAWK_E_INFEASIBLE). 0 (the default) = the paper's space.
+   Affects hawk_variant_space, hawk_explore and the model's picks. */
+enum { HAWK_DIM_ROBIN_HOOD = 1, HAWK_DIM_UNROLL = 2, HAWK_DIM_SIMD_FILTER = 4 };
+hawk_status hawk_ctx_set_variant_dims(hawk_ctx* ctx, uint32_t dims);
+/* Text form "strat=mp,mem=coal,pred=br,ht=lin,hash=murmur,agg=local,tm=64,wg=256"
+   (",unroll=U" and ",filter=simd" follow when set; ht=robin for robin hood). */
 hawk_status hawk_variant_format(const hawk_variant* v, char* buf, int32_t cap);
 
 /* ------------------------------------------------------------ execution */

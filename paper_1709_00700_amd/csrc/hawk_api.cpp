@@ -272,6 +272,14 @@ extern "C" void hawk_ctx_destroy(hawk_ctx* ctx) {
 
 extern "C" const char* hawk_last_error(const hawk_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+extern "C" hawk_status hawk_ctx_set_variant_dims(hawk_ctx* ctx, uint32_t dims) {
+  if (!ctx) return HAWK_E_ARG;
+  if (dims & ~static_cast<uint32_t>(HAWK_DIM_ROBIN_HOOD | HAWK_DIM_UNROLL | HAWK_DIM_SIMD_FILTER))
+    return set_error(ctx, HAWK_E_ARG, "unknown variant dimension");
+  ctx->variant_dims = dims;
+  return HAWK_OK;
+}
+
 extern "C" hawk_status hawk_ctx_set_jit(hawk_ctx* ctx, int32_t on) {
   if (!ctx) return HAWK_E_ARG;
   if (ctx->device < 0 && on) return set_error(ctx, HAWK_E_DEVICE, "planning context cannot execute");
@@ -731,25 +739,50 @@ static void push_variant(std::vector<hawk_variant>& v, int ps, int mem, int pred
   v.push_back(x);
 }
 
+// The variant space of Section 9.2 (32 projection / 896 aggregation
+// variants), with the context's extra dimensions multiplied in where they
+// apply: robin-hood join tables for pipelines with probes, loop unrolling
+// (1, 2, 4 rows per iteration) for multi-pass coalesced projections and the
+// SIMD filter for those without probes.
 std::vector<hawk_variant> variant_space(const hawk_query* q) {
   std::vector<hawk_variant> v;
-  const int nht = q->has_table ? 2 : 1;
+  const uint32_t dims = q->ctx ? q->ctx->variant_dims : 0;
+  const int nht = !q->has_table ? 1 : (dims & HAWK_DIM_ROBIN_HOOD) && q->main.nprobes > 0 ? 3 : 2;
+  const int nhs = q->has_table ? 2 : 1;
+  // the SIMD filter: filters without probes or a cross join, over 16-byte aligned columns
+  bool simd_ok = q->main.nprobes == 0 && q->main.nfilters > 0 && q->main.xinner == 0;
+  for (int c = 0; c < q->main.ncolA && simd_ok; ++c)
+    simd_ok = reinterpret_cast<uintptr_t>(q->main.colA[c].ptr) % 16 == 0;
   if (q->kind == 1) {
     for (int ps = 0; ps < 2; ++ps)
       for (int mem = 0; mem < 2; ++mem)
         for (int pred = 0; pred < 2; ++pred)
           for (int ht = 0; ht < nht; ++ht)
-            for (int hs = 0; hs < nht; ++hs) {
-              if (ps == HAWK_SINGLE_PASS) push_variant(v, ps, mem, pred, ht, hs, 0, 1, 64);
-              else
-                for (uint32_t tm : kMults) push_variant(v, ps, mem, pred, ht, hs, 0, tm, 256);
+            for (int hs = 0; hs < nhs; ++hs) {
+              if (ps == HAWK_SINGLE_PASS) {
+                push_variant(v, ps, mem, pred, ht, hs, 0, 1, 64);
+                continue;
+              }
+              for (uint32_t tm : kMults) {
+                push_variant(v, ps, mem, pred, ht, hs, 0, tm, 256);
+                if (mem != HAWK_COALESCED) continue;
+                if (dims & HAWK_DIM_UNROLL)
+                  for (uint8_t u : {uint8_t(2), uint8_t(1)}) {
+                    push_variant(v, ps, mem, pred, ht, hs, 0, tm, 256);
+                    v.back().unroll = u;
+                  }
+                if ((dims & HAWK_DIM_SIMD_FILTER) && simd_ok) {
+                  push_variant(v, ps, mem, pred, ht, hs, 0, tm, 256);
+                  v.back().filter_mode = HAWK_FILTER_SIMD;
+                }
+              }
             }
   } else {
     for (int as = 0; as < 2; ++as)
       for (int mem = 0; mem < 2; ++mem)
         for (int pred = 0; pred < 2; ++pred)
           for (int ht = 0; ht < nht; ++ht)
-            for (int hs = 0; hs < nht; ++hs) {
+            for (int hs = 0; hs < nhs; ++hs) {
               if (as == HAWK_LOCAL) {
                 for (uint32_t tm : kMults)
                   for (uint32_t wg : kWgs) push_variant(v, 1, mem, pred, ht, hs, as, tm, wg);
@@ -774,10 +807,12 @@ extern "C" hawk_status hawk_variant_space(const hawk_query* q, hawk_variant* out
 
 extern "C" hawk_status hawk_variant_format(const hawk_variant* v, char* buf, int32_t cap) {
   if (!v || !buf || cap <= 0) return HAWK_E_ARG;
-  int k = std::snprintf(buf, static_cast<size_t>(cap), "strat=%s,mem=%s,pred=%s,ht=%s,hash=%s,agg=%s,tm=%u,wg=%u",
+  int k = std::snprintf(buf, static_cast<size_t>(cap), "strat=%s,mem=%s,pred=%s,ht=%s,hash=%s,agg=%s,tm=%u,wg=%u%s%s%s",
                         v->proj_strategy ? "mp" : "sp", v->mem ? "coal" : "seq", v->pred ? "pred" : "br",
-                        v->ht ? "cuckoo" : "lin", v->hash ? "mulshift" : "murmur", v->agg_strategy ? "global" : "local",
-                        v->thread_mult, v->wg_size);
+                        v->ht == HAWK_ROBIN_HOOD ? "robin" : v->ht ? "cuckoo" : "lin", v->hash ? "mulshift" : "murmur",
+                        v->agg_strategy ? "global" : "local", v->thread_mult, v->wg_size,
+                        v->unroll == 1 ? ",unroll=1" : v->unroll == 2 ? ",unroll=2" : "",
+                        v->filter_mode ? ",filter=simd" : "", "");
   return k < cap ? HAWK_OK : HAWK_E_ARG;
 }
 
@@ -973,6 +1008,7 @@ struct Exec {
   int32_t next_out = 0;
   int64_t need_rows = 0;       // largest result column requested so far
   const void* d_plans = nullptr;  // device copy of [main plan][builds] read by build and finalize kernels
+  bool robin = false;            // the variant's join tables use robin-hood linear probing
 
   bool sizing() const { return mem == EXEC_ARENA && !base; }
   void* get(size_t bytes, bool owned) {
@@ -1102,7 +1138,7 @@ hawk_status run_builds(Exec& X, HkPlan& main, const HkHash& h, int grow) {
     uint64_t *slots = m.slots, *side = m.side;
     if (X.mem == EXEC_ARENA) {
       ALLOC(slots, uint64_t*, (static_cast<size_t>(1) << l2) * 8, false);
-      ALLOC(side, uint64_t*, 8, false);
+      ALLOC(side, uint64_t*, 16, false);
     } else if (!m.slots || m.log2cap != l2) {
       if (m.slots) {
         HIPCHK(hipStreamSynchronize(X.st), "synchronize");
@@ -1110,7 +1146,7 @@ hawk_status run_builds(Exec& X, HkPlan& main, const HkHash& h, int grow) {
         (void)hipFree(m.side);
         m.slots = m.side = nullptr;
       }
-      if (hipMalloc(&m.slots, (static_cast<size_t>(1) << l2) * 8) != hipSuccess || hipMalloc(&m.side, 8) != hipSuccess)
+      if (hipMalloc(&m.slots, (static_cast<size_t>(1) << l2) * 8) != hipSuccess || hipMalloc(&m.side, 16) != hipSuccess)
         return set_error(X.ctx, HAWK_E_OOM, "join table allocation failed");
       m.log2cap = l2;
       slots = m.slots;
@@ -1124,6 +1160,7 @@ hawk_status run_builds(Exec& X, HkPlan& main, const HkHash& h, int grow) {
     b.payload = B.payload;
     b.t.slots = slots;
     b.t.side = side;
+    b.t.robin = X.robin ? 1 : 0;
     b.t.log2cap = l2;
     bs.push_back(b);
   }
@@ -1132,7 +1169,7 @@ hawk_status run_builds(Exec& X, HkPlan& main, const HkHash& h, int grow) {
   if (st) return st;
   for (size_t i = 0; i < bs.size(); ++i) {
     LAUNCH(hk_fill_u64(X.st, bs[i].t.slots, int64_t(1) << bs[i].t.log2cap, HK_EMPTY), "fill join table");
-    LAUNCH(hk_fill_u64(X.st, bs[i].t.side, 1, 0), "fill side slot");
+    LAUNCH(hk_fill_u64(X.st, bs[i].t.side, 2, 0), "fill side words");
     ProfScope ps(X.prof(), "k_build");
     LAUNCH(hk_build(X.st, bs[i], dev_build(X, i), X.v->ht, X.v->hash, X.res->d_err), "build");
   }
@@ -1171,9 +1208,17 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
     ALLOC(counts, uint32_t*, static_cast<size_t>(m) * 4, false);
     ALLOC(offsets, uint32_t*, static_cast<size_t>(m) * 4, false);
     ALLOC(tmp, uint32_t*, static_cast<size_t>(hk_scan_tmp_words(m)) * 4, false);
+    if (v->filter_mode == HAWK_FILTER_SIMD) {
+      // vector loads of 4 rows: a coalesced scan of filter columns without probes, 16-byte aligned
+      bool ok = v->mem == HAWK_COALESCED && P.nprobes == 0 && P.nfilters > 0 && P.xinner == 0;
+      for (int c = 0; c < P.ncolA && ok; ++c) ok = reinterpret_cast<uintptr_t>(P.colA[c].ptr) % 16 == 0;
+      if (!ok) return set_error(ctx, HAWK_E_INFEASIBLE, "the SIMD filter needs a coalesced scan of 16-byte aligned "
+                                                        "filter columns without probes");
+    }
     {
       ProfScope ps(X.prof(), "k_mp_filter");
-      LAUNCH(hk_mp_filter(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, counts), "filter kernel");
+      LAUNCH(hk_mp_filter(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, counts, v->unroll, v->filter_mode),
+             "filter kernel");
     }
     {
       ProfScope ps(X.prof(), "k_scan");
@@ -1360,10 +1405,18 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
 // One execution of (X.q, X.v) as set up in X: the flags cleared, the build
 // pipelines, then the main pipeline's kernels.
 hawk_status run_query(Exec& X, int grow) {
-  const hawk_variant* v = X.v;
-  if (v->mem > 1 || v->pred > 1 || v->ht > 1 || v->hash > 1 || v->agg_strategy > 1 || v->proj_strategy > 1 ||
-      v->thread_mult < 1)
+  if (X.v->mem > 1 || X.v->pred > 1 || X.v->ht > 2 || X.v->hash > 1 || X.v->agg_strategy > 1 ||
+      X.v->proj_strategy > 1 || X.v->thread_mult < 1 || X.v->unroll > 4 || X.v->filter_mode > 1)
     return set_error(X.ctx, HAWK_E_ARG, "variant value out of range");
+  // robin-hood join tables: the kernels of linear probing, the tables marked
+  hawk_variant vk = *X.v;
+  if (vk.ht == HAWK_ROBIN_HOOD) {
+    if (X.q->main.nprobes == 0) return set_error(X.ctx, HAWK_E_INFEASIBLE, "robin hood applies to join tables");
+    vk.ht = HAWK_LINEAR_PROBING;
+    X.robin = true;
+  }
+  X.v = &vk;
+  const hawk_variant* v = X.v;
   void* flags;
   ALLOC(flags, void*, 16, true);
   X.res->d_count = static_cast<uint64_t*>(flags);

@@ -202,11 +202,11 @@ hawk_status setup_memory(hawk_batch* B) {
       t.log2cap = std::max<uint32_t>(4, clog2(static_cast<uint64_t>(std::max<int64_t>(1, qb.nrows)) * 2));
       if (t.log2cap > 31) return berr(B, HAWK_E_CAPACITY, "join table beyond 2^31 slots");
       t.slots = static_cast<uint64_t*>(balloc(B, (static_cast<size_t>(1) << t.log2cap) * 8, B->allocs));
-      t.side = static_cast<uint64_t*>(balloc(B, 8, B->allocs));
+      t.side = static_cast<uint64_t*>(balloc(B, 16, B->allocs));
       if (!t.slots || !t.side) return berr(B, HAWK_E_OOM, "batch join table");
       const uint64_t e = HK_EMPTY;
       add_fill(B, t.slots, int64_t(1) << t.log2cap, &e, 1);
-      add_zero(B, t.side, 1);
+      add_zero(B, t.side, 2);
       HkBuild b;
       std::memset(&b, 0, sizeof(b));
       b.p = qb.plan;
@@ -471,7 +471,7 @@ extern "C" hawk_status hawk_batch_create(hawk_ctx* ctx, hawk_query* const* qs, i
     B->qs.push_back(qs[i]);
     if (variants) {
       const hawk_variant& v = variants[i];
-      if (v.thread_mult != 0 && (v.mem > 1 || v.pred > 1 || v.ht > 1 || v.hash > 1 || v.agg_strategy > 1 ||
+      if (v.thread_mult != 0 && (v.mem > 1 || v.pred > 1 || v.ht > 2 || v.hash > 1 || v.agg_strategy > 1 ||
                                  v.proj_strategy > 1 || v.wg_size < 1 || v.wg_size > 1024)) {
         delete B;
         return set_error(ctx, HAWK_E_ARG, "variant value out of range");

@@ -137,6 +137,62 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 // ------------------------------------------------------------------ join tables
 // slot word: key (high 32 bits) | payload (low 32 bits); all-ones = empty;
 // key -1 would look empty and lives in the side word (bit 32 = present)
+
+// Robin-hood linear probing (the extension Section 7.5.1 names): an entry's
+// displacement is its distance from its home slot; an insertion that meets
+// an entry displaced less than itself takes that slot and carries the
+// evicted entry on (atomic compare-exchange per step), so displacements stay
+// even. side[1] records the largest displacement, which bounds a lookup.
+template <int HASH>
+__device__ __forceinline__ void robin_insert(const HkJoinTable& t, const HkHash& h, uint64_t w, int* err) {
+  const uint32_t mask = (1u << t.log2cap) - 1u;
+  const uint32_t key = static_cast<uint32_t>(w >> 32);
+  uint64_t cur = w;
+  uint32_t pos = hslot<HASH>(key, h.a[0], t.log2cap);
+  uint32_t d = 0;
+  while (d <= HK_ROBIN_MAX_DISP && d <= mask) {
+    const uint64_t old = t.slots[pos];
+    if (old == HK_EMPTY) {
+      if (at_cas<false>(&t.slots[pos], HK_EMPTY, cur) == HK_EMPTY) {
+        at_max<false>(t.side + 1, static_cast<int64_t>(d));
+        return;
+      }
+      continue;  // taken meanwhile: look at the slot again
+    }
+    if (static_cast<uint32_t>(old >> 32) == static_cast<uint32_t>(cur >> 32)) {
+      set_err(err, HK_ERR_DUPKEY);
+      return;
+    }
+    const uint32_t dold = (pos - hslot<HASH>(static_cast<uint32_t>(old >> 32), h.a[0], t.log2cap)) & mask;
+    if (dold < d) {
+      if (at_cas<false>(&t.slots[pos], old, cur) != old) continue;  // changed meanwhile
+      at_max<false>(t.side + 1, static_cast<int64_t>(d));
+      cur = old;  // the richer entry moves on
+      d = dold;
+    }
+    pos = (pos + 1) & mask;
+    ++d;
+  }
+  set_err(err, HK_ERR_CAPACITY);
+}
+
+template <int HASH>
+__device__ __forceinline__ bool robin_lookup(const HkJoinTable& t, const HkHash& h, uint32_t key, int32_t& pay) {
+  const uint32_t mask = (1u << t.log2cap) - 1u;
+  const uint32_t maxd = static_cast<uint32_t>(t.side[1]);
+  uint32_t pos = hslot<HASH>(key, h.a[0], t.log2cap);
+  for (uint32_t d = 0; d <= maxd; ++d) {
+    const uint64_t w = t.slots[pos];
+    if (w == HK_EMPTY) return false;
+    if (static_cast<uint32_t>(w >> 32) == key) {
+      pay = static_cast<int32_t>(static_cast<uint32_t>(w));
+      return true;
+    }
+    pos = (pos + 1) & mask;
+  }
+  return false;
+}
+
 template <int HT, int HASH>
 __device__ __forceinline__ bool join_lookup(const HkJoinTable& t, const HkHash& h, int32_t key, int32_t& pay) {
   if (key == -1) {
@@ -145,6 +201,7 @@ __device__ __forceinline__ bool join_lookup(const HkJoinTable& t, const HkHash& 
     return (s >> 32) != 0;
   }
   const uint64_t k64 = static_cast<uint32_t>(key);
+  if (HT == HK_LIN && t.robin) return robin_lookup<HASH>(t, h, static_cast<uint32_t>(key), pay);
   if (HT == HK_LIN) {
     const uint32_t mask = (1u << t.log2cap) - 1u;
     uint32_t s = hslot<HASH>(k64, h.a[0], t.log2cap);
@@ -180,6 +237,10 @@ __device__ __forceinline__ void join_insert(const HkJoinTable& t, const HkHash& 
     return;
   }
   const uint64_t w = (static_cast<uint64_t>(static_cast<uint32_t>(key)) << 32) | static_cast<uint32_t>(pay);
+  if (HT == HK_LIN && t.robin) {
+    robin_insert<HASH>(t, h, w, err);
+    return;
+  }
   if (HT == HK_LIN) {
     const uint32_t mask = (1u << t.log2cap) - 1u;
     uint32_t s = hslot<HASH>(static_cast<uint32_t>(key), h.a[0], t.log2cap);

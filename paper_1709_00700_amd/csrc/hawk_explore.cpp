@@ -108,8 +108,11 @@ hawk_status query_features(const hawk_query* q, const hawk_variant* v, int num_c
   f[6] = static_cast<float>(strat);
   f[7] = static_cast<float>(std::log2(threads));
   f[8] = static_cast<float>(std::log2(wg));
-  f[9] = static_cast<float>(v->pred);
-  f[10] = static_cast<float>(v->mem);
+  // the extra dimensions share ordinal codes with the paper's: SIMD filter
+  // with predication, unrolling with the access pattern (the default 4 rows
+  // per iteration codes as 0), robin hood as a third table kind
+  f[9] = static_cast<float>(v->pred + 2 * v->filter_mode);
+  f[10] = static_cast<float>(v->mem + 2 * (v->unroll == 2 ? 1 : v->unroll == 1 ? 2 : 0));
   f[11] = static_cast<float>(q->has_table ? v->ht * 2 + v->hash : 0);
   return HAWK_OK;
 }
@@ -134,6 +137,7 @@ struct Space {
   int kind;
   bool table;
   std::vector<int32_t> sizes;
+  int iu = -1, isimd = -1;  // positions of the unrolling and filter-mode dimensions (extra dimensions)
   hawk_variant at(const std::vector<int32_t>& c) const {
     hawk_variant v;
     std::memset(&v, 0, sizeof(v));
@@ -148,6 +152,9 @@ struct Space {
         v.hash = static_cast<uint8_t>(c[5]);
       }
       v.agg_strategy = 0;
+      static const uint8_t kUnroll[3] = {0, 2, 1};  // the default 4 rows per iteration first
+      if (iu >= 0) v.unroll = kUnroll[c[iu]];
+      if (isimd >= 0) v.filter_mode = static_cast<uint8_t>(c[isimd]);
     } else {
       v.proj_strategy = 1;
       v.agg_strategy = static_cast<uint8_t>(c[0]);
@@ -328,8 +335,19 @@ extern "C" hawk_status hawk_explore(hawk_ctx* ctx, hawk_query* const* W, int32_t
   }
   if (E.space.kind == 1) E.space.sizes = {2, 7, 2, 2};
   else E.space.sizes = {2, 7, 7, 2, 2};
+  // the context's extra dimensions (hawk_ctx_set_variant_dims): a third
+  // table kind for joins, unrolling and the SIMD filter for projections
+  // (values that do not apply to a query make it infeasible: +inf)
   if (E.space.table) {
+    E.space.sizes.push_back(ctx->variant_dims & HAWK_DIM_ROBIN_HOOD ? 3 : 2);
     E.space.sizes.push_back(2);
+  }
+  if (E.space.kind == 1 && (ctx->variant_dims & HAWK_DIM_UNROLL)) {
+    E.space.iu = static_cast<int>(E.space.sizes.size());
+    E.space.sizes.push_back(3);
+  }
+  if (E.space.kind == 1 && (ctx->variant_dims & HAWK_DIM_SIMD_FILTER)) {
+    E.space.isimd = static_cast<int>(E.space.sizes.size());
     E.space.sizes.push_back(2);
   }
   E.sig = workload_signature(W, k, ctx->num_cus);

@@ -42,6 +42,7 @@ struct hawk_ctx {
   size_t stage_bytes = 0;
   uint64_t* h_flags = nullptr;  // pinned: row count and error flags read back by the non-allocating execution
   bool jit = false;       // grouped aggregation runs kernels specialised at run time for the plan
+  uint32_t variant_dims = 0;  // extra variant dimensions in variant spaces (HAWK_DIM_*)
   JitCache jit_cache;
   // live handles; destroying the context releases their device state and
   // orphans them (their *_free then only releases host memory)

@@ -19,8 +19,10 @@ hipError_t hk_init_aggtable(hipStream_t st, uint64_t* words, int64_t nslots, con
 hipError_t hk_build(hipStream_t st, const HkBuild& B, const HkBuild* dB, int ht, int hash, int* err);
 
 // multi-pass projection: filter kernel, scan, projection kernel
+// unroll (coalesced): rows per loop iteration, 1, 2 or 4 (0 = 4); simd: FILTER
+// in SIMD mode (4 rows per lane from vector loads; coalesced, no probes)
 hipError_t hk_mp_filter(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t threads,
-                        uint64_t* masks, uint32_t* counts);
+                        uint64_t* masks, uint32_t* counts, int unroll = 0, int simd = 0);
 hipError_t hk_mp_project(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t threads,
                          const uint64_t* masks, const uint32_t* offsets, const uint64_t* total, int64_t nact,
                          int64_t* const* out, int64_t dump);

@@ -41,6 +41,7 @@ typedef __hip_internal::uint64_t uint64_t;
 enum { HK_SEQ = 0, HK_COAL = 1 };
 enum { HK_BR = 0, HK_PRED = 1 };
 enum { HK_LIN = 0, HK_CUCKOO = 1 };
+#define HK_ROBIN_MAX_DISP 4096   // displacement bound of a robin-hood insertion before it fails
 enum { HK_MURMUR = 0, HK_MULSHIFT = 1 };
 enum { HK_LOCAL = 0, HK_GLOBAL = 1 };
 
@@ -58,8 +59,11 @@ struct HkCol { const void* ptr; int16_t dtype; int16_t side; int32_t reg; };
 struct HkFilter { int64_t lo, hi; int32_t reg; int32_t pad; };
 // hash functions of one query: murmur xor keys or multiply-shift odd multipliers
 struct HkHash { uint64_t a[HK_CUCKOO_D]; };
-// a join hash table: 64-bit slots (key << 32 | payload), plus a side word for key -1
-struct HkJoinTable { uint64_t* slots; uint64_t* side; uint32_t log2cap; int32_t pad; };
+// a join hash table: 64-bit slots (key << 32 | payload), plus side words:
+// side[0] holds key -1, side[1] (robin hood) the largest displacement of any
+// entry; robin = 1: robin-hood linear probing (kernels instantiated for
+// linear probing take this form at run time)
+struct HkJoinTable { uint64_t* slots; uint64_t* side; uint32_t log2cap; int32_t robin; };
 struct HkProbe { HkJoinTable t; int32_t fk_reg; int32_t pay_reg; };
 struct HkArith { int64_t cx, cy; int8_t op, dst, x, y, xc, yc, pad0, pad1; };
 struct HkAgg { int8_t fn, wide, reg, pad; int32_t word; };

@@ -64,6 +64,34 @@ __global__ void __launch_bounds__(256) k_build_verify(const HkBuild* Bp, int* er
   }
 }
 
+// Robin-hood builds insert concurrently: two insertions of one key may both
+// land. Every qualifying build row counts the copies of its key within the
+// largest displacement from its home slot: two or more is a duplicate key,
+// none an insertion that failed.
+template <int HASH>
+__global__ void __launch_bounds__(256) k_build_verify_robin(const HkBuild* Bp, int* err) {
+  const HkBuild& B = *Bp;
+  v16i64 r = {};
+  const int64_t T = (int64_t)gridDim.x * blockDim.x;
+  const uint32_t mask = (1u << B.t.log2cap) - 1u;
+  for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < B.p.nrows; row += T) {
+    if (!eval_row<HK_BR, HK_LIN, HASH, false, HkShapeG>(B.p, row, r)) continue;
+    const int32_t key = static_cast<int32_t>(load_col(B.key, row));
+    if (key == -1) continue;
+    const uint32_t maxd = static_cast<uint32_t>(B.t.side[1]);
+    uint32_t pos = hslot<HASH>(static_cast<uint32_t>(key), B.p.hash.a[0], B.t.log2cap);
+    int copies = 0;
+    for (uint32_t d = 0; d <= maxd && d <= mask; ++d) {
+      const uint64_t w = B.t.slots[pos];
+      if (w == HK_EMPTY) break;
+      copies += static_cast<uint32_t>(w >> 32) == static_cast<uint32_t>(key);
+      pos = (pos + 1) & mask;
+    }
+    if (copies > 1) set_err(err, HK_ERR_DUPKEY);
+    if (copies == 0) set_err(err, HK_ERR_CAPACITY);
+  }
+}
+
 // ------------------------------------------------------------------ exclusive scan (u32 counts -> u32 offsets)
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 #pragma unroll
@@ -282,6 +310,8 @@ hipError_t hk_build(hipStream_t st, const HkBuild& B, const HkBuild* dB, int ht,
   DISPATCH2(ht, HT, DISPATCH2(hash, HS, hipLaunchKernelGGL((k_build<HT, HS>), g, b, 0, st, dB, err)));
   if (ht == HK_CUCKOO) {
     DISPATCH2(hash, HS, hipLaunchKernelGGL((k_build_verify<HS>), g, b, 0, st, dB, err));
+  } else if (B.t.robin) {
+    DISPATCH2(hash, HS, hipLaunchKernelGGL((k_build_verify_robin<HS>), g, b, 0, st, dB, err));
   }
   HK_CHECK_LAUNCH();
 }

@@ -22,7 +22,7 @@ hipError_t hk_scalar_shape(hipStream_t st, const HkPlan& P, const HkAggTable& T,
                            int strat, int64_t groups, int32_t wg, const HkIdent& id);
 template <class S>
 hipError_t hk_mp_filter_shape(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t threads,
-                              uint64_t* masks, uint32_t* counts);
+                              uint64_t* masks, uint32_t* counts, int unroll, int simd);
 template <class S>
 hipError_t hk_mp_project_shape(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t threads,
                                const uint64_t* masks, const uint32_t* offsets, const uint64_t* total, int64_t nact,
@@ -75,8 +75,8 @@ hipError_t hk_scalar_agg(hipStream_t st, const HkPlan& P, const HkAggTable& T, i
 }
 
 hipError_t hk_mp_filter(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t threads,
-                        uint64_t* masks, uint32_t* counts) {
-  BY_SHAPE(P, hk_mp_filter_shape<S>(st, P, mem, pred, ht, hash, threads, masks, counts));
+                        uint64_t* masks, uint32_t* counts, int unroll, int simd) {
+  BY_SHAPE(P, hk_mp_filter_shape<S>(st, P, mem, pred, ht, hash, threads, masks, counts, unroll, simd));
 }
 
 hipError_t hk_mp_project(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t threads,

@@ -16,7 +16,10 @@
 // bit per row (64-bit words, one per 64-row block) plus the number of flags
 // per scan unit (a 64-row block for coalesced access, a thread's chunk for
 // sequential access).
-template <int MEM, int PRED, int HT, int HASH, class S>
+// U (coalesced access): rows per loop iteration, the loop unrolled U times
+// with element access offsets 0..U-1 (Section 6.1); the first load phase of
+// the next U-1 rows is in flight while one is evaluated.
+template <int MEM, int PRED, int HT, int HASH, class S, int U>
 __global__ void __launch_bounds__(256) k_mp_filter(HkPlan P, uint64_t* __restrict__ masks, uint32_t* __restrict__ counts) {
   v16i64 r = {};
   const int64_t n = P.nrows;
@@ -27,7 +30,7 @@ __global__ void __launch_bounds__(256) k_mp_filter(HkPlan P, uint64_t* __restric
     // id += threads. Software pipeline: the first load phase of the next AH
     // blocks is in flight while a block is evaluated; the loop is unrolled by
     // the ring size so every buffer index is a constant.
-    constexpr int AH = 3, NB = AH + 1;
+    constexpr int NB = U, AH = U - 1;
     HkFirst<S> f[NB] = {};
     const int64_t b0 = gt - __lane_id();
     // rows past the end fetch the last row again (the fetch count stays fixed)
@@ -69,6 +72,86 @@ __global__ void __launch_bounds__(256) k_mp_filter(HkPlan P, uint64_t* __restric
       cnt += static_cast<uint32_t>(__popcll(m));
     }
     counts[gt] = cnt;
+  }
+}
+
+// Phase 1 with FILTER in SIMD mode (coalesced, no probes): the scan of Zhou
+// and Ross checks the predicate on several tuples at once. Each lane loads 4
+// consecutive rows of every filter column with one vector load and evaluates
+// the conjunction on all 4; a wave covers 256 rows, whose four 64-bit flag
+// words are interleaved from four ballots (lane i's row j is bit 4i + j of
+// its word). Filter columns are 16-byte aligned (checked on the host).
+__device__ __forceinline__ uint64_t spread4(uint64_t x) {  // bit i -> bit 4i, i < 16
+  x &= 0xFFFFull;
+  x = (x | (x << 24)) & 0x000000FF000000FFull;
+  x = (x | (x << 12)) & 0x000F000F000F000Full;
+  x = (x | (x << 6)) & 0x0303030303030303ull;
+  x = (x | (x << 3)) & 0x1111111111111111ull;
+  return x;
+}
+
+__device__ __forceinline__ void load4(const HkCol& c, int64_t r0, int64_t* v) {
+  if (c.dtype == HK_T_I32) {
+    const int4 q = *reinterpret_cast<const int4*>(static_cast<const int32_t*>(c.ptr) + r0);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  } else if (c.dtype == HK_T_I64) {
+    const longlong2 a = *reinterpret_cast<const longlong2*>(static_cast<const int64_t*>(c.ptr) + r0);
+    const longlong2 b = *reinterpret_cast<const longlong2*>(static_cast<const int64_t*>(c.ptr) + r0 + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  } else {
+    const int32_t q = *reinterpret_cast<const int32_t*>(static_cast<const int8_t*>(c.ptr) + r0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = static_cast<int8_t>(static_cast<uint32_t>(q) >> (8 * j));
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) k_mp_filter_simd(HkPlan P, uint64_t* __restrict__ masks,
+                                                         uint32_t* __restrict__ counts) {
+  const int64_t n = P.nrows;
+  const int64_t T = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = __lane_id();
+  for (int64_t base = 4 * (gt - lane); base < n; base += 4 * T) {
+    const int64_t r0 = base + 4 * lane;
+    int64_t v[S::colA > 0 ? S::colA : 1][4];
+    if (r0 + 3 < n) {
+#pragma unroll
+      for (int c = 0; c < S::colA; ++c)
+        if (c < P.ncolA) load4(P.colA[c], r0, v[c]);
+    } else {
+      // the last rows, one at a time (no load past the column's end)
+#pragma unroll
+      for (int c = 0; c < S::colA; ++c)
+        if (c < P.ncolA)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[c][j] = r0 + j < n ? load_col(P.colA[c], r0 + j) : 0;
+    }
+    uint32_t m4 = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bool pass = r0 + j < n;
+#pragma unroll
+      for (int f = 0; f < S::filters; ++f) {
+        if (f >= P.nfilters) break;
+        int64_t x = 0;
+#pragma unroll
+        for (int c = 0; c < S::colA; ++c)
+          if (c < P.ncolA && P.colA[c].reg == P.filters[f].reg) x = v[c][j];
+        pass = pass & (x >= P.filters[f].lo) & (x <= P.filters[f].hi);
+      }
+      m4 |= static_cast<uint32_t>(pass) << j;
+    }
+    uint64_t b[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = __ballot((m4 >> j) & 1u);
+    if (lane < 4 && base + 64 * lane < n) {
+      uint64_t w = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) w |= spread4(b[j] >> (16 * lane)) << j;
+      masks[(base >> 6) + lane] = w;
+      counts[(base >> 6) + lane] = static_cast<uint32_t>(__popcll(w));
+    }
   }
 }
 
@@ -276,10 +359,29 @@ __global__ void __launch_bounds__(64) k_sp(HkPlan P, HkOut tmp, int64_t region, 
 // ================================================================== launchers for one shape class
 template <class S>
 hipError_t hk_mp_filter_shape(hipStream_t st, const HkPlan& P, int mem, int pred, int ht, int hash, int64_t threads,
-                              uint64_t* masks, uint32_t* counts) {
+                              uint64_t* masks, uint32_t* counts, int unroll, int simd) {
   const dim3 g(static_cast<uint32_t>((threads + 255) / 256)), b(256);
-  DISPATCH2(mem, M, DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS,
-            hipLaunchKernelGGL((k_mp_filter<M, PR, HT, HS, S>), g, b, 0, st, P, masks, counts)))));
+  if (simd) {
+    // coalesced scans of filter columns only (no probes)
+    if constexpr (S::filters > 0) {
+      if (mem != HK_COAL || P.nprobes > 0) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_mp_filter_simd<S>), g, b, 0, st, P, masks, counts);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+  if (mem == HK_COAL) {
+    const int u = unroll == 1 ? 1 : unroll == 2 ? 2 : 4;  // 0: the default 4
+    DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS, switch (u) {
+      case 1: hipLaunchKernelGGL((k_mp_filter<HK_COAL, PR, HT, HS, S, 1>), g, b, 0, st, P, masks, counts); break;
+      case 2: hipLaunchKernelGGL((k_mp_filter<HK_COAL, PR, HT, HS, S, 2>), g, b, 0, st, P, masks, counts); break;
+      default: hipLaunchKernelGGL((k_mp_filter<HK_COAL, PR, HT, HS, S, 4>), g, b, 0, st, P, masks, counts);
+    })));
+  } else {
+    DISPATCH2(pred, PR, DISPATCH2(ht, HT, DISPATCH2(hash, HS,
+              hipLaunchKernelGGL((k_mp_filter<HK_SEQ, PR, HT, HS, S, 1>), g, b, 0, st, P, masks, counts))));
+  }
   return hipGetLastError();
 }
 
@@ -303,7 +405,7 @@ hipError_t hk_sp_shape(hipStream_t st, const HkPlan& P, int mem, int pred, int h
 }
 
 template hipError_t hk_mp_filter_shape<HK_SHAPE_CLASS>(hipStream_t, const HkPlan&, int, int, int, int, int64_t,
-                                                       uint64_t*, uint32_t*);
+                                                       uint64_t*, uint32_t*, int, int);
 template hipError_t hk_mp_project_shape<HK_SHAPE_CLASS>(hipStream_t, const HkPlan&, int, int, int, int, int64_t,
                                                         const uint64_t*, const uint32_t*, const uint64_t*, int64_t,
                                                         const HkOut&);

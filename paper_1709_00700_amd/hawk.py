@@ -29,6 +29,8 @@ HAWK_RES_I64, HAWK_RES_I128, HAWK_RES_F64 = 3, 4, 5
 ARITH = {"add": 1, "sub": 2, "mul": 3}
 AGG_FN = {"count": 1, "sum": 2, "min": 3, "max": 4, "avg": 5}
 HAWK_EXPLORE_EXHAUSTIVE, HAWK_EXPLORE_FEATURE_WISE = 0, 1
+HAWK_LINEAR_PROBING, HAWK_CUCKOO, HAWK_ROBIN_HOOD = 0, 1, 2
+HAWK_DIM_ROBIN_HOOD, HAWK_DIM_UNROLL, HAWK_DIM_SIMD_FILTER = 1, 2, 4
 
 # every symbol include/hawk.h declares
 EXPORTS = [
@@ -45,7 +47,7 @@ EXPORTS = [
     "hawk_model_train", "hawk_model_predict", "hawk_mlp_forward_dev", "hawk_mlp_grad_dev", "hawk_model_pick",
     "hawk_model_pick_ensemble",
     "hawk_batch_create", "hawk_batch_free", "hawk_batch_run", "hawk_batch_time", "hawk_batch_autotune",
-    "hawk_batch_opts_get", "hawk_batch_result", "hawk_ctx_set_jit", "hawk_jit_stats",
+    "hawk_batch_opts_get", "hawk_batch_result", "hawk_ctx_set_jit", "hawk_jit_stats", "hawk_ctx_set_variant_dims",
 ]
 
 
@@ -90,7 +92,7 @@ class hawk_rel(ctypes.Structure):
 class hawk_variant(ctypes.Structure):
     _fields_ = [("proj_strategy", ctypes.c_uint8), ("mem", ctypes.c_uint8), ("pred", ctypes.c_uint8),
                 ("ht", ctypes.c_uint8), ("hash", ctypes.c_uint8), ("agg_strategy", ctypes.c_uint8),
-                ("reserved0", ctypes.c_uint8), ("reserved1", ctypes.c_uint8),
+                ("unroll", ctypes.c_uint8), ("filter_mode", ctypes.c_uint8),
                 ("thread_mult", ctypes.c_uint32), ("wg_size", ctypes.c_uint32)]
 
     def as_dict(self):
@@ -186,6 +188,7 @@ def L():
             "hawk_batch_opts_get": ([vp, P(hawk_batch_opts)], i32),
             "hawk_batch_result": ([vp, i32, P(vp)], i32),
             "hawk_ctx_set_jit": ([vp, i32], i32),
+            "hawk_ctx_set_variant_dims": ([vp, ctypes.c_uint32], i32),
             "hawk_jit_stats": ([vp, P(i64), P(ctypes.c_double)], i32),
         }
         for name, (args, res) in sig.items():
@@ -203,8 +206,9 @@ def check(st: int, ctx=None):
 
 
 # ---------------------------------------------------------------- variants
-def variant(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=1024, wg_size=256):
-    return hawk_variant(proj_strategy, mem, pred, ht, hash, agg_strategy, 0, 0, thread_mult, wg_size)
+def variant(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=1024, wg_size=256, unroll=0,
+            filter_mode=0):
+    return hawk_variant(proj_strategy, mem, pred, ht, hash, agg_strategy, unroll, filter_mode, thread_mult, wg_size)
 
 
 def format_variant(v: hawk_variant) -> str:
@@ -255,6 +259,10 @@ class Context:
         """Run-time compiled aggregation kernels for each plan structure (see hawk.h)."""
         check(L().hawk_ctx_set_jit(self.handle, int(on)), self.handle)
         self.jit = bool(on)
+
+    def set_variant_dims(self, dims: int):
+        """Extra variant dimensions (HAWK_DIM_*; 0 = the paper's space)."""
+        check(L().hawk_ctx_set_variant_dims(self.handle, int(dims)), self.handle)
 
     def jit_stats(self):
         """(kernels compiled, total compile milliseconds)."""

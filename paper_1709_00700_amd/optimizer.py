@@ -68,7 +68,7 @@ def variant_key(q, v, tabled: bool | None = None) -> str:
     if tabled is None:
         tabled = any(x.ht or x.hash for x in hawk.variant_space(q))
     if not tabled:
-        v = hawk.hawk_variant(v.proj_strategy, v.mem, v.pred, 0, 0, v.agg_strategy, v.reserved0, v.reserved1,
+        v = hawk.hawk_variant(v.proj_strategy, v.mem, v.pred, 0, 0, v.agg_strategy, v.unroll, v.filter_mode,
                               v.thread_mult, v.wg_size)
     return hawk.format_variant(v)
 

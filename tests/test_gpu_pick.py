@@ -67,3 +67,37 @@ def test_learned_picks_beat_algorithm1_per_workload(ctx):
     assert pq["model"]["total_ratio"] < pq["alg1"]["total_ratio"]
     assert pq["model"]["geomean_ratio"] <= 1.15
     ens.free()
+
+
+def test_learned_picks_on_the_extended_space(ctx):
+    """The same evaluation over the space with the extra dimensions (robin
+    hood, unrolling, SIMD filter): the network, retrained on timings sampled
+    from that space, picks within 1.15x of the exhaustive best on the
+    geometric mean and beats Algorithm 1's per-workload variants (searched
+    over the same space) on total time."""
+    ctx.set_variant_dims(hawk.HAWK_DIM_ROBIN_HOOD | hawk.HAWK_DIM_UNROLL | hawk.HAWK_DIM_SIMD_FILTER)
+    pool, lim = 2_000_000, 10.0
+    seed_train, seed_test = dg.MASTER_SEED + 2005, dg.MASTER_SEED + 25
+    tr_pools = dg.c5_pools(pool, seed_train)
+    tr = dg.c5_queries(40, pool, seed_train, min_rows=10_000, max_rows=pool)
+    tr_h = optimizer.register_c5(ctx, tr_pools, tr, prefix="xtrain_")
+    te_pools = dg.c5_pools(pool, seed_test)
+    te = dg.c5_queries(12, pool, seed_test, min_rows=10_000, max_rows=pool)
+    te_h = optimizer.register_c5(ctx, te_pools, te, prefix="xtest_")
+    say("extended space sizes", sorted({len(hawk.variant_space(h)) for h in te_h}))
+    X, y = optimizer.training_set(ctx, tr_h, 64, reps=2, limit_ms=lim, seed=9, progress=say)
+    ens = optimizer.Ensemble(ctx, size=5, penalty=1.0, seed=11)
+    ens.train(X, y, epochs=300, batch=512, lr=3e-3, seed=2)
+    X, y = optimizer.refine(ctx, tr_h, ens, X, y, top=4, rounds=2, reps=2, limit_ms=lim, progress=say,
+                            epochs=300, batch=512, lr=3e-3, seed=2)
+    alg1 = optimizer.alg1_per_kind(ctx, te_h, reps=2, limit_ms=lim)
+    picker = optimizer.WithFallback(ens, {k: v for k, (v, _) in alg1.items()})
+    pq = optimizer.pick_quality(ctx, te_h, picker, reps=2, limit_ms=lim, alg1=alg1, progress=say,
+                                extra={"ensemble": ens}, confirm_reps=5)
+    say(json.dumps({k: pq[k] for k in ("model", "ensemble", "alg1")}))
+    new = [r for r in pq["per_query"] if any(t in r["best"] for t in ("robin", "unroll", "simd"))]
+    say("queries whose best variant uses an extra dimension:", len(new), "of", len(pq["per_query"]))
+    assert pq["model"]["pruned_picks"] == 0
+    assert pq["model"]["geomean_ratio"] <= 1.15
+    assert pq["model"]["total_ratio"] <= pq["alg1"]["total_ratio"]
+    ens.free()

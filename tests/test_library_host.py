@@ -323,3 +323,44 @@ def test_cross_join_quotient_by_reciprocal():
         for v in vs + [d - 1, d, d + 1, 2 * d - 1]:
             if v < 1 << 32:
                 assert (m * v) >> 64 == v // d, (d, v)
+
+
+def test_extra_variant_dimensions(plan_ctx):
+    """Extra dimensions (hawk_ctx_set_variant_dims) multiply in where they
+    apply: unrolling (2, 1) and the SIMD filter for multi-pass coalesced
+    projections (the filter only without probes), robin hood as a third
+    table kind for pipelines with probes; features code them ordinally."""
+    tables, c1 = dg.c1_projection(n=10)
+    plan_ctx.register_shapes({"xd_t": tables["t"]})
+    c1["main"]["table"] = "xd_t"
+    tables, c3 = dg.c3_star_join(n=10, dims=(5, 5, 5, 5))
+    plan_ctx.register_shapes({"xd_" + t: c for t, c in tables.items()})
+    c3["main"]["table"] = "xd_f"
+    for b in c3["builds"]:
+        b["table"] = "xd_" + b["table"]
+    proj_probe = {"builds": c3["builds"][:1],
+                  "main": {"table": "xd_f", "filters": [], "probes": [("fk0", 0, "p")], "arith": [], "project": ["p"]}}
+    q1, q3, qp = (hawk.build_query(plan_ctx, s) for s in (c1, c3, proj_probe))
+    assert [len(hawk.variant_space(q)) for q in (q1, q3, qp)] == [32, 896, 128]
+    plan_ctx.set_variant_dims(hawk.HAWK_DIM_UNROLL)
+    assert len(hawk.variant_space(q1)) == 4 + 14 + 14 * 3
+    plan_ctx.set_variant_dims(hawk.HAWK_DIM_UNROLL | hawk.HAWK_DIM_SIMD_FILTER)
+    vs = hawk.variant_space(q1)
+    assert len(vs) == 4 + 14 + 14 * 4
+    simd = [v for v in vs if v.filter_mode]
+    assert len(simd) == 14 and all(v.mem == 1 and v.proj_strategy == 1 for v in simd)
+    assert "filter=simd" in hawk.format_variant(simd[0])
+    assert q1.features(simd[0])[9] == simd[0].pred + 2
+    u1 = next(v for v in vs if v.unroll == 1)
+    assert q1.features(u1)[10] == 1 + 2 * 2 and "unroll=1" in hawk.format_variant(u1)
+    plan_ctx.set_variant_dims(hawk.HAWK_DIM_ROBIN_HOOD | hawk.HAWK_DIM_SIMD_FILTER)
+    assert len(hawk.variant_space(q3)) == 896 // 4 * 6       # three table kinds with probes
+    vp = hawk.variant_space(qp)
+    assert len(vp) == 128 // 4 * 6                          # no SIMD filter with probes
+    robin = next(v for v in vp if v.ht == hawk.HAWK_ROBIN_HOOD)
+    assert "ht=robin" in hawk.format_variant(robin) and qp.features(robin)[11] == 2 * 2 + robin.hash
+    assert len(hawk.variant_space(q1)) == 32 + 14             # no table: no robin hood
+    plan_ctx.set_variant_dims(0)
+    assert [len(hawk.variant_space(q)) for q in (q1, q3, qp)] == [32, 896, 128]
+    with pytest.raises(hawk.HawkError):
+        plan_ctx.set_variant_dims(64)
