@@ -48,9 +48,10 @@ DEFAULT_VARIANTS = {
     "c3": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=1, agg_strategy=0, thread_mult=8, wg_size=512),
     "c4": dict(proj_strategy=1, mem=1, pred=1, ht=0, hash=1, agg_strategy=0, thread_mult=8, wg_size=512),
 }
-# the 256M-row point: the exhaustive search's best over the 32 projection variants
+# the 256M-row point: the best multi-pass variant of the extended space
+# (the SIMD filter; the best of the paper's 32 is the same without it)
 DEFAULT_VARIANTS["c1_256m"] = dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=65536,
-                                   wg_size=256)
+                                   wg_size=256, filter_mode=1)
 
 # algorithmic bytes per input row: the columns a pipeline must read once, plus
 # (projection) the qualifying rows' other columns and outputs at the

@@ -1215,10 +1215,23 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
       if (!ok) return set_error(ctx, HAWK_E_INFEASIBLE, "the SIMD filter needs a coalesced scan of 16-byte aligned "
                                                         "filter columns without probes");
     }
+    // kernels compiled at run time for the plan's structure when the context does so
+    const bool jit = X.allow_jit && ctx->jit && P.xinner == 0;
+    std::string jmsg;
+    auto jit_err = [&](hipError_t e) {
+      if (e != hipSuccess && !jmsg.empty()) ctx->jit_cache.last_error = jmsg;
+      return e;
+    };
     {
       ProfScope ps(X.prof(), "k_mp_filter");
-      LAUNCH(hk_mp_filter(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, counts, v->unroll, v->filter_mode),
-             "filter kernel");
+      if (jit)
+        LAUNCH(jit_err(jit_mp_filter_launch(ctx->jit_cache, jmsg, X.st, P, v->filter_mode, v->mem, v->pred, v->ht,
+                                            v->hash, v->unroll, threads, masks, counts)),
+               "filter kernel");
+      else
+        LAUNCH(hk_mp_filter(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, counts, v->unroll,
+                            v->filter_mode),
+               "filter kernel");
     }
     {
       ProfScope ps(X.prof(), "k_scan");
@@ -1226,8 +1239,17 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
     }
     {
       ProfScope ps(X.prof(), "k_mp_project");
-      LAUNCH(hk_mp_project(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, offsets, res->d_count, nact,
-                           out, n), "projection kernel");
+      if (jit) {
+        HkOut O = {};
+        for (int c = 0; c < P.nproj; ++c) O.col[c] = out[c];
+        O.dump = n;
+        LAUNCH(jit_err(jit_mp_project_launch(ctx->jit_cache, jmsg, X.st, P, v->mem, v->pred, v->ht, v->hash, threads,
+                                             masks, offsets, res->d_count, nact, O)),
+               "projection kernel");
+      } else {
+        LAUNCH(hk_mp_project(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, offsets, res->d_count, nact,
+                             out, n), "projection kernel");
+      }
     }
   } else {
     const int64_t inst = ctx->num_cus;  // one pipeline instance per compute unit
@@ -1568,8 +1590,22 @@ extern "C" hawk_status hawk_execute_noalloc(hawk_ctx* ctx, const hawk_query* q, 
 // ------------------------------------------------------------------ timing
 // Compiles the run-time kernel that executing (q, v) will launch, so that a
 // timed run measures the kernels and not the compiler.
-static hawk_status prepare_run_time_kernel(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v) {
-  if (!ctx->jit || q->kind == 1 || q->main.ngroup == 0 || v->ht != HAWK_LINEAR_PROBING || q->main.xinner > 0)
+static hawk_status prepare_run_time_kernel(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* vin) {
+  // robin-hood join tables run the kernels of linear probing
+  hawk_variant vv = *vin;
+  if (vv.ht == HAWK_ROBIN_HOOD) vv.ht = HAWK_LINEAR_PROBING;
+  const hawk_variant* v = &vv;
+  if (ctx->jit && q->kind == 1 && v->proj_strategy == HAWK_MULTI_PASS && q->main.xinner == 0 && v->ht <= 1) {
+    // the multi-pass projection's filter and projection kernels
+    const int ht = v->ht;
+    std::string msg;
+    const int which = v->filter_mode ? JIT_MP_FILTER_SIMD : JIT_MP_FILTER;
+    if (jit_proj_prepare(ctx->jit_cache, msg, q->main, which, v->mem, v->pred, ht, v->hash, v->unroll) != hipSuccess ||
+        jit_proj_prepare(ctx->jit_cache, msg, q->main, JIT_MP_PROJECT, v->mem, v->pred, ht, v->hash, 0) != hipSuccess)
+      return set_error(ctx, HAWK_E_DEVICE, "run-time compilation: " + msg);
+    return HAWK_OK;
+  }
+  if (!ctx->jit || q->kind == 1 || q->main.ngroup == 0 || v->ht == HAWK_CUCKOO || q->main.xinner > 0)
     return HAWK_OK;  // (plans with a CROSS_JOIN run the kernels compiled ahead of time)
   if (v->wg_size < 1 || v->wg_size > 1024 || v->thread_mult < 1) return HAWK_OK;  // execution reports it
   HkAggTable T{};

@@ -28,19 +28,15 @@ void JitCache::release() {
   kernels.clear();
 }
 
-std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash, int strat, bool spill,
-                           size_t lds_bytes) {
-  std::ostringstream o;
-  // the local table is a static LDS array of the launch's size (no dynamic LDS)
-  const size_t words = lds_bytes / 8 > 0 ? (lds_bytes + 7) / 8 : 1;
-  o << "#include \"hk_agg_body.h\"\n"
-       "extern \"C\" __global__ void __launch_bounds__(1024) hk_jit_agg(HkPlan Prt, HkAggTable T, uint32_t llog2,\n"
-       "    HkIdent id, int64_t nwg, int* err, HkSpill sp, int32_t reps) {\n"
-       "  __shared__ uint64_t lds[" << words << "];\n"
-       "  HkPlan P;\n"
+namespace {
+
+// `P`'s structure as constants of a local plan P; the data that differs
+// between queries of one structure is copied from the argument Prt
+void emit_structure(std::ostringstream& o, const HkPlan& P) {
+  o << "  HkPlan P;\n"
        "  P.nrows = Prt.nrows;\n  P.hash = Prt.hash;\n";
   o << "  P.ncolA = " << P.ncolA << "; P.ncolB = " << P.ncolB << "; P.ncolC = " << P.ncolC
-    << "; P.nfilters = " << P.nfilters << ";\n";
+    << "; P.nfilters = " << P.nfilters << "; P.liveA = " << P.liveA << "u; P.xinner = 0;\n";
   for (int c = 0; c < P.ncolA; ++c) emit_col(o, "colA", c, P.colA[c]);
   for (int c = 0; c < P.ncolB; ++c) emit_col(o, "colB", c, P.colB[c]);
   for (int c = 0; c < P.ncolC; ++c) emit_col(o, "colC", c, P.colC[c]);
@@ -65,23 +61,72 @@ std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash,
     o << "  P.aggs[" << a << "].fn = " << int(A.fn) << "; P.aggs[" << a << "].wide = " << int(A.wide) << "; P.aggs["
       << a << "].reg = " << int(A.reg) << "; P.aggs[" << a << "].word = " << A.word << ";\n";
   }
-  o << "  P.nproj = 0;\n  P.slot_words = " << P.slot_words << ";\n";
-  o << "  agg_body<" << mem << ", " << pred << ", " << ht << ", " << hash << ", " << strat << ", HkShape<" << P.ncolA
-    << ", " << P.nfilters << ", " << P.ncolB << ", " << P.nprobes << ", " << P.ncolC << ", " << P.narith << ", "
-    << P.naggs << ", 0>, " << (spill ? "true" : "false") << ">(P, T, llog2, id, nwg, err, sp, reps, lds);\n}\n";
+  o << "  P.nproj = " << P.nproj << ";\n";
+  for (int c = 0; c < P.nproj; ++c) o << "  P.preg[" << c << "] = " << P.preg[c] << ";\n";
+  o << "  P.slot_words = " << P.slot_words << ";\n";
+}
+
+// the compile-time shape of exactly this plan's counts
+std::string exact_shape(const HkPlan& P, int naggs, int nproj) {
+  std::ostringstream o;
+  o << "HkShape<" << P.ncolA << ", " << P.nfilters << ", " << P.ncolB << ", " << P.nprobes << ", " << P.ncolC << ", "
+    << P.narith << ", " << naggs << ", " << nproj << ">";
+  return o.str();
+}
+
+}  // namespace
+
+std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash, int strat, bool spill,
+                           size_t lds_bytes) {
+  std::ostringstream o;
+  // the local table is a static LDS array of the launch's size (no dynamic LDS)
+  const size_t words = lds_bytes / 8 > 0 ? (lds_bytes + 7) / 8 : 1;
+  o << "#include \"hk_agg_body.h\"\n"
+       "extern \"C\" __global__ void __launch_bounds__(1024) hk_jit_agg(HkPlan Prt, HkAggTable T, uint32_t llog2,\n"
+       "    HkIdent id, int64_t nwg, int* err, HkSpill sp, int32_t reps) {\n"
+       "  __shared__ uint64_t lds[" << words << "];\n";
+  HkPlan Q = P;
+  Q.nproj = 0;
+  emit_structure(o, Q);
+  o << "  agg_body<" << mem << ", " << pred << ", " << ht << ", " << hash << ", " << strat << ", "
+    << exact_shape(P, P.naggs, 0) << ", " << (spill ? "true" : "false") << ">(P, T, llog2, id, nwg, err, sp, reps, lds);\n}\n";
+  return o.str();
+}
+
+std::string jit_proj_source(const HkPlan& P, int which, int mem, int pred, int ht, int hash, int unroll) {
+  std::ostringstream o;
+  const std::string S = exact_shape(P, 0, P.nproj);
+  const int u = unroll == 1 ? 1 : unroll == 2 ? 2 : 4;
+  o << "#include \"hk_proj_body.h\"\n";
+  if (which == JIT_MP_PROJECT) {
+    o << "extern \"C\" __global__ void __launch_bounds__(256) hk_jit_proj(HkPlan Prt, const uint64_t* masks,\n"
+         "    const uint32_t* offsets, const uint64_t* total, int64_t nact, HkOut O) {\n";
+    emit_structure(o, P);
+    o << "  mp_project_body<" << mem << ", " << pred << ", " << ht << ", " << hash << ", " << S
+      << ">(P, masks, offsets, total, nact, O);\n}\n";
+  } else {
+    o << "extern \"C\" __global__ void __launch_bounds__(256) hk_jit_proj(HkPlan Prt, uint64_t* masks,\n"
+         "    uint32_t* counts) {\n";
+    emit_structure(o, P);
+    if (which == JIT_MP_FILTER_SIMD) o << "  mp_filter_simd_body<" << S << ">(P, masks, counts);\n}\n";
+    else
+      o << "  mp_filter_body<" << mem << ", " << pred << ", " << ht << ", " << hash << ", " << S << ", "
+        << (mem == HK_COAL ? u : 1) << ">(P, masks, counts);\n}\n";
+  }
   return o.str();
 }
 
 namespace {
 
-hipError_t get_kernel(JitCache& cache, std::string& err_msg, const std::string& src, hipFunction_t& fn) {
+hipError_t get_kernel(JitCache& cache, std::string& err_msg, const std::string& src, hipFunction_t& fn,
+                      const char* name = "hk_jit_agg") {
   auto it = cache.kernels.find(src);
   if (it == cache.kernels.end()) {
     const auto t0 = std::chrono::steady_clock::now();
     hiprtcProgram prog;
-    const char* hs[] = {kSrcPlan, kSrcDevice, kSrcAggBody};
-    const char* hn[] = {"hawk_plan.h", "hawk_device.h", "hk_agg_body.h"};
-    if (hiprtcCreateProgram(&prog, src.c_str(), "hk_jit_agg.hip", 3, hs, hn) != HIPRTC_SUCCESS) {
+    const char* hs[] = {kSrcPlan, kSrcDevice, kSrcAggBody, kSrcProjBody};
+    const char* hn[] = {"hawk_plan.h", "hawk_device.h", "hk_agg_body.h", "hk_proj_body.h"};
+    if (hiprtcCreateProgram(&prog, src.c_str(), "hk_jit.hip", 4, hs, hn) != HIPRTC_SUCCESS) {
       err_msg = "hipRTC: program creation failed";
       return hipErrorInvalidValue;
     }
@@ -108,7 +153,7 @@ hipError_t get_kernel(JitCache& cache, std::string& err_msg, const std::string& 
       err_msg = "module load of the specialised kernel failed";
       return e;
     }
-    e = hipModuleGetFunction(&k.fn, k.module, "hk_jit_agg");
+    e = hipModuleGetFunction(&k.fn, k.module, name);
     if (e != hipSuccess) {
       (void)hipModuleUnload(k.module);
       err_msg = "specialised kernel not found in its module";
@@ -161,4 +206,37 @@ hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st,
   void* args[] = {&Pa, &Ta, &ll, &ida, &nwg, &erra, &spa, &rp};
   const dim3 g = hk_wg_grid(groups);
   return hipModuleLaunchKernel(fn, g.x, g.y, 1, static_cast<uint32_t>(wg), 1, 1, 0, st, args, nullptr);
+}
+
+hipError_t jit_proj_prepare(JitCache& cache, std::string& err_msg, const HkPlan& P, int which, int mem, int pred,
+                            int ht, int hash, int unroll) {
+  hipFunction_t fn;
+  return get_kernel(cache, err_msg, jit_proj_source(P, which, mem, pred, ht, hash, unroll), fn, "hk_jit_proj");
+}
+
+hipError_t jit_mp_filter_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P, int simd,
+                                int mem, int pred, int ht, int hash, int unroll, int64_t threads, uint64_t* masks,
+                                uint32_t* counts) {
+  hipFunction_t fn;
+  const int which = simd ? JIT_MP_FILTER_SIMD : JIT_MP_FILTER;
+  const hipError_t ge =
+      get_kernel(cache, err_msg, jit_proj_source(P, which, mem, pred, ht, hash, unroll), fn, "hk_jit_proj");
+  if (ge != hipSuccess) return ge;
+  HkPlan Pa = P;
+  void* args[] = {&Pa, &masks, &counts};
+  return hipModuleLaunchKernel(fn, static_cast<uint32_t>((threads + 255) / 256), 1, 1, 256, 1, 1, 0, st, args, nullptr);
+}
+
+hipError_t jit_mp_project_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P, int mem,
+                                 int pred, int ht, int hash, int64_t threads, const uint64_t* masks,
+                                 const uint32_t* offsets, const uint64_t* total, int64_t nact, const HkOut& O) {
+  hipFunction_t fn;
+  const hipError_t ge =
+      get_kernel(cache, err_msg, jit_proj_source(P, JIT_MP_PROJECT, mem, pred, ht, hash, 0), fn, "hk_jit_proj");
+  if (ge != hipSuccess) return ge;
+  HkPlan Pa = P;
+  HkOut Oa = O;
+  int64_t na = nact;
+  void* args[] = {&Pa, &masks, &offsets, &total, &na, &Oa};
+  return hipModuleLaunchKernel(fn, static_cast<uint32_t>((threads + 255) / 256), 1, 1, 256, 1, 1, 0, st, args, nullptr);
 }

@@ -36,3 +36,17 @@ hipError_t jit_agg_prepare(JitCache& cache, std::string& err_msg, const HkPlan& 
 hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P,
                           const HkAggTable& T, int mem, int pred, int hash, int strat, int64_t groups, int32_t wg,
                           uint32_t llog2, const HkIdent& id, int* err, const HkSpill* sp, int32_t reps);
+
+// Run-time specialisation of the multi-pass projection kernels (bodies in
+// hk_proj_body.h) for one plan structure, same arguments and launch shape as
+// the ahead-of-time kernels.
+enum { JIT_MP_FILTER = 0, JIT_MP_FILTER_SIMD = 1, JIT_MP_PROJECT = 2 };
+std::string jit_proj_source(const HkPlan& P, int which, int mem, int pred, int ht, int hash, int unroll);
+hipError_t jit_proj_prepare(JitCache& cache, std::string& err_msg, const HkPlan& P, int which, int mem, int pred,
+                            int ht, int hash, int unroll);
+hipError_t jit_mp_filter_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P, int simd,
+                                int mem, int pred, int ht, int hash, int unroll, int64_t threads, uint64_t* masks,
+                                uint32_t* counts);
+hipError_t jit_mp_project_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P, int mem,
+                                 int pred, int ht, int hash, int64_t threads, const uint64_t* masks,
+                                 const uint32_t* offsets, const uint64_t* total, int64_t nact, const HkOut& O);

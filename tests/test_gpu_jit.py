@@ -78,3 +78,35 @@ def test_jit_kernels_are_shared_by_one_structure(ctx):
         spec["main"]["filters"] = [("v", lo, hi)]
         run_variants(ctx, tables, spec, [v], label=f"share{i}")
     assert ctx.jit_stats()[0] == 1
+
+
+@pytest.mark.parametrize("n", [1, 4097, 1_000_000])
+def test_jit_projection_every_multi_pass_variant(ctx, n):
+    """The multi-pass filter and projection kernels compiled at run time for
+    the plan: every multi-pass variant of C1, with the extra dimensions
+    (unrolling, SIMD filter), against the oracle."""
+    ctx.set_variant_dims(hawk.HAWK_DIM_UNROLL | hawk.HAWK_DIM_SIMD_FILTER)
+    tables, spec = dg.c1_projection(n=n)
+    tables = {f"jp{n}": tables["t"]}
+    spec["main"]["table"] = f"jp{n}"
+    p = hawk.PlanningContext()
+    p.set_variant_dims(hawk.HAWK_DIM_UNROLL | hawk.HAWK_DIM_SIMD_FILTER)
+    p.register_shapes(tables)
+    vs = [v for v in hawk.variant_space(hawk.build_query(p, spec)) if v.proj_strategy == 1]
+    p.close()
+    k0 = ctx.jit_stats()[0]
+    run_variants(ctx, tables, spec, vs, label=f"jit-proj n={n}")
+    assert ctx.jit_stats()[0] > k0
+
+
+def test_jit_projection_with_probes(ctx):
+    tables, spec = dg.c3_star_join(n=30_000, dims=(50, 400, 60, 160), sel=(60, 50, 60, 40))
+    spec["main"] = {"table": "f", "filters": [("rev", 0, 700_000)],
+                    "probes": [("fk0", 0, "p0"), ("fk2", 2, "p2")],
+                    "arith": [("x", "mul", "p0", "rev"), ("y", "sub", "x", "p2")],
+                    "project": ["y", "fk0", "p2"]}
+    spec["builds"] = spec["builds"][:3]
+    vs = [hawk.variant(proj_strategy=1, mem=m, pred=pr, ht=h, hash=x, thread_mult=64)
+          for m in (0, 1) for pr in (0, 1) for h in (0, 1, 2) for x in (0, 1)]
+    ctx.set_variant_dims(hawk.HAWK_DIM_ROBIN_HOOD)
+    run_variants(ctx, tables, spec, vs, label="jit-proj-join")
