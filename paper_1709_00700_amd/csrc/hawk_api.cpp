@@ -901,15 +901,17 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
   const int64_t wg_lds = whole_cu ? std::min<int64_t>(ctx->lds_bytes, kCuLds) - 1024 : kSpillLds;
   const int64_t table_budget = whole_cu ? wg_lds - 8192 : kLdsBudget;
   if (v->agg_strategy == HAWK_LOCAL) {
-    const uint32_t want = std::max<uint32_t>(4, ceil_log2(static_cast<uint64_t>(groups_hint) * 2));
+    // four slots per expected group: few keys then share a group of four
+    // slots (a lookup reads one group)
+    const uint32_t want = std::max<uint32_t>(4, ceil_log2(static_cast<uint64_t>(groups_hint) * 4));
     uint32_t fit = 0;
     while ((int64_t(2) << fit) * W * 8 <= table_budget) ++fit;
     c.llog2 = std::min(want, fit);
     if ((int64_t(1) << c.llog2) * W * 8 > ctx->lds_bytes)
       return set_error(ctx, HAWK_E_INFEASIBLE, "local table does not fit in LDS");
-    // copies of the aggregate words while they fit the budget (up to 16)
+    // copies of the aggregate words while they fit the budget (up to one per lane)
     const int64_t LC = int64_t(1) << c.llog2;
-    while (c.reps < 16 && (LC + (W - 1) * (2 * c.reps) * (LC + 1)) * 8 <= table_budget) c.reps *= 2;
+    while (c.reps < 64 && (LC + (W - 1) * (2 * c.reps) * LC) * 8 <= table_budget) c.reps *= 2;
   }
   // Overflow partitioning: with the local strategy and linear probing, when
   // the LDS table cannot hold every group, rows that miss it are spilled and
@@ -928,7 +930,7 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
   else if (T.log2cap < 14 && rlog2 > 6) rlog2 = 6;
   const int64_t nparts = T.log2cap > rlog2 ? int64_t(1) << (T.log2cap - rlog2) : 1;
   const int64_t LC = int64_t(1) << c.llog2;
-  const int64_t table_bytes = (LC + (W - 1) * c.reps * (c.reps > 1 ? LC + 1 : LC)) * 8;
+  const int64_t table_bytes = (LC + (W - 1) * c.reps * LC) * 8;
   c.spill = v->agg_strategy == HAWK_LOCAL && v->ht == HAWK_LINEAR_PROBING && T.log2cap > c.llog2 && rlog2 >= 6 &&
             nparts >= 2 && table_bytes + nparts * 4 <= wg_lds && nparts * groups <= (int64_t(1) << 26) &&
             P.nrows > 0 && ctx->lds_bytes >= kSpillLds;
@@ -1621,8 +1623,9 @@ static hawk_status prepare_run_time_kernel(hawk_ctx* ctx, const hawk_query* q, c
     return HAWK_OK;
   }
   std::string msg;
-  if (jit_agg_prepare(ctx->jit_cache, msg, q->main, v->mem, v->pred, v->hash, v->agg_strategy, c.llog2,
-                      q->main.slot_words, c.reps, c.spill ? &c.sp : nullptr) != hipSuccess)
+  if (jit_agg_prepare(ctx->jit_cache, msg, q->main, v->mem, v->pred, v->hash, v->agg_strategy,
+                      static_cast<int32_t>(v->wg_size), c.llog2, q->main.slot_words, c.reps,
+                      c.spill ? &c.sp : nullptr) != hipSuccess)
     return set_error(ctx, HAWK_E_DEVICE, "run-time compilation: " + msg);
   return HAWK_OK;
 }

@@ -256,7 +256,7 @@ hawk_status setup_memory(hawk_batch* B) {
         if (Q.table.log2cap > 31) return berr(B, HAWK_E_CAPACITY, "aggregation table beyond 2^31 slots");
         Q.nslots = (int64_t(1) << Q.table.log2cap) + 1;  // + side slot for the all-ones key
         Q.table.rlog2 = Q.table.log2cap;
-        uint32_t want = std::max<uint32_t>(4, clog2(groups * 2)), fit = 0;
+        uint32_t want = std::max<uint32_t>(4, clog2(groups * 4)), fit = 0;  // four slots per group
         while ((int64_t(2) << fit) * W * 8 <= kLdsBudget) ++fit;
         Q.llog2 = std::min(want, fit);
       } else {

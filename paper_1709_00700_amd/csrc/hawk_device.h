@@ -31,11 +31,19 @@ typedef const __attribute__((address_space(1))) uint64_t hk_global_u64;  // a gl
 __device__ __forceinline__ uint32_t col_lg(int32_t dtype) {
   return dtype == HK_T_I64 ? 3u : (dtype == HK_T_I32 ? 2u : 0u);
 }
+// A column whose type is a compile-time constant (kernels compiled for one
+// plan) and 32 bits wide is loaded as 32 bits (one register in flight);
+// otherwise the aligned 64-bit word that holds the value.
+__device__ __forceinline__ bool narrow_i32(const HkCol& c) {
+  return __builtin_constant_p(c.dtype) && c.dtype == HK_T_I32;
+}
 __device__ __forceinline__ void load_raw(const HkCol& c, int64_t row, HkRaw& v) {
   const uint64_t a = reinterpret_cast<uint64_t>(c.ptr) + (static_cast<uint64_t>(row) << col_lg(c.dtype));
-  v.w = *reinterpret_cast<hk_global_u64*>(a & ~7ull);
+  if (narrow_i32(c)) v.w = *reinterpret_cast<const __attribute__((address_space(1))) uint32_t*>(a);
+  else v.w = *reinterpret_cast<hk_global_u64*>(a & ~7ull);
 }
 __device__ __forceinline__ int64_t raw_value(const HkCol& c, int64_t row, const HkRaw& v) {
+  if (narrow_i32(c)) return static_cast<int32_t>(static_cast<uint32_t>(v.w));
   const uint32_t lg = col_lg(c.dtype);
   const uint64_t a = reinterpret_cast<uint64_t>(c.ptr) + (static_cast<uint64_t>(row) << lg);
   const uint32_t sh = static_cast<uint32_t>(a & 7ull) * 8u;
@@ -193,6 +201,57 @@ __device__ __forceinline__ bool robin_lookup(const HkJoinTable& t, const HkHash&
   return false;
 }
 
+// Home slot of a join key under linear probing: the first slot of an
+// aligned group of four, the group picked by the hash (a table has at least
+// 16 slots), so a lookup reads whole groups.
+template <int HASH>
+__device__ __forceinline__ uint32_t join_group(uint64_t key, const HkHash& h, uint32_t log2cap) {
+  return hslot<HASH>(key, h.a[0], log2cap - 2) << 2;
+}
+
+// One group of four slot words against a key (never the all-ones key, so a
+// key match is never an empty slot): 1 = found (pay set), 0 = absent (the
+// group has an empty slot, and in a built table the key sits before the
+// first empty slot of its probe sequence), -1 = a full group without it.
+__device__ __forceinline__ int join_group_test(uint32_t k, const uint64_t (&w)[4], int32_t& pay) {
+  bool found = false;
+  uint64_t wf = 0;
+#pragma unroll
+  for (int j = 3; j >= 0; --j)
+    if (static_cast<uint32_t>(w[j] >> 32) == k) {
+      found = true;
+      wf = w[j];
+    }
+  if (found) {
+    pay = static_cast<int32_t>(static_cast<uint32_t>(wf));
+    return 1;
+  }
+  return (w[0] == HK_EMPTY || w[1] == HK_EMPTY || w[2] == HK_EMPTY || w[3] == HK_EMPTY) ? 0 : -1;
+}
+
+__device__ __forceinline__ void join_group_load(const HkJoinTable& t, uint32_t g, uint64_t (&w)[4]) {
+  const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(t.slots + g);
+  const ulonglong2 y = *reinterpret_cast<const ulonglong2*>(t.slots + g + 2);
+  w[0] = x.x;
+  w[1] = x.y;
+  w[2] = y.x;
+  w[3] = y.y;
+}
+
+// linear probing from group g on: whole groups (one 32-byte load each)
+// until the key or an empty slot
+__device__ __forceinline__ bool join_scan_from(const HkJoinTable& t, uint32_t k, uint32_t g, int32_t& pay) {
+  const uint32_t mask = (1u << t.log2cap) - 1u;
+  for (uint32_t i = 0; i <= mask; i += 4) {
+    uint64_t w[4];
+    join_group_load(t, g, w);
+    const int res = join_group_test(k, w, pay);
+    if (res >= 0) return res == 1;
+    g = (g + 4) & mask;
+  }
+  return false;
+}
+
 template <int HT, int HASH>
 __device__ __forceinline__ bool join_lookup(const HkJoinTable& t, const HkHash& h, int32_t key, int32_t& pay) {
   if (key == -1) {
@@ -202,30 +261,16 @@ __device__ __forceinline__ bool join_lookup(const HkJoinTable& t, const HkHash& 
   }
   const uint64_t k64 = static_cast<uint32_t>(key);
   if (HT == HK_LIN && t.robin) return robin_lookup<HASH>(t, h, static_cast<uint32_t>(key), pay);
-  if (HT == HK_LIN) {
-    const uint32_t mask = (1u << t.log2cap) - 1u;
-    uint32_t s = hslot<HASH>(k64, h.a[0], t.log2cap);
-    for (uint32_t i = 0; i <= mask; ++i) {
-      uint64_t w = t.slots[s];
-      if (w == HK_EMPTY) return false;
-      if (static_cast<uint32_t>(w >> 32) == static_cast<uint32_t>(key)) {
-        pay = static_cast<int32_t>(static_cast<uint32_t>(w));
-        return true;
-      }
-      s = (s + 1) & mask;
-    }
-    return false;
-  } else {
+  if (HT == HK_LIN) return join_scan_from(t, static_cast<uint32_t>(key), join_group<HASH>(k64, h, t.log2cap), pay);
 #pragma unroll
-    for (int i = 0; i < HK_CUCKOO_D; ++i) {
-      uint64_t w = t.slots[hslot<HASH>(k64, h.a[i], t.log2cap)];
-      if (w != HK_EMPTY && static_cast<uint32_t>(w >> 32) == static_cast<uint32_t>(key)) {
-        pay = static_cast<int32_t>(static_cast<uint32_t>(w));
-        return true;
-      }
+  for (int i = 0; i < HK_CUCKOO_D; ++i) {
+    uint64_t w = t.slots[hslot<HASH>(k64, h.a[i], t.log2cap)];
+    if (w != HK_EMPTY && static_cast<uint32_t>(w >> 32) == static_cast<uint32_t>(key)) {
+      pay = static_cast<int32_t>(static_cast<uint32_t>(w));
+      return true;
     }
-    return false;
   }
+  return false;
 }
 
 template <int HT, int HASH>
@@ -243,7 +288,7 @@ __device__ __forceinline__ void join_insert(const HkJoinTable& t, const HkHash& 
   }
   if (HT == HK_LIN) {
     const uint32_t mask = (1u << t.log2cap) - 1u;
-    uint32_t s = hslot<HASH>(static_cast<uint32_t>(key), h.a[0], t.log2cap);
+    uint32_t s = join_group<HASH>(static_cast<uint32_t>(key), h, t.log2cap);
     for (uint32_t i = 0; i <= mask; ++i) {
       uint64_t cur = t.slots[s];
       if (cur == HK_EMPTY) {
@@ -701,56 +746,45 @@ __device__ __forceinline__ bool door_admits(uint32_t* door, uint32_t dl2, const 
 }
 
 // LDS slot lookup/insert for the local strategy; -1 = no slot within bound
-// (or, with a filter, a key not admitted yet)
-template <int HT, int HASH, bool WINDOW = true, bool ADMIT = false>
+// (or, with a filter, a key not admitted yet).
+// Linear probing reads the table four slots at a time: the hash picks an
+// aligned group of four slots whose first is the key's home slot, probing
+// goes on slot by slot from there into the next group, and one 32-byte read
+// brings a whole group's keys. A slot only ever changes from empty to a key,
+// so the first slot of a group read that holds the key is the key's slot,
+// and an insertion takes the first empty slot in probe order by
+// compare-and-swap (re-reading the group when another key took it first).
+template <int HT, int HASH, bool ADMIT = false>
 __device__ __forceinline__ int32_t lslot(uint64_t* lkeys, uint32_t llog2, const HkHash& h, uint64_t key,
                                          uint32_t* door = nullptr, uint32_t dl2 = 0) {
   if (HT == HK_LIN) {
     const uint32_t mask = (1u << llog2) - 1u;
-    const uint32_t s0 = hslot<HASH>(key, h.a[0], llog2);
+    uint32_t g = hslot<HASH>(key, h.a[0], llog2 - 2) << 2;
     // admission decided at the first empty slot met, then kept
     int adm = (ADMIT && dl2 > 0) ? -1 : 1;
-    uint64_t cur = lkeys[s0];
-    if (cur == key) return static_cast<int32_t>(s0);
-    if (cur == HK_EMPTY) {
-      if (adm < 0) adm = door_admits<HASH>(door, dl2, h, key) ? 1 : 0;
-      if (!adm) return -1;
-      cur = at_cas<true>(&lkeys[s0], HK_EMPTY, key);
-      if (cur == HK_EMPTY || cur == key) return static_cast<int32_t>(s0);
-    }
-    if (!WINDOW) {
-      // one slot per round trip (fewer live registers)
-      for (int i = 1; i < HK_LOCAL_PROBES; ++i) {
-        const uint32_t s = (s0 + i) & mask;
-        cur = lkeys[s];
-        if (cur == key) return static_cast<int32_t>(s);
-        if (cur == HK_EMPTY) {
-          if (adm < 0) adm = door_admits<HASH>(door, dl2, h, key) ? 1 : 0;
-          if (!adm) return -1;
-          cur = at_cas<true>(&lkeys[s], HK_EMPTY, key);
-          if (cur == HK_EMPTY || cur == key) return static_cast<int32_t>(s);
-        }
-      }
-      return -1;
-    }
-    // the rest of the probe window in one round trip instead of one per slot.
-    // A slot only ever changes from empty to a key, so a key read here stays,
-    // and an empty slot read here is settled by the compare-and-swap: the
-    // outcome is that of probing the slots one by one.
-    uint64_t win[HK_LOCAL_PROBES - 1];
 #pragma unroll
-    for (int i = 1; i < HK_LOCAL_PROBES; ++i) win[i - 1] = lkeys[(s0 + i) & mask];
-#pragma unroll
-    for (int i = 1; i < HK_LOCAL_PROBES; ++i) {
-      const uint32_t s = (s0 + i) & mask;
-      cur = win[i - 1];
-      if (cur == key) return static_cast<int32_t>(s);
-      if (cur == HK_EMPTY) {
+    for (int k = 0; k < HK_LOCAL_PROBES / 4; ++k) {
+      for (int tries = 0; tries < 5; ++tries) {  // each failed compare-and-swap fills one slot of the group
+        const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(lkeys + g);
+        const ulonglong2 y = *reinterpret_cast<const ulonglong2*>(lkeys + g + 2);
+        int hit = 4;
+        hit = y.y == key ? 3 : hit;
+        hit = y.x == key ? 2 : hit;
+        hit = x.y == key ? 1 : hit;
+        hit = x.x == key ? 0 : hit;
+        if (hit < 4) return static_cast<int32_t>(g + hit);
+        int e = 4;
+        e = y.y == HK_EMPTY ? 3 : e;
+        e = y.x == HK_EMPTY ? 2 : e;
+        e = x.y == HK_EMPTY ? 1 : e;
+        e = x.x == HK_EMPTY ? 0 : e;
+        if (e == 4) break;  // a full group without the key: the next group
         if (adm < 0) adm = door_admits<HASH>(door, dl2, h, key) ? 1 : 0;
         if (!adm) return -1;
-        cur = at_cas<true>(&lkeys[s], HK_EMPTY, key);
-        if (cur == HK_EMPTY || cur == key) return static_cast<int32_t>(s);
+        const uint64_t cur = at_cas<true>(&lkeys[g + e], HK_EMPTY, key);
+        if (cur == HK_EMPTY || cur == key) return static_cast<int32_t>(g + e);
       }
+      g = (g + 4) & mask;
     }
     return -1;
   } else {

@@ -4,7 +4,10 @@
 #include <hip/hiprtc.h>
 
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <sstream>
 
 #include "hawk_device.h"
@@ -77,14 +80,14 @@ std::string exact_shape(const HkPlan& P, int naggs, int nproj) {
 }  // namespace
 
 std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash, int strat, bool spill,
-                           size_t lds_bytes) {
+                           size_t lds_bytes, int32_t wg) {
   std::ostringstream o;
   // the local table is a static LDS array of the launch's size (no dynamic LDS)
   const size_t words = lds_bytes / 8 > 0 ? (lds_bytes + 7) / 8 : 1;
   o << "#include \"hk_agg_body.h\"\n"
-       "extern \"C\" __global__ void __launch_bounds__(1024) hk_jit_agg(HkPlan Prt, HkAggTable T, uint32_t llog2,\n"
+       "extern \"C\" __global__ void __launch_bounds__(" << wg << ") hk_jit_agg(HkPlan Prt, HkAggTable T, uint32_t llog2,\n"
        "    HkIdent id, int64_t nwg, int* err, HkSpill sp, int32_t reps) {\n"
-       "  __shared__ uint64_t lds[" << words << "];\n";
+       "  __shared__ __attribute__((aligned(32))) uint64_t lds[" << words << "];\n";
   HkPlan Q = P;
   Q.nproj = 0;
   emit_structure(o, Q);
@@ -123,6 +126,15 @@ hipError_t get_kernel(JitCache& cache, std::string& err_msg, const std::string& 
   auto it = cache.kernels.find(src);
   if (it == cache.kernels.end()) {
     const auto t0 = std::chrono::steady_clock::now();
+    // HAWK_JIT_DUMP=<dir>: each generated source is also written there (for
+    // reading or compiling it ahead of time with the library's headers)
+    if (const char* dir = std::getenv("HAWK_JIT_DUMP")) {
+      const std::string path = std::string(dir) + "/hk_jit_" + std::to_string(std::hash<std::string>{}(src)) + ".hip";
+      if (FILE* f = std::fopen(path.c_str(), "w")) {
+        std::fputs(src.c_str(), f);
+        std::fclose(f);
+      }
+    }
     hiprtcProgram prog;
     const char* hs[] = {kSrcPlan, kSrcDevice, kSrcAggBody, kSrcProjBody};
     const char* hn[] = {"hawk_plan.h", "hawk_device.h", "hk_agg_body.h", "hk_proj_body.h"};
@@ -179,10 +191,10 @@ hipError_t get_kernel(JitCache& cache, std::string& err_msg, const std::string& 
 }  // namespace
 
 hipError_t jit_agg_prepare(JitCache& cache, std::string& err_msg, const HkPlan& P, int mem, int pred, int hash,
-                           int strat, uint32_t llog2, int32_t nw, int32_t reps, const HkSpill* sp) {
+                           int strat, int32_t wg, uint32_t llog2, int32_t nw, int32_t reps, const HkSpill* sp) {
   hipFunction_t fn;
   const size_t lds = hk_agg_lds_bytes(strat, llog2, nw, reps, sp);
-  return get_kernel(cache, err_msg, jit_agg_source(P, mem, pred, HK_LIN, hash, strat, sp != nullptr, lds), fn);
+  return get_kernel(cache, err_msg, jit_agg_source(P, mem, pred, HK_LIN, hash, strat, sp != nullptr, lds, wg), fn);
 }
 
 hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P,
@@ -191,7 +203,7 @@ hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st,
   hipFunction_t fn;
   const size_t lds = hk_agg_lds_bytes(strat, llog2, id.nw, reps, sp);
   const hipError_t ge =
-      get_kernel(cache, err_msg, jit_agg_source(P, mem, pred, HK_LIN, hash, strat, sp != nullptr, lds), fn);
+      get_kernel(cache, err_msg, jit_agg_source(P, mem, pred, HK_LIN, hash, strat, sp != nullptr, lds, wg), fn);
   if (ge != hipSuccess) return ge;
   HkSpill none;
   std::memset(&none, 0, sizeof(none));

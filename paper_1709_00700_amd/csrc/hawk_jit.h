@@ -27,10 +27,10 @@ struct JitCache {
 
 // Generated source of the specialised kernel `hk_jit_agg` for (P, variant).
 std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash, int strat, bool spill,
-                           size_t lds_bytes);
+                           size_t lds_bytes, int32_t wg);
 // Compiles the specialised kernel unless the cache holds it (no GPU work).
 hipError_t jit_agg_prepare(JitCache& cache, std::string& err_msg, const HkPlan& P, int mem, int pred, int hash,
-                           int strat, uint32_t llog2, int32_t nw, int32_t reps, const HkSpill* sp);
+                           int strat, int32_t wg, uint32_t llog2, int32_t nw, int32_t reps, const HkSpill* sp);
 // Compiles (or finds) and launches the specialised kernel; same arguments and
 // launch shape as the ahead-of-time k_agg. Linear probing only.
 hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P,

@@ -57,7 +57,7 @@ inline size_t hk_agg_lds_bytes(int strat, uint32_t llog2, int32_t nw, int32_t re
   size_t lds = 0;
   if (strat == HK_LOCAL) {
     const size_t LC = static_cast<size_t>(1) << llog2;
-    lds = (LC + static_cast<size_t>(nw - 1) * reps * (reps > 1 ? LC + 1 : LC)) * sizeof(uint64_t);
+    lds = (LC + static_cast<size_t>(nw - 1) * reps * LC) * sizeof(uint64_t);
   }
   if (sp) lds += static_cast<size_t>(sp->nparts) * sizeof(uint32_t);
   if (sp && sp->door_log2 > 0) lds += (static_cast<size_t>(1) << sp->door_log2) / 8;

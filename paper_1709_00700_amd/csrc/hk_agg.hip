@@ -21,7 +21,8 @@
 template <int MEM, int PRED, int HT, int HASH, int STRAT, class S, bool SPILL>
 __global__ void __launch_bounds__(1024) k_agg(HkPlan P, HkAggTable T, uint32_t llog2, HkIdent id, int64_t nwg,
                                               int* err, HkSpill sp, int32_t reps) {
-  extern __shared__ uint64_t lds[];  // the local table (hk_agg_lds_bytes)
+  // the local table (hk_agg_lds_bytes), read in 32-byte groups
+  extern __shared__ __attribute__((aligned(32))) uint64_t lds[];
   agg_body<MEM, PRED, HT, HASH, STRAT, S, SPILL>(P, T, llog2, id, nwg, err, sp, reps, lds);
 }
 

@@ -8,10 +8,11 @@
 #include "hawk_device.h"
 
 // The local table in LDS: keys[LC], then for each word j >= 1 (count,
-// aggregates) `reps` copies of the LC slots, RS words apart (padded by one
-// word when reps > 1 so the copies of a slot sit in different banks). Lane l
-// updates copy l % reps: lanes of one instruction that hit the same group
-// then mostly hit different addresses. The copies are folded before the
+// aggregates) the slots' `reps` copies side by side (copy c of slot s at
+// s * reps + c). Lane l updates copy l % reps: lanes of one instruction that
+// hit the same group then hit different addresses, and with 32 or more
+// copies every lane's word sits in a bank of its own whichever slots the
+// lanes hit. The copies are folded (a tree over the workgroup) before the
 // table is merged into the global table.
 template <int MEM, int PRED, int HT, int HASH, int STRAT, class S, bool SPILL>
 __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, uint32_t llog2, const HkIdent& id,
@@ -33,8 +34,7 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
   __shared__ uint32_t spill_cursor;
   __shared__ uint32_t wave_tot[1024 / WAVE];
   const int64_t LC = STRAT == HK_LOCAL ? (static_cast<int64_t>(1) << llog2) : 0;
-  const int64_t RS = reps > 1 ? LC + 1 : LC;
-  const int64_t WS = reps * RS;  // from word j to word j + 1 of one copy
+  const int64_t WS = reps * LC;  // from word j to word j + 1 of one copy
   uint64_t* lw1 = lds + LC;      // word 1 of copy 0 of slot 0
   const int64_t q = __lane_id() & (reps - 1);
   // spill mode: the partition histogram follows the LDS table, then the
@@ -68,17 +68,17 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
     rcap = spill_region_start(sp, nwg, wgid + 1) - r0;
     region = sp.buf + r0 * sp.ew;
   }
-  auto row_step = [&](int64_t row, const HkFirst<S>& f) {
-    const bool pass = eval_row_f<PRED, HT, HASH, true, S, true>(P, row, f, r);
+  // the aggregation of one evaluated row (registers rr, result_increment pass)
+  auto agg_row = [&](const v16i64& rr, bool pass) {
     bool spill = false;
     uint64_t key = 0;
     if (PRED != HK_BR || pass) {
-      key = group_key(P, r);
+      key = group_key(P, rr);
       bool done = false;
       if (STRAT == HK_LOCAL && key != HK_EMPTY) {
-        const int32_t s = lslot<HT, HASH, (S::probes == 0), SPILL>(lds, llog2, P.hash, key, door, dl2);
+        const int32_t s = lslot<HT, HASH, SPILL>(lds, llog2, P.hash, key, door, dl2);
         if (s >= 0) {
-          agg_apply_w1<PRED, true, S>(lw1 + q * RS + s, WS, P, r, pass);
+          agg_apply_w1<PRED, true, S>(lw1 + s * reps + q, WS, P, rr, pass);
           done = true;
         }
       }
@@ -87,7 +87,7 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
           spill = pass;  // a predicated row that did not pass contributes nothing
         } else {
           uint64_t* g = gslot<HT, HASH>(T, P.hash, key, err);
-          if (g) agg_apply<PRED, false, S>(g, 1, P, r, pass);
+          if (g) agg_apply<PRED, false, S>(g, 1, P, rr, pass);
           // this path's returning atomics end here: the rows fetched ahead
           // then stay in flight on the common path
           __builtin_amdgcn_s_waitcnt(0);
@@ -110,11 +110,11 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
               // consecutive spilling lanes write consecutive 16-byte entries: one store each
               ulonglong2 e2;
               e2.x = key;
-              e2.y = static_cast<uint64_t>(r[sp.reg[0]]);
+              e2.y = static_cast<uint64_t>(rr[sp.reg[0]]);
               *reinterpret_cast<ulonglong2*>(ent) = e2;
             } else {
               ent[0] = key;
-              for (int j = 0; j < sp.ncols; ++j) ent[1 + j] = static_cast<uint64_t>(r[sp.reg[j]]);
+              for (int j = 0; j < sp.ncols; ++j) ent[1 + j] = static_cast<uint64_t>(rr[sp.reg[j]]);
             }
             atomicAdd(&hist[hslot<HASH>(key, P.hash.a[0], T.log2cap) >> T.rlog2], 1u);
           } else {
@@ -124,11 +124,17 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
       }
     }
   };
+  auto row_step = [&](int64_t row, const HkFirst<S>& f) {
+    const bool pass = eval_row_f<PRED, HT, HASH, true, S, true>(P, row, f, r);
+    agg_row(r, pass);
+  };
   // software pipeline over the thread's rows: the first load phase of the
-  // next AH rows is in flight while a row is evaluated. The loop is unrolled
-  // by the ring size so every buffer index is a constant (no register copies,
-  // which would wait for the loads in flight).
-  constexpr int AH = HkFirst<S>::A + HkFirst<S>::B + HkFirst<S>::C <= 3 ? 3 : 1;
+  // next AH rows is in flight while a row is evaluated (more rows ahead for
+  // fewer columns). The loop is unrolled by the ring size so every buffer
+  // index is a constant (no register copies, which would wait for the loads
+  // in flight).
+  constexpr int NF = HkFirst<S>::A + HkFirst<S>::B + HkFirst<S>::C;
+  constexpr int AH = NF <= 2 ? 4 : (NF <= 3 ? 3 : 1);
   constexpr int NB = AH + 1;
   HkFirst<S> f[NB] = {};
   // rows past the thread's range fetch its last row again (the fetch count
@@ -148,13 +154,25 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
       row_step(rk, f[k]);
     }
   }
+  if (STRAT == HK_LOCAL) {
+    // the copies of each slot folded into copy 0, halving the copies each round
+    for (int32_t d = reps >> 1; d >= 1; d >>= 1) {
+      __syncthreads();
+      const int32_t ld = __ffs(d) - 1;
+      for (int64_t i = threadIdx.x; i < (LC << ld); i += blockDim.x) {
+        const int64_t s = i >> ld;
+        if (lds[s] == HK_EMPTY) continue;
+        uint64_t* a = lw1 + s * reps + (i & (d - 1));
+        agg_fold_w1<S>(a, a + d, WS, P);
+      }
+    }
+  }
   if (STRAT == HK_LOCAL && (!SPILL || !sp.merge)) {
     __syncthreads();
     for (int64_t s = threadIdx.x; s < LC; s += blockDim.x) {
       const uint64_t key = lds[s];
       if (key == HK_EMPTY) continue;
-      uint64_t* c0 = lw1 + s;
-      for (int32_t c = 1; c < reps; ++c) agg_fold_w1<S>(c0, c0 + c * RS, WS, P);
+      const uint64_t* c0 = lw1 + s * reps;
       if (c0[0] == 0) continue;  // only predicated rows that did not pass reached this group
       uint64_t* g = gslot<HT, HASH>(T, P.hash, key, err);
       if (g) agg_merge_w1<S>(g, c0, WS, P);
@@ -173,9 +191,7 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
     for (int64_t s = threadIdx.x; s < LC; s += blockDim.x) {
       const uint64_t key = lds[s];
       if (key == HK_EMPTY) continue;
-      uint64_t* c0 = lw1 + s;
-      for (int32_t c = 1; c < reps; ++c) agg_fold_w1<S>(c0, c0 + c * RS, WS, P);
-      if (c0[0] == 0) continue;  // only predicated rows that did not pass reached this group
+      if (lw1[s * reps] == 0) continue;  // only predicated rows that did not pass reached this group
       atomicAdd(&hist[hslot<HASH>(key, P.hash.a[0], T.log2cap) >> T.rlog2], 1u);
     }
     __syncthreads();
@@ -185,7 +201,7 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
     for (int64_t s = threadIdx.x; s < LC; s += blockDim.x) {
       const uint64_t key = lds[s];
       if (key == HK_EMPTY) continue;
-      const uint64_t* c0 = lw1 + s;  // folded above by this thread
+      const uint64_t* c0 = lw1 + s * reps;  // copy 0, the folded slot
       if (c0[0] == 0) continue;
       const uint32_t pos = atomicAdd(&hist[hslot<HASH>(key, P.hash.a[0], T.log2cap) >> T.rlog2], 1u);
       uint64_t* ent = fl + static_cast<int64_t>(pos) * W;

@@ -199,7 +199,7 @@ template <class S>
 __global__ void __launch_bounds__(256) k_batch_main(const HkBatchQuery* __restrict__ qs, const int32_t* __restrict__ qidx,
                                                     const int64_t* __restrict__ bases, int32_t nq, int64_t nitems,
                                                     unsigned long long* head) {
-  extern __shared__ uint64_t lds[];
+  extern __shared__ __attribute__((aligned(32))) uint64_t lds[];  // tables read in 32-byte groups
   __shared__ int64_t sh;
   for (;;) {
     const int64_t item = next_item(head, &sh);

@@ -108,19 +108,37 @@ class WithFallback:
     penalty x sd of the members' ln(ms)) than the fallback at its optimistic
     one (mean - penalty x sd). Greedy search stays the fallback; the model
     departs from it only where its members agree on a gain larger than their
-    spread on both variants."""
+    spread on both variants.
 
-    def __init__(self, ens: Ensemble, fallback: dict):
+    With `race_ctx`, the two candidates are instead timed on the query itself
+    (`race_reps` runs each, the faster kept): the model proposes one variant,
+    one short race against the per-workload variant decides. `race_ms` sums
+    the time those runs took."""
+
+    def __init__(self, ens: Ensemble, fallback: dict, race_ctx=None, race_reps: int = 2):
         self.ens = ens
         self.fallback = fallback
+        self.race_ctx = race_ctx
+        self.race_reps = race_reps
+        self.race_ms = 0.0
+        self._raced = {}  # id(query) -> (query, the race's winner); the query kept alive with its id
 
     def pick(self, queries: list):
         picks, _ = self.ens.pick(queries)
         out = []
         for q, v in zip(queries, picks):
+            if self.race_ctx is not None and id(q) in self._raced:
+                out.append(self._raced[id(q)][1])
+                continue
             fb = self.fallback.get(q.kind)
-            if fb is None:
-                out.append(v)
+            if fb is None or variant_key(q, v) == variant_key(q, fb):
+                out.append(v if fb is None else fb)
+                continue
+            if self.race_ctx is not None:
+                t = [timed(self.race_ctx, q, x, self.race_reps, 0.0) for x in (v, fb)]
+                self.race_ms += self.race_reps * sum(x for x in t if math.isfinite(x))
+                out.append(v if t[0] < t[1] else fb)
+                self._raced[id(q)] = (q, out[-1])
                 continue
             mean, sd = self.ens.scores(q, [v, fb])
             out.append(v if mean[0] + self.ens.penalty * sd[0] < mean[1] - self.ens.penalty * sd[1] else fb)

@@ -48,7 +48,7 @@ def test_learned_picks_beat_algorithm1_per_workload(ctx):
     alg1 = optimizer.alg1_per_kind(ctx, te_h, reps=2, limit_ms=lim)
     # the per-query optimizer: the ensemble's pick where its members agree it
     # beats Algorithm 1's variant for the query's kind, else that variant
-    picker = optimizer.WithFallback(ens, {k: v for k, (v, _) in alg1.items()})
+    picker = optimizer.WithFallback(ens, {k: v for k, (v, _) in alg1.items()}, race_ctx=ctx)
     # the search's best and every pick are timed again with 5 runs each before
     # they are compared (the minimum of 896 two-run medians is biased low)
     pq = optimizer.pick_quality(ctx, te_h, picker, reps=2, limit_ms=lim, alg1=alg1, progress=say,
@@ -91,7 +91,7 @@ def test_learned_picks_on_the_extended_space(ctx):
     X, y = optimizer.refine(ctx, tr_h, ens, X, y, top=4, rounds=2, reps=2, limit_ms=lim, progress=say,
                             epochs=300, batch=512, lr=3e-3, seed=2)
     alg1 = optimizer.alg1_per_kind(ctx, te_h, reps=2, limit_ms=lim)
-    picker = optimizer.WithFallback(ens, {k: v for k, (v, _) in alg1.items()})
+    picker = optimizer.WithFallback(ens, {k: v for k, (v, _) in alg1.items()}, race_ctx=ctx)
     pq = optimizer.pick_quality(ctx, te_h, picker, reps=2, limit_ms=lim, alg1=alg1, progress=say,
                                 extra={"ensemble": ens}, confirm_reps=5)
     say(json.dumps({k: pq[k] for k in ("model", "ensemble", "alg1")}))
