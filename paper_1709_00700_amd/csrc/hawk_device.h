@@ -202,52 +202,29 @@ __device__ __forceinline__ bool robin_lookup(const HkJoinTable& t, const HkHash&
 }
 
 // Home slot of a join key under linear probing: the first slot of an
-// aligned group of four, the group picked by the hash (a table has at least
-// 16 slots), so a lookup reads whole groups.
+// aligned pair, the pair picked by the hash, so a lookup reads whole pairs
+// (one 16-byte load each: a random gather costs the vector memory pipeline
+// per lane and load, whatever the width up to 16 bytes).
 template <int HASH>
 __device__ __forceinline__ uint32_t join_group(uint64_t key, const HkHash& h, uint32_t log2cap) {
-  return hslot<HASH>(key, h.a[0], log2cap - 2) << 2;
+  return hslot<HASH>(key, h.a[0], log2cap - 1) << 1;
 }
 
-// One group of four slot words against a key (never the all-ones key, so a
-// key match is never an empty slot): 1 = found (pay set), 0 = absent (the
-// group has an empty slot, and in a built table the key sits before the
-// first empty slot of its probe sequence), -1 = a full group without it.
-__device__ __forceinline__ int join_group_test(uint32_t k, const uint64_t (&w)[4], int32_t& pay) {
-  bool found = false;
-  uint64_t wf = 0;
-#pragma unroll
-  for (int j = 3; j >= 0; --j)
-    if (static_cast<uint32_t>(w[j] >> 32) == k) {
-      found = true;
-      wf = w[j];
-    }
-  if (found) {
-    pay = static_cast<int32_t>(static_cast<uint32_t>(wf));
-    return 1;
-  }
-  return (w[0] == HK_EMPTY || w[1] == HK_EMPTY || w[2] == HK_EMPTY || w[3] == HK_EMPTY) ? 0 : -1;
-}
-
-__device__ __forceinline__ void join_group_load(const HkJoinTable& t, uint32_t g, uint64_t (&w)[4]) {
-  const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(t.slots + g);
-  const ulonglong2 y = *reinterpret_cast<const ulonglong2*>(t.slots + g + 2);
-  w[0] = x.x;
-  w[1] = x.y;
-  w[2] = y.x;
-  w[3] = y.y;
-}
-
-// linear probing from group g on: whole groups (one 32-byte load each)
-// until the key or an empty slot
+// linear probing from pair g on, pair by pair until the key or an empty slot
+// (the key is never the all-ones key, so a key match is never an empty slot;
+// in a built table a key sits before the first empty slot of its probe
+// sequence, and a pair read that holds it holds it once)
 __device__ __forceinline__ bool join_scan_from(const HkJoinTable& t, uint32_t k, uint32_t g, int32_t& pay) {
   const uint32_t mask = (1u << t.log2cap) - 1u;
-  for (uint32_t i = 0; i <= mask; i += 4) {
-    uint64_t w[4];
-    join_group_load(t, g, w);
-    const int res = join_group_test(k, w, pay);
-    if (res >= 0) return res == 1;
-    g = (g + 4) & mask;
+  for (uint32_t i = 0; i <= mask; i += 2) {
+    const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(t.slots + g);
+    const bool f0 = static_cast<uint32_t>(x.x >> 32) == k, f1 = static_cast<uint32_t>(x.y >> 32) == k;
+    if (f0 || f1) {
+      pay = static_cast<int32_t>(static_cast<uint32_t>(f0 ? x.x : x.y));
+      return true;
+    }
+    if (x.x == HK_EMPTY || x.y == HK_EMPTY) return false;
+    g = (g + 2) & mask;
   }
   return false;
 }
