@@ -973,7 +973,7 @@ hipError_t agg_kernel_launch(hawk_ctx* ctx, hipStream_t st, const hawk_variant* 
     const hipError_t e = jit_agg_launch(ctx->jit_cache, msg, st, P, T, v->mem, v->pred, v->hash, v->agg_strategy,
                                         c.groups, wg, c.llog2, id, err, sp, c.reps);
     if (e != hipSuccess && !msg.empty()) ctx->jit_cache.last_error = msg;
-    return e;
+    if (e != hipErrorNotSupported) return e;
   }
   return hk_agg(st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, c.groups, wg, c.llog2, ident, W, err,
                 sp, c.reps);
@@ -1226,10 +1226,11 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
     };
     {
       ProfScope ps(X.prof(), "k_mp_filter");
-      if (jit)
-        LAUNCH(jit_err(jit_mp_filter_launch(ctx->jit_cache, jmsg, X.st, P, v->filter_mode, v->mem, v->pred, v->ht,
-                                            v->hash, v->unroll, threads, masks, counts)),
-               "filter kernel");
+      hipError_t je = hipErrorNotSupported;
+      if (jit && X.launch)  // (a sizing pass enqueues nothing)
+        je = jit_err(jit_mp_filter_launch(ctx->jit_cache, jmsg, X.st, P, v->filter_mode, v->mem, v->pred, v->ht,
+                                          v->hash, v->unroll, threads, masks, counts));
+      if (je != hipErrorNotSupported) LAUNCH(je, "filter kernel");
       else
         LAUNCH(hk_mp_filter(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, counts, v->unroll,
                             v->filter_mode),
@@ -1241,17 +1242,18 @@ hawk_status run_projection(Exec& X, const HkPlan& P) {
     }
     {
       ProfScope ps(X.prof(), "k_mp_project");
-      if (jit) {
+      hipError_t je = hipErrorNotSupported;
+      if (jit && X.launch) {  // (a sizing pass enqueues nothing)
         HkOut O = {};
         for (int c = 0; c < P.nproj; ++c) O.col[c] = out[c];
         O.dump = n;
-        LAUNCH(jit_err(jit_mp_project_launch(ctx->jit_cache, jmsg, X.st, P, v->mem, v->pred, v->ht, v->hash, threads,
-                                             masks, offsets, res->d_count, nact, O)),
-               "projection kernel");
-      } else {
+        je = jit_err(jit_mp_project_launch(ctx->jit_cache, jmsg, X.st, P, v->mem, v->pred, v->ht, v->hash, threads,
+                                           masks, offsets, res->d_count, nact, O));
+      }
+      if (je != hipErrorNotSupported) LAUNCH(je, "projection kernel");
+      else
         LAUNCH(hk_mp_project(X.st, P, v->mem, v->pred, v->ht, v->hash, threads, masks, offsets, res->d_count, nact,
                              out, n), "projection kernel");
-      }
     }
   } else {
     const int64_t inst = ctx->num_cus;  // one pipeline instance per compute unit
@@ -1602,9 +1604,13 @@ static hawk_status prepare_run_time_kernel(hawk_ctx* ctx, const hawk_query* q, c
     const int ht = v->ht;
     std::string msg;
     const int which = v->filter_mode ? JIT_MP_FILTER_SIMD : JIT_MP_FILTER;
-    if (jit_proj_prepare(ctx->jit_cache, msg, q->main, which, v->mem, v->pred, ht, v->hash, v->unroll) != hipSuccess ||
-        jit_proj_prepare(ctx->jit_cache, msg, q->main, JIT_MP_PROJECT, v->mem, v->pred, ht, v->hash, 0) != hipSuccess)
-      return set_error(ctx, HAWK_E_DEVICE, "run-time compilation: " + msg);
+    // a refused kernel (hipErrorNotSupported) leaves the execution to the precompiled one
+    for (const hipError_t e : {jit_proj_prepare(ctx->jit_cache, msg, q->main, which, v->mem, v->pred, ht, v->hash,
+                                                v->unroll),
+                               jit_proj_prepare(ctx->jit_cache, msg, q->main, JIT_MP_PROJECT, v->mem, v->pred, ht,
+                                                v->hash, 0)})
+      if (e != hipSuccess && e != hipErrorNotSupported)
+        return set_error(ctx, HAWK_E_DEVICE, "run-time compilation: " + msg);
     return HAWK_OK;
   }
   if (!ctx->jit || q->kind == 1 || q->main.ngroup == 0 || v->ht == HAWK_CUCKOO || q->main.xinner > 0)
@@ -1623,10 +1629,10 @@ static hawk_status prepare_run_time_kernel(hawk_ctx* ctx, const hawk_query* q, c
     return HAWK_OK;
   }
   std::string msg;
-  if (jit_agg_prepare(ctx->jit_cache, msg, q->main, v->mem, v->pred, v->hash, v->agg_strategy,
-                      static_cast<int32_t>(v->wg_size), c.llog2, q->main.slot_words, c.reps,
-                      c.spill ? &c.sp : nullptr) != hipSuccess)
-    return set_error(ctx, HAWK_E_DEVICE, "run-time compilation: " + msg);
+  const hipError_t e = jit_agg_prepare(ctx->jit_cache, msg, q->main, v->mem, v->pred, v->hash, v->agg_strategy,
+                                       static_cast<int32_t>(v->wg_size), c.llog2, q->main.slot_words, c.reps,
+                                       c.spill ? &c.sp : nullptr);
+  if (e != hipSuccess && e != hipErrorNotSupported) return set_error(ctx, HAWK_E_DEVICE, "run-time compilation: " + msg);
   return HAWK_OK;
 }
 

@@ -27,7 +27,8 @@ void emit_col(std::ostringstream& o, const char* arr, int c, const HkCol& col) {
 }  // namespace
 
 void JitCache::release() {
-  for (auto& k : kernels) (void)hipModuleUnload(k.second.module);
+  for (auto& k : kernels)
+    if (k.second.module) (void)hipModuleUnload(k.second.module);
   kernels.clear();
 }
 
@@ -182,9 +183,20 @@ hipError_t get_kernel(JitCache& cache, std::string& err_msg, const std::string& 
     }
     cache.compile_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     ++cache.compiled;
+    // a kernel that spills registers to scratch memory is not launched: the
+    // caller runs the kernel compiled ahead of time instead (kept as refused)
+    int priv = 0;
+    if (hipFuncGetAttribute(&priv, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, k.fn) != hipSuccess || priv > 0) {
+      (void)hipModuleUnload(k.module);
+      k = JitKernel{};
+    }
     it = cache.kernels.emplace(src, k).first;
   }
   fn = it->second.fn;
+  if (!fn) {
+    err_msg = "the specialised kernel needs scratch memory";
+    return hipErrorNotSupported;
+  }
   return hipSuccess;
 }
 

@@ -16,6 +16,8 @@
 
 #include "hawk_plan.h"
 
+// fn == nullptr: compiled but refused (the launch functions then return
+// hipErrorNotSupported and the caller runs the ahead-of-time kernel)
 struct JitKernel { hipModule_t module; hipFunction_t fn; };
 struct JitCache {
   std::map<std::string, JitKernel> kernels;
