@@ -111,18 +111,18 @@ def make_pipeline(name, rows=None):
 # 1.000). Valid only for the kernel sources it was measured on, with the same
 # variant: reported as null otherwise.
 TRAFFIC = {
-    "c4": {"sources_sha": "c87c076b2139d5e4", "variant_sha": "0152c414afb56411", "total": 13524595730,
-            "per_kernel": {"k_agg": 13524560564, "k_finalize": 14975, "k_init_aggtable": 20191}},
-    "c2u": {"sources_sha": "c87c076b2139d5e4", "variant_sha": "c903adb01ef30859", "total": 806225876,
-            "per_kernel": {"k_agg": 806201076, "k_finalize": 12448, "k_init_aggtable": 12352}},
-    "c2z": {"sources_sha": "c87c076b2139d5e4", "variant_sha": "366d68d5fd79efd4", "total": 2250838088,
-            "per_kernel": {"k_agg": 1157513566, "k_spill_agg": 414456132, "k_spill_scatter": 677752283, "k_scan": 1102587, "k_finalize": 8584, "k_init_aggtable": 4936}},
-    "c3": {"sources_sha": "c87c076b2139d5e4", "variant_sha": "a84f6d0e820b4e49", "total": 3290343098,
-            "per_kernel": {"k_agg": 3277479111, "k_build": 7003761, "k_finalize": 168121, "k_scan": 1102680, "k_spill_scatter": 4388693, "k_spill_agg": 63486, "k_init_aggtable": 137246}},
-    "c1_256m": {"sources_sha": "c87c076b2139d5e4", "variant_sha": "e551c2cb51e36aaa", "total": 5246462354,
-            "per_kernel": {"k_mp_project": 3012413797, "k_mp_filter": 2198468539, "k_scan": 35580018}},
-    "c1": {"sources_sha": "c87c076b2139d5e4", "variant_sha": "928f3ef35614eef6", "total": 19641681,
-            "per_kernel": {"k_scan": 131549, "k_mp_filter": 8304979, "k_mp_project": 11205153}},
+    "c4": {"sources_sha": "9482a60233e9e284", "variant_sha": "0152c414afb56411", "total": 13534306309,
+            "per_kernel": {"k_agg": 13534271143, "k_finalize": 14975, "k_init_aggtable": 20191}},
+    "c2u": {"sources_sha": "9482a60233e9e284", "variant_sha": "c903adb01ef30859", "total": 806223052,
+            "per_kernel": {"k_agg": 806198252, "k_finalize": 12448, "k_init_aggtable": 12352}},
+    "c2z": {"sources_sha": "9482a60233e9e284", "variant_sha": "366d68d5fd79efd4", "total": 2250853714,
+            "per_kernel": {"k_agg": 1157519227, "k_spill_agg": 414465810, "k_spill_scatter": 677752569, "k_scan": 1102596, "k_finalize": 8576, "k_init_aggtable": 4936}},
+    "c3": {"sources_sha": "9482a60233e9e284", "variant_sha": "a84f6d0e820b4e49", "total": 3290669629,
+            "per_kernel": {"k_agg": 3277806302, "k_build": 7003124, "k_finalize": 168130, "k_scan": 1102639, "k_spill_scatter": 4388701, "k_spill_agg": 63486, "k_init_aggtable": 137247}},
+    "c1_256m": {"sources_sha": "9482a60233e9e284", "variant_sha": "e551c2cb51e36aaa", "total": 5246696664,
+            "per_kernel": {"k_mp_project": 3012679467, "k_mp_filter": 2198483709, "k_scan": 35533488}},
+    "c1": {"sources_sha": "9482a60233e9e284", "variant_sha": "928f3ef35614eef6", "total": 19641725,
+            "per_kernel": {"k_scan": 131549, "k_mp_filter": 8304994, "k_mp_project": 11205182}},
 }
 TRAFFIC_SOURCES = ["hk_agg.hip", "hk_agg_body.h", "hawk_jit.cpp", "hawk_device.h", "hawk_plan.h", "hk_proj.hip",
                    "hk_proj_body.h", "hk_common.hip", "hk_scalar.hip"]
