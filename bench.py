@@ -392,11 +392,34 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(name, budget_s=15.0):
+def same_answer(got, ref):
+    """The device's answer equals the oracle's (AVG within 1e-12 relative)."""
+    import numpy as np
+    if got["rows"] != ref["rows"]:
+        return False
+    if "cols" in ref:
+        return all(np.array_equal(np.asarray(a), np.asarray(b)) for a, b in zip(got["cols"], ref["cols"]))
+    if not all(np.array_equal(np.asarray(a), np.asarray(b)) for a, b in zip(got["keys"], ref["keys"])):
+        return False
+    if not np.array_equal(np.asarray(got["count"]), np.asarray(ref["count"])):
+        return False
+    for a, b in zip(got["aggs"], ref["aggs"]):
+        for u, v in zip(list(a), list(b)):
+            if isinstance(u, float) or isinstance(v, float):
+                if not ((u != u and v != v) or abs(u - v) <= 1e-12 * abs(v)):
+                    return False
+            elif int(u) != int(v):
+                return False
+    return True
+
+
+def cpu_baseline(name, budget_s=15.0, ctx=None, variant=None):
     """The oracle as it stands on a bounded sample of the timed workload (its
     first n rows, n doubling from 2^20 while the budget lasts): on all host
     cores of this GPU's share (row-partitioned: contiguous ranges, one thread
-    each, partial results merged), and on one core."""
+    each, partial results merged), and on one core. With ctx, the largest
+    sample also runs on the device in the timed variant and its answer is
+    compared element by element with the oracle's."""
     import oracle
     from paper_1709_00700_amd import datagen as dg
     try:
@@ -409,16 +432,31 @@ def cpu_baseline(name, budget_s=15.0):
         rows_done, secs, samples, last = 0, 0.0, [], 0.0
         n = 1 << 20
         # the next sample (twice the rows) is taken while it should end within the budget
+        keep = None
         while (not samples or secs + 2.2 * last <= budget_s) and n <= (1 << 28):
             tables, spec = make_pipeline(name, rows=n)
             t0 = time.perf_counter()
-            oracle.run(tables, spec, threads=th)
+            ref = oracle.run(tables, spec, threads=th)
             last = time.perf_counter() - t0
             secs += last
             rows_done += n
             samples.append(n)
+            keep = (tables, spec, ref, n) if leg == "all" else None
             del tables
             n *= 2
+        if keep is not None and ctx is not None:
+            from paper_1709_00700_amd import hawk
+            tables, spec, ref, nv = keep
+            ren = {t: "verify_" + t for t in tables}
+            spec["main"]["table"] = ren[spec["main"]["table"]]
+            for b in spec["builds"]:
+                b["table"] = ren[b["table"]]
+            ctx.register_numpy({ren[t]: c for t, c in tables.items()})
+            r = hawk.execute(ctx, hawk.build_query(ctx, spec), variant)
+            got = r.to_numpy(spec)
+            r.free()
+            out["verify"] = {"rows": nv, "matches_oracle": same_answer(got, ref)}
+        keep = None
         out[leg] = {"value": rows_done / secs, "cores": th, "seconds": secs,
                     "sample": f"first rows of the same seeded {name} workload, n = {samples[0]}..{samples[-1]} "
                               f"doubling ({rows_done} rows in all)"}
@@ -426,6 +464,8 @@ def cpu_baseline(name, budget_s=15.0):
            "sample": out["all"]["sample"] + ", row-partitioned over threads",
            "single_core": {"value": out["one"]["value"], "cores": 1, "sample": out["one"]["sample"]},
            "host": {"cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity": share}}
+    if "verify" in out:
+        res["verified"] = out["verify"]
     return res
 
 
@@ -597,10 +637,13 @@ def main():
            "roofline": roofline, "per_pipeline": per, **out, "wall_s_timed": wall}
     if not args.no_cpu_baseline and head_pipes:
         log("[bench] cpu baseline (oracle)")
-        res["cpu_baseline"] = cpu_baseline(head_pipes[0][0], args.cpu_budget)
+        res["cpu_baseline"] = cpu_baseline(head_pipes[0][0], args.cpu_budget, ctx, head_pipes[0][2])
     res["run_s"] = time.perf_counter() - t_run
     print(json.dumps(res), flush=True)
     ctx.close()
+    if not res.get("cpu_baseline", {}).get("verified", {}).get("matches_oracle", True):
+        print("bench.py: the device's answer on the baseline sample differs from the oracle's", file=sys.stderr)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

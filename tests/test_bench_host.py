@@ -57,3 +57,26 @@ def test_every_timed_pipeline_has_bytes_and_a_variant(bench):
         for n in names:
             assert n in bench.DEFAULT_VARIANTS and n in bench.ALGO_BYTES_PER_ROW
     assert bench.HEADLINE["all"] == "c4"
+
+
+def test_same_answer_catches_any_difference(bench):
+    """The check of the device's answer on the baseline sample: equal
+    answers pass, a changed count, key, sum or AVG beyond 1e-12 fails."""
+    import copy
+    import oracle
+    tables, spec = bench.make_pipeline("c4", rows=5000)
+    ref = oracle.run(tables, spec)
+    assert bench.same_answer(copy.deepcopy(ref), ref)
+    for mutate in (lambda a: a["count"].__setitem__(0, a["count"][0] + 1),
+                   lambda a: a["keys"][0].__setitem__(0, a["keys"][0][0] + 7),
+                   lambda a: a["aggs"][1].__setitem__(0, a["aggs"][1][0] + 1),
+                   lambda a: a["aggs"][7].__setitem__(0, a["aggs"][7][0] * (1 + 1e-9))):
+        got = copy.deepcopy(ref)
+        mutate(got)
+        assert not bench.same_answer(got, ref)
+    tables, spec = bench.make_pipeline("c1", rows=5000)
+    ref = oracle.run(tables, spec)
+    got = copy.deepcopy(ref)
+    assert bench.same_answer(got, ref)
+    got["cols"][0][3] += 1
+    assert not bench.same_answer(got, ref)
