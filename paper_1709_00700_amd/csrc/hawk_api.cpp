@@ -909,9 +909,22 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
     c.llog2 = std::min(want, fit);
     if ((int64_t(1) << c.llog2) * W * 8 > ctx->lds_bytes)
       return set_error(ctx, HAWK_E_INFEASIBLE, "local table does not fit in LDS");
-    // copies of the aggregate words while they fit the budget (up to one per lane)
-    const int64_t LC = int64_t(1) << c.llog2;
-    while (c.reps < 64 && (LC + (W - 1) * (2 * c.reps) * LC) * 8 <= table_budget) c.reps *= 2;
+    // copies of the aggregate words while they fit the budget (up to one per
+    // lane); a table of few groups gives up slots (down to two per group, at
+    // least 16) for more copies: its rows' atomics then meet on fewer
+    // addresses
+    auto copies = [&](uint32_t l2) {
+      const int64_t lc = int64_t(1) << l2;
+      int32_t r = 1;
+      while (r < 64 && (lc + (W - 1) * (2 * r) * lc) * 8 <= table_budget) r *= 2;
+      return r;
+    };
+    c.reps = copies(c.llog2);
+    const uint32_t floor2 = std::max<uint32_t>(4, ceil_log2(static_cast<uint64_t>(groups_hint) * 2));
+    while (c.reps < 64 && c.llog2 > floor2 && copies(c.llog2 - 1) > c.reps) {
+      --c.llog2;
+      c.reps = copies(c.llog2);
+    }
   }
   // Overflow partitioning: with the local strategy and linear probing, when
   // the LDS table cannot hold every group, rows that miss it are spilled and
