@@ -959,6 +959,8 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
       if (!seen) sp.reg[sp.ncols++] = P.aggs[a].reg;
     }
     sp.ew = 1 + sp.ncols;
+    // one 32-bit group attribute and one input value: 12-byte entries
+    sp.e12 = sp.ew == 2 && P.ngroup == 1 ? 1 : 0;
     sp.nrows = P.nrows;
     sp.bs = static_cast<int32_t>(v->wg_size);
     sp.coal = v->mem == HAWK_COALESCED ? 1 : 0;
@@ -1387,13 +1389,16 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
       const int64_t m = cfg.nparts * groups;
       uint32_t *offs, *stmp;
       uint64_t *total, *part, *scratch;
-      ALLOC(sp.buf, uint64_t*, static_cast<size_t>(P.nrows * sp.ew) * 8, false);
+      // 12-byte entries: keys, then values from a 16-byte boundary (SpillArr)
+      const size_t spill_bytes = static_cast<size_t>(
+          sp.e12 ? (P.nrows * 4 + 15) / 16 * 16 + P.nrows * 8 : P.nrows * 8 * sp.ew);
+      ALLOC(sp.buf, uint64_t*, spill_bytes, false);
       ALLOC(sp.hist, uint32_t*, static_cast<size_t>(m) * 4, false);
       ALLOC(sp.cnt, uint32_t*, static_cast<size_t>(groups) * 4, false);
       ALLOC(offs, uint32_t*, static_cast<size_t>(m) * 4, false);
       ALLOC(stmp, uint32_t*, static_cast<size_t>(hk_scan_tmp_words(m)) * 4, false);
       ALLOC(total, uint64_t*, 8, false);
-      ALLOC(part, uint64_t*, static_cast<size_t>(P.nrows * sp.ew) * 8, false);
+      ALLOC(part, uint64_t*, spill_bytes, false);
       scratch = nullptr;
       if (sp.merge) {
         ALLOC(sp.flush, uint64_t*, static_cast<size_t>(groups * sp.fcap * W) * 8, false);

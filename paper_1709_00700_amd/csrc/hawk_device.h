@@ -472,6 +472,51 @@ __device__ __forceinline__ bool wg_without_rows(int64_t n, int64_t wgid, int64_t
   return first * chunk >= n;
 }
 
+// A spilled row of a plan with one 32-bit group attribute and one input
+// value takes 12 bytes: its buffers hold two arrays over their n entries,
+// the keys (4 bytes each) and then, from the next 16-byte boundary, the
+// values (8 bytes each). Other two-word plans store 16-byte entries
+// (ulonglong2, key then value). SpillArr<E> reads and writes entries of
+// either form at index i of a buffer (or of an LDS tile) of n entries.
+struct HkE12 { uint32_t k; uint64_t v; };
+__device__ __forceinline__ uint64_t spill_key(const ulonglong2& e) { return e.x; }
+__device__ __forceinline__ uint64_t spill_key(const HkE12& e) { return e.k; }
+__device__ __forceinline__ int64_t spill_value(const ulonglong2& e) { return static_cast<int64_t>(e.y); }
+__device__ __forceinline__ int64_t spill_value(const HkE12& e) { return static_cast<int64_t>(e.v); }
+// LDS bytes of a tile of te spill entries (te a multiple of 4)
+template <class E> struct SpillEntryBytes { static constexpr int64_t value = 16; };
+template <> struct SpillEntryBytes<HkE12> { static constexpr int64_t value = 12; };
+template <class E>
+__host__ __device__ constexpr int64_t spill_tile_bytes(int64_t te) {
+  return te * SpillEntryBytes<E>::value;
+}
+template <class E> struct SpillArr;
+template <>
+struct SpillArr<ulonglong2> {
+  ulonglong2* a;
+  __device__ SpillArr(void* buf, int64_t, int64_t off) : a(static_cast<ulonglong2*>(buf) + off) {}
+  __device__ ulonglong2 get(int64_t i) const { return a[i]; }
+  __device__ void put(int64_t i, const ulonglong2& e) const { a[i] = e; }
+};
+template <>
+struct SpillArr<HkE12> {
+  uint32_t* k;
+  uint64_t* v;
+  __device__ SpillArr(void* buf, int64_t n, int64_t off)
+      : k(static_cast<uint32_t*>(buf) + off),
+        v(reinterpret_cast<uint64_t*>(static_cast<char*>(buf) + (n * 4 + 15) / 16 * 16) + off) {}
+  __device__ HkE12 get(int64_t i) const {
+    HkE12 e;
+    e.k = k[i];
+    e.v = v[i];
+    return e;
+  }
+  __device__ void put(int64_t i, const HkE12& e) const {
+    k[i] = e.k;
+    v[i] = e.v;
+  }
+};
+
 // first spill entry of workgroup w: the rows scanned by workgroups before it
 // (closed form of the coalesced and the sequential row mapping), so regions
 // hold exactly the scan's rows in all

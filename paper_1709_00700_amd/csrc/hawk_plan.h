@@ -180,5 +180,5 @@ struct HkSpill {
   int32_t fcap;               // merge entries per workgroup, at most (its LDS table's slots)
   int32_t merge;              // 1: LDS tables leave as merge entries; 0: they merge into the table with device-scope atomics
   int32_t door_log2;          // > 0: a key enters the LDS table at its second miss (a 2^door_log2-bit filter in LDS)
-  int32_t pad;
+  int32_t e12;                // 1: 12-byte entries (32-bit key, one 64-bit value; ew == 2), else ew words
 };

@@ -7,6 +7,7 @@
 
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -41,24 +42,32 @@ __global__ void __launch_bounds__(1024) k_spill_scatter(HkSpill sp, const uint32
   for (int p = threadIdx.x; p < sp.nparts; p += blockDim.x) cur[p] = offs[static_cast<int64_t>(p) * nwg + wgid];
   __syncthreads();
   const int64_t cnt = sp.cnt[wgid];
-  const uint64_t* region = sp.buf + spill_region_start(sp, nwg, wgid) * sp.ew;
+  const int64_t start = spill_region_start(sp, nwg, wgid);
+  const uint64_t* region = sp.buf + start * sp.ew;  // (entries of ew words)
   const int64_t stride = static_cast<int64_t>(blockDim.x) * SPILL_SU;
-  if (sp.ew == 2) {
-    const ulonglong2* src = reinterpret_cast<const ulonglong2*>(region);
-    ulonglong2* dst = reinterpret_cast<ulonglong2*>(out);
+  auto move = [&](auto tag) {
+    using E = decltype(tag);
+    const SpillArr<E> src(sp.buf, sp.nrows, start), dst(out, sp.nrows, 0);
     for (int64_t i0 = threadIdx.x; i0 < cnt; i0 += stride) {
-      ulonglong2 v[SPILL_SU];
+      E v[SPILL_SU];
 #pragma unroll
       for (int u = 0; u < SPILL_SU; ++u) {
         const int64_t i = i0 + u * static_cast<int64_t>(blockDim.x);
-        if (i < cnt) v[u] = src[i];
+        if (i < cnt) v[u] = src.get(i);
       }
 #pragma unroll
       for (int u = 0; u < SPILL_SU; ++u) {
         const int64_t i = i0 + u * static_cast<int64_t>(blockDim.x);
-        if (i < cnt) dst[atomicAdd(&cur[hslot<HASH>(v[u].x, h.a[0], log2cap) >> rlog2], 1u)] = v[u];
+        if (i < cnt) dst.put(atomicAdd(&cur[hslot<HASH>(spill_key(v[u]), h.a[0], log2cap) >> rlog2], 1u), v[u]);
       }
     }
+  };
+  if (sp.e12) {
+    move(HkE12{});
+    return;
+  }
+  if (sp.ew == 2) {
+    move(ulonglong2{});
     return;
   }
   for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
@@ -78,7 +87,7 @@ __global__ void __launch_bounds__(1024) k_spill_scatter(HkSpill sp, const uint32
 // 16-byte stores per instruction. LDS: the tile, then per partition the
 // running output cursor, the tile counts and the tile offsets (nparts + 1),
 // then one word per wave.
-template <int HASH, int SU>
+template <int HASH, int SU, class E>
 __global__ void __launch_bounds__(1024) k_spill_scatter_lds(HkSpill sp, const uint32_t* __restrict__ offs,
                                                             int64_t nwg, HkHash h, uint32_t log2cap, uint32_t rlog2,
                                                             uint64_t* __restrict__ out) {
@@ -86,33 +95,32 @@ __global__ void __launch_bounds__(1024) k_spill_scatter_lds(HkSpill sp, const ui
   if (wgid >= nwg) return;
   constexpr int TE = SU * 1024;
   extern __shared__ uint64_t sm[];
-  ulonglong2* tile = reinterpret_cast<ulonglong2*>(sm);
+  const SpillArr<E> tile(sm, TE, 0);  // (12-byte entries: TE keys, then TE values)
   const int np = sp.nparts;
-  uint32_t* gcur = reinterpret_cast<uint32_t*>(sm + 2 * TE);
+  uint32_t* gcur = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(sm) + spill_tile_bytes<E>(TE));
   uint32_t* tcnt = gcur + np;
   uint32_t* toff = tcnt + np;
   uint32_t* wave_tot = toff + np + 1;
   const int t = threadIdx.x, bs = blockDim.x;
   for (int p = t; p < np; p += bs) gcur[p] = offs[static_cast<int64_t>(p) * nwg + wgid];
   const int64_t cnt = sp.cnt[wgid];
-  const ulonglong2* src = reinterpret_cast<const ulonglong2*>(sp.buf + spill_region_start(sp, nwg, wgid) * sp.ew);
-  ulonglong2* dst = reinterpret_cast<ulonglong2*>(out);
+  const SpillArr<E> src(sp.buf, sp.nrows, spill_region_start(sp, nwg, wgid)), dst(out, sp.nrows, 0);
   for (int64_t base = 0; base < cnt; base += TE) {
     const int n = cnt - base < TE ? static_cast<int>(cnt - base) : TE;
     for (int p = t; p < np; p += bs) tcnt[p] = 0;
     __syncthreads();
-    ulonglong2 v[SU];
+    E v[SU];
     uint32_t pr[SU], rk[SU];
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
       const int i = t + u * bs;
-      if (i < n) v[u] = src[base + i];
+      if (i < n) v[u] = src.get(base + i);
     }
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
       const int i = t + u * bs;
       if (i < n) {
-        pr[u] = hslot<HASH>(v[u].x, h.a[0], log2cap) >> rlog2;
+        pr[u] = hslot<HASH>(spill_key(v[u]), h.a[0], log2cap) >> rlog2;
         rk[u] = atomicAdd(&tcnt[pr[u]], 1u);
       }
     }
@@ -121,16 +129,16 @@ __global__ void __launch_bounds__(1024) k_spill_scatter_lds(HkSpill sp, const ui
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
       const int i = t + u * bs;
-      if (i < n) tile[toff[pr[u]] + rk[u]] = v[u];
+      if (i < n) tile.put(toff[pr[u]] + rk[u], v[u]);
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
       const int j = t + u * bs;
       if (j < n) {
-        const ulonglong2 e = tile[j];
-        const uint32_t p = hslot<HASH>(e.x, h.a[0], log2cap) >> rlog2;
-        dst[static_cast<int64_t>(gcur[p]) + (j - toff[p])] = e;
+        const E e = tile.get(j);
+        const uint32_t p = hslot<HASH>(spill_key(e), h.a[0], log2cap) >> rlog2;
+        dst.put(static_cast<int64_t>(gcur[p]) + (j - toff[p]), e);
       }
     }
     __syncthreads();
@@ -216,27 +224,33 @@ __global__ void __launch_bounds__(1024) k_spill_agg(HkPlan P, HkAggTable T, HkSp
     const int32_t found = find(key);
     if (found >= 0) agg_apply<HK_BR, true, S>(lt + found, R, P, r, true);
   };
-  if (sp.ew == 2) {
-    // one input value per entry: SU entries per thread and round, loaded first
-    const ulonglong2* src = reinterpret_cast<const ulonglong2*>(in);
+  // one input value per entry: SU entries per thread and round, loaded first
+  auto apply_all = [&](auto tag) {
+    using E = decltype(tag);
+    const SpillArr<E> src(const_cast<uint64_t*>(in), sp.nrows, 0);
     const int reg = sp.reg[0];
     const int64_t stride = static_cast<int64_t>(blockDim.x) * SPILL_SU;
     for (int64_t i0 = b + threadIdx.x; i0 < e; i0 += stride) {
-      ulonglong2 v[SPILL_SU];
+      E v[SPILL_SU];
 #pragma unroll
       for (int u = 0; u < SPILL_SU; ++u) {
         const int64_t i = i0 + u * static_cast<int64_t>(blockDim.x);
-        if (i < e) v[u] = src[i];
+        if (i < e) v[u] = src.get(i);
       }
 #pragma unroll
       for (int u = 0; u < SPILL_SU; ++u) {
         const int64_t i = i0 + u * static_cast<int64_t>(blockDim.x);
         if (i < e) {
-          r[reg] = static_cast<long long>(v[u].y);
-          apply(v[u].x);
+          r[reg] = spill_value(v[u]);
+          apply(spill_key(v[u]));
         }
       }
     }
+  };
+  if (sp.e12) {
+    apply_all(HkE12{});
+  } else if (sp.ew == 2) {
+    apply_all(ulonglong2{});
   } else {
     for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
       const uint64_t* ent = in + i * sp.ew;
@@ -390,24 +404,29 @@ hipError_t hk_spill_shape(hipStream_t st, int step, const HkPlan& P, const HkAgg
     if (ae != hipSuccess) return ae;
     const int maxl = device_max_lds(dev);
     const size_t side = (3 * static_cast<size_t>(sp.nparts) + 1) * sizeof(uint32_t) + (1024 / WAVE) * sizeof(uint32_t);
-    const size_t l8 = 8192 * 16 + side, l4 = 4096 * 16 + side;
-    if (sp.ew == 2 && l8 <= static_cast<size_t>(maxl)) {
+    const size_t l8 = (sp.e12 ? spill_tile_bytes<HkE12>(8192) : spill_tile_bytes<ulonglong2>(8192)) + side;
+    const size_t l4 = (sp.e12 ? spill_tile_bytes<HkE12>(4096) : spill_tile_bytes<ulonglong2>(4096)) + side;
+    auto tiles = [&](auto su, auto* ent, size_t l) {
+      constexpr int SU = decltype(su)::value;
+      using E = typename std::remove_pointer<decltype(ent)>::type;
       hipError_t le = hipSuccess;
       DISPATCH2(hash, HS, {
-        le = lds_fits(k_spill_scatter_lds<HS, 8>, l8);
+        le = lds_fits(k_spill_scatter_lds<HS, SU, E>, l);
         if (le == hipSuccess)
-          hipLaunchKernelGGL((k_spill_scatter_lds<HS, 8>), hk_wg_grid(nwg), dim3(1024), l8, st, sp, offs, nwg, P.hash,
-                             T.log2cap, T.rlog2, part);
+          hipLaunchKernelGGL((k_spill_scatter_lds<HS, SU, E>), hk_wg_grid(nwg), dim3(1024), l, st, sp, offs, nwg,
+                             P.hash, T.log2cap, T.rlog2, part);
       });
+      return le;
+    };
+    using su8 = std::integral_constant<int, 8>;
+    using su4 = std::integral_constant<int, 4>;
+    if (sp.ew == 2 && l8 <= static_cast<size_t>(maxl)) {
+      const hipError_t le = sp.e12 ? tiles(su8{}, static_cast<HkE12*>(nullptr), l8)
+                                   : tiles(su8{}, static_cast<ulonglong2*>(nullptr), l8);
       if (le != hipSuccess) return le;
     } else if (sp.ew == 2 && l4 <= static_cast<size_t>(maxl)) {
-      hipError_t le = hipSuccess;
-      DISPATCH2(hash, HS, {
-        le = lds_fits(k_spill_scatter_lds<HS, 4>, l4);
-        if (le == hipSuccess)
-          hipLaunchKernelGGL((k_spill_scatter_lds<HS, 4>), hk_wg_grid(nwg), dim3(1024), l4, st, sp, offs, nwg, P.hash,
-                             T.log2cap, T.rlog2, part);
-      });
+      const hipError_t le = sp.e12 ? tiles(su4{}, static_cast<HkE12*>(nullptr), l4)
+                                   : tiles(su4{}, static_cast<ulonglong2*>(nullptr), l4);
       if (le != hipSuccess) return le;
     } else {
       const size_t lds = static_cast<size_t>(sp.nparts) * sizeof(uint32_t);

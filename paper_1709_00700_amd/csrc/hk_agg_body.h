@@ -61,12 +61,12 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
   int64_t b, e, step;
   if (MEM == HK_COAL) { b = gt; e = n; step = Tn; }
   else { seq_range(n, gt, Tn, 1, b, e); step = 1; }
-  int64_t rcap = 0;
+  int64_t rcap = 0, r0 = 0;
   uint64_t* region = nullptr;
   if (SPILL) {
-    const int64_t r0 = spill_region_start(sp, nwg, wgid);
+    r0 = spill_region_start(sp, nwg, wgid);
     rcap = spill_region_start(sp, nwg, wgid + 1) - r0;
-    region = sp.buf + r0 * sp.ew;
+    region = sp.buf + r0 * sp.ew;  // (entries of ew words)
   }
   // the aggregation of one evaluated row (registers rr, result_increment pass)
   auto agg_row = [&](const v16i64& rr, bool pass) {
@@ -105,14 +105,20 @@ __device__ __forceinline__ void agg_body(const HkPlan& P, const HkAggTable& T, u
         if (spill) {
           const int64_t pos = static_cast<int64_t>(base) + __popcll(m & lanemask_lt());
           if (pos < rcap) {
-            uint64_t* ent = region + pos * sp.ew;
-            if (sp.ew == 2) {
+            if (sp.e12) {
+              // consecutive spilling lanes write consecutive keys and values
+              HkE12 e3;
+              e3.k = static_cast<uint32_t>(key);
+              e3.v = static_cast<uint64_t>(rr[sp.reg[0]]);
+              SpillArr<HkE12>(sp.buf, sp.nrows, r0).put(pos, e3);
+            } else if (sp.ew == 2) {
               // consecutive spilling lanes write consecutive 16-byte entries: one store each
               ulonglong2 e2;
               e2.x = key;
               e2.y = static_cast<uint64_t>(rr[sp.reg[0]]);
-              *reinterpret_cast<ulonglong2*>(ent) = e2;
+              reinterpret_cast<ulonglong2*>(region)[pos] = e2;
             } else {
+              uint64_t* ent = region + pos * sp.ew;
               ent[0] = key;
               for (int j = 0; j < sp.ncols; ++j) ent[1 + j] = static_cast<uint64_t>(rr[sp.reg[j]]);
             }
