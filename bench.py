@@ -111,18 +111,18 @@ def make_pipeline(name, rows=None):
 # 1.000). Valid only for the kernel sources it was measured on, with the same
 # variant: reported as null otherwise.
 TRAFFIC = {
-    "c4": {"sources_sha": "9482a60233e9e284", "variant_sha": "0152c414afb56411", "total": 13534306309,
-            "per_kernel": {"k_agg": 13534271143, "k_finalize": 14975, "k_init_aggtable": 20191}},
-    "c2u": {"sources_sha": "9482a60233e9e284", "variant_sha": "c903adb01ef30859", "total": 806223052,
-            "per_kernel": {"k_agg": 806198252, "k_finalize": 12448, "k_init_aggtable": 12352}},
-    "c2z": {"sources_sha": "9482a60233e9e284", "variant_sha": "366d68d5fd79efd4", "total": 2250853714,
-            "per_kernel": {"k_agg": 1157519227, "k_spill_agg": 414465810, "k_spill_scatter": 677752569, "k_scan": 1102596, "k_finalize": 8576, "k_init_aggtable": 4936}},
-    "c3": {"sources_sha": "9482a60233e9e284", "variant_sha": "a84f6d0e820b4e49", "total": 3290669629,
-            "per_kernel": {"k_agg": 3277806302, "k_build": 7003124, "k_finalize": 168130, "k_scan": 1102639, "k_spill_scatter": 4388701, "k_spill_agg": 63486, "k_init_aggtable": 137247}},
-    "c1_256m": {"sources_sha": "9482a60233e9e284", "variant_sha": "e551c2cb51e36aaa", "total": 5246696664,
-            "per_kernel": {"k_mp_project": 3012679467, "k_mp_filter": 2198483709, "k_scan": 35533488}},
-    "c1": {"sources_sha": "9482a60233e9e284", "variant_sha": "928f3ef35614eef6", "total": 19641725,
-            "per_kernel": {"k_scan": 131549, "k_mp_filter": 8304994, "k_mp_project": 11205182}},
+    "c4": {"sources_sha": "00b7ef10999e9558", "variant_sha": "0152c414afb56411", "total": 13528008136,
+            "per_kernel": {"k_agg": 13527972970, "k_finalize": 14975, "k_init_aggtable": 20191}},
+    "c2u": {"sources_sha": "00b7ef10999e9558", "variant_sha": "c903adb01ef30859", "total": 806222992,
+            "per_kernel": {"k_agg": 806198192, "k_finalize": 12448, "k_init_aggtable": 12352}},
+    "c2z": {"sources_sha": "00b7ef10999e9558", "variant_sha": "366d68d5fd79efd4", "total": 1972806844,
+            "per_kernel": {"k_agg": 1076096097, "k_spill_agg": 332706079, "k_spill_scatter": 562888467, "k_scan": 1102689, "k_finalize": 8576, "k_init_aggtable": 4936}},
+    "c3": {"sources_sha": "00b7ef10999e9558", "variant_sha": "a84f6d0e820b4e49", "total": 3315270201,
+            "per_kernel": {"k_agg": 3302408869, "k_build": 7003047, "k_finalize": 168147, "k_scan": 1102621, "k_spill_scatter": 4386784, "k_spill_agg": 63486, "k_init_aggtable": 137247}},
+    "c1_256m": {"sources_sha": "00b7ef10999e9558", "variant_sha": "e551c2cb51e36aaa", "total": 5246409899,
+            "per_kernel": {"k_mp_project": 3012403714, "k_mp_filter": 2198462703, "k_scan": 35543482}},
+    "c1": {"sources_sha": "00b7ef10999e9558", "variant_sha": "928f3ef35614eef6", "total": 19641681,
+            "per_kernel": {"k_scan": 131549, "k_mp_filter": 8304983, "k_mp_project": 11205149}},
 }
 TRAFFIC_SOURCES = ["hk_agg.hip", "hk_agg_body.h", "hawk_jit.cpp", "hawk_device.h", "hawk_plan.h", "hk_proj.hip",
                    "hk_proj_body.h", "hk_common.hip", "hk_scalar.hip"]
