@@ -355,7 +355,8 @@ hawk_status hawk_explore(hawk_ctx* ctx, hawk_query* const* W, int32_t k, int32_t
                          const hawk_explore_opts* opts, hawk_variant* best, hawk_explore_report* rep);
 
 /* ------------------------------------------------------------ run-time code generation */
-/* When on, grouped aggregation with linear probing runs a kernel compiled at
+/* When on, grouped aggregation with linear probing and the multi-pass
+   projection (filter or SIMD filter, then projection) run kernels compiled at
    run time (hipRTC, gfx950) for the plan's structure: column types and
    registers, filter and probe registers, arithmetic operators, group and
    aggregate layout are constants of the generated code, as in the paper's
@@ -364,7 +365,10 @@ hawk_status hawk_explore(hawk_ctx* ctx, hawk_query* const* W, int32_t k, int32_t
    arguments, so queries of one structure share a kernel. The first execution
    of a (structure, variant) pair compiles it (about a second); kernels are
    cached in the context until hawk_ctx_destroy. Off by default: every other
-   path, and this one when off, uses the kernels compiled ahead of time.
+   path, and this one when off, uses the kernels compiled ahead of time, as
+   do plans with a CROSS_JOIN and a generated kernel that would need scratch
+   memory (register spills). With the environment variable HAWK_JIT_DUMP set
+   to a directory, each generated source is also written there.
    Errors: HAWK_E_ARG, HAWK_E_DEVICE (planning context). A compilation
    failure is reported by the execution as HAWK_E_DEVICE with the compiler
    log in hawk_last_error. */
