@@ -375,6 +375,13 @@ hawk_status hawk_explore(hawk_ctx* ctx, hawk_query* const* W, int32_t k, int32_t
 hawk_status hawk_ctx_set_jit(hawk_ctx* ctx, int32_t on);
 /* Kernels compiled so far and their total compile time. */
 hawk_status hawk_jit_stats(const hawk_ctx* ctx, int64_t* kernels, double* compile_ms);
+/* Generates and compiles (hipRTC, gfx950) the run-time kernels that executing
+   q in variant v would launch with run-time compilation on, and keeps none of
+   them: a check of the generated sources that needs no device (a planning
+   context works; the context's setting of hawk_ctx_set_jit is left as it
+   is). A plan or variant without run-time kernels passes trivially.
+   Errors: HAWK_E_ARG; HAWK_E_DEVICE with the compiler log in hawk_last_error. */
+hawk_status hawk_jit_compile_check(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v);
 
 /* ------------------------------------------------------------ kernel profiling */
 /* When on, every launch of the library's kernel families is bracketed by HIP

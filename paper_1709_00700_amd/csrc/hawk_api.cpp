@@ -1654,6 +1654,18 @@ static hawk_status prepare_run_time_kernel(hawk_ctx* ctx, const hawk_query* q, c
   return HAWK_OK;
 }
 
+extern "C" hawk_status hawk_jit_compile_check(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v) {
+  if (!ctx) return HAWK_E_ARG;
+  if (!q || !v) return set_error(ctx, HAWK_E_ARG, "bad argument");
+  const bool was = ctx->jit;
+  ctx->jit = true;
+  ctx->jit_cache.compile_only = true;
+  const hawk_status st = prepare_run_time_kernel(ctx, q, v);
+  ctx->jit_cache.compile_only = false;
+  ctx->jit = was;
+  return st;
+}
+
 extern "C" hawk_status hawk_time_variant(hawk_ctx* ctx, const hawk_query* q, const hawk_variant* v, int32_t reps,
                                          double limit_ms, double* median_ms) {
   if (!ctx) return HAWK_E_ARG;

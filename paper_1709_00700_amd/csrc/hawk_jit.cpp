@@ -160,6 +160,14 @@ hipError_t get_kernel(JitCache& cache, std::string& err_msg, const std::string& 
     std::vector<char> code(cs);
     (void)hiprtcGetCode(prog, code.data());
     (void)hiprtcDestroyProgram(&prog);
+    if (cache.compile_only) {
+      fn = nullptr;
+      if (cs == 0) {
+        err_msg = "hipRTC: empty code object";
+        return hipErrorInvalidValue;
+      }
+      return hipSuccess;
+    }
     JitKernel k{};
     hipError_t e = hipModuleLoadData(&k.module, code.data());
     if (e != hipSuccess) {

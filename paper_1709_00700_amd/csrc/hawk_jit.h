@@ -21,6 +21,7 @@
 struct JitKernel { hipModule_t module; hipFunction_t fn; };
 struct JitCache {
   std::map<std::string, JitKernel> kernels;
+  bool compile_only = false;  // compile, load nothing and keep nothing (hawk_jit_compile_check)
   int64_t compiled = 0;
   double compile_ms = 0;
   std::string last_error;  // compiler log of the last failed compilation

@@ -47,7 +47,8 @@ EXPORTS = [
     "hawk_model_train", "hawk_model_predict", "hawk_mlp_forward_dev", "hawk_mlp_grad_dev", "hawk_model_pick",
     "hawk_model_pick_ensemble",
     "hawk_batch_create", "hawk_batch_free", "hawk_batch_run", "hawk_batch_time", "hawk_batch_autotune",
-    "hawk_batch_opts_get", "hawk_batch_result", "hawk_ctx_set_jit", "hawk_jit_stats", "hawk_ctx_set_variant_dims",
+    "hawk_batch_opts_get", "hawk_batch_result", "hawk_ctx_set_jit", "hawk_jit_stats", "hawk_jit_compile_check",
+    "hawk_ctx_set_variant_dims",
 ]
 
 
@@ -190,6 +191,7 @@ def L():
             "hawk_ctx_set_jit": ([vp, i32], i32),
             "hawk_ctx_set_variant_dims": ([vp, ctypes.c_uint32], i32),
             "hawk_jit_stats": ([vp, P(i64), P(ctypes.c_double)], i32),
+            "hawk_jit_compile_check": ([vp, vp, P(hawk_variant)], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -554,6 +556,11 @@ def execute_noalloc(ctx: Context, query: Query, v: hawk_variant, cols=None, cap_
     check(L().hawk_execute_noalloc(ctx.handle, query.handle, ctypes.byref(v), arr, len(cols), cap_rows,
                                    ctypes.byref(n)), ctx.handle)
     return n.value
+
+
+def jit_compile_check(ctx: Context, query: Query, v: hawk_variant):
+    """Compiles the run-time kernels of (query, v) without a device; raises HawkError with the compiler log."""
+    check(L().hawk_jit_compile_check(ctx.handle, query.handle, ctypes.byref(v)), ctx.handle)
 
 
 def time_variant(ctx: Context, query: Query, v: hawk_variant, reps=5, limit_ms=0.0) -> float:

@@ -1,0 +1,61 @@
+"""The kernels generated for run-time compilation compile (hipRTC, gfx950)
+without a device: for every benchmark pipeline in its timed variant and in
+variants that switch on the other generated code paths (predication,
+Murmur hashing, spilling, probes, the SIMD filter and unrolling). A source
+that fails to compile would otherwise show only on a GPU, at its first
+execution."""
+import pytest
+
+from paper_1709_00700_amd import hawk
+
+import bench
+
+
+@pytest.fixture(scope="module")
+def plan_ctx():
+    c = hawk.PlanningContext()
+    yield c
+    _QUERIES.clear()
+    c.close()
+
+
+_QUERIES = {}
+
+
+def query_of(ctx, name):
+    if name in _QUERIES:
+        return _QUERIES[name]
+    tables, spec = bench.make_pipeline(name, rows=4096)
+    # the full workload's row counts (spilling depends on them)
+    full = {"c1": 1_000_000, "c1_256m": 256 << 20, "c2u": 64 << 20, "c2z": 64 << 20, "c3": 120_000_000,
+            "c4": 600_000_000}[name]
+    main = spec["main"]["table"]
+    shapes = {t: {c: (a.dtype, full if t == main else len(a)) for c, a in cols.items()} for t, cols in tables.items()}
+    ctx.register_shapes(shapes)
+    _QUERIES[name] = hawk.build_query(ctx, spec)
+    return _QUERIES[name]
+
+
+CASES = [(w, {}) for w in ("c1", "c1_256m", "c2u", "c2z", "c3", "c4")] + [
+    ("c2u", {"pred": 0, "hash": 0}),
+    ("c2z", {"pred": 1}),
+    ("c3", {"pred": 1, "hash": 0}),
+    ("c4", {"pred": 0, "thread_mult": 1, "wg_size": 1024}),
+    ("c1", {"filter_mode": 1, "thread_mult": 65536}),
+    ("c1", {"unroll": 2, "pred": 1}),
+]
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=[f"{w}-{i}" for i, (w, _) in enumerate(CASES)])
+def test_generated_kernels_compile(plan_ctx, name, kw):
+    q = query_of(plan_ctx, name)
+    v = hawk.variant(**dict(bench.DEFAULT_VARIANTS[name], **kw))
+    hawk.jit_compile_check(plan_ctx, q, v)
+    # the context's own setting is left as it was: nothing was kept
+    assert plan_ctx.jit_stats()[0] == 0
+
+
+def test_compile_check_reports_bad_arguments(plan_ctx):
+    q = query_of(plan_ctx, "c2u")
+    assert hawk.L().hawk_jit_compile_check(plan_ctx.handle, q.handle, None) == hawk.HAWK_E_ARG
+    assert hawk.L().hawk_jit_compile_check(None, q.handle, None) == hawk.HAWK_E_ARG
