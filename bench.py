@@ -45,7 +45,7 @@ DEFAULT_VARIANTS = {
     "c1": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=0, agg_strategy=0, thread_mult=1024, wg_size=256),
     "c2u": dict(proj_strategy=1, mem=1, pred=1, ht=0, hash=1, agg_strategy=0, thread_mult=1, wg_size=1024),
     "c2z": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=1, agg_strategy=0, thread_mult=1, wg_size=1024),
-    "c3": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=1, agg_strategy=0, thread_mult=8, wg_size=512),
+    "c3": dict(proj_strategy=1, mem=1, pred=0, ht=0, hash=1, agg_strategy=0, thread_mult=1, wg_size=1024),
     "c4": dict(proj_strategy=1, mem=1, pred=1, ht=0, hash=1, agg_strategy=0, thread_mult=4, wg_size=256),
 }
 # the 256M-row point: the best multi-pass variant of the extended space

@@ -898,8 +898,24 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
   // 1 KB for static words); a wider grid keeps two workgroups per CU. The
   // table then leaves 8 KB for a spill histogram.
   const bool whole_cu = groups <= ctx->num_cus;
-  const int64_t wg_lds = whole_cu ? std::min<int64_t>(ctx->lds_bytes, kCuLds) - 1024 : kSpillLds;
-  const int64_t table_budget = whole_cu ? wg_lds - 8192 : kLdsBudget;
+  int64_t wg_lds = whole_cu ? std::min<int64_t>(ctx->lds_bytes, kCuLds) - 1024 : kSpillLds;
+  int64_t table_budget = whole_cu ? wg_lds - 8192 : kLdsBudget;
+  // The run-time kernel copies small join tables into LDS, in plan order
+  // while they take at most half of a workgroup's LDS (all of it without a
+  // local table): their lookups then wait on LDS alone, not behind the
+  // column loads in flight. The local table takes what remains.
+  if (ctx->jit && v->ht == HAWK_LINEAR_PROBING && P.xinner == 0) {
+    const int64_t budget = v->agg_strategy == HAWK_LOCAL ? wg_lds / 2 : wg_lds;
+    for (int i = 0; i < P.nprobes; ++i) {
+      const int64_t tb = int64_t(8) << P.probes[i].t.log2cap;
+      if (P.probes[i].t.log2cap >= 4 && c.stage_bytes + tb <= budget) {
+        c.stage[c.nstage++] = i;
+        c.stage_bytes += tb;
+      }
+    }
+    wg_lds -= c.stage_bytes;
+    table_budget = std::min(table_budget, wg_lds - (whole_cu ? 8192 : 0));
+  }
   if (v->agg_strategy == HAWK_LOCAL) {
     // four slots per expected group: few keys then share a group of four
     // slots (a lookup reads one group)
@@ -986,7 +1002,7 @@ hipError_t agg_kernel_launch(hawk_ctx* ctx, hipStream_t st, const hawk_variant* 
     id.nw = W;
     std::string msg;
     const hipError_t e = jit_agg_launch(ctx->jit_cache, msg, st, P, T, v->mem, v->pred, v->hash, v->agg_strategy,
-                                        c.groups, wg, c.llog2, id, err, sp, c.reps);
+                                        c.groups, wg, c.llog2, id, err, sp, c.reps, c.stage, c.nstage);
     if (e != hipSuccess && !msg.empty()) ctx->jit_cache.last_error = msg;
     if (e != hipErrorNotSupported) return e;
   }
@@ -1143,6 +1159,11 @@ const HkBuild* dev_build(const Exec& X, size_t i) {
   return reinterpret_cast<const HkBuild*>(static_cast<const char*>(X.d_plans) + sizeof(HkPlan)) + i;
 }
 
+// slots of a join table (log2): at least twice the build's rows, doubled per retry
+uint32_t join_log2cap(int64_t build_rows, int grow) {
+  return std::max<uint32_t>(4, ceil_log2(static_cast<uint64_t>(std::max<int64_t>(1, build_rows)) * 2)) + grow;
+}
+
 hawk_status run_builds(Exec& X, HkPlan& main, const HkHash& h, int grow) {
   hawk_query* q = const_cast<hawk_query*>(X.q);
   if (q->jt.size() != q->builds.size()) q->jt.resize(q->builds.size());
@@ -1150,7 +1171,7 @@ hawk_status run_builds(Exec& X, HkPlan& main, const HkHash& h, int grow) {
   for (size_t i = 0; i < q->builds.size(); ++i) {
     const QueryBuild& B = q->builds[i];
     JoinTableMem& m = q->jt[i];
-    const uint32_t l2 = std::max<uint32_t>(4, ceil_log2(static_cast<uint64_t>(std::max<int64_t>(1, B.nrows)) * 2)) + grow;
+    const uint32_t l2 = join_log2cap(B.nrows, grow);
     if (l2 > 31) return set_error(X.ctx, HAWK_E_CAPACITY, "join table beyond 2^31 slots");
     uint64_t *slots = m.slots, *side = m.side;
     if (X.mem == EXEC_ARENA) {
@@ -1641,15 +1662,19 @@ static hawk_status prepare_run_time_kernel(hawk_ctx* ctx, const hawk_query* q, c
   const int64_t groups = v->agg_strategy == HAWK_LOCAL
                              ? static_cast<int64_t>(v->thread_mult) * ctx->num_cus
                              : static_cast<int64_t>(ctx->num_cus) * std::max<int64_t>(1, 2048 / v->wg_size);
+  // the join tables' sizes as the builds will make them
+  HkPlan P = q->main;
+  for (int i = 0; i < P.nprobes; ++i)
+    P.probes[i].t.log2cap = join_log2cap(q->builds[q->probe_build[i]].nrows, 0);
   AggConfig c;
-  if (agg_config(ctx, q->main, T, q->groups_hint, v, groups, c)) {
+  if (agg_config(ctx, P, T, q->groups_hint, v, groups, c)) {
     ctx->err.clear();  // the execution reports it
     return HAWK_OK;
   }
   std::string msg;
-  const hipError_t e = jit_agg_prepare(ctx->jit_cache, msg, q->main, v->mem, v->pred, v->hash, v->agg_strategy,
+  const hipError_t e = jit_agg_prepare(ctx->jit_cache, msg, P, v->mem, v->pred, v->hash, v->agg_strategy,
                                        static_cast<int32_t>(v->wg_size), c.llog2, q->main.slot_words, c.reps,
-                                       c.spill ? &c.sp : nullptr);
+                                       c.spill ? &c.sp : nullptr, c.stage, c.nstage);
   if (e != hipSuccess && e != hipErrorNotSupported) return set_error(ctx, HAWK_E_DEVICE, "run-time compilation: " + msg);
   return HAWK_OK;
 }

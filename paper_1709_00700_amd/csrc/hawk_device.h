@@ -229,6 +229,18 @@ __device__ __forceinline__ bool join_scan_from(const HkJoinTable& t, uint32_t k,
   return false;
 }
 
+// Copies a join table's slots into LDS (all threads of the workgroup, 16
+// bytes each per step) and points the table there: its lookups then read
+// LDS. The caller synchronises the workgroup before the first lookup.
+__device__ __forceinline__ void stage_join(HkJoinTable& t, uint64_t* dst, uint32_t log2cap) {
+  const ulonglong2* s = reinterpret_cast<const ulonglong2*>(t.slots);
+  ulonglong2* d = reinterpret_cast<ulonglong2*>(dst);
+  const uint32_t n = (1u << log2cap) / 2;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
+  t.slots = dst;
+  t.log2cap = log2cap;
+}
+
 template <int HT, int HASH>
 __device__ __forceinline__ bool join_lookup(const HkJoinTable& t, const HkHash& h, int32_t key, int32_t& pay) {
   if (key == -1) {

@@ -123,6 +123,11 @@ struct AggConfig {
   uint32_t rlog2;   // table region (log2 slots); the whole table without spilling
   int64_t nparts;
   HkSpill sp;       // sizes and registers; buffers are the caller's
+  // join tables that the run-time kernel copies into each workgroup's LDS
+  // (probe indices in plan order) and their bytes
+  int32_t nstage;
+  int32_t stage[HK_MAX_PROBES];
+  int64_t stage_bytes;
 };
 hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int64_t groups_hint,
                        const hawk_variant* v, int64_t groups, AggConfig& c);

@@ -81,10 +81,14 @@ std::string exact_shape(const HkPlan& P, int naggs, int nproj) {
 }  // namespace
 
 std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash, int strat, bool spill,
-                           size_t lds_bytes, int32_t wg) {
+                           size_t lds_bytes, int32_t wg, const int32_t* stage, int32_t nstage) {
   std::ostringstream o;
-  // the local table is a static LDS array of the launch's size (no dynamic LDS)
-  const size_t words = lds_bytes / 8 > 0 ? (lds_bytes + 7) / 8 : 1;
+  // the local table is a static LDS array of the launch's size (no dynamic
+  // LDS), followed by the join tables copied into LDS (32-byte aligned)
+  const size_t table_words = (lds_bytes + 31) / 32 * 4;
+  size_t words = table_words;
+  for (int32_t i = 0; i < nstage; ++i) words += size_t(1) << P.probes[stage[i]].t.log2cap;
+  if (words == 0) words = 1;
   o << "#include \"hk_agg_body.h\"\n"
        "extern \"C\" __global__ void __launch_bounds__(" << wg << ") hk_jit_agg(HkPlan Prt, HkAggTable T, uint32_t llog2,\n"
        "    HkIdent id, int64_t nwg, int* err, HkSpill sp, int32_t reps) {\n"
@@ -92,6 +96,15 @@ std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash,
   HkPlan Q = P;
   Q.nproj = 0;
   emit_structure(o, Q);
+  if (nstage > 0) {
+    size_t off = table_words;
+    for (int32_t i = 0; i < nstage; ++i) {
+      const uint32_t l2 = P.probes[stage[i]].t.log2cap;
+      o << "  stage_join(P.probes[" << stage[i] << "].t, lds + " << off << ", " << l2 << "u);\n";
+      off += size_t(1) << l2;
+    }
+    o << "  __syncthreads();\n";
+  }
   o << "  agg_body<" << mem << ", " << pred << ", " << ht << ", " << hash << ", " << strat << ", "
     << exact_shape(P, P.naggs, 0) << ", " << (spill ? "true" : "false") << ">(P, T, llog2, id, nwg, err, sp, reps, lds);\n}\n";
   return o.str();
@@ -211,19 +224,22 @@ hipError_t get_kernel(JitCache& cache, std::string& err_msg, const std::string& 
 }  // namespace
 
 hipError_t jit_agg_prepare(JitCache& cache, std::string& err_msg, const HkPlan& P, int mem, int pred, int hash,
-                           int strat, int32_t wg, uint32_t llog2, int32_t nw, int32_t reps, const HkSpill* sp) {
+                           int strat, int32_t wg, uint32_t llog2, int32_t nw, int32_t reps, const HkSpill* sp,
+                           const int32_t* stage, int32_t nstage) {
   hipFunction_t fn;
   const size_t lds = hk_agg_lds_bytes(strat, llog2, nw, reps, sp);
-  return get_kernel(cache, err_msg, jit_agg_source(P, mem, pred, HK_LIN, hash, strat, sp != nullptr, lds, wg), fn);
+  return get_kernel(cache, err_msg,
+                    jit_agg_source(P, mem, pred, HK_LIN, hash, strat, sp != nullptr, lds, wg, stage, nstage), fn);
 }
 
 hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P,
                           const HkAggTable& T, int mem, int pred, int hash, int strat, int64_t groups, int32_t wg,
-                          uint32_t llog2, const HkIdent& id, int* err, const HkSpill* sp, int32_t reps) {
+                          uint32_t llog2, const HkIdent& id, int* err, const HkSpill* sp, int32_t reps,
+                          const int32_t* stage, int32_t nstage) {
   hipFunction_t fn;
   const size_t lds = hk_agg_lds_bytes(strat, llog2, id.nw, reps, sp);
-  const hipError_t ge =
-      get_kernel(cache, err_msg, jit_agg_source(P, mem, pred, HK_LIN, hash, strat, sp != nullptr, lds, wg), fn);
+  const hipError_t ge = get_kernel(
+      cache, err_msg, jit_agg_source(P, mem, pred, HK_LIN, hash, strat, sp != nullptr, lds, wg, stage, nstage), fn);
   if (ge != hipSuccess) return ge;
   HkSpill none;
   std::memset(&none, 0, sizeof(none));

@@ -29,16 +29,20 @@ struct JitCache {
 };
 
 // Generated source of the specialised kernel `hk_jit_agg` for (P, variant).
+// The join tables of probes stage[0..nstage) (sizes from P) are copied into
+// each workgroup's LDS after its lds_bytes of local table.
 std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash, int strat, bool spill,
-                           size_t lds_bytes, int32_t wg);
+                           size_t lds_bytes, int32_t wg, const int32_t* stage, int32_t nstage);
 // Compiles the specialised kernel unless the cache holds it (no GPU work).
 hipError_t jit_agg_prepare(JitCache& cache, std::string& err_msg, const HkPlan& P, int mem, int pred, int hash,
-                           int strat, int32_t wg, uint32_t llog2, int32_t nw, int32_t reps, const HkSpill* sp);
+                           int strat, int32_t wg, uint32_t llog2, int32_t nw, int32_t reps, const HkSpill* sp,
+                           const int32_t* stage, int32_t nstage);
 // Compiles (or finds) and launches the specialised kernel; same arguments and
 // launch shape as the ahead-of-time k_agg. Linear probing only.
 hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P,
                           const HkAggTable& T, int mem, int pred, int hash, int strat, int64_t groups, int32_t wg,
-                          uint32_t llog2, const HkIdent& id, int* err, const HkSpill* sp, int32_t reps);
+                          uint32_t llog2, const HkIdent& id, int* err, const HkSpill* sp, int32_t reps,
+                          const int32_t* stage, int32_t nstage);
 
 // Run-time specialisation of the multi-pass projection kernels (bodies in
 // hk_proj_body.h) for one plan structure, same arguments and launch shape as

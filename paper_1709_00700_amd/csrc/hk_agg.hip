@@ -224,27 +224,34 @@ __global__ void __launch_bounds__(1024) k_spill_agg(HkPlan P, HkAggTable T, HkSp
     const int32_t found = find(key);
     if (found >= 0) agg_apply<HK_BR, true, S>(lt + found, R, P, r, true);
   };
-  // one input value per entry: SU entries per thread and round, loaded first
+  // one input value per entry: SU entries per thread and round; the next
+  // round's entries are loaded while this round's are applied (the applies
+  // wait only on LDS, so the loads in flight stay in flight)
   auto apply_all = [&](auto tag) {
     using E = decltype(tag);
     const SpillArr<E> src(const_cast<uint64_t*>(in), sp.nrows, 0);
     const int reg = sp.reg[0];
-    const int64_t stride = static_cast<int64_t>(blockDim.x) * SPILL_SU;
-    for (int64_t i0 = b + threadIdx.x; i0 < e; i0 += stride) {
-      E v[SPILL_SU];
+    const int64_t bd = blockDim.x;
+    const int64_t stride = bd * SPILL_SU;
+    E v[SPILL_SU] = {}, nx[SPILL_SU] = {};
+    int64_t i0 = b + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < SPILL_SU; ++u)
+      if (i0 + u * bd < e) v[u] = src.get(i0 + u * bd);
+    for (; i0 < e; i0 += stride) {
+      const int64_t n0 = i0 + stride;
+#pragma unroll
+      for (int u = 0; u < SPILL_SU; ++u)
+        if (n0 + u * bd < e) nx[u] = src.get(n0 + u * bd);
 #pragma unroll
       for (int u = 0; u < SPILL_SU; ++u) {
-        const int64_t i = i0 + u * static_cast<int64_t>(blockDim.x);
-        if (i < e) v[u] = src.get(i);
-      }
-#pragma unroll
-      for (int u = 0; u < SPILL_SU; ++u) {
-        const int64_t i = i0 + u * static_cast<int64_t>(blockDim.x);
-        if (i < e) {
+        if (i0 + u * bd < e) {
           r[reg] = spill_value(v[u]);
           apply(spill_key(v[u]));
         }
       }
+#pragma unroll
+      for (int u = 0; u < SPILL_SU; ++u) v[u] = nx[u];
     }
   };
   if (sp.e12) {
