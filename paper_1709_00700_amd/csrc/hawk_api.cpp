@@ -1205,11 +1205,26 @@ hawk_status run_builds(Exec& X, HkPlan& main, const HkHash& h, int grow) {
   for (int i = 0; i < main.nprobes; ++i) main.probes[i].t = bs[q->probe_build[i]].t;
   hawk_status st = upload_plans(X, main, bs);
   if (st) return st;
+  // every table and its side words cleared in one launch, then every build
+  // in one launch (the builds are independent)
+  HkFills f{};
+  int32_t k = 0;
   for (size_t i = 0; i < bs.size(); ++i) {
-    LAUNCH(hk_fill_u64(X.st, bs[i].t.slots, int64_t(1) << bs[i].t.log2cap, HK_EMPTY), "fill join table");
-    LAUNCH(hk_fill_u64(X.st, bs[i].t.side, 2, 0), "fill side words");
+    f.p[k] = bs[i].t.slots;
+    f.n[k] = int64_t(1) << bs[i].t.log2cap;
+    f.v[k++] = HK_EMPTY;
+    f.p[k] = bs[i].t.side;
+    f.n[k] = 2;
+    f.v[k++] = 0;
+    if (k + 2 > HK_MAX_FILLS || i + 1 == bs.size()) {
+      LAUNCH(hk_fill_multi(X.st, f, k), "fill join tables");
+      k = 0;
+    }
+  }
+  if (!bs.empty()) {
     ProfScope ps(X.prof(), "k_build");
-    LAUNCH(hk_build(X.st, bs[i], dev_build(X, i), X.v->ht, X.v->hash, X.res->d_err), "build");
+    LAUNCH(hk_build(X.st, bs.data(), dev_build(X, 0), static_cast<int32_t>(bs.size()), X.v->ht, X.v->hash,
+                    X.res->d_err), "build");
   }
   return HAWK_OK;
 }

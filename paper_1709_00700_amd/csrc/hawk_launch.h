@@ -12,11 +12,21 @@
 // kernels read the copy the query keeps in device memory (dB / dP).
 
 hipError_t hk_fill_u64(hipStream_t st, uint64_t* p, int64_t n, uint64_t v);
+// fills 0..k-1 of f (k <= HK_MAX_FILLS) in one launch
+#define HK_MAX_FILLS 16
+struct HkFills {
+  uint64_t* p[HK_MAX_FILLS];
+  int64_t n[HK_MAX_FILLS];
+  uint64_t v[HK_MAX_FILLS];
+};
+hipError_t hk_fill_multi(hipStream_t st, const HkFills& f, int32_t k);
 hipError_t hk_init_aggtable(hipStream_t st, uint64_t* words, int64_t nslots, const uint64_t* ident, int32_t nw);
 
-// build pipeline: FILTER part of B.p (colA columns), then HASH_PUT of key -> payload into B.t;
-// B is the host copy (sizes), dB the same struct in device memory (read by the kernels)
-hipError_t hk_build(hipStream_t st, const HkBuild& B, const HkBuild* dB, int ht, int hash, int* err);
+// build pipelines: FILTER part of B.p (colA columns), then HASH_PUT of key ->
+// payload into B.t, for the nb builds B[0..nb) in one launch (one grid row
+// each); B is the host copy (sizes), dB the same array in device memory (read
+// by the kernels)
+hipError_t hk_build(hipStream_t st, const HkBuild* B, const HkBuild* dB, int32_t nb, int ht, int hash, int* err);
 
 // multi-pass projection: filter kernel, scan, projection kernel
 // unroll (coalesced): rows per loop iteration, 1, 2 or 4 (0 = 4); simd: FILTER

@@ -16,6 +16,15 @@ __global__ void __launch_bounds__(256) k_fill_u64(uint64_t* p, int64_t n, uint64
     p[i] = v;
 }
 
+// several fills in one launch, one per grid row
+__global__ void __launch_bounds__(256) k_fill_multi(HkFills f) {
+  uint64_t* p = f.p[blockIdx.y];
+  const int64_t n = f.n[blockIdx.y];
+  const uint64_t v = f.v[blockIdx.y];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 __global__ void __launch_bounds__(256) k_init_aggtable(uint64_t* words, int64_t nslots, HkIdent id) {
   __shared__ uint64_t w[2 + 2 * HK_MAX_AGGS];
   if (threadIdx.x == 0)
@@ -26,9 +35,12 @@ __global__ void __launch_bounds__(256) k_init_aggtable(uint64_t* words, int64_t 
     words[i] = w[i % id.nw];
 }
 
+// The build kernels take an array of builds, one per grid row (blockIdx.y):
+// the builds of a query are independent (each fills its own table), so one
+// launch runs them all.
 template <int HT, int HASH>
 __global__ void __launch_bounds__(256) k_build(const HkBuild* Bp, int* err) {
-  const HkBuild& B = *Bp;  // build plan in device memory
+  const HkBuild& B = Bp[blockIdx.y];  // build plan in device memory
   v16i64 r = {};
   const int64_t T = (int64_t)gridDim.x * blockDim.x;
   for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < B.p.nrows; row += T) {
@@ -41,7 +53,7 @@ __global__ void __launch_bounds__(256) k_build(const HkBuild* Bp, int* err) {
 // a cuckoo table may hold two copies of a key inserted twice; count copies
 template <int HASH>
 __global__ void __launch_bounds__(256) k_build_verify(const HkBuild* Bp, int* err) {
-  const HkBuild& B = *Bp;  // build plan in device memory
+  const HkBuild& B = Bp[blockIdx.y];  // build plan in device memory
   v16i64 r = {};
   const int64_t T = (int64_t)gridDim.x * blockDim.x;
   for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < B.p.nrows; row += T) {
@@ -70,7 +82,7 @@ __global__ void __launch_bounds__(256) k_build_verify(const HkBuild* Bp, int* er
 // none an insertion that failed.
 template <int HASH>
 __global__ void __launch_bounds__(256) k_build_verify_robin(const HkBuild* Bp, int* err) {
-  const HkBuild& B = *Bp;
+  const HkBuild& B = Bp[blockIdx.y];
   v16i64 r = {};
   const int64_t T = (int64_t)gridDim.x * blockDim.x;
   const uint32_t mask = (1u << B.t.log2cap) - 1u;
@@ -305,12 +317,28 @@ hipError_t hk_init_aggtable(hipStream_t st, uint64_t* words, int64_t nslots, con
   HK_CHECK_LAUNCH();
 }
 
-hipError_t hk_build(hipStream_t st, const HkBuild& B, const HkBuild* dB, int ht, int hash, int* err) {
-  const dim3 g(hk_grid_for(B.p.nrows, 256, 4096)), b(256);
+hipError_t hk_fill_multi(hipStream_t st, const HkFills& f, int32_t k) {
+  if (k <= 0) return hipSuccess;
+  if (k > HK_MAX_FILLS) return hipErrorInvalidValue;
+  int64_t n = 1;
+  for (int32_t i = 0; i < k; ++i) n = std::max(n, f.n[i]);
+  hipLaunchKernelGGL(k_fill_multi, dim3(hk_grid_for(n, 256, 8192), static_cast<uint32_t>(k)), dim3(256), 0, st, f);
+  HK_CHECK_LAUNCH();
+}
+
+hipError_t hk_build(hipStream_t st, const HkBuild* B, const HkBuild* dB, int32_t nb, int ht, int hash, int* err) {
+  if (nb <= 0) return hipSuccess;
+  int64_t rows = 1;
+  bool robin = false;
+  for (int32_t i = 0; i < nb; ++i) {
+    rows = std::max(rows, B[i].p.nrows);
+    robin = robin || B[i].t.robin;
+  }
+  const dim3 g(hk_grid_for(rows, 256, 4096), static_cast<uint32_t>(nb)), b(256);
   DISPATCH2(ht, HT, DISPATCH2(hash, HS, hipLaunchKernelGGL((k_build<HT, HS>), g, b, 0, st, dB, err)));
   if (ht == HK_CUCKOO) {
     DISPATCH2(hash, HS, hipLaunchKernelGGL((k_build_verify<HS>), g, b, 0, st, dB, err));
-  } else if (B.t.robin) {
+  } else if (robin) {
     DISPATCH2(hash, HS, hipLaunchKernelGGL((k_build_verify_robin<HS>), g, b, 0, st, dB, err));
   }
   HK_CHECK_LAUNCH();
