@@ -111,18 +111,18 @@ def make_pipeline(name, rows=None):
 # 1.000). Valid only for the kernel sources it was measured on, with the same
 # variant: reported as null otherwise.
 TRAFFIC = {
-    "c4": {"sources_sha": "cf3676b888458226", "variant_sha": "e6de8da543c2592a", "total": 13316694544,
-            "per_kernel": {"k_agg": 13316659378, "k_finalize": 14975, "k_init_aggtable": 20191}},
-    "c2u": {"sources_sha": "cf3676b888458226", "variant_sha": "c903adb01ef30859", "total": 806228148,
-            "per_kernel": {"k_agg": 806203348, "k_finalize": 12448, "k_init_aggtable": 12352}},
-    "c2z": {"sources_sha": "cf3676b888458226", "variant_sha": "366d68d5fd79efd4", "total": 1972869433,
-            "per_kernel": {"k_agg": 1076114398, "k_spill_agg": 332704718, "k_spill_scatter": 562934219, "k_scan": 1102578, "k_finalize": 8584, "k_init_aggtable": 4936}},
-    "c3": {"sources_sha": "cf3676b888458226", "variant_sha": "a84f6d0e820b4e49", "total": 3289937139,
-            "per_kernel": {"k_agg": 3277076664, "k_build": 7002091, "k_finalize": 168095, "k_scan": 1102757, "k_spill_scatter": 4386800, "k_spill_agg": 63486, "k_init_aggtable": 137246}},
-    "c1_256m": {"sources_sha": "cf3676b888458226", "variant_sha": "e551c2cb51e36aaa", "total": 5246332374,
-            "per_kernel": {"k_mp_project": 3012321913, "k_mp_filter": 2198469149, "k_scan": 35541312}},
-    "c1": {"sources_sha": "cf3676b888458226", "variant_sha": "928f3ef35614eef6", "total": 19641696,
-            "per_kernel": {"k_scan": 131549, "k_mp_filter": 8304982, "k_mp_project": 11205165}},
+    "c4": {"sources_sha": "92a5adc69260ea50", "variant_sha": "e6de8da543c2592a", "total": 13315155129,
+            "per_kernel": {"k_agg": 13315120603, "k_finalize": 14335, "k_init_aggtable": 20191}},
+    "c2u": {"sources_sha": "92a5adc69260ea50", "variant_sha": "c903adb01ef30859", "total": 806228217,
+            "per_kernel": {"k_agg": 806204057, "k_finalize": 11808, "k_init_aggtable": 12352}},
+    "c2z": {"sources_sha": "92a5adc69260ea50", "variant_sha": "366d68d5fd79efd4", "total": 1974944895,
+            "per_kernel": {"k_agg": 1076106222, "k_spill_agg": 334798300, "k_spill_scatter": 562908599, "k_scan": 1118894, "k_finalize": 7944, "k_init_aggtable": 4936}},
+    "c3": {"sources_sha": "92a5adc69260ea50", "variant_sha": "366d68d5fd79efd4", "total": 3443860461,
+            "per_kernel": {"k_agg": 3428532482, "k_build": 6550434, "k_spill_agg": 935673, "k_fill_multi": 6905027, "k_scan": 139686, "k_spill_scatter": 784191, "k_finalize": 7936, "k_init_aggtable": 5032}},
+    "c1_256m": {"sources_sha": "92a5adc69260ea50", "variant_sha": "e551c2cb51e36aaa", "total": 5246218471,
+            "per_kernel": {"k_mp_project": 3012325005, "k_mp_filter": 2198472484, "k_scan": 35420982}},
+    "c1": {"sources_sha": "92a5adc69260ea50", "variant_sha": "928f3ef35614eef6", "total": 19643753,
+            "per_kernel": {"k_scan": 133597, "k_mp_filter": 8305061, "k_mp_project": 11205095}},
 }
 TRAFFIC_SOURCES = ["hk_agg.hip", "hk_agg_body.h", "hawk_jit.cpp", "hawk_device.h", "hawk_plan.h", "hk_proj.hip",
                    "hk_proj_body.h", "hk_common.hip", "hk_scalar.hip"]

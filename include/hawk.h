@@ -367,7 +367,10 @@ hawk_status hawk_explore(hawk_ctx* ctx, hawk_query* const* W, int32_t k, int32_t
    cached in the context until hawk_ctx_destroy. Off by default: every other
    path, and this one when off, uses the kernels compiled ahead of time, as
    do plans with a CROSS_JOIN and a generated kernel that would need scratch
-   memory (register spills). With the environment variable HAWK_JIT_DUMP set
+   memory (register spills). A generated aggregation kernel also copies the
+   join tables that fit (in plan order, up to half of a workgroup's LDS beside
+   a local table) into each workgroup's LDS and probes them there; the
+   results are the same. With the environment variable HAWK_JIT_DUMP set
    to a directory, each generated source is also written there.
    Errors: HAWK_E_ARG, HAWK_E_DEVICE (planning context). A compilation
    failure is reported by the execution as HAWK_E_DEVICE with the compiler

@@ -59,3 +59,32 @@ def test_compile_check_reports_bad_arguments(plan_ctx):
     q = query_of(plan_ctx, "c2u")
     assert hawk.L().hawk_jit_compile_check(plan_ctx.handle, q.handle, None) == hawk.HAWK_E_ARG
     assert hawk.L().hawk_jit_compile_check(None, q.handle, None) == hawk.HAWK_E_ARG
+
+
+def _generated_sources(ctx, q, v, tmp_path, monkeypatch):
+    d = tmp_path / "gen"
+    d.mkdir()
+    monkeypatch.setenv("HAWK_JIT_DUMP", str(d))
+    hawk.jit_compile_check(ctx, q, v)
+    return [p.read_text() for p in sorted(d.glob("*.hip"))]
+
+
+def test_small_join_table_staged_in_lds(plan_ctx, tmp_path, monkeypatch):
+    # the star join's first dimension (2.5k rows: 8192 slots, 64 KiB) fits
+    # half of a whole-CU workgroup's LDS and is copied there; the others
+    # (0.5-4 MB) are probed in device memory
+    q = query_of(plan_ctx, "c3")
+    v = hawk.variant(**dict(bench.DEFAULT_VARIANTS["c3"], thread_mult=1, wg_size=1024))
+    (src,) = _generated_sources(plan_ctx, q, v, tmp_path, monkeypatch)
+    assert "stage_join(P.probes[0].t, lds + " in src and ", 13u);" in src
+    assert "stage_join(P.probes[1]" not in src and "stage_join(P.probes[3]" not in src
+    assert "__syncthreads();" in src
+
+
+def test_no_staging_where_the_table_would_cost_residency(plan_ctx, tmp_path, monkeypatch):
+    # eight workgroups per CU keep two local tables per CU: the 64 KiB
+    # table does not fit beside one
+    q = query_of(plan_ctx, "c3")
+    v = hawk.variant(**dict(bench.DEFAULT_VARIANTS["c3"], thread_mult=8, wg_size=512))
+    (src,) = _generated_sources(plan_ctx, q, v, tmp_path, monkeypatch)
+    assert "stage_join" not in src
