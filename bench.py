@@ -117,8 +117,8 @@ TRAFFIC = {
             "per_kernel": {"k_agg": 806204057, "k_finalize": 11808, "k_init_aggtable": 12352}},
     "c2z": {"sources_sha": "92a5adc69260ea50", "variant_sha": "366d68d5fd79efd4", "total": 1974944895,
             "per_kernel": {"k_agg": 1076106222, "k_spill_agg": 334798300, "k_spill_scatter": 562908599, "k_scan": 1118894, "k_finalize": 7944, "k_init_aggtable": 4936}},
-    "c3": {"sources_sha": "92a5adc69260ea50", "variant_sha": "366d68d5fd79efd4", "total": 3443860461,
-            "per_kernel": {"k_agg": 3428532482, "k_build": 6550434, "k_spill_agg": 935673, "k_fill_multi": 6905027, "k_scan": 139686, "k_spill_scatter": 784191, "k_finalize": 7936, "k_init_aggtable": 5032}},
+    "c3": {"sources_sha": "92a5adc69260ea50", "variant_sha": "366d68d5fd79efd4", "total": 3436955434,
+            "per_kernel": {"k_agg": 3428532482, "k_build": 6550434, "k_spill_agg": 935673, "k_scan": 139686, "k_spill_scatter": 784191, "k_finalize": 7936, "k_init_aggtable": 5032}},
     "c1_256m": {"sources_sha": "92a5adc69260ea50", "variant_sha": "e551c2cb51e36aaa", "total": 5246218471,
             "per_kernel": {"k_mp_project": 3012325005, "k_mp_filter": 2198472484, "k_scan": 35420982}},
     "c1": {"sources_sha": "92a5adc69260ea50", "variant_sha": "928f3ef35614eef6", "total": 19643753,
