@@ -110,3 +110,30 @@ def test_jit_projection_with_probes(ctx):
           for m in (0, 1) for pr in (0, 1) for h in (0, 1, 2) for x in (0, 1)]
     ctx.set_variant_dims(hawk.HAWK_DIM_ROBIN_HOOD)
     run_variants(ctx, tables, spec, vs, label="jit-proj-join")
+
+
+def test_jit_join_tables_in_lds_side_key_and_robin(ctx):
+    # one small dimension: the run-time kernel copies its join table into
+    # LDS (one workgroup per CU, and eight per CU) and probes it there; the
+    # key -1 stays in the table's side word in device memory, and robin-hood
+    # tables are probed from LDS as well. Fact keys 300..319 find no match.
+    rng = np.random.default_rng(16)
+    n = 90_001
+    dk = np.arange(-1, 299, dtype=np.int32)
+    rng.shuffle(dk)
+    d = {"key": dk, "g": rng.integers(-3, 7, size=dk.size).astype(np.int32),
+         "f": rng.integers(0, 10, size=dk.size).astype(np.int32)}
+    d["f"][dk == -1] = 0  # key -1 passes the dimension's filter
+    fact = {"fk": rng.integers(-1, 320, size=n).astype(np.int32),
+            "v": rng.integers(-(1 << 40), 1 << 40, size=n, dtype=np.int64)}
+    fact["fk"][::97] = -1
+    spec = {"builds": [{"table": "d", "filters": [("f", 0, 6)], "key": "key", "payload": "g"}],
+            "main": {"table": "f", "filters": [], "probes": [("fk", 0, "p0")], "arith": [],
+                     "group_by": ["p0"], "aggs": [("sum", "v", False), ("count", None, False),
+                                                  ("min", "v", False)],
+                     "groups_hint": 10}}
+    vs = [hawk.variant(agg_strategy=a, ht=ht, hash=h, mem=1, pred=p, thread_mult=tm, wg_size=wg)
+          for ht in (hawk.HAWK_LINEAR_PROBING, hawk.HAWK_ROBIN_HOOD) for h in (0, 1) for p in (0, 1)
+          for (a, tm, wg) in ((0, 1, 1024), (0, 8, 256), (1, 1, 512))]
+    _, ref = run_variants(ctx, {"d": d, "f": fact}, spec, vs, label="jit-lds-join")
+    assert -1 in set(int(k) for k in dk[d["f"] <= 6])
