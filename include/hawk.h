@@ -355,9 +355,9 @@ hawk_status hawk_explore(hawk_ctx* ctx, hawk_query* const* W, int32_t k, int32_t
                          const hawk_explore_opts* opts, hawk_variant* best, hawk_explore_report* rep);
 
 /* ------------------------------------------------------------ run-time code generation */
-/* When on, grouped aggregation with linear probing and the multi-pass
-   projection (filter or SIMD filter, then projection) run kernels compiled at
-   run time (hipRTC, gfx950) for the plan's structure: column types and
+/* When on, aggregation with linear probing (grouped, and without grouping
+   attributes) and the multi-pass projection (filter or SIMD filter, then
+   projection) run kernels compiled at run time (hipRTC, gfx950) for the plan's structure: column types and
    registers, filter and probe registers, arithmetic operators, group and
    aggregate layout are constants of the generated code, as in the paper's
    per-query code generation (Section 7); column pointers, filter bounds,

@@ -17,7 +17,7 @@ SOURCES = ["hk_batch.hip", "hk_common.hip", "hk_dispatch.hip", "hk_mlp.hip", "ha
            "hawk_model.cpp", "hawk_batch.cpp", "hawk_jit.cpp", "hawk_planner.cpp"]
 # device headers embedded into the library for run-time compilation (hawk_jit.cpp)
 EMBEDDED = [("kSrcPlan", "hawk_plan.h"), ("kSrcDevice", "hawk_device.h"), ("kSrcAggBody", "hk_agg_body.h"),
-            ("kSrcProjBody", "hk_proj_body.h")]
+            ("kSrcProjBody", "hk_proj_body.h"), ("kSrcScalarBody", "hk_scalar_body.h")]
 # kernel families compiled once per shape class (see HkShape in hawk_plan.h)
 SHAPED = ["hk_agg.hip", "hk_proj.hip", "hk_scalar.hip"]
 SHAPES = ["A", "F", "J", "W", "G"]

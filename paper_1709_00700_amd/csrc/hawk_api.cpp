@@ -1010,6 +1010,25 @@ hipError_t agg_kernel_launch(hawk_ctx* ctx, hipStream_t st, const hawk_variant* 
                 sp, c.reps);
 }
 
+// the AGGREGATE kernel without grouping of variant v: compiled at run time
+// for the plan when the context does so (linear probing), else the
+// precompiled one
+hipError_t scalar_kernel_launch(hawk_ctx* ctx, hipStream_t st, const hawk_variant* v, const HkPlan& P,
+                                const HkAggTable& T, int64_t groups, int32_t wg, const uint64_t* ident, int32_t W,
+                                int* err, bool allow_jit) {
+  if (allow_jit && ctx->jit && v->ht == HAWK_LINEAR_PROBING && P.xinner == 0) {
+    HkIdent id = {};
+    for (int i = 0; i < W; ++i) id.w[i] = ident[i];
+    id.nw = W;
+    std::string msg;
+    const hipError_t e = jit_scalar_launch(ctx->jit_cache, msg, st, P, T, v->mem, v->pred, v->hash, v->agg_strategy,
+                                           groups, wg, id);
+    if (e != hipSuccess && !msg.empty()) ctx->jit_cache.last_error = msg;
+    if (e != hipErrorNotSupported) return e;
+  }
+  return hk_scalar_agg(st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, ident, W, err);
+}
+
 namespace {
 
 // Where the device buffers of one execution come from.
@@ -1470,8 +1489,8 @@ hawk_status run_aggregation(Exec& X, const HkPlan& P, int grow) {
     }
   } else {
     ProfScope ps(X.prof(), "k_scalar_agg");
-    LAUNCH(hk_scalar_agg(X.st, P, T, v->mem, v->pred, v->ht, v->hash, v->agg_strategy, groups, wg, ident, W,
-                         res->d_err), "aggregation kernel");
+    LAUNCH(scalar_kernel_launch(ctx, X.st, v, P, T, groups, wg, ident, W, res->d_err, X.allow_jit),
+           "aggregation kernel");
   }
   {
     ProfScope ps(X.prof(), "k_finalize");
@@ -1667,9 +1686,18 @@ static hawk_status prepare_run_time_kernel(hawk_ctx* ctx, const hawk_query* q, c
         return set_error(ctx, HAWK_E_DEVICE, "run-time compilation: " + msg);
     return HAWK_OK;
   }
-  if (!ctx->jit || q->kind == 1 || q->main.ngroup == 0 || v->ht == HAWK_CUCKOO || q->main.xinner > 0)
+  if (!ctx->jit || q->kind == 1 || v->ht == HAWK_CUCKOO || q->main.xinner > 0)
     return HAWK_OK;  // (plans with a CROSS_JOIN run the kernels compiled ahead of time)
   if (v->wg_size < 1 || v->wg_size > 1024 || v->thread_mult < 1) return HAWK_OK;  // execution reports it
+  if (q->main.ngroup == 0) {
+    // AGGREGATE without grouping attributes
+    std::string msg;
+    const hipError_t e = jit_scalar_prepare(ctx->jit_cache, msg, q->main, v->mem, v->pred, v->hash, v->agg_strategy,
+                                            static_cast<int32_t>(v->wg_size));
+    if (e != hipSuccess && e != hipErrorNotSupported)
+      return set_error(ctx, HAWK_E_DEVICE, "run-time compilation: " + msg);
+    return HAWK_OK;
+  }
   HkAggTable T{};
   T.slot_words = q->main.slot_words;
   T.log2cap = std::max<uint32_t>(6, ceil_log2(static_cast<uint64_t>(q->groups_hint) * 2));

@@ -133,6 +133,10 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
                        const hawk_variant* v, int64_t groups, AggConfig& c);
 // the aggregation kernel of variant v: compiled at run time for the plan when
 // the context does so (linear probing), else the precompiled one
+// the same for AGGREGATE without grouping attributes
+hipError_t scalar_kernel_launch(hawk_ctx* ctx, hipStream_t st, const hawk_variant* v, const HkPlan& P,
+                                const HkAggTable& T, int64_t groups, int32_t wg, const uint64_t* ident, int32_t W,
+                                int* err, bool allow_jit = true);
 hipError_t agg_kernel_launch(hawk_ctx* ctx, hipStream_t st, const hawk_variant* v, const HkPlan& P,
                              const HkAggTable& T, const AggConfig& c, const uint64_t* ident, int32_t W, int* err,
                              const HkSpill* sp, bool allow_jit = true);

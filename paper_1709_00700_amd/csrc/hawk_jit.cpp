@@ -110,6 +110,19 @@ std::string jit_agg_source(const HkPlan& P, int mem, int pred, int ht, int hash,
   return o.str();
 }
 
+std::string jit_scalar_source(const HkPlan& P, int mem, int pred, int hash, int strat, int32_t wg) {
+  std::ostringstream o;
+  o << "#include \"hk_scalar_body.h\"\n"
+       "extern \"C\" __global__ void __launch_bounds__(" << wg << ") hk_jit_scalar(HkPlan Prt, HkAggTable T,\n"
+       "    HkIdent id, int64_t nwg) {\n";
+  HkPlan Q = P;
+  Q.nproj = 0;
+  emit_structure(o, Q);
+  o << "  scalar_body<" << mem << ", " << pred << ", " << HK_LIN << ", " << hash << ", " << strat << ", "
+    << exact_shape(P, P.naggs, 0) << ">(P, T, id, nwg);\n}\n";
+  return o.str();
+}
+
 std::string jit_proj_source(const HkPlan& P, int which, int mem, int pred, int ht, int hash, int unroll) {
   std::ostringstream o;
   const std::string S = exact_shape(P, 0, P.nproj);
@@ -150,9 +163,9 @@ hipError_t get_kernel(JitCache& cache, std::string& err_msg, const std::string& 
       }
     }
     hiprtcProgram prog;
-    const char* hs[] = {kSrcPlan, kSrcDevice, kSrcAggBody, kSrcProjBody};
-    const char* hn[] = {"hawk_plan.h", "hawk_device.h", "hk_agg_body.h", "hk_proj_body.h"};
-    if (hiprtcCreateProgram(&prog, src.c_str(), "hk_jit.hip", 4, hs, hn) != HIPRTC_SUCCESS) {
+    const char* hs[] = {kSrcPlan, kSrcDevice, kSrcAggBody, kSrcProjBody, kSrcScalarBody};
+    const char* hn[] = {"hawk_plan.h", "hawk_device.h", "hk_agg_body.h", "hk_proj_body.h", "hk_scalar_body.h"};
+    if (hiprtcCreateProgram(&prog, src.c_str(), "hk_jit.hip", 5, hs, hn) != HIPRTC_SUCCESS) {
       err_msg = "hipRTC: program creation failed";
       return hipErrorInvalidValue;
     }
@@ -252,6 +265,28 @@ hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st,
   uint32_t ll = llog2;
   int32_t rp = reps;
   void* args[] = {&Pa, &Ta, &ll, &ida, &nwg, &erra, &spa, &rp};
+  const dim3 g = hk_wg_grid(groups);
+  return hipModuleLaunchKernel(fn, g.x, g.y, 1, static_cast<uint32_t>(wg), 1, 1, 0, st, args, nullptr);
+}
+
+hipError_t jit_scalar_prepare(JitCache& cache, std::string& err_msg, const HkPlan& P, int mem, int pred, int hash,
+                              int strat, int32_t wg) {
+  hipFunction_t fn;
+  return get_kernel(cache, err_msg, jit_scalar_source(P, mem, pred, hash, strat, wg), fn, "hk_jit_scalar");
+}
+
+hipError_t jit_scalar_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P,
+                             const HkAggTable& T, int mem, int pred, int hash, int strat, int64_t groups, int32_t wg,
+                             const HkIdent& id) {
+  hipFunction_t fn;
+  const hipError_t ge =
+      get_kernel(cache, err_msg, jit_scalar_source(P, mem, pred, hash, strat, wg), fn, "hk_jit_scalar");
+  if (ge != hipSuccess) return ge;
+  HkPlan Pa = P;
+  HkAggTable Ta = T;
+  HkIdent ida = id;
+  int64_t nwg = groups;
+  void* args[] = {&Pa, &Ta, &ida, &nwg};
   const dim3 g = hk_wg_grid(groups);
   return hipModuleLaunchKernel(fn, g.x, g.y, 1, static_cast<uint32_t>(wg), 1, 1, 0, st, args, nullptr);
 }

@@ -44,6 +44,16 @@ hipError_t jit_agg_launch(JitCache& cache, std::string& err_msg, hipStream_t st,
                           uint32_t llog2, const HkIdent& id, int* err, const HkSpill* sp, int32_t reps,
                           const int32_t* stage, int32_t nstage);
 
+// Run-time specialisation of the AGGREGATE kernel without grouping
+// attributes (body in hk_scalar_body.h), `hk_jit_scalar`; same arguments and
+// launch shape as the ahead-of-time k_scalar_agg. Linear probing only.
+std::string jit_scalar_source(const HkPlan& P, int mem, int pred, int hash, int strat, int32_t wg);
+hipError_t jit_scalar_prepare(JitCache& cache, std::string& err_msg, const HkPlan& P, int mem, int pred, int hash,
+                              int strat, int32_t wg);
+hipError_t jit_scalar_launch(JitCache& cache, std::string& err_msg, hipStream_t st, const HkPlan& P,
+                             const HkAggTable& T, int mem, int pred, int hash, int strat, int64_t groups, int32_t wg,
+                             const HkIdent& id);
+
 // Run-time specialisation of the multi-pass projection kernels (bodies in
 // hk_proj_body.h) for one plan structure, same arguments and launch shape as
 // the ahead-of-time kernels.

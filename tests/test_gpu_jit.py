@@ -137,3 +137,26 @@ def test_jit_join_tables_in_lds_side_key_and_robin(ctx):
           for (a, tm, wg) in ((0, 1, 1024), (0, 8, 256), (1, 1, 512))]
     _, ref = run_variants(ctx, {"d": d, "f": fact}, spec, vs, label="jit-lds-join")
     assert -1 in set(int(k) for k in dk[d["f"] <= 6])
+
+
+@pytest.mark.parametrize("shape", ["wide", "join"])
+def test_jit_scalar_aggregate(ctx, shape):
+    # AGGREGATE without grouping attributes through its run-time kernel: the
+    # wide workload's arithmetic with 128-bit sums and a narrow AVG whose sum
+    # passes 2^63, or a star join's probes; every sampled variant against the
+    # oracle
+    if shape == "wide":
+        tables, spec = dg.c4_wide(n=100_003, price_hi=1 << 40)
+        # the last aggregate becomes a narrow AVG of charge (about 2^53 per row)
+        spec["main"]["aggs"] = list(spec["main"]["aggs"])[:-1] + [("avg", "charge", False)]
+    else:
+        tables, spec = dg.c3_star_join(n=150_000, dims=(250, 2000, 300, 800), sel=(60, 50, 60, 40))
+        spec["main"]["aggs"] = [("sum", "rev", False), ("count", None, False), ("min", "rev", False),
+                                ("max", "rev", False)]
+    spec["main"]["group_by"] = []
+    spec["main"].pop("groups_hint", None)
+    before = ctx.jit_stats()[0]
+    vs = lin_variants(ctx, tables, spec, 24, 17)
+    say("jit scalar", shape, len(vs))
+    run_variants(ctx, tables, spec, vs, label=f"jit-scalar-{shape}")
+    assert ctx.jit_stats()[0] > before

@@ -63,7 +63,7 @@ def test_compile_check_reports_bad_arguments(plan_ctx):
 
 def _generated_sources(ctx, q, v, tmp_path, monkeypatch):
     d = tmp_path / "gen"
-    d.mkdir()
+    d.mkdir(parents=True)
     monkeypatch.setenv("HAWK_JIT_DUMP", str(d))
     hawk.jit_compile_check(ctx, q, v)
     return [p.read_text() for p in sorted(d.glob("*.hip"))]
@@ -88,3 +88,20 @@ def test_no_staging_where_the_table_would_cost_residency(plan_ctx, tmp_path, mon
     v = hawk.variant(**dict(bench.DEFAULT_VARIANTS["c3"], thread_mult=8, wg_size=512))
     (src,) = _generated_sources(plan_ctx, q, v, tmp_path, monkeypatch)
     assert "stage_join" not in src
+
+
+def test_scalar_aggregate_kernel_generated(plan_ctx, tmp_path, monkeypatch):
+    # AGGREGATE without grouping attributes: its run-time kernel is
+    # generated and compiles, in both aggregation strategies
+    from paper_1709_00700_amd import datagen as dg
+    tables, spec = dg.c4_wide(n=4096)
+    spec["main"]["group_by"] = []
+    spec["main"].pop("groups_hint", None)
+    tables = {"scalar_t": tables["t"]}
+    spec["main"]["table"] = "scalar_t"
+    plan_ctx.register_shapes({t: {c: (a.dtype, len(a)) for c, a in cols.items()} for t, cols in tables.items()})
+    q = hawk.build_query(plan_ctx, spec)
+    for strat in (0, 1):
+        v = hawk.variant(mem=1, pred=strat, ht=0, hash=1, agg_strategy=strat, thread_mult=4, wg_size=256)
+        (src,) = _generated_sources(plan_ctx, q, v, tmp_path / f"s{strat}", monkeypatch)
+        assert "hk_jit_scalar" in src and "scalar_body<" in src
