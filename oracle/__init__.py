@@ -27,7 +27,11 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SANITIZED=1 loads a build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (for a process started with the ASan runtime
+# preloaded; see tests/test_oracle_sanitized.py)
+_SANITIZED = os.environ.get("ORACLE_SANITIZED") == "1"
+_SO = os.path.join(_HERE, "liboracle_san.so" if _SANITIZED else "liboracle.so")
 _lib = None
 
 ORC_I8, ORC_I32, ORC_I64 = 1, 2, 3
@@ -83,13 +87,20 @@ class _Main(ctypes.Structure):
                 ("naggs", ctypes.c_int32), ("aggs", ctypes.POINTER(_Agg))]
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with g++ (plain host code)."""
-    if force or not os.path.exists(_SO):
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-o", _SO + ".tmp",
-                               os.path.join(_HERE, "hawk_oracle.cpp")])
-        os.replace(_SO + ".tmp", _SO)
-    return _SO
+def build(force: bool = True, sanitized: bool | None = None) -> str:
+    """Compile the oracle with g++ (plain host code); sanitized: with
+    AddressSanitizer and UndefinedBehaviorSanitizer (any report aborts)."""
+    san = _SANITIZED if sanitized is None else sanitized
+    so = os.path.join(_HERE, "liboracle_san.so" if san else "liboracle.so")
+    if force or not os.path.exists(so):
+        flags = ["-O2"]
+        if san:
+            flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                     "-fno-sanitize-recover=undefined"]
+        subprocess.check_call(["g++"] + flags + ["-std=c++17", "-shared", "-fPIC", "-pthread", "-o", so + ".tmp",
+                                                 os.path.join(_HERE, "hawk_oracle.cpp")])
+        os.replace(so + ".tmp", so)
+    return so
 
 
 def _load():
