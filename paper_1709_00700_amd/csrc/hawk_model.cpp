@@ -2,7 +2,7 @@
 // mini-batch Adam with the library's own forward/backward kernels, and
 // per-query variant picks (argmin of the predicted time over the variant
 // space). Exhaustive search and Algorithm 1 stay available as the fallback
-// and as the judge of the picks.
+// and as the reference the picks are scored against.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
