@@ -17,7 +17,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhawk.so")
+# HAWK_LIBRARY names another build of the library to load (the host tests
+# load one built with sanitizers this way)
+LIB_PATH = os.environ.get("HAWK_LIBRARY") or os.path.join(HERE, "libhawk.so")
 
 # status codes
 HAWK_OK, HAWK_E_ARG, HAWK_E_NOTFOUND, HAWK_E_TYPE, HAWK_E_PLAN = 0, -1, -2, -3, -4
