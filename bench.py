@@ -111,18 +111,18 @@ def make_pipeline(name, rows=None):
 # 1.000). Valid only for the kernel sources it was measured on, with the same
 # variant: reported as null otherwise.
 TRAFFIC = {
-    "c4": {"sources_sha": "92a5adc69260ea50", "variant_sha": "e6de8da543c2592a", "total": 13315155129,
-            "per_kernel": {"k_agg": 13315120603, "k_finalize": 14335, "k_init_aggtable": 20191}},
-    "c2u": {"sources_sha": "92a5adc69260ea50", "variant_sha": "c903adb01ef30859", "total": 806228217,
-            "per_kernel": {"k_agg": 806204057, "k_finalize": 11808, "k_init_aggtable": 12352}},
-    "c2z": {"sources_sha": "92a5adc69260ea50", "variant_sha": "366d68d5fd79efd4", "total": 1974944895,
-            "per_kernel": {"k_agg": 1076106222, "k_spill_agg": 334798300, "k_spill_scatter": 562908599, "k_scan": 1118894, "k_finalize": 7944, "k_init_aggtable": 4936}},
-    "c3": {"sources_sha": "92a5adc69260ea50", "variant_sha": "366d68d5fd79efd4", "total": 3436955434,
-            "per_kernel": {"k_agg": 3428532482, "k_build": 6550434, "k_spill_agg": 935673, "k_scan": 139686, "k_spill_scatter": 784191, "k_finalize": 7936, "k_init_aggtable": 5032}},
-    "c1_256m": {"sources_sha": "92a5adc69260ea50", "variant_sha": "e551c2cb51e36aaa", "total": 5246218471,
-            "per_kernel": {"k_mp_project": 3012325005, "k_mp_filter": 2198472484, "k_scan": 35420982}},
-    "c1": {"sources_sha": "92a5adc69260ea50", "variant_sha": "928f3ef35614eef6", "total": 19643753,
-            "per_kernel": {"k_scan": 133597, "k_mp_filter": 8305061, "k_mp_project": 11205095}},
+    "c4": {"sources_sha": "b78525f97deeea9c", "variant_sha": "e6de8da543c2592a", "total": 13292939821,
+            "per_kernel": {"k_agg": 13292905295, "k_finalize": 14335, "k_init_aggtable": 20191}},
+    "c2u": {"sources_sha": "b78525f97deeea9c", "variant_sha": "c903adb01ef30859", "total": 806226194,
+            "per_kernel": {"k_agg": 806202034, "k_finalize": 11808, "k_init_aggtable": 12352}},
+    "c2z": {"sources_sha": "b78525f97deeea9c", "variant_sha": "366d68d5fd79efd4", "total": 1974709602,
+            "per_kernel": {"k_agg": 1076107356, "k_spill_agg": 334582720, "k_spill_scatter": 562887701, "k_scan": 1118945, "k_finalize": 7944, "k_init_aggtable": 4936}},
+    "c3": {"sources_sha": "b78525f97deeea9c", "variant_sha": "366d68d5fd79efd4", "total": 3434010192,
+            "per_kernel": {"k_agg": 3425588047, "k_build": 6550022, "k_spill_agg": 935313, "k_scan": 139686, "k_spill_scatter": 784156, "k_finalize": 7936, "k_init_aggtable": 5032}},
+    "c1_256m": {"sources_sha": "b78525f97deeea9c", "variant_sha": "e551c2cb51e36aaa", "total": 5246297115,
+            "per_kernel": {"k_mp_project": 3012298547, "k_mp_filter": 2198474609, "k_scan": 35523959}},
+    "c1": {"sources_sha": "b78525f97deeea9c", "variant_sha": "928f3ef35614eef6", "total": 19643731,
+            "per_kernel": {"k_scan": 133597, "k_mp_filter": 8304984, "k_mp_project": 11205150}},
 }
 TRAFFIC_SOURCES = ["hk_agg.hip", "hk_agg_body.h", "hawk_jit.cpp", "hawk_device.h", "hawk_plan.h", "hk_proj.hip",
                    "hk_proj_body.h", "hk_common.hip", "hk_scalar.hip"]
