@@ -275,6 +275,26 @@ def c5_batch(ctx, dev, pools_np, nq, pool_rows, schedule, autotune, steps, warmu
         out["learned_variants"] = {"ms": pms, "rows_per_s": total_rows / (pms / 1e3),
                                    "algo_gb_per_s": out["algo_bytes"] / (pms / 1e3) / 1e9, "kinds": kinds,
                                    "distinct_variants": len({hawk.format_variant(v) for v in picks})}
+        if jit:
+            # the same picks with the run-time compiled kernels (compiled
+            # before the capture, outside the timing)
+            try:
+                bp = hawk.Batch(ctx, hs, variants=picks, **out["schedule"])
+                rms = bp.time(reps=3)
+                bp.free()
+                rk = {}
+                for kind in (1, 2, 3):
+                    sub = [(h, v) for h, v, q in zip(hs, picks, qs) if q["kind"] == kind]
+                    rows = sum(q["rows"] for q in qs if q["kind"] == kind)
+                    bk = hawk.Batch(ctx, [h for h, _ in sub], variants=[v for _, v in sub], **out["schedule"])
+                    kms = bk.time(reps=3)
+                    bk.free()
+                    rk[str(kind)] = {"ms": kms, "rows_per_s": rows / (kms / 1e3)}
+                out["learned_variants"]["run_time_kernels"] = {
+                    "ms": rms, "rows_per_s": total_rows / (rms / 1e3),
+                    "algo_gb_per_s": out["algo_bytes"] / (rms / 1e3) / 1e9, "kinds": rk}
+            except hawk.HawkError as e:
+                out["learned_variants"]["run_time_kernels"] = {"error": str(e)}
     torch.cuda.synchronize()
     return out
 

@@ -207,3 +207,28 @@ def test_batch_cross_join_queries(ctx):
         b.run()
         check_batch(b, fake, refs, "cross joins" if variants is None else "cross joins, own variants")
         b.free()
+
+
+def test_batch_per_query_variants_run_time_kernels(ctx):
+    """Per-query variants in one graph with run-time compiled kernels: star
+    joins on one 1024-thread workgroup per CU (their first join table copied
+    into LDS), aggregations and projections in variants of their own; every
+    result against the oracle over two replays."""
+    say("batch: per-query variants, run-time kernels")
+    ctx.set_jit(True)
+    qs, hs, refs = c5_setup(ctx, 12, 1_000_000, 1000, 1_000_000, seed=dg.MASTER_SEED + 62)
+    assert 3 in {q["kind"] for q in qs}
+    variants = []
+    for q in qs:
+        if q["kind"] == 3:
+            variants.append(hawk.variant(agg_strategy=0, ht=0, hash=1, mem=1, pred=0, thread_mult=1, wg_size=1024))
+        elif q["kind"] == 2:
+            variants.append(hawk.variant(agg_strategy=0, ht=0, hash=1, mem=1, pred=1, thread_mult=1, wg_size=1024))
+        else:
+            variants.append(hawk.variant(proj_strategy=1, mem=1, pred=0, thread_mult=1024, wg_size=256))
+    b = hawk.Batch(ctx, hs, variants=variants, tile_rows_log2=15, wgs_per_cu=4, order=0)
+    for rep in range(2):
+        b.run()
+        check_batch(b, qs, refs, f"run-time kernels, replay {rep}")
+    b.free()
+    assert ctx.jit_stats()[0] >= 2
