@@ -369,8 +369,9 @@ hawk_status hawk_explore(hawk_ctx* ctx, hawk_query* const* W, int32_t k, int32_t
    do plans with a CROSS_JOIN and a generated kernel that would need scratch
    memory (register spills). A generated aggregation kernel also copies the
    join tables that fit (in plan order, up to half of a workgroup's LDS beside
-   a local table) into each workgroup's LDS and probes them there; the
-   results are the same. With the environment variable HAWK_JIT_DUMP set
+   a local table; without one, as much as leaves room for 16 resident waves
+   per CU) into each workgroup's LDS and probes them there; the results are
+   the same. With the environment variable HAWK_JIT_DUMP set
    to a directory, each generated source is also written there.
    Errors: HAWK_E_ARG, HAWK_E_DEVICE (planning context). A compilation
    failure is reported by the execution as HAWK_E_DEVICE with the compiler

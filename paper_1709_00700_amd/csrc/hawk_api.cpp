@@ -905,7 +905,14 @@ hawk_status agg_config(hawk_ctx* ctx, const HkPlan& P, const HkAggTable& T, int6
   // local table): their lookups then wait on LDS alone, not behind the
   // column loads in flight. The local table takes what remains.
   if (ctx->jit && v->ht == HAWK_LINEAR_PROBING && P.xinner == 0) {
-    const int64_t budget = v->agg_strategy == HAWK_LOCAL ? wg_lds / 2 : wg_lds;
+    int64_t budget = v->agg_strategy == HAWK_LOCAL ? wg_lds / 2 : wg_lds;
+    if (v->agg_strategy != HAWK_LOCAL) {
+      // without a local table the copies alone bound the resident
+      // workgroups: they leave room for at least 16 waves per CU
+      const int64_t waves = std::max<int64_t>(1, (v->wg_size + 63) / 64);
+      const int64_t wgs = (16 + waves - 1) / waves;
+      budget = std::min<int64_t>(budget, kCuLds / wgs - 1024);
+    }
     for (int i = 0; i < P.nprobes; ++i) {
       const int64_t tb = int64_t(8) << P.probes[i].t.log2cap;
       if (P.probes[i].t.log2cap >= 4 && c.stage_bytes + tb <= budget) {

@@ -105,3 +105,12 @@ def test_scalar_aggregate_kernel_generated(plan_ctx, tmp_path, monkeypatch):
         v = hawk.variant(mem=1, pred=strat, ht=0, hash=1, agg_strategy=strat, thread_mult=4, wg_size=256)
         (src,) = _generated_sources(plan_ctx, q, v, tmp_path / f"s{strat}", monkeypatch)
         assert "hk_jit_scalar" in src and "scalar_body<" in src
+
+
+def test_staging_keeps_small_global_workgroups_resident(plan_ctx, tmp_path, monkeypatch):
+    # the global strategy has no local table: with 64-thread workgroups the
+    # 64 KiB table would leave two waves per CU, so it stays in device memory
+    q = query_of(plan_ctx, "c3")
+    v = hawk.variant(**dict(bench.DEFAULT_VARIANTS["c3"], agg_strategy=1, wg_size=64))
+    (src,) = _generated_sources(plan_ctx, q, v, tmp_path, monkeypatch)
+    assert "stage_join" not in src
