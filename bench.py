@@ -152,7 +152,9 @@ def traffic_for(name):
 
 
 def copy_calibration(nbytes):
-    """A plain device copy of known size, for scaling the HBM byte counters."""
+    """A plain device copy of known size, for scaling the HBM byte counters;
+    also the bandwidth that the copy and a plain read (torch's int64 sum)
+    reach on this device, as practical reference points beside the peak."""
     import torch
     n = nbytes // 8
     src = torch.arange(n, dtype=torch.int64, device="cuda")
@@ -162,7 +164,23 @@ def copy_calibration(nbytes):
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_calibration_bytes": n * 8, "copies": 4}), flush=True)
+
+    def timed(f, reps=10):
+        f()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            f()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    copy_ms = timed(lambda: dst.copy_(src))
+    sum_ms = timed(lambda: src.sum())
+    print(json.dumps({"copy_calibration_bytes": n * 8, "copies": 4,
+                      "copy_gb_per_s": 2 * n * 8 / (copy_ms / 1e3) / 1e9,
+                      "read_sum_gb_per_s": n * 8 / (sum_ms / 1e3) / 1e9}), flush=True)
 
 
 def explore(ctx, pipes, mode, timing_db, args_limit_ms):
